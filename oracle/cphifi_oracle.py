@@ -42,6 +42,7 @@ import scipy.linalg as sla
 __all__ = [
     "vec", "unvec", "khatri_rao_rows", "khatri_rao", "forward_matrix",
     "mttkrp_observed", "rhs_matrix", "system_matrix", "objective", "solve_dense",
+    "solve_dense_with_error",
     "solve_lstsq", "gram_V", "matvec_twostep", "precond_matrix", "precond_diag",
     "precond_apply", "kernel_eig", "pcg", "PcgResult", "solve_pcg",
     "solve_aligned_full", "solve_decoupled", "solve_aligned_rho_kron",
@@ -97,12 +98,18 @@ def forward_matrix(K: np.ndarray, Zhat: np.ndarray, obs_t: np.ndarray) -> np.nda
     return (Zhat[:, :, None] * Khat[:, None, :]).reshape(q, r * n)
 
 
+def _segment_sum(idx: np.ndarray, vals: np.ndarray, n: int) -> np.ndarray:
+    """out[s, :] = sum of vals[l, :] over l with idx[l] == s (column by column)."""
+    out = np.zeros((n, vals.shape[1]))
+    for c in range(vals.shape[1]):
+        out[:, c] = np.bincount(idx, weights=vals[:, c], minlength=n)
+    return out
+
+
 def mttkrp_observed(y: np.ndarray, Zhat: np.ndarray, obs_t: np.ndarray,
                     n: int) -> np.ndarray:
     """B = T Z with T zero outside Omega (Section 4): B(s,:) = sum_{l: t_l=s} y_l Zhat(l,:)."""
-    Bm = np.zeros((n, Zhat.shape[1]))
-    np.add.at(Bm, obs_t, y[:, None] * Zhat)
-    return Bm
+    return _segment_sum(obs_t, y[:, None] * Zhat, n)
 
 
 def rhs_matrix(K: np.ndarray, Bm: np.ndarray) -> np.ndarray:
@@ -146,6 +153,27 @@ def solve_dense(K: np.ndarray, Zhat: np.ndarray, obs_t: np.ndarray, y: np.ndarra
     rhs = F.T @ y
     c = sla.cho_factor(H, lower=True)
     return unvec(sla.cho_solve(c, rhs), n, r)
+
+
+def solve_dense_with_error(K: np.ndarray, Zhat: np.ndarray, obs_t: np.ndarray,
+                           y: np.ndarray, lam: float, rho: float):
+    """O-dense plus an estimate of its own forward error in K W.
+
+    Returns (W, delta) where W is the Cholesky solution of :func:`solve_dense`
+    and delta = ||K D||_F / ||K W||_F for the FP64 iterative-refinement
+    correction D = unvec(H^{-1}(F^T y - H w)).  For ill-conditioned instances
+    delta is what limits any comparison against W."""
+    n = K.shape[0]
+    r = Zhat.shape[1]
+    F = forward_matrix(K, Zhat, obs_t)
+    H = system_matrix(F, K, lam, rho)
+    rhs = F.T @ y
+    c = sla.cho_factor(H, lower=True)
+    w = sla.cho_solve(c, rhs)
+    dw = sla.cho_solve(c, rhs - H @ w)
+    W = unvec(w, n, r)
+    delta = float(np.linalg.norm(K @ unvec(dw, n, r)) / np.linalg.norm(K @ W))
+    return W, delta
 
 
 def solve_lstsq(K: np.ndarray, Zhat: np.ndarray, obs_t: np.ndarray, y: np.ndarray,
@@ -193,8 +221,7 @@ def matvec_twostep(K: np.ndarray, Zhat: np.ndarray, obs_t: np.ndarray, lam: floa
     """
     Xhat = K @ X
     xbar = np.sum(Xhat[obs_t] * Zhat, axis=1)
-    Yhat1 = np.zeros_like(X)
-    np.add.at(Yhat1, obs_t, xbar[:, None] * Zhat)
+    Yhat1 = _segment_sum(obs_t, xbar[:, None] * Zhat, X.shape[0])
     return K @ Yhat1 + lam * Xhat + rho * X
 
 

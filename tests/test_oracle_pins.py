@@ -118,6 +118,21 @@ def test_lstsq_and_cholesky_agree():
     assert O.e_fit(p.K, Zhat, p.obs_t, Wl, Wd) < 1e-10
 
 
+def test_dense_error_estimate_tracks_conditioning():
+    """The refinement-based error estimate is at rounding level for a well-
+    conditioned system and grows with cond(H) (rho -> 0 makes H singular)."""
+    p = _tiny(q=25, lam=1e-1, rho=1e-1)
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    W, d_good = O.solve_dense_with_error(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho)
+    assert np.array_equal(W, O.solve_dense(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho))
+    assert 0 <= d_good < 1e-14
+    q = make_small(41, n=40, I=4, J=4, r=3, q=200, kernel_param=0.3, lam=1e-6, rho=1e-12)
+    Zq = O.khatri_rao_rows(q.A, q.B, q.obs_i, q.obs_j)
+    _, d_bad = O.solve_dense_with_error(q.K, Zq, q.obs_t, q.y, q.lam, q.rho)
+    assert d_bad > 100 * d_good
+    assert d_bad < 1e-3
+
+
 def test_rhs_is_F_transpose_y():
     """F^T y = vec(K B) with B the observed MTTKRP (Section 4, eq. unaligned-infinite-1)."""
     p = _tiny(seed=7, q=30)
