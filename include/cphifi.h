@@ -1,0 +1,211 @@
+/*
+ * cphifi.h -- C ABI of libcphifi.so, an MI355X (gfx950) solver for the
+ * unaligned infinite-dimensional (RKHS) mode subproblem of CP-HIFI tensor
+ * decompositions (Brust & Kolda, "Fast and Accurate CP-HIFI Tensor
+ * Decompositions Exploiting Kronecker Structure", Section 4).
+ *
+ * The subproblem (Section 4.1, eq. unaligned-infinite-1): given the psd kernel
+ * matrix K (n x n) of the RKHS mode, the observed entries Omega of the data
+ * tensor (q of them, each with a time index t_l in [0,n), indices i_l, j_l
+ * into the two other modes and a value y_l), the other modes' factor rows and
+ * the regularisers lambda > 0 and rho >= 0, find W (n x r) solving
+ *
+ *     (F^T F + lambda (I_r kron K) + rho I) vec(W) = vec(K B),
+ *
+ * where row l of F is Zhat(l,:) kron K(t_l,:) (eq. F), Zhat(l,:) =
+ * A(i_l,:) * B(j_l,:) (eq. zhat) and B(s,:) = sum_{l: t_l = s} y_l Zhat(l,:)
+ * is the observed MTTKRP.  The time factor used by CP-HIFI is K W.
+ *
+ * Method (Section 4.4): preconditioned conjugate gradients with the two-step
+ * Kronecker product (Section 4.4.1, eqs. vl, yhat1) and the preconditioner
+ * M = gamma V kron K^2 + lambda I kron K + rho I applied through the
+ * eigendecompositions of K and V = Z^T Z (Section 4.4.2, eqs. precon, fx).
+ *
+ * Conventions
+ *  - Every matrix argument is a DEVICE pointer unless stated otherwise, owned by
+ *    the caller, and must stay valid for the plan's lifetime.
+ *  - n x r unknowns (W, X, B, ...) are row-major: element (s, c) at [s*r + c].
+ *    (The paper's vec is column-major; vec(W)[c*n + s] = W[s*r + c].)
+ *  - K and UK are n x n with row stride `ldk` >= n (elements).  UK holds the
+ *    eigenvectors of K in LAPACK (column-major) order: eigenvector k occupies
+ *    UK[k*ldk + 0 .. k*ldk + n-1], with eigenvalue dK[k].
+ *  - All work is enqueued on the plan's HIP stream (`stream`, a hipStream_t;
+ *    NULL = the null stream).  Functions marked "async" return before the GPU
+ *    finishes; those marked "sync" synchronise the stream before returning.
+ *  - Every function returns a status code (CPHIFI_*).  No exception crosses
+ *    the ABI.  On failure cphifi_last_error() gives a thread-local message.
+ *  - The library never allocates device memory on the solve path: the caller
+ *    provides a workspace of cphifi_ui_workspace_bytes() bytes.
+ *  - A plan is not thread-safe.  Distinct plans may run on distinct streams.
+ */
+#ifndef CPHIFI_H
+#define CPHIFI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define CPHIFI_API __attribute__((visibility("default")))
+#else
+#define CPHIFI_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------------- status */
+enum cphifi_status {
+  CPHIFI_OK = 0,
+  CPHIFI_INVALID_ARG = 1,    /* bad size, null pointer, bad parameter, small workspace */
+  CPHIFI_HIP_ERROR = 2,      /* a HIP runtime call failed; detail in cphifi_last_error() */
+  CPHIFI_UNSUPPORTED = 3,    /* valid request this build does not implement */
+  CPHIFI_BREAKDOWN = 4,      /* PCG breakdown: p^T A p <= 0 or r^T z <= 0 */
+  CPHIFI_NUMERIC = 5,        /* NaN or Inf met in the iteration */
+  CPHIFI_NOT_CONVERGED = 6   /* soft: iteration cap reached; W and info still written */
+};
+
+/* ------------------------------------------------------------- precision */
+enum cphifi_precision {
+  CPHIFI_FP64 = 0,        /* PCG of Section 4.4 entirely in FP64 (paper form) */
+  CPHIFI_MIXED_FP32 = 1,  /* FP64 iterative refinement around an FP32-MFMA inner PCG */
+  CPHIFI_MIXED_BF16 = 2   /* same, with the eigenvector products in BF16 MFMA */
+};
+
+/* ------------------------------------------------------------------ flags */
+enum cphifi_flags {
+  CPHIFI_FLAG_WARM_START = 1,   /* W holds x0 on entry to solve (else x0 = 0) */
+  CPHIFI_FLAG_VALIDATE = 2,     /* plan_create checks obs_* ranges on the host */
+  CPHIFI_FLAG_TIME_KERNELS = 4, /* record HIP events around each n x n product */
+  CPHIFI_FLAG_NO_PRECOND = 8,   /* plain CG (identity preconditioner), FP64 only */
+  CPHIFI_FLAG_EIGENBASIS = 16   /* FP64 PCG in the eigenbasis of K (2 n x n passes
+                                   per iteration instead of 4); same solution */
+};
+
+/* Problem description (host struct). */
+typedef struct cphifi_ui_desc {
+  int64_t n;          /* design points of the RKHS mode (rows of K), >= 1 */
+  int64_t r;          /* CP rank, 1..64 */
+  int64_t q;          /* number of observations, >= 0 */
+  int64_t I, J;       /* rows of A and B (implicit factor form); ignored with Zhat */
+  int64_t ldk;        /* row stride of K and UK in elements, >= n; 0 means n */
+  double lambda;      /* RKHS regulariser, > 0 */
+  double rho;         /* shift of Section 4.1, >= 0 */
+  double gamma;       /* density of the preconditioner; <= 0 means q / (n I J) */
+  double tol;         /* relative residual target ||b - A w|| / ||b|| */
+  double inner_tol;   /* mixed forms: inner PCG relative tolerance (<= 0: 1e-3) */
+  int32_t precision;  /* enum cphifi_precision */
+  int32_t flags;      /* OR of enum cphifi_flags */
+  int32_t maxit;      /* PCG iteration cap (FP64) or inner cap (mixed); <= 0: 500 */
+  int32_t max_refine; /* mixed forms: outer refinement steps; <= 0: 30 */
+  int32_t check_every;/* host convergence poll period in iterations; <= 0: auto */
+  int32_t reserved;
+} cphifi_ui_desc;
+
+/* Device inputs (caller-owned; must outlive the plan). */
+typedef struct cphifi_ui_inputs {
+  const double* K;         /* n x n (stride ldk), symmetric psd */
+  const double* UK;        /* n x n (stride ldk), eigenvectors of K, column-major */
+  const double* dK;        /* n eigenvalues of K (same order as UK) */
+  const int32_t* obs_ptr;  /* n+1, CSR by time: observations of time s are
+                              obs_ptr[s] .. obs_ptr[s+1]-1; obs_ptr[0] = 0,
+                              obs_ptr[n] = q, nondecreasing */
+  const int32_t* obs_i;    /* q, index into A's rows (implicit form) */
+  const int32_t* obs_j;    /* q, index into B's rows (implicit form) */
+  const double* A;         /* I x r row-major, or NULL with Zhat */
+  const double* B;         /* J x r row-major, or NULL with Zhat */
+  const double* Zhat;      /* q x r row-major per-observation Khatri-Rao rows
+                              (eq. zhat, any tensor order); NULL = implicit form */
+  const double* V;         /* r x r Gram Z^T Z; required with Zhat, optional
+                              otherwise (NULL: computed as (A^T A) had (B^T B)) */
+} cphifi_ui_inputs;
+
+typedef struct cphifi_solve_info {
+  int32_t status;          /* CPHIFI_* of the solve */
+  int32_t iters;           /* PCG iterations (FP64) / total inner iterations (mixed) */
+  int32_t refine_steps;    /* mixed forms: outer steps taken */
+  int32_t gemm_launches;   /* with CPHIFI_FLAG_TIME_KERNELS: timed n x n products */
+  double relres_true;      /* ||vec(KB) - A w|| / ||vec(KB)||, recomputed in FP64 */
+  double relres_recursive; /* last recursively updated residual (FP64 PCG) */
+  double gemm_ms;          /* with CPHIFI_FLAG_TIME_KERNELS: summed event time */
+  double* history;         /* optional HOST buffer of maxit+1 doubles receiving the
+                              recursive relative residual per iteration, or NULL */
+} cphifi_solve_info;
+
+typedef struct cphifi_plan cphifi_plan;
+
+/* Bytes of device workspace a plan for `d` needs (host-only; no GPU call). */
+CPHIFI_API int cphifi_ui_workspace_bytes(const cphifi_ui_desc* d, size_t* bytes);
+
+/* Validate `d` and `in`, carve `workspace` (device, >= workspace_bytes bytes,
+ * 256-byte aligned) and prepare per-K state: observation work lists and, for
+ * the mixed forms, the low-precision copies of U_K.  sync.
+ * Errors: INVALID_ARG (n, r, q, I, J out of range; r > 64; lambda <= 0; rho < 0;
+ * tol <= 0; missing pointers; both or neither of Zhat / (A,B); Zhat without V;
+ * workspace too small or misaligned; with FLAG_VALIDATE an obs index out of
+ * range), HIP_ERROR. */
+CPHIFI_API int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d,
+                          const cphifi_ui_inputs* in, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* Per-solve setup of Section 4.4.2: V = Z^T Z (unless given), the
+ * eigendecomposition V = U_V D_V U_V^T (eq. eigV, one-workgroup Jacobi) and
+ * D(s,c) = 1 / (gamma dV_c dK_s^2 + lambda dK_s + rho) with dK clamped at 0.
+ * async. */
+CPHIFI_API int cphifi_ui_setup(cphifi_plan* p);
+
+/* Right-hand side of eq. unaligned-infinite-1: b = K B with the observed
+ * MTTKRP B(s,:) = sum_{l: t_l = s} y_l Zhat(l,:).  y: q doubles (device);
+ * b: n x r row-major (device).  async. */
+CPHIFI_API int cphifi_ui_rhs(cphifi_plan* p, const double* y, double* b);
+
+/* y = (F^T F + lambda I kron K + rho I) x by the two-step product of Section
+ * 4.4.1, in FP64.  x, y: n x r row-major device buffers (distinct).  async. */
+CPHIFI_API int cphifi_ui_apply(cphifi_plan* p, const double* x, double* y);
+
+/* z = M^{-1} x by eq. fx in FP64 (requires cphifi_ui_setup).  async. */
+CPHIFI_API int cphifi_ui_precond(cphifi_plan* p, const double* x, double* z);
+
+/* Operator in the eigenbasis of K at the plan's precision:
+ * ybar = D_K Ut G(Ut^T D_K xbar) + lambda D_K xbar + rho xbar, where Ut is
+ * U_K rounded to the plan precision and G is the gather-scatter of eqs. vl and
+ * yhat1.  Equals U_K^T A U_K xbar for exact Ut.  async. */
+CPHIFI_API int cphifi_ui_apply_lowp(cphifi_plan* p, const double* xbar, double* ybar);
+
+/* Solve A w = b (b: n x r device, e.g. from cphifi_ui_rhs) by the plan's
+ * method; W (n x r device) receives the solution (and holds x0 on entry when
+ * FLAG_WARM_START is set).  info (host) is filled; its status is also the
+ * return value unless an argument or HIP error occurred first.  sync. */
+CPHIFI_API int cphifi_ui_solve(cphifi_plan* p, const double* b, double* W,
+                    cphifi_solve_info* info);
+
+/* Whole subproblem from the observed values: setup, right-hand side, solve
+ * and the FP64 true residual.  y: q doubles (device).  sync. */
+CPHIFI_API int cphifi_ui_solve_subproblem(cphifi_plan* p, const double* y, double* W,
+                               cphifi_solve_info* info);
+
+/* Release host-side plan state (the workspace belongs to the caller). */
+CPHIFI_API int cphifi_ui_plan_destroy(cphifi_plan* p);
+
+/* One-time eigendecomposition K = U_K D_K U_K^T (eq. eigK) on the device
+ * with rocSOLVER's divide-and-conquer symmetric eigensolver.  K (n x n,
+ * stride ldk) is read; UK (n x n, stride ldk, column-major eigenvectors) and
+ * dK (n, ascending) are written.  Allocates and frees its own scratch (setup
+ * path only).  sync.  Errors: INVALID_ARG, HIP_ERROR, NUMERIC (solver failed
+ * to converge). */
+CPHIFI_API int cphifi_kernel_eig(int64_t n, const double* K, int64_t ldk, double* UK,
+                      double* dK, void* stream);
+
+/* Human-readable name of a status code (static string). */
+CPHIFI_API const char* cphifi_status_string(int status);
+
+/* Detail of the last error on the calling thread ("" if none). */
+CPHIFI_API const char* cphifi_last_error(void);
+
+/* Library version string, e.g. "cphifi 0.1.0 gfx950". */
+CPHIFI_API const char* cphifi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPHIFI_H */

@@ -1,0 +1,240 @@
+"""ctypes binding of libcphifi.so (the C ABI in include/cphifi.h).
+
+Functions keep the C names and take plain integers for device pointers and the
+HIP stream.  Nothing here computes: every step of the solve runs in the
+library's HIP kernels.  The library must be built in-tree
+(``python -m paper_2603_25691_amd.build``); importing this module raises if it
+is missing, and there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcphifi.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "cphifi.h")
+
+# ------------------------------------------------------------ constants
+OK = 0
+INVALID_ARG = 1
+HIP_ERROR = 2
+UNSUPPORTED = 3
+BREAKDOWN = 4
+NUMERIC = 5
+NOT_CONVERGED = 6
+
+FP64 = 0
+MIXED_FP32 = 1
+MIXED_BF16 = 2
+
+FLAG_WARM_START = 1
+FLAG_VALIDATE = 2
+FLAG_TIME_KERNELS = 4
+FLAG_NO_PRECOND = 8
+FLAG_EIGENBASIS = 16
+
+PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
+
+
+class cphifi_ui_desc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("r", C.c_int64), ("q", C.c_int64), ("I", C.c_int64),
+        ("J", C.c_int64), ("ldk", C.c_int64),
+        ("lambda_", C.c_double), ("rho", C.c_double), ("gamma", C.c_double),
+        ("tol", C.c_double), ("inner_tol", C.c_double),
+        ("precision", C.c_int32), ("flags", C.c_int32), ("maxit", C.c_int32),
+        ("max_refine", C.c_int32), ("check_every", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class cphifi_ui_inputs(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in
+                ("K", "UK", "dK", "obs_ptr", "obs_i", "obs_j", "A", "B", "Zhat", "V")]
+
+
+class cphifi_solve_info(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("iters", C.c_int32), ("refine_steps", C.c_int32),
+        ("gemm_launches", C.c_int32), ("relres_true", C.c_double),
+        ("relres_recursive", C.c_double), ("gemm_ms", C.c_double),
+        ("history", C.c_void_p),
+    ]
+
+    def as_dict(self):
+        return {
+            "status": status_string(self.status), "iters": self.iters,
+            "refine_steps": self.refine_steps, "relres_true": self.relres_true,
+            "relres_recursive": self.relres_recursive, "gemm_ms": self.gemm_ms,
+            "gemm_launches": self.gemm_launches,
+        }
+
+
+class CphifiError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {status_string(status)}: {detail}")
+        self.status = status
+
+
+def _single_hip_runtime() -> None:
+    """torch ships its own libamdhip64 under the same SONAME as ROCm's.  Loading
+    torch first makes the dynamic linker resolve this library's HIP runtime to
+    torch's copy, so device memory from torch and kernels launched here live in
+    one runtime.  (Loading this library first would give the process two HIP
+    runtimes, and the second one to initialise sees no device.)"""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
+def _load() -> C.CDLL:
+    _single_hip_runtime()
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2603_25691_amd.build` "
+            "(the HIP library is the only implementation; there is no fallback)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "cphifi_ui_workspace_bytes": (C.c_int, [C.POINTER(cphifi_ui_desc), C.POINTER(C.c_size_t)]),
+        "cphifi_ui_plan_create": (C.c_int, [C.POINTER(P), C.POINTER(cphifi_ui_desc),
+                                            C.POINTER(cphifi_ui_inputs), P, C.c_size_t, P]),
+        "cphifi_ui_setup": (C.c_int, [P]),
+        "cphifi_ui_rhs": (C.c_int, [P, P, P]),
+        "cphifi_ui_apply": (C.c_int, [P, P, P]),
+        "cphifi_ui_precond": (C.c_int, [P, P, P]),
+        "cphifi_ui_apply_lowp": (C.c_int, [P, P, P]),
+        "cphifi_ui_solve": (C.c_int, [P, P, P, C.POINTER(cphifi_solve_info)]),
+        "cphifi_ui_solve_subproblem": (C.c_int, [P, P, P, C.POINTER(cphifi_solve_info)]),
+        "cphifi_ui_plan_destroy": (C.c_int, [P]),
+        "cphifi_kernel_eig": (C.c_int, [C.c_int64, P, C.c_int64, P, P, P]),
+        "cphifi_status_string": (C.c_char_p, [C.c_int]),
+        "cphifi_last_error": (C.c_char_p, []),
+        "cphifi_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> C.CDLL:
+    return _lib
+
+
+def declared_functions(header: str = HEADER_PATH):
+    """Names of the functions include/cphifi.h declares."""
+    text = open(header).read()
+    return sorted(set(re.findall(r"CPHIFI_API\s+[\w\s\*]+?\b(cphifi_\w+)\s*\(", text)))
+
+
+def status_string(status: int) -> str:
+    return _lib.cphifi_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return _lib.cphifi_last_error().decode()
+
+
+def version() -> str:
+    return _lib.cphifi_version().decode()
+
+
+def _check(status: int, where: str, soft_ok: bool = False) -> int:
+    if status == OK or (soft_ok and status == NOT_CONVERGED):
+        return status
+    raise CphifiError(status, where, last_error())
+
+
+def cphifi_ui_workspace_bytes(desc: cphifi_ui_desc) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.cphifi_ui_workspace_bytes(C.byref(desc), C.byref(out)),
+           "cphifi_ui_workspace_bytes")
+    return int(out.value)
+
+
+def cphifi_ui_plan_create(desc: cphifi_ui_desc, inputs: cphifi_ui_inputs, workspace: int,
+                          workspace_bytes: int, stream: int) -> int:
+    plan = C.c_void_p(0)
+    _check(_lib.cphifi_ui_plan_create(C.byref(plan), C.byref(desc), C.byref(inputs),
+                                      C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+                                      C.c_void_p(stream)), "cphifi_ui_plan_create")
+    return int(plan.value)
+
+
+def cphifi_ui_setup(plan: int) -> None:
+    _check(_lib.cphifi_ui_setup(C.c_void_p(plan)), "cphifi_ui_setup")
+
+
+def cphifi_ui_rhs(plan: int, y: int, b: int) -> None:
+    _check(_lib.cphifi_ui_rhs(C.c_void_p(plan), C.c_void_p(y), C.c_void_p(b)), "cphifi_ui_rhs")
+
+
+def cphifi_ui_apply(plan: int, x: int, y: int) -> None:
+    _check(_lib.cphifi_ui_apply(C.c_void_p(plan), C.c_void_p(x), C.c_void_p(y)),
+           "cphifi_ui_apply")
+
+
+def cphifi_ui_precond(plan: int, x: int, z: int) -> None:
+    _check(_lib.cphifi_ui_precond(C.c_void_p(plan), C.c_void_p(x), C.c_void_p(z)),
+           "cphifi_ui_precond")
+
+
+def cphifi_ui_apply_lowp(plan: int, xbar: int, ybar: int) -> None:
+    _check(_lib.cphifi_ui_apply_lowp(C.c_void_p(plan), C.c_void_p(xbar), C.c_void_p(ybar)),
+           "cphifi_ui_apply_lowp")
+
+
+def cphifi_ui_solve(plan: int, b: int, W: int, history=None) -> cphifi_solve_info:
+    info = cphifi_solve_info()
+    if history is not None:
+        info.history = history.ctypes.data
+    st = _lib.cphifi_ui_solve(C.c_void_p(plan), C.c_void_p(b), C.c_void_p(W), C.byref(info))
+    _check(st, "cphifi_ui_solve", soft_ok=True)
+    return info
+
+
+def cphifi_ui_solve_subproblem(plan: int, y: int, W: int, history=None) -> cphifi_solve_info:
+    info = cphifi_solve_info()
+    if history is not None:
+        info.history = history.ctypes.data
+    st = _lib.cphifi_ui_solve_subproblem(C.c_void_p(plan), C.c_void_p(y), C.c_void_p(W),
+                                         C.byref(info))
+    _check(st, "cphifi_ui_solve_subproblem", soft_ok=True)
+    return info
+
+
+def cphifi_ui_plan_destroy(plan: int) -> None:
+    _check(_lib.cphifi_ui_plan_destroy(C.c_void_p(plan)), "cphifi_ui_plan_destroy")
+
+
+def cphifi_kernel_eig(n: int, K: int, ldk: int, UK: int, dK: int, stream: int) -> None:
+    _check(_lib.cphifi_kernel_eig(C.c_int64(n), C.c_void_p(K), C.c_int64(ldk), C.c_void_p(UK),
+                                  C.c_void_p(dK), C.c_void_p(stream)), "cphifi_kernel_eig")
+
+
+def make_desc(n: int, r: int, q: int, I: int = 0, J: int = 0, lam: float = 1e-3,
+              rho: float = 1e-6, gamma: float = 0.0, tol: float = 1e-10,
+              precision: int = FP64, flags: int = 0, maxit: int = 0, max_refine: int = 0,
+              inner_tol: float = 0.0, check_every: int = 0, ldk: int = 0) -> cphifi_ui_desc:
+    d = cphifi_ui_desc()
+    d.n, d.r, d.q, d.I, d.J, d.ldk = n, r, q, I, J, ldk
+    d.lambda_, d.rho, d.gamma, d.tol, d.inner_tol = lam, rho, gamma, tol, inner_tol
+    d.precision, d.flags, d.maxit, d.max_refine = precision, flags, maxit, max_refine
+    d.check_every = check_every
+    return d
+
+
+def make_inputs(**ptrs: Optional[int]) -> cphifi_ui_inputs:
+    inp = cphifi_ui_inputs()
+    for k, v in ptrs.items():
+        setattr(inp, k, None if v is None else int(v))
+    return inp

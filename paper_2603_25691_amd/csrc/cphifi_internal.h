@@ -1,0 +1,185 @@
+// Internal declarations shared by the libcphifi translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/cphifi.h"
+
+namespace cphifi {
+
+// ----------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define CPHIFI_HIP(call)                                                         \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ::cphifi::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                          __FILE__, __LINE__);                                   \
+      return CPHIFI_HIP_ERROR;                                                   \
+    }                                                                            \
+  } while (0)
+
+#define CPHIFI_CHECK_LAUNCH()                                                    \
+  do {                                                                           \
+    hipError_t e_ = hipGetLastError();                                           \
+    if (e_ != hipSuccess) {                                                      \
+      ::cphifi::set_error("kernel launch failed: %s (%s:%d)",                    \
+                          hipGetErrorString(e_), __FILE__, __LINE__);            \
+      return CPHIFI_HIP_ERROR;                                                   \
+    }                                                                            \
+  } while (0)
+
+constexpr int kMaxRank = 64;
+constexpr int kWave = 64;
+constexpr int kVecThreads = 256;     // threads of the elementwise / reduction kernels
+constexpr int kMaxVecBlocks = 1024;  // upper bound on their grid (reduction partials)
+constexpr int kMaxSplit = 16;        // upper bound on split-K of the n x n products
+constexpr int kObsChunk = 1024;      // max observations per gather-scatter task
+constexpr int kLowpAlign = 256;      // row stride alignment (elements) of the low-precision copies
+
+// Scalars of one PCG run, resident in device memory so the whole iteration is
+// enqueued without host round trips.  rz is double-buffered by iteration
+// parity: iteration `it` reads rz[it & 1] and writes rz[(it + 1) & 1].
+struct DevScalars {
+  double rz[2];
+  double bb;      // ||b||^2
+  double rr;      // last ||r||^2
+  double pq;      // last p^T A p
+  double tol2;    // (tol)^2 * bb, convergence threshold on ||r||^2
+  double scratch[2];
+  int32_t done;   // 1 once converged or failed: every later kernel of the run exits
+  int32_t iters;  // iterations completed when done was set
+  int32_t status; // CPHIFI_* decided on the device
+  int32_t zero;   // always 0: "not done" flag for kernels run outside a PCG loop
+};
+
+// Element type of the eigenvector / kernel matrix operand of a product.
+enum class Elt { F64 = 0, F32 = 1, BF16 = 2 };
+
+// ------------------------------------------------------------ n x n products
+// part[sp][i][c] (row stride ldp = 16*ceil(r/16)) receives
+//   sum_{k in split sp} op(U)[i][k] * xscale[k] * X[k][c]
+// with op(U) = U (row-major, stride ldu) or U^T when `trans`.
+// F64: double partials; F32/BF16: float partials.
+struct GemmPlan {
+  int ksplit = 1;
+  int64_t kper = 0;
+  int mw = 2;   // 16-row MFMA blocks per wave (4 waves per workgroup)
+  int s = 8;    // MFMA steps per k chunk (chunk = 4*s rows of X; 32*s for BF16)
+};
+GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu);
+// Plan with an explicit tile; ksplit_req <= 0 picks the split from the CU count.
+GemmPlan make_gemm_plan(Elt elt, int64_t n, int mw, int s, int ksplit_req, int num_cu);
+bool gemm_cfg_valid(Elt elt, int mw, int s);
+int gemm_bk(Elt elt, int s);  // k-chunk of the kernel (kper is a multiple of it)
+int launch_gemm(Elt elt, bool trans, const GemmPlan& gp, const void* U, int64_t ldu,
+                int64_t n, const double* X, int64_t ldx, int r, const double* xscale,
+                void* part, const int32_t* done, hipStream_t st);
+// BF16 product: X is first split (launch_split_bf16) into hi/lo bf16 parts,
+// c-major rows of stride ldxt >= round_up(n, chunk) in xt_hi / xt_lo; U has row
+// stride ldu >= that too and zero padding beyond column n.
+int launch_split_bf16(const double* X, int64_t ldx, int r, const double* xscale, int64_t n,
+                      __bf16* xt_hi, __bf16* xt_lo, int64_t ldxt, const int32_t* done,
+                      hipStream_t st);
+int launch_gemm_bf16(const GemmPlan& gp, const __bf16* U, int64_t ldu, int64_t n,
+                     const double* X, int64_t ldx, int r, const double* xscale, void* part,
+                     __bf16* xt_hi, __bf16* xt_lo, int64_t ldxt, const int32_t* done,
+                     hipStream_t st);
+
+// --------------------------------------------------- gather-dot-scatter (a5/a6)
+struct ObsTasks {
+  int32_t ntask = 0;
+  int32_t nmulti = 0;          // segments split over several tasks
+  int32_t* seg = nullptr;      // [ntask] segment (time index) of the task
+  int32_t* beg = nullptr;      // [ntask] first observation
+  int32_t* end = nullptr;      // [ntask] one past the last observation
+  int32_t* slot = nullptr;     // [ntask] -1: sole task of its segment, else partial row
+  int32_t* first = nullptr;    // [ntask] 1 if first task of its segment
+  int32_t* mseg = nullptr;     // [nmulti] segments with several tasks
+  int32_t* mptr = nullptr;     // [nmulti+1] their task-slot ranges
+};
+
+struct ObsArgs {
+  int64_t n;
+  int r;
+  const int32_t* obs_i;
+  const int32_t* obs_j;
+  const double* A;
+  const double* B;
+  const double* Zhat;
+  const double* y;          // MTTKRP mode: observed values
+  const void* part;         // gather mode: split partials of Xhat (double or float)
+  int ksplit;
+  int ldp;
+  double* Xhat;             // gather mode: receives Xhat (may be null)
+  double* out;              // n x r result (Yhat1 or the MTTKRP B)
+  double* tpart;            // partial rows of split segments
+  const int32_t* done;
+};
+enum class ObsMode { Gather = 0, Mttkrp = 1 };
+// I, J bound the implicit-form indices (clamped on the device; range errors are
+// reported by plan validation, never turned into out-of-bounds reads).
+int launch_obs(ObsMode mode, bool part_is_float, const ObsTasks& t, const ObsArgs& a,
+               int64_t I, int64_t J, hipStream_t st);
+
+// ----------------------------------------------------------- vector kernels
+// Reductions are two-stage and deterministic: a producing kernel writes one
+// partial per block into `red` (grid <= kMaxVecBlocks), and every consumer
+// sums those partials in the same fixed order.
+int vec_blocks(int64_t len);
+// out[s][c] = sum_sp part[sp][s][c]; with dotwith: red[blk] = sum dotwith . out
+int launch_reduce_partials(const void* part, bool is_float, int ksplit, int ldp, int64_t n,
+                           int r, double* out, const double* dotwith, double* red,
+                           int* nblk_out, const int32_t* done, hipStream_t st);
+// q = Y + lam*xhat + rho*p (paper form), or q = d*(Y + lam*p) + rho*p when dscale
+// is given (eigenbasis form), Y = sum of partials; red[blk] = sum p . q.
+int launch_apply_finish(const void* part, bool is_float, int ksplit, int ldp, int64_t n,
+                        int r, const double* xhat, const double* p, const double* dscale,
+                        double lam, double rho, double* q, double* red, int* nblk_out,
+                        const int32_t* done, hipStream_t st);
+int launch_dot(const double* a, const double* b, int64_t len, double* red, int* nblk_out,
+               const int32_t* done, hipStream_t st);
+int launch_update_xr(double* x, double* r, const double* p, const double* q, int64_t len,
+                     const double* red_pq, int nblk_pq, double* red_rr, int* nblk_out,
+                     DevScalars* sc, int it, hipStream_t st);
+int launch_check_conv(const double* red_rr, int nblk, DevScalars* sc, int it, double* hist,
+                      int hist_len, hipStream_t st);
+// out[s,:] = ((in[s,:] U_V) * D[s,:]) U_V^T with in = sum of partials when part is
+// given; with dotwith: red[blk] = sum dotwith . out.
+int launch_prec_mid(const void* part, bool is_float, int ksplit, int ldp, const double* in,
+                    int64_t n, int r, const double* UV, const double* D, double* out,
+                    const double* dotwith, double* red, int* nblk_out, const int32_t* done,
+                    hipStream_t st);
+int launch_update_p(double* p, const double* z, int64_t len, const double* red_rz,
+                    int nblk, DevScalars* sc, int it, hipStream_t st);
+int launch_pcg_init(DevScalars* sc, const double* red_bb, int nblk_bb, const double* red_rr,
+                    int nblk_rr, const double* red_rz, int nblk_rz, double tol, double* hist,
+                    int hist_len, hipStream_t st);
+// sc->scratch[slot] = sum of partials (single block)
+int launch_store_sum(const double* red, int nblk, DevScalars* sc, int slot, hipStream_t st);
+int launch_axpby(double* y, double a, const double* x, double b, int64_t len,
+                 const int32_t* done, hipStream_t st);
+int launch_copy(double* dst, const double* src, int64_t len, hipStream_t st);
+int launch_fill(double* dst, double v, int64_t len, hipStream_t st);
+int launch_fill_i32(int32_t* dst, int32_t v, int64_t len, hipStream_t st);
+int launch_gram(const double* A, int64_t I, const double* B, int64_t J, int r, double* V,
+                hipStream_t st);
+int launch_jacobi_eig(const double* V, int r, double* UV, double* dV, hipStream_t st);
+int launch_precond_diag(const double* dK, const double* dV, int64_t n, int r, double gamma,
+                        double lam, double rho, double* D, hipStream_t st);
+int launch_clamp_nonneg(const double* src, double* dst, int64_t n, hipStream_t st);
+// dst (n rows, stride ld_dst, zero-padded to ld_dst columns) = lowp(src) or
+// lowp(src^T); src is n x n with stride ld_src.
+int launch_convert_lowp(Elt elt, bool transpose, const double* src, int64_t ld_src, int64_t n,
+                        void* dst, int64_t ld_dst, hipStream_t st);
+
+}  // namespace cphifi

@@ -1,0 +1,968 @@
+// Plan, operators and solvers behind the C ABI of cphifi.h.
+//
+// The FP64 method is Section 4.4 of the paper: PCG on
+//   (F^T F + lambda I kron K + rho I) vec(W) = vec(K B)
+// with the two-step product (Section 4.4.1) and the eq. (fx) preconditioner
+// (Section 4.4.2).  The mixed forms keep that FP64 system as the target of an
+// iterative-refinement loop whose inner solves run in the eigenbasis of K
+// (x = U_K xbar, the rotation the paper uses for the aligned PCG of Section
+// 3.3): there the operator is D_K U^T G(U D_K xbar) + lambda D_K xbar + rho xbar,
+// which stays symmetric positive definite when U is rounded to FP32 or BF16,
+// and the preconditioner of eq. (fx) reduces to its r x r middle step.
+#include "cphifi_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+
+namespace cphifi {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace cphifi
+
+using namespace cphifi;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+enum VecSlot {
+  V_R = 0, V_Z, V_P, V_Q,           // outer / FP64 PCG vectors
+  V_XHAT, V_Y1, V_T2, V_B,          // product intermediates, internal right-hand side
+  V_RF, V_RB, V_XB,                 // refinement residual, its eigenbasis image, correction
+  V_R2, V_Z2, V_P2, V_Q2,           // eigenbasis PCG vectors
+  V_TMP,
+  NVEC
+};
+
+struct Layout {
+  size_t vec[NVEC];
+  size_t part, tpart;
+  size_t tseg, tbeg, tend, tslot, tfirst, mseg, mptr;
+  size_t red[3];
+  size_t sc, sc2, hist;
+  size_t V, UV, dV, D, dKc;
+  size_t ulp, utlp, xthi, xtlo;
+  size_t total;
+  int64_t ldl;
+  int64_t ntask_max, nslot_max, nmulti_max;
+  int hist_len;
+};
+
+int64_t eff_ldk(const cphifi_ui_desc& d) { return d.ldk > 0 ? d.ldk : d.n; }
+int eff_maxit(const cphifi_ui_desc& d) { return d.maxit > 0 ? d.maxit : 500; }
+
+Layout make_layout(const cphifi_ui_desc& d) {
+  Layout L{};
+  const int64_t n = d.n, r = d.r, q = d.q;
+  const int64_t nr = n * r;
+  const int64_t ldp = round_up(r, 16);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align_up(off, kAlign);
+    const size_t o = off;
+    off += std::max<size_t>(bytes, 1);
+    return o;
+  };
+  for (int i = 0; i < NVEC; ++i) L.vec[i] = take(sizeof(double) * nr);
+  L.part = take(sizeof(double) * (size_t)kMaxSplit * n * ldp);
+  L.ntask_max = n + q / kObsChunk + 1;
+  L.nslot_max = 2 * (q / kObsChunk) + 2;
+  L.nmulti_max = q / kObsChunk + 1;
+  L.tpart = take(sizeof(double) * (size_t)L.nslot_max * r);
+  L.tseg = take(sizeof(int32_t) * L.ntask_max);
+  L.tbeg = take(sizeof(int32_t) * L.ntask_max);
+  L.tend = take(sizeof(int32_t) * L.ntask_max);
+  L.tslot = take(sizeof(int32_t) * L.ntask_max);
+  L.tfirst = take(sizeof(int32_t) * L.ntask_max);
+  L.mseg = take(sizeof(int32_t) * L.nmulti_max);
+  L.mptr = take(sizeof(int32_t) * (L.nmulti_max + 1));
+  for (int i = 0; i < 3; ++i) L.red[i] = take(sizeof(double) * kMaxVecBlocks);
+  L.sc = take(sizeof(DevScalars));
+  L.sc2 = take(sizeof(DevScalars));
+  L.hist_len = eff_maxit(d) + 2;
+  L.hist = take(sizeof(double) * L.hist_len);
+  L.V = take(sizeof(double) * r * r);
+  L.UV = take(sizeof(double) * r * r);
+  L.dV = take(sizeof(double) * r);
+  L.D = take(sizeof(double) * nr);
+  L.dKc = take(sizeof(double) * n);
+  L.ldl = round_up(n, kLowpAlign);
+  if (d.precision == CPHIFI_MIXED_BF16) {
+    L.ulp = take(sizeof(__bf16) * (size_t)n * L.ldl);
+    L.utlp = take(sizeof(__bf16) * (size_t)n * L.ldl);
+    L.xthi = take(sizeof(__bf16) * (size_t)ldp * L.ldl);
+    L.xtlo = take(sizeof(__bf16) * (size_t)ldp * L.ldl);
+  } else if (d.precision == CPHIFI_MIXED_FP32) {
+    L.utlp = take(sizeof(float) * (size_t)n * L.ldl);
+  }
+  L.total = align_up(off, kAlign);
+  return L;
+}
+
+}  // namespace
+
+struct cphifi_plan {
+  cphifi_ui_desc d{};
+  cphifi_ui_inputs in{};
+  hipStream_t st = nullptr;
+  int64_t n = 0, r = 0, q = 0, ldk = 0, I = 0, J = 0;
+  int ldp = 16;
+  double gamma = 0.0;
+  int num_cu = 256;
+  Layout L{};
+  char* ws = nullptr;
+  double* vec[NVEC]{};
+  void* part = nullptr;
+  double* tpart = nullptr;
+  ObsTasks tasks{};
+  double* red[3]{};
+  DevScalars* sc = nullptr;
+  DevScalars* sc2 = nullptr;
+  double* hist = nullptr;
+  double *V = nullptr, *UV = nullptr, *dV = nullptr, *D = nullptr, *dKc = nullptr;
+  Elt lp = Elt::F64;
+  void* ulp = nullptr;   // U_K rounded, row-major U (BF16 form only)
+  void* utlp = nullptr;  // U_K rounded, row-major U^T (eigenvector k = row k)
+  __bf16 *xthi = nullptr, *xtlo = nullptr;
+  GemmPlan gp64{}, gplp{};
+  DevScalars* h_sc = nullptr;  // pinned host mirror
+  bool timing = false;
+  Elt timed_elt = Elt::F64;  // product type whose launches are timed ...
+  bool timed_trans = false;  // ... and orientation (one kernel symbol)
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  bool setup_done = false;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ timing
+int timed_begin(cphifi_plan* p, Elt elt, bool trans, hipEvent_t* out) {
+  *out = nullptr;
+  if (!p->timing || elt != p->timed_elt || trans != p->timed_trans) return CPHIFI_OK;
+  if (p->ev_used + 2 > p->ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      CPHIFI_HIP(hipEventCreate(&e));
+      p->ev.push_back(e);
+    }
+  }
+  *out = p->ev[p->ev_used];
+  CPHIFI_HIP(hipEventRecord(*out, p->st));
+  return CPHIFI_OK;
+}
+
+int timed_end(cphifi_plan* p, hipEvent_t start) {
+  if (start == nullptr) return CPHIFI_OK;
+  CPHIFI_HIP(hipEventRecord(p->ev[p->ev_used + 1], p->st));
+  p->ev_used += 2;
+  return CPHIFI_OK;
+}
+
+int timing_collect(cphifi_plan* p, double* ms, int* count) {
+  *ms = 0.0;
+  *count = 0;
+  if (!p->timing) return CPHIFI_OK;
+  for (size_t i = 0; i + 1 < p->ev_used; i += 2) {
+    float t = 0.f;
+    CPHIFI_HIP(hipEventElapsedTime(&t, p->ev[i], p->ev[i + 1]));
+    *ms += t;
+    ++*count;
+  }
+  p->ev_used = 0;
+  return CPHIFI_OK;
+}
+
+#define TRY(x)                       \
+  do {                               \
+    const int s_ = (x);              \
+    if (s_ != CPHIFI_OK) return s_;  \
+  } while (0)
+
+// ------------------------------------------------------------ n x n products
+// part <- K X (K symmetric: the row-major NN product).
+int prod_K(cphifi_plan* p, const double* X, const int32_t* done) {
+  hipEvent_t e0;
+  TRY(timed_begin(p, Elt::F64, false, &e0));
+  TRY(launch_gemm(Elt::F64, false, p->gp64, p->in.K, p->ldk, p->n, X, p->r, (int)p->r, nullptr,
+                  p->part, done, p->st));
+  return timed_end(p, e0);
+}
+
+// part <- U (diag(xscale) X) at element type elt.  UK holds U^T row-major
+// (LAPACK column-major U), so in FP64/FP32 this is the transposed product.
+int prod_U(cphifi_plan* p, Elt elt, const double* X, const double* xscale,
+           const int32_t* done) {
+  if (elt == Elt::BF16)
+    TRY(launch_split_bf16(X, p->r, (int)p->r, xscale, p->n, p->xthi, p->xtlo, p->L.ldl, done,
+                          p->st));
+  hipEvent_t e0;
+  TRY(timed_begin(p, elt, elt != Elt::BF16, &e0));
+  switch (elt) {
+    case Elt::F64:
+      TRY(launch_gemm(Elt::F64, true, p->gp64, p->in.UK, p->ldk, p->n, X, p->r, (int)p->r,
+                      xscale, p->part, done, p->st));
+      break;
+    case Elt::F32:
+      TRY(launch_gemm(Elt::F32, true, p->gplp, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
+                      xscale, p->part, done, p->st));
+      break;
+    case Elt::BF16:
+      TRY(launch_gemm_bf16(p->gplp, (const __bf16*)p->ulp, p->L.ldl, p->n, X, p->r, (int)p->r,
+                           xscale, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st));
+      break;
+  }
+  return timed_end(p, e0);
+}
+
+// part <- U^T X at element type elt (row-major NN product on U^T).
+int prod_Ut(cphifi_plan* p, Elt elt, const double* X, const int32_t* done) {
+  if (elt == Elt::BF16)
+    TRY(launch_split_bf16(X, p->r, (int)p->r, nullptr, p->n, p->xthi, p->xtlo, p->L.ldl, done,
+                          p->st));
+  hipEvent_t e0;
+  TRY(timed_begin(p, elt, false, &e0));
+  switch (elt) {
+    case Elt::F64:
+      TRY(launch_gemm(Elt::F64, false, p->gp64, p->in.UK, p->ldk, p->n, X, p->r, (int)p->r,
+                      nullptr, p->part, done, p->st));
+      break;
+    case Elt::F32:
+      TRY(launch_gemm(Elt::F32, false, p->gplp, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
+                      nullptr, p->part, done, p->st));
+      break;
+    case Elt::BF16:
+      TRY(launch_gemm_bf16(p->gplp, (const __bf16*)p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
+                           nullptr, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st));
+      break;
+  }
+  return timed_end(p, e0);
+}
+
+int ksplit_of(const cphifi_plan* p, Elt elt) {
+  return elt == Elt::F64 ? p->gp64.ksplit : p->gplp.ksplit;
+}
+
+// Gather-dot-scatter over the observations: out <- G applied to the product
+// held in part (gather mode), optionally storing Xhat.
+int obs_gather(cphifi_plan* p, Elt elt, double* xhat, double* out, const int32_t* done) {
+  ObsArgs a{};
+  a.n = p->n;
+  a.r = (int)p->r;
+  a.obs_i = p->in.obs_i;
+  a.obs_j = p->in.obs_j;
+  a.A = p->in.A;
+  a.B = p->in.B;
+  a.Zhat = p->in.Zhat;
+  a.y = nullptr;
+  a.part = p->part;
+  a.ksplit = ksplit_of(p, elt);
+  a.ldp = p->ldp;
+  a.Xhat = xhat;
+  a.out = out;
+  a.tpart = p->tpart;
+  a.done = done;
+  return launch_obs(ObsMode::Gather, elt != Elt::F64, p->tasks, a, p->I, p->J, p->st);
+}
+
+// ------------------------------------------------------------------ operators
+// y = A x in FP64, paper form (Section 4.4.1); red <- partials of x . y.
+int op_apply_paper(cphifi_plan* p, const double* x, double* y, double* red, int* nblk,
+                   const int32_t* done) {
+  TRY(prod_K(p, x, done));
+  TRY(obs_gather(p, Elt::F64, p->vec[V_XHAT], p->vec[V_Y1], done));
+  TRY(prod_K(p, p->vec[V_Y1], done));
+  return launch_apply_finish(p->part, false, p->gp64.ksplit, p->ldp, p->n, (int)p->r,
+                             p->vec[V_XHAT], x, nullptr, p->d.lambda, p->d.rho, y, red, nblk,
+                             done, p->st);
+}
+
+// z = M^{-1} x in FP64 (eq. fx); red <- partials of x . z.
+int op_precond_paper(cphifi_plan* p, const double* x, double* z, double* red, int* nblk,
+                     const int32_t* done) {
+  if (p->d.flags & CPHIFI_FLAG_NO_PRECOND) {
+    TRY(launch_copy(z, x, p->n * p->r, p->st));
+    return red ? launch_dot(x, z, p->n * p->r, red, nblk, done, p->st) : CPHIFI_OK;
+  }
+  TRY(prod_Ut(p, Elt::F64, x, done));
+  TRY(launch_prec_mid(p->part, false, p->gp64.ksplit, p->ldp, nullptr, p->n, (int)p->r, p->UV,
+                      p->D, p->vec[V_T2], nullptr, nullptr, nullptr, done, p->st));
+  TRY(prod_U(p, Elt::F64, p->vec[V_T2], nullptr, done));
+  return launch_reduce_partials(p->part, false, p->gp64.ksplit, p->ldp, p->n, (int)p->r, z, x,
+                                red, nblk, done, p->st);
+}
+
+// ybar = D_K U^T G(U D_K xbar) + lambda D_K xbar + rho xbar at element type elt.
+int op_apply_eig(cphifi_plan* p, Elt elt, const double* xb, double* yb, double* red, int* nblk,
+                 const int32_t* done) {
+  TRY(prod_U(p, elt, xb, p->dKc, done));
+  TRY(obs_gather(p, elt, nullptr, p->vec[V_Y1], done));
+  TRY(prod_Ut(p, elt, p->vec[V_Y1], done));
+  return launch_apply_finish(p->part, elt != Elt::F64, ksplit_of(p, elt), p->ldp, p->n,
+                             (int)p->r, nullptr, xb, p->dKc, p->d.lambda, p->d.rho, yb, red, nblk,
+                             done, p->st);
+}
+
+// zbar = ((xbar U_V) had D) U_V^T: eq. (fx) in the eigenbasis of K.
+int op_precond_eig(cphifi_plan* p, const double* xb, double* zb, double* red, int* nblk,
+                   const int32_t* done) {
+  return launch_prec_mid(nullptr, false, 1, p->ldp, xb, p->n, (int)p->r, p->UV, p->D, zb, xb,
+                         red, nblk, done, p->st);
+}
+
+// out <- U^T x (elt) with the partials reduced in FP64.
+int rotate_in(cphifi_plan* p, Elt elt, const double* x, double* out) {
+  TRY(prod_Ut(p, elt, x, nullptr));
+  return launch_reduce_partials(p->part, elt != Elt::F64, ksplit_of(p, elt), p->ldp, p->n,
+                                (int)p->r, out, nullptr, nullptr, nullptr, nullptr, p->st);
+}
+
+// out <- U x (elt).
+int rotate_out(cphifi_plan* p, Elt elt, const double* x, double* out) {
+  TRY(prod_U(p, elt, x, nullptr, nullptr));
+  return launch_reduce_partials(p->part, elt != Elt::F64, ksplit_of(p, elt), p->ldp, p->n,
+                                (int)p->r, out, nullptr, nullptr, nullptr, nullptr, p->st);
+}
+
+using OpFn = std::function<int(const double*, double*, double*, int*, const int32_t*)>;
+
+struct PcgVecs {
+  double *R, *Z, *P, *Q;
+};
+
+struct PcgOut {
+  int iters = 0;
+  int status = CPHIFI_OK;
+  double relres = 0.0;
+};
+
+int poll(cphifi_plan* p, DevScalars* sc) {
+  CPHIFI_HIP(hipMemcpyAsync(p->h_sc, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, p->st));
+  CPHIFI_HIP(hipStreamSynchronize(p->st));
+  return CPHIFI_OK;
+}
+
+int check_every(const cphifi_plan* p) {
+  if (p->d.check_every > 0) return p->d.check_every;
+  return p->n >= 4096 ? 1 : 8;
+}
+
+// Textbook PCG with device-resident scalars.  Every kernel of an iteration
+// checks sc->done, so iterations can be enqueued ahead of the host's poll.
+int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double* b, double* x,
+            bool have_x0, double tol, int maxit, const PcgVecs& v, DevScalars* sc,
+            double* hist, int hist_len, PcgOut* out) {
+  const int64_t len = p->n * p->r;
+  hipStream_t st = p->st;
+  int nb_bb = 0, nb_rr = 0, nb_rz = 0, nb_pq = 0;
+  double* red0 = p->red[0];
+  double* red1 = p->red[1];
+  double* red2 = p->red[2];
+  // red0 <- ||b||^2 partials are consumed by pcg_init; keep them in red0 until then.
+  TRY(launch_dot(b, b, len, red0, &nb_bb, nullptr, st));
+  TRY(launch_copy(v.R, b, len, st));
+  if (have_x0) {
+    TRY(apply(x, v.Q, nullptr, nullptr, nullptr));
+    TRY(launch_axpby(v.R, -1.0, v.Q, 1.0, len, nullptr, st));
+  } else {
+    TRY(launch_fill(x, 0.0, len, st));
+  }
+  TRY(launch_dot(v.R, v.R, len, red1, &nb_rr, nullptr, st));
+  TRY(precond(v.R, v.Z, red2, &nb_rz, nullptr));
+  TRY(launch_copy(v.P, v.Z, len, st));
+  TRY(launch_pcg_init(sc, red0, nb_bb, red1, nb_rr, red2, nb_rz, tol, hist, hist_len, st));
+  const int every = check_every(p);
+  bool stopped = false;
+  for (int it = 0; it < maxit; ++it) {
+    TRY(apply(v.P, v.Q, red0, &nb_pq, &sc->done));
+    TRY(launch_update_xr(x, v.R, v.P, v.Q, len, red0, nb_pq, red1, &nb_rr, sc, it, st));
+    TRY(launch_check_conv(red1, nb_rr, sc, it, hist, hist_len, st));
+    if ((it + 1) % every == 0 || it + 1 == maxit) {
+      TRY(poll(p, sc));
+      if (p->h_sc->done) {
+        stopped = true;
+        break;
+      }
+    }
+    if (it + 1 == maxit) break;
+    TRY(precond(v.R, v.Z, red2, &nb_rz, &sc->done));
+    TRY(launch_update_p(v.P, v.Z, len, red2, nb_rz, sc, it, st));
+  }
+  if (!stopped) TRY(poll(p, sc));
+  const DevScalars& h = *p->h_sc;
+  out->iters = h.done ? h.iters : maxit;
+  out->status = h.done ? h.status : CPHIFI_NOT_CONVERGED;
+  out->relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
+  return CPHIFI_OK;
+}
+
+// ||b - A x|| / ||b|| with the FP64 paper-form product (residual certificate).
+int true_relres(cphifi_plan* p, const double* b, const double* x, double* rel) {
+  const int64_t len = p->n * p->r;
+  int nb = 0, nbb = 0;
+  TRY(op_apply_paper(p, x, p->vec[V_Q], nullptr, nullptr, nullptr));
+  TRY(launch_copy(p->vec[V_RF], b, len, p->st));
+  TRY(launch_axpby(p->vec[V_RF], -1.0, p->vec[V_Q], 1.0, len, nullptr, p->st));
+  TRY(launch_dot(p->vec[V_RF], p->vec[V_RF], len, p->red[0], &nb, nullptr, p->st));
+  TRY(launch_store_sum(p->red[0], nb, p->sc2, 0, p->st));
+  TRY(launch_dot(b, b, len, p->red[1], &nbb, nullptr, p->st));
+  TRY(launch_store_sum(p->red[1], nbb, p->sc2, 1, p->st));
+  TRY(poll(p, p->sc2));
+  const double rr = p->h_sc->scratch[0], bb = p->h_sc->scratch[1];
+  *rel = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+  return CPHIFI_OK;
+}
+
+int solve_fp64(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* info) {
+  const bool warm = (p->d.flags & CPHIFI_FLAG_WARM_START) != 0;
+  const int maxit = eff_maxit(p->d);
+  PcgOut o;
+  if (p->d.flags & CPHIFI_FLAG_EIGENBASIS) {
+    // x = U xbar: PCG on the rotated system, then rotate back.
+    TRY(rotate_in(p, Elt::F64, b, p->vec[V_RB]));
+    if (warm) TRY(rotate_in(p, Elt::F64, W, p->vec[V_XB]));
+    OpFn A = [p](const double* x, double* y, double* red, int* nb, const int32_t* done) {
+      return op_apply_eig(p, Elt::F64, x, y, red, nb, done);
+    };
+    OpFn M = [p](const double* x, double* z, double* red, int* nb, const int32_t* done) {
+      return op_precond_eig(p, x, z, red, nb, done);
+    };
+    TRY(run_pcg(p, A, M, p->vec[V_RB], p->vec[V_XB], warm, p->d.tol, maxit,
+                PcgVecs{p->vec[V_R2], p->vec[V_Z2], p->vec[V_P2], p->vec[V_Q2]}, p->sc, p->hist,
+                p->L.hist_len, &o));
+    TRY(rotate_out(p, Elt::F64, p->vec[V_XB], W));
+  } else {
+    OpFn A = [p](const double* x, double* y, double* red, int* nb, const int32_t* done) {
+      return op_apply_paper(p, x, y, red, nb, done);
+    };
+    OpFn M = [p](const double* x, double* z, double* red, int* nb, const int32_t* done) {
+      return op_precond_paper(p, x, z, red, nb, done);
+    };
+    TRY(run_pcg(p, A, M, b, W, warm, p->d.tol, maxit,
+                PcgVecs{p->vec[V_R], p->vec[V_Z], p->vec[V_P], p->vec[V_Q]}, p->sc, p->hist,
+                p->L.hist_len, &o));
+  }
+  info->iters = o.iters;
+  info->refine_steps = 0;
+  info->relres_recursive = o.relres;
+  if (info->history != nullptr) {
+    const int cnt = std::min(o.iters + 1, p->L.hist_len);
+    CPHIFI_HIP(hipMemcpyAsync(info->history, p->hist, sizeof(double) * cnt,
+                              hipMemcpyDeviceToHost, p->st));
+  }
+  // Timing covers the solve only: the certificate below is not part of it.
+  TRY(timing_collect(p, &info->gemm_ms, &info->gemm_launches));
+  const bool t = p->timing;
+  p->timing = false;
+  double rel = 0.0;
+  const int rs = true_relres(p, b, W, &rel);
+  p->timing = t;
+  TRY(rs);
+  info->relres_true = rel;
+  int status = o.status;
+  if (status == CPHIFI_OK && !(rel <= 10.0 * p->d.tol)) status = CPHIFI_NOT_CONVERGED;
+  if (!std::isfinite(rel)) status = CPHIFI_NUMERIC;
+  info->status = status;
+  return status;
+}
+
+// FP64 iterative refinement around inner PCG solves in the eigenbasis of K at
+// the plan's low precision.
+int solve_mixed(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* info) {
+  const bool warm = (p->d.flags & CPHIFI_FLAG_WARM_START) != 0;
+  const int64_t len = p->n * p->r;
+  const int maxit = eff_maxit(p->d);
+  const int max_refine = p->d.max_refine > 0 ? p->d.max_refine : 30;
+  const double inner_tol = p->d.inner_tol > 0.0 ? p->d.inner_tol : 1e-3;
+  const Elt elt = p->lp;
+  int nb = 0;
+  TRY(launch_dot(b, b, len, p->red[1], &nb, nullptr, p->st));
+  TRY(launch_store_sum(p->red[1], nb, p->sc2, 1, p->st));
+  if (!warm) TRY(launch_fill(W, 0.0, len, p->st));
+  OpFn A = [p, elt](const double* x, double* y, double* red, int* nbk, const int32_t* done) {
+    return op_apply_eig(p, elt, x, y, red, nbk, done);
+  };
+  OpFn M = [p](const double* x, double* z, double* red, int* nbk, const int32_t* done) {
+    return op_precond_eig(p, x, z, red, nbk, done);
+  };
+  int total_inner = 0, k = 0, status = CPHIFI_NOT_CONVERGED;
+  double rel = INFINITY;
+  for (k = 0;; ++k) {
+    // FP64 residual of the original system.
+    if (k == 0 && !warm) {
+      TRY(launch_copy(p->vec[V_RF], b, len, p->st));
+    } else {
+      TRY(op_apply_paper(p, W, p->vec[V_Q], nullptr, nullptr, nullptr));
+      TRY(launch_copy(p->vec[V_RF], b, len, p->st));
+      TRY(launch_axpby(p->vec[V_RF], -1.0, p->vec[V_Q], 1.0, len, nullptr, p->st));
+    }
+    TRY(launch_dot(p->vec[V_RF], p->vec[V_RF], len, p->red[0], &nb, nullptr, p->st));
+    TRY(launch_store_sum(p->red[0], nb, p->sc2, 0, p->st));
+    TRY(poll(p, p->sc2));
+    const double rr = p->h_sc->scratch[0], bb = p->h_sc->scratch[1];
+    rel = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+    if (!std::isfinite(rel)) {
+      status = CPHIFI_NUMERIC;
+      break;
+    }
+    if (rel <= p->d.tol) {
+      status = CPHIFI_OK;
+      break;
+    }
+    if (k >= max_refine) break;
+    // The rotations into and out of the eigenbasis use the FP64 eigenvectors:
+    // a rounded U_K is not orthogonal, and its error, mapped through the
+    // ill-conditioned system, makes the refinement diverge.  Only the inner
+    // operator runs at low precision; the FP64 residual corrects its error.
+    TRY(rotate_in(p, Elt::F64, p->vec[V_RF], p->vec[V_RB]));
+    PcgOut o;
+    TRY(run_pcg(p, A, M, p->vec[V_RB], p->vec[V_XB], false, inner_tol, maxit,
+                PcgVecs{p->vec[V_R2], p->vec[V_Z2], p->vec[V_P2], p->vec[V_Q2]}, p->sc, nullptr, 0,
+                &o));
+    total_inner += o.iters;
+    if (o.status == CPHIFI_NUMERIC) {
+      status = CPHIFI_NUMERIC;
+      break;
+    }
+    TRY(rotate_out(p, Elt::F64, p->vec[V_XB], p->vec[V_TMP]));
+    TRY(launch_axpby(W, 1.0, p->vec[V_TMP], 1.0, len, nullptr, p->st));
+  }
+  info->iters = total_inner;
+  info->refine_steps = k;
+  info->relres_true = rel;
+  info->relres_recursive = rel;
+  TRY(timing_collect(p, &info->gemm_ms, &info->gemm_launches));
+  info->status = status;
+  return status;
+}
+
+int validate_desc(const cphifi_ui_desc* d) {
+  if (d == nullptr) {
+    set_error("desc is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  if (d->n < 1 || d->r < 1 || d->r > kMaxRank || d->q < 0 || d->q > INT32_MAX ||
+      d->n > INT32_MAX) {
+    set_error("bad sizes n=%lld r=%lld q=%lld (need n >= 1, 1 <= r <= 64, 0 <= q < 2^31)",
+              (long long)d->n, (long long)d->r, (long long)d->q);
+    return CPHIFI_INVALID_ARG;
+  }
+  if (d->ldk != 0 && d->ldk < d->n) {
+    set_error("ldk=%lld < n=%lld", (long long)d->ldk, (long long)d->n);
+    return CPHIFI_INVALID_ARG;
+  }
+  if (!(d->lambda > 0.0) || !(d->rho >= 0.0) || !std::isfinite(d->lambda) ||
+      !std::isfinite(d->rho)) {
+    set_error("need lambda > 0 and rho >= 0 (lambda=%g rho=%g)", d->lambda, d->rho);
+    return CPHIFI_INVALID_ARG;
+  }
+  if (!(d->tol > 0.0)) {
+    set_error("need tol > 0");
+    return CPHIFI_INVALID_ARG;
+  }
+  if (d->precision != CPHIFI_FP64 && d->precision != CPHIFI_MIXED_FP32 &&
+      d->precision != CPHIFI_MIXED_BF16) {
+    set_error("unknown precision %d", d->precision);
+    return CPHIFI_INVALID_ARG;
+  }
+  if (d->precision != CPHIFI_FP64 && (d->flags & CPHIFI_FLAG_NO_PRECOND)) {
+    set_error("FLAG_NO_PRECOND is only available with CPHIFI_FP64");
+    return CPHIFI_INVALID_ARG;
+  }
+  return CPHIFI_OK;
+}
+
+// Optional tile override "mw,s,ksplit" from the environment (tuning sweeps).
+GemmPlan plan_from_env(const char* var, Elt elt, int64_t n, const GemmPlan& dflt, int num_cu) {
+  const char* s = std::getenv(var);
+  if (s == nullptr) return dflt;
+  int mw = 0, ss = 0, ks = 0;
+  if (std::sscanf(s, "%d,%d,%d", &mw, &ss, &ks) < 2 || !gemm_cfg_valid(elt, mw, ss)) return dflt;
+  return make_gemm_plan(elt, n, mw, ss, ks, num_cu);
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+const char* cphifi_status_string(int status) {
+  switch (status) {
+    case CPHIFI_OK: return "CPHIFI_OK";
+    case CPHIFI_INVALID_ARG: return "CPHIFI_INVALID_ARG";
+    case CPHIFI_HIP_ERROR: return "CPHIFI_HIP_ERROR";
+    case CPHIFI_UNSUPPORTED: return "CPHIFI_UNSUPPORTED";
+    case CPHIFI_BREAKDOWN: return "CPHIFI_BREAKDOWN";
+    case CPHIFI_NUMERIC: return "CPHIFI_NUMERIC";
+    case CPHIFI_NOT_CONVERGED: return "CPHIFI_NOT_CONVERGED";
+  }
+  return "CPHIFI_UNKNOWN";
+}
+
+const char* cphifi_last_error(void) { return g_last_error.c_str(); }
+
+const char* cphifi_version(void) { return "cphifi 0.1.0 gfx950"; }
+
+int cphifi_ui_workspace_bytes(const cphifi_ui_desc* d, size_t* bytes) {
+  clear_error();
+  if (bytes == nullptr) {
+    set_error("bytes is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  TRY(validate_desc(d));
+  *bytes = make_layout(*d).total;
+  return CPHIFI_OK;
+}
+
+int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphifi_ui_inputs* in,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+  clear_error();
+  if (out == nullptr || in == nullptr) {
+    set_error("out / inputs is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  *out = nullptr;
+  TRY(validate_desc(d));
+  const bool expl = in->Zhat != nullptr;
+  if (in->K == nullptr || in->UK == nullptr || in->dK == nullptr || in->obs_ptr == nullptr) {
+    set_error("K, UK, dK and obs_ptr are required");
+    return CPHIFI_INVALID_ARG;
+  }
+  if (expl) {
+    if (in->A != nullptr || in->B != nullptr) {
+      set_error("give either Zhat or (A, B), not both");
+      return CPHIFI_INVALID_ARG;
+    }
+    if (in->V == nullptr) {
+      set_error("the explicit Zhat form needs V (the full Khatri-Rao Gram)");
+      return CPHIFI_INVALID_ARG;
+    }
+  } else {
+    if (in->A == nullptr || in->B == nullptr || d->I < 1 || d->J < 1) {
+      set_error("the implicit form needs A (I x r), B (J x r) with I, J >= 1");
+      return CPHIFI_INVALID_ARG;
+    }
+    if (d->q > 0 && (in->obs_i == nullptr || in->obs_j == nullptr)) {
+      set_error("obs_i / obs_j are required");
+      return CPHIFI_INVALID_ARG;
+    }
+  }
+  const Layout L = make_layout(*d);
+  if (workspace == nullptr || workspace_bytes < L.total ||
+      (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) {
+    set_error("workspace must be >= %zu bytes and 256-byte aligned (got %zu)", L.total,
+              workspace_bytes);
+    return CPHIFI_INVALID_ARG;
+  }
+  const int64_t n = d->n, q = d->q;
+  hipStream_t st = (hipStream_t)stream;
+
+  // Observation CSR: check it on the host and build the task list.
+  std::vector<int32_t> ptr(n + 1);
+  CPHIFI_HIP(hipMemcpyAsync(ptr.data(), in->obs_ptr, sizeof(int32_t) * (n + 1),
+                            hipMemcpyDeviceToHost, st));
+  CPHIFI_HIP(hipStreamSynchronize(st));
+  if (ptr[0] != 0 || ptr[n] != q) {
+    set_error("obs_ptr must start at 0 and end at q=%lld (got %d .. %d)", (long long)q, ptr[0],
+              ptr[n]);
+    return CPHIFI_INVALID_ARG;
+  }
+  for (int64_t s = 0; s < n; ++s)
+    if (ptr[s + 1] < ptr[s]) {
+      set_error("obs_ptr decreases at %lld", (long long)s);
+      return CPHIFI_INVALID_ARG;
+    }
+  if ((d->flags & CPHIFI_FLAG_VALIDATE) && !expl && q > 0) {
+    std::vector<int32_t> oi(q), oj(q);
+    CPHIFI_HIP(hipMemcpyAsync(oi.data(), in->obs_i, sizeof(int32_t) * q, hipMemcpyDeviceToHost,
+                              st));
+    CPHIFI_HIP(hipMemcpyAsync(oj.data(), in->obs_j, sizeof(int32_t) * q, hipMemcpyDeviceToHost,
+                              st));
+    CPHIFI_HIP(hipStreamSynchronize(st));
+    for (int64_t l = 0; l < q; ++l)
+      if (oi[l] < 0 || oi[l] >= d->I || oj[l] < 0 || oj[l] >= d->J) {
+        set_error("observation %lld has index (%d, %d) outside I=%lld, J=%lld", (long long)l,
+                  oi[l], oj[l], (long long)d->I, (long long)d->J);
+        return CPHIFI_INVALID_ARG;
+      }
+  }
+  std::vector<int32_t> tseg, tbeg, tend, tslot, tfirst, mseg, mptr;
+  int32_t nslot = 0;
+  for (int64_t s = 0; s < n; ++s) {
+    const int32_t b0 = ptr[s], e0 = ptr[s + 1];
+    const int32_t cnt = e0 - b0;
+    const int32_t nt = std::max<int32_t>(1, (cnt + kObsChunk - 1) / kObsChunk);
+    if (nt == 1) {
+      tseg.push_back((int32_t)s);
+      tbeg.push_back(b0);
+      tend.push_back(e0);
+      tslot.push_back(-1);
+      tfirst.push_back(1);
+    } else {
+      mseg.push_back((int32_t)s);
+      mptr.push_back(nslot);
+      for (int32_t j = 0; j < nt; ++j) {
+        tseg.push_back((int32_t)s);
+        tbeg.push_back(b0 + j * kObsChunk);
+        tend.push_back(std::min<int32_t>(e0, b0 + (j + 1) * kObsChunk));
+        tslot.push_back(nslot++);
+        tfirst.push_back(j == 0 ? 1 : 0);
+      }
+    }
+  }
+  mptr.push_back(nslot);
+  const int64_t ntask = (int64_t)tseg.size();
+  if (ntask > L.ntask_max || nslot > L.nslot_max || (int64_t)mseg.size() > L.nmulti_max) {
+    set_error("internal: observation task list exceeds its bound");
+    return CPHIFI_INVALID_ARG;
+  }
+
+  cphifi_plan* p = new cphifi_plan();
+  p->d = *d;
+  p->in = *in;
+  p->st = st;
+  p->n = n;
+  p->r = d->r;
+  p->q = q;
+  p->ldk = eff_ldk(*d);
+  p->I = expl ? 0 : d->I;
+  p->J = expl ? 0 : d->J;
+  p->ldp = (int)round_up(d->r, 16);
+  p->L = L;
+  p->ws = (char*)workspace;
+  p->timing = (d->flags & CPHIFI_FLAG_TIME_KERNELS) != 0;
+  if (d->gamma > 0.0) {
+    p->gamma = d->gamma;
+  } else if (!expl) {
+    p->gamma = (double)q / ((double)n * (double)d->I * (double)d->J);
+  } else {
+    delete p;
+    set_error("gamma must be given (> 0) with the explicit Zhat form");
+    return CPHIFI_INVALID_ARG;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cu > 0)
+      p->num_cu = cu;
+  }
+  char* ws = p->ws;
+  for (int i = 0; i < NVEC; ++i) p->vec[i] = (double*)(ws + L.vec[i]);
+  p->part = ws + L.part;
+  p->tpart = (double*)(ws + L.tpart);
+  for (int i = 0; i < 3; ++i) p->red[i] = (double*)(ws + L.red[i]);
+  p->sc = (DevScalars*)(ws + L.sc);
+  p->sc2 = (DevScalars*)(ws + L.sc2);
+  p->hist = (double*)(ws + L.hist);
+  p->V = (double*)(ws + L.V);
+  p->UV = (double*)(ws + L.UV);
+  p->dV = (double*)(ws + L.dV);
+  p->D = (double*)(ws + L.D);
+  p->dKc = (double*)(ws + L.dKc);
+  p->tasks.ntask = (int32_t)ntask;
+  p->tasks.nmulti = (int32_t)mseg.size();
+  p->tasks.seg = (int32_t*)(ws + L.tseg);
+  p->tasks.beg = (int32_t*)(ws + L.tbeg);
+  p->tasks.end = (int32_t*)(ws + L.tend);
+  p->tasks.slot = (int32_t*)(ws + L.tslot);
+  p->tasks.first = (int32_t*)(ws + L.tfirst);
+  p->tasks.mseg = (int32_t*)(ws + L.mseg);
+  p->tasks.mptr = (int32_t*)(ws + L.mptr);
+
+  auto fail = [&](int code) {
+    if (p->h_sc) (void)hipHostFree(p->h_sc);
+    delete p;
+    return code;
+  };
+  auto up = [&](int32_t* dst, const std::vector<int32_t>& v) -> int {
+    if (v.empty()) return CPHIFI_OK;
+    CPHIFI_HIP(hipMemcpyAsync(dst, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice,
+                              st));
+    return CPHIFI_OK;
+  };
+  if (hipHostMalloc((void**)&p->h_sc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
+    p->h_sc = nullptr;
+    set_error("hipHostMalloc of the scalar mirror failed");
+    return fail(CPHIFI_HIP_ERROR);
+  }
+  int rc = CPHIFI_OK;
+  if ((rc = up(p->tasks.seg, tseg)) || (rc = up(p->tasks.beg, tbeg)) ||
+      (rc = up(p->tasks.end, tend)) || (rc = up(p->tasks.slot, tslot)) ||
+      (rc = up(p->tasks.first, tfirst)) || (rc = up(p->tasks.mseg, mseg)) ||
+      (rc = up(p->tasks.mptr, mptr)))
+    return fail(rc);
+
+  p->gp64 = plan_from_env("CPHIFI_TILE_F64", Elt::F64, n,
+                          choose_gemm(Elt::F64, false, n, (int)d->r, p->num_cu), p->num_cu);
+  if (d->precision == CPHIFI_MIXED_BF16) {
+    p->lp = Elt::BF16;
+    p->timed_elt = Elt::BF16;
+    p->ulp = ws + L.ulp;
+    p->utlp = ws + L.utlp;
+    p->xthi = (__bf16*)(ws + L.xthi);
+    p->xtlo = (__bf16*)(ws + L.xtlo);
+    p->gplp = plan_from_env("CPHIFI_TILE_BF16", Elt::BF16, n,
+                            choose_gemm(Elt::BF16, false, n, (int)d->r, p->num_cu), p->num_cu);
+    if ((rc = launch_convert_lowp(Elt::BF16, false, in->UK, p->ldk, n, p->utlp, L.ldl, st)) ||
+        (rc = launch_convert_lowp(Elt::BF16, true, in->UK, p->ldk, n, p->ulp, L.ldl, st)))
+      return fail(rc);
+  } else if (d->precision == CPHIFI_MIXED_FP32) {
+    p->lp = Elt::F32;
+    p->timed_elt = Elt::F32;
+    p->utlp = ws + L.utlp;
+    p->gplp = plan_from_env("CPHIFI_TILE_F32", Elt::F32, n,
+                            choose_gemm(Elt::F32, false, n, (int)d->r, p->num_cu), p->num_cu);
+    if ((rc = launch_convert_lowp(Elt::F32, false, in->UK, p->ldk, n, p->utlp, L.ldl, st)))
+      return fail(rc);
+  }
+  // scalars start in a defined state
+  if ((rc = launch_fill((double*)p->sc, 0.0, sizeof(DevScalars) / sizeof(double), st)) ||
+      (rc = launch_fill((double*)p->sc2, 0.0, sizeof(DevScalars) / sizeof(double), st)))
+    return fail(rc);
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    set_error("plan_create: stream synchronisation failed");
+    return fail(CPHIFI_HIP_ERROR);
+  }
+  *out = p;
+  return CPHIFI_OK;
+}
+
+int cphifi_ui_setup(cphifi_plan* p) {
+  clear_error();
+  if (p == nullptr) {
+    set_error("plan is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  const int r = (int)p->r;
+  if (p->in.V != nullptr) {
+    TRY(launch_copy(p->V, p->in.V, (int64_t)r * r, p->st));
+  } else {
+    TRY(launch_gram(p->in.A, p->I, p->in.B, p->J, r, p->V, p->st));
+  }
+  TRY(launch_jacobi_eig(p->V, r, p->UV, p->dV, p->st));
+  TRY(launch_clamp_nonneg(p->in.dK, p->dKc, p->n, p->st));
+  TRY(launch_precond_diag(p->in.dK, p->dV, p->n, r, p->gamma, p->d.lambda, p->d.rho, p->D,
+                          p->st));
+  p->setup_done = true;
+  return CPHIFI_OK;
+}
+
+int cphifi_ui_rhs(cphifi_plan* p, const double* y, double* b) {
+  clear_error();
+  if (p == nullptr || b == nullptr || (y == nullptr && p->q > 0)) {
+    set_error("rhs: NULL argument");
+    return CPHIFI_INVALID_ARG;
+  }
+  ObsArgs a{};
+  a.n = p->n;
+  a.r = (int)p->r;
+  a.obs_i = p->in.obs_i;
+  a.obs_j = p->in.obs_j;
+  a.A = p->in.A;
+  a.B = p->in.B;
+  a.Zhat = p->in.Zhat;
+  a.y = y;
+  a.out = p->vec[V_Y1];
+  a.tpart = p->tpart;
+  a.done = nullptr;
+  TRY(launch_obs(ObsMode::Mttkrp, false, p->tasks, a, p->I, p->J, p->st));
+  const bool t = p->timing;
+  p->timing = false;
+  const int rc = prod_K(p, p->vec[V_Y1], nullptr);
+  p->timing = t;
+  TRY(rc);
+  return launch_reduce_partials(p->part, false, p->gp64.ksplit, p->ldp, p->n, (int)p->r, b,
+                                nullptr, nullptr, nullptr, nullptr, p->st);
+}
+
+int cphifi_ui_apply(cphifi_plan* p, const double* x, double* y) {
+  clear_error();
+  if (p == nullptr || x == nullptr || y == nullptr || x == y) {
+    set_error("apply: bad arguments");
+    return CPHIFI_INVALID_ARG;
+  }
+  return op_apply_paper(p, x, y, nullptr, nullptr, nullptr);
+}
+
+int cphifi_ui_precond(cphifi_plan* p, const double* x, double* z) {
+  clear_error();
+  if (p == nullptr || x == nullptr || z == nullptr || x == z) {
+    set_error("precond: bad arguments");
+    return CPHIFI_INVALID_ARG;
+  }
+  if (!p->setup_done) {
+    set_error("precond: call cphifi_ui_setup first");
+    return CPHIFI_INVALID_ARG;
+  }
+  return op_precond_paper(p, x, z, nullptr, nullptr, nullptr);
+}
+
+int cphifi_ui_apply_lowp(cphifi_plan* p, const double* xbar, double* ybar) {
+  clear_error();
+  if (p == nullptr || xbar == nullptr || ybar == nullptr || xbar == ybar) {
+    set_error("apply_lowp: bad arguments");
+    return CPHIFI_INVALID_ARG;
+  }
+  TRY(launch_clamp_nonneg(p->in.dK, p->dKc, p->n, p->st));
+  return op_apply_eig(p, p->lp, xbar, ybar, nullptr, nullptr, nullptr);
+}
+
+int cphifi_ui_solve(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* info) {
+  clear_error();
+  if (p == nullptr || b == nullptr || W == nullptr || info == nullptr || b == W) {
+    set_error("solve: bad arguments");
+    return CPHIFI_INVALID_ARG;
+  }
+  if (!p->setup_done) {
+    set_error("solve: call cphifi_ui_setup first");
+    return CPHIFI_INVALID_ARG;
+  }
+  double* hist = info->history;
+  std::memset(info, 0, sizeof(*info));
+  info->history = hist;
+  p->ev_used = 0;
+  if (p->d.precision == CPHIFI_FP64) return solve_fp64(p, b, W, info);
+  return solve_mixed(p, b, W, info);
+}
+
+int cphifi_ui_solve_subproblem(cphifi_plan* p, const double* y, double* W,
+                               cphifi_solve_info* info) {
+  clear_error();
+  if (p == nullptr || W == nullptr || info == nullptr) {
+    set_error("solve_subproblem: bad arguments");
+    return CPHIFI_INVALID_ARG;
+  }
+  TRY(cphifi_ui_setup(p));
+  TRY(cphifi_ui_rhs(p, y, p->vec[V_B]));
+  return cphifi_ui_solve(p, p->vec[V_B], W, info);
+}
+
+int cphifi_ui_plan_destroy(cphifi_plan* p) {
+  clear_error();
+  if (p == nullptr) return CPHIFI_OK;
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  if (p->h_sc) (void)hipHostFree(p->h_sc);
+  delete p;
+  return CPHIFI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,650 @@
+// FP64 vector kernels of the PCG iteration (Section 4.4; the recurrence is the
+// textbook preconditioned CG), the r x r steps of the preconditioner (eq. fx),
+// the per-solve setup of Section 4.4.2 (Gram V, eigendecomposition of V, the
+// inverse diagonal D) and the low-precision copies of U_K.
+//
+// Every reduction is two-stage and deterministic: a kernel writes one partial
+// per block, and each consumer adds all partials in one fixed order.  Kernels
+// that need a finished scalar (alpha, beta, the convergence test) recompute it
+// from the partials themselves, so no host round trip sits inside an iteration.
+#include "cphifi_internal.h"
+
+#include <cmath>
+
+namespace cphifi {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic sum over a 256-thread block; result valid in every thread.
+__device__ double block_sum(double v) {
+  __shared__ double ws[4];
+  __shared__ double total;
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) ws[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) total = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+  __syncthreads();
+  return total;
+}
+
+// Sum of red[0..nblk) in a fixed order (identical in every block that calls it).
+__device__ double sum_partials(const double* red, int nblk) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += red[i];
+  return block_sum(v);
+}
+
+__device__ __forceinline__ bool is_done(const int32_t* done) { return done != nullptr && *done; }
+
+template <typename PT>
+__device__ __forceinline__ double part_sum(const PT* part, int ksplit, int64_t n, int ldp,
+                                           int64_t s, int c) {
+  double v = 0.0;
+  for (int sp = 0; sp < ksplit; ++sp) v += (double)part[((int64_t)sp * n + s) * ldp + c];
+  return v;
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const PT* part, int ksplit, int ldp,
+                                                              int64_t n, int r, double* out,
+                                                              const double* dotwith, double* red,
+                                                              const int32_t* done) {
+  if (is_done(done)) return;
+  const int64_t len = n * r;
+  double loc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / r;
+    const int c = (int)(e % r);
+    const double v = part_sum(part, ksplit, n, ldp, s, c);
+    out[e] = v;
+    if (dotwith != nullptr) loc += dotwith[e] * v;
+  }
+  if (red != nullptr) {
+    const double b = block_sum(loc);
+    if (threadIdx.x == 0) red[blockIdx.x] = b;
+  }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void apply_finish_kernel(const PT* part, int ksplit, int ldp,
+                                                           int64_t n, int r, const double* xhat,
+                                                           const double* p, const double* dscale,
+                                                           double lam, double rho, double* q,
+                                                           double* red, const int32_t* done) {
+  if (is_done(done)) return;
+  const int64_t len = n * r;
+  double loc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / r;
+    const int c = (int)(e % r);
+    const double y = part_sum(part, ksplit, n, ldp, s, c);
+    const double pe = p[e];
+    double v;
+    if (dscale != nullptr)
+      v = dscale[s] * (y + lam * pe) + rho * pe;
+    else
+      v = y + lam * xhat[e] + rho * pe;
+    q[e] = v;
+    loc += pe * v;
+  }
+  if (red != nullptr) {
+    const double b = block_sum(loc);
+    if (threadIdx.x == 0) red[blockIdx.x] = b;
+  }
+}
+
+__global__ __launch_bounds__(256) void dot_kernel(const double* a, const double* b, int64_t len,
+                                                  double* red, const int32_t* done) {
+  if (is_done(done)) return;
+  double loc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    loc += a[e] * b[e];
+  const double s = block_sum(loc);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+// alpha = rz / p^T q; x += alpha p; r -= alpha q; partial ||r||^2.
+__global__ __launch_bounds__(256) void update_xr_kernel(double* x, double* r, const double* p,
+                                                        const double* q, int64_t len,
+                                                        const double* red_pq, int nblk_pq,
+                                                        double* red_rr, DevScalars* sc, int it) {
+  if (sc->done) return;
+  const double pq = sum_partials(red_pq, nblk_pq);
+  const double rz = sc->rz[it & 1];
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->pq = pq;
+      sc->status = (isfinite(pq) && isfinite(rz)) ? CPHIFI_BREAKDOWN : CPHIFI_NUMERIC;
+      sc->iters = it;
+      sc->done = 1;
+    }
+    return;
+  }
+  const double alpha = rz / pq;
+  double loc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    x[e] += alpha * p[e];
+    const double rv = r[e] - alpha * q[e];
+    r[e] = rv;
+    loc += rv * rv;
+  }
+  const double b = block_sum(loc);
+  if (threadIdx.x == 0) red_rr[blockIdx.x] = b;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->pq = pq;
+}
+
+__global__ __launch_bounds__(256) void check_conv_kernel(const double* red_rr, int nblk,
+                                                         DevScalars* sc, int it, double* hist,
+                                                         int hist_len) {
+  if (sc->done) return;
+  const double rr = sum_partials(red_rr, nblk);
+  if (threadIdx.x == 0) {
+    sc->rr = rr;
+    if (hist != nullptr && it + 1 < hist_len) hist[it + 1] = sqrt(rr / sc->bb);
+    if (!isfinite(rr)) {
+      sc->status = CPHIFI_NUMERIC;
+      sc->iters = it + 1;
+      sc->done = 1;
+    } else if (rr <= sc->tol2) {
+      sc->status = CPHIFI_OK;
+      sc->iters = it + 1;
+      sc->done = 1;
+    }
+  }
+}
+
+// beta = r+^T z+ / r^T z; p = z + beta p.
+__global__ __launch_bounds__(256) void update_p_kernel(double* p, const double* z, int64_t len,
+                                                       const double* red_rz, int nblk,
+                                                       DevScalars* sc, int it) {
+  if (sc->done) return;
+  const double rz_new = sum_partials(red_rz, nblk);
+  const double rz_old = sc->rz[it & 1];
+  if (!(rz_new > 0.0) || !isfinite(rz_new)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->status = isfinite(rz_new) ? CPHIFI_BREAKDOWN : CPHIFI_NUMERIC;
+      sc->iters = it + 1;
+      sc->done = 1;
+    }
+    return;
+  }
+  const double beta = rz_new / rz_old;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = z[e] + beta * p[e];
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->rz[(it + 1) & 1] = rz_new;
+}
+
+__global__ __launch_bounds__(256) void pcg_init_kernel(DevScalars* sc, const double* red_bb,
+                                                       int nblk_bb, const double* red_rr,
+                                                       int nblk_rr, const double* red_rz,
+                                                       int nblk_rz, double tol, double* hist,
+                                                       int hist_len) {
+  const double bb = sum_partials(red_bb, nblk_bb);
+  const double rr = sum_partials(red_rr, nblk_rr);
+  const double rz = red_rz != nullptr ? sum_partials(red_rz, nblk_rz) : 1.0;
+  if (threadIdx.x == 0) {
+    sc->bb = bb;
+    sc->rr = rr;
+    sc->rz[0] = rz;
+    sc->rz[1] = rz;
+    sc->pq = 0.0;
+    sc->tol2 = tol * tol * bb;
+    sc->iters = 0;
+    sc->status = CPHIFI_OK;
+    sc->done = 0;
+    sc->zero = 0;
+    if (hist != nullptr && hist_len > 0) hist[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz)) {
+      sc->status = CPHIFI_NUMERIC;
+      sc->done = 1;
+    } else if (bb == 0.0 || rr <= sc->tol2) {
+      sc->done = 1;  // already converged (x is the answer; b == 0 gives x = 0)
+    } else if (!(rz > 0.0)) {
+      sc->status = CPHIFI_BREAKDOWN;
+      sc->done = 1;
+    }
+  }
+}
+
+__global__ void store_sum_kernel(const double* red, int nblk, DevScalars* sc, int slot) {
+  const double v = sum_partials(red, nblk);
+  if (threadIdx.x == 0) sc->scratch[slot] = v;
+}
+
+// out[s,:] = ((t U_V) * D[s,:]) U_V^T, t = in[s,:] or the sum of partials.
+// One wave per row; U_V sits in LDS, t and u are exchanged through LDS.
+template <typename PT>
+__global__ __launch_bounds__(256) void prec_mid_kernel(const PT* part, int ksplit, int ldp,
+                                                       const double* in, int64_t n, int r,
+                                                       const double* UV, const double* D,
+                                                       double* out, const double* dotwith,
+                                                       double* red, const int32_t* done) {
+  if (is_done(done)) return;
+  __shared__ double uv[kMaxRank * kMaxRank];
+  __shared__ double buf[4][kMaxRank];
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) uv[e] = UV[e];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, c = threadIdx.x & 63;
+  double loc = 0.0;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < n; s += (int64_t)gridDim.x * 4) {
+    double t = 0.0;
+    if (c < r) t = part != nullptr ? part_sum(part, ksplit, n, ldp, s, c) : in[s * r + c];
+    buf[wave][c] = t;
+    __builtin_amdgcn_wave_barrier();
+    double u = 0.0;
+    if (c < r) {
+      for (int j = 0; j < r; ++j) u += buf[wave][j] * uv[j * r + c];
+      u *= D[s * r + c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    buf[wave][c] = u;
+    __builtin_amdgcn_wave_barrier();
+    if (c < r) {
+      double o = 0.0;
+      for (int j = 0; j < r; ++j) o += buf[wave][j] * uv[c * r + j];
+      out[s * r + c] = o;
+      if (dotwith != nullptr) loc += dotwith[s * r + c] * o;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (red != nullptr) {
+    const double b = block_sum(loc);
+    if (threadIdx.x == 0) red[blockIdx.x] = b;
+  }
+}
+
+__global__ void axpby_kernel(double* y, double a, const double* x, double b, int64_t len,
+                             const int32_t* done) {
+  if (is_done(done)) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = a * x[e] + b * y[e];
+}
+
+__global__ void copy_kernel(double* dst, const double* src, int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+__global__ void fill_kernel(double* dst, double v, int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = v;
+}
+
+__global__ void fill_i32_kernel(int32_t* dst, int32_t v, int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = v;
+}
+
+// V = (A^T A) had (B^T B): the Gram of the Khatri-Rao product of the other
+// modes' factors (Section 3, reused in Section 4.4.2).  One block.
+__global__ __launch_bounds__(256) void gram_kernel(const double* A, int64_t I, const double* B,
+                                                   int64_t J, int r, double* V) {
+  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+    const int a = e / r, b = e % r;
+    if (b < a) continue;
+    double ga = 0.0, gb = 0.0;
+    for (int64_t i = 0; i < I; ++i) ga += A[i * r + a] * A[i * r + b];
+    for (int64_t j = 0; j < J; ++j) gb += B[j * r + a] * B[j * r + b];
+    V[a * r + b] = ga * gb;
+    V[b * r + a] = ga * gb;
+  }
+}
+
+// Cyclic Jacobi eigensolver for the symmetric r x r Gram V (eq. eigV), one
+// block.  Disjoint rotation pairs of a round-robin schedule are applied in
+// parallel: rows first (J^T A), then columns (A J) and the eigenvector
+// accumulator (V J).  Stops when the off-diagonal mass is below (1e-15)^2 of
+// the Frobenius mass, or after 60 sweeps.
+__global__ __launch_bounds__(256) void jacobi_kernel(const double* Vin, int r, double* UV,
+                                                     double* dV) {
+  constexpr int L = kMaxRank + 1;
+  __shared__ double a[kMaxRank * L];
+  __shared__ double v[kMaxRank * L];
+  __shared__ double cs[kMaxRank / 2][2];
+  __shared__ int pr[kMaxRank / 2][2];
+  const int tid = threadIdx.x;
+  const int m = r + (r & 1);  // even player count; index r is a dummy when r is odd
+  for (int e = tid; e < m * m; e += blockDim.x) {
+    const int i = e / m, j = e % m;
+    a[i * L + j] = (i < r && j < r) ? Vin[i * r + j] : 0.0;
+    v[i * L + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double fro = 0.0;
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const double x = a[(e / r) * L + (e % r)];
+    fro += x * x;
+  }
+  fro = block_sum(fro);
+  for (int sweep = 0; sweep < 60 && m > 1; ++sweep) {
+    double off = 0.0;
+    for (int e = tid; e < r * r; e += blockDim.x) {
+      const int i = e / r, j = e % r;
+      if (i != j) off += a[i * L + j] * a[i * L + j];
+    }
+    off = block_sum(off);
+    if (!(off > 1e-30 * fro)) break;
+    for (int round = 0; round < m - 1; ++round) {
+      if (tid < m / 2) {
+        // circle method: player 0 fixed, others rotate
+        int p, q;
+        if (tid == 0) {
+          p = 0;
+          q = 1 + (round % (m - 1));
+        } else {
+          p = 1 + ((round + tid) % (m - 1));
+          q = 1 + ((round + (m - 1) - tid) % (m - 1));
+        }
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        if (q < r) {
+          const double apq = a[p * L + q];
+          if (apq != 0.0) {
+            const double tau = (a[q * L + q] - a[p * L + p]) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pr[tid][0] = p;
+        pr[tid][1] = q;
+        cs[tid][0] = c;
+        cs[tid][1] = s;
+      }
+      __syncthreads();
+      for (int e = tid; e < (m / 2) * m; e += blockDim.x) {  // rows
+        const int k = e / m, j = e % m;
+        const int p = pr[k][0], q = pr[k][1];
+        const double c = cs[k][0], s = cs[k][1];
+        const double ap = a[p * L + j], aq = a[q * L + j];
+        a[p * L + j] = c * ap - s * aq;
+        a[q * L + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      for (int e = tid; e < (m / 2) * m; e += blockDim.x) {  // columns and vectors
+        const int k = e / m, i = e % m;
+        const int p = pr[k][0], q = pr[k][1];
+        const double c = cs[k][0], s = cs[k][1];
+        const double ap = a[i * L + p], aq = a[i * L + q];
+        a[i * L + p] = c * ap - s * aq;
+        a[i * L + q] = s * ap + c * aq;
+        const double vp = v[i * L + p], vq = v[i * L + q];
+        v[i * L + p] = c * vp - s * vq;
+        v[i * L + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = tid; e < r * r; e += blockDim.x) UV[e] = v[(e / r) * L + (e % r)];
+  for (int i = tid; i < r; i += blockDim.x) dV[i] = a[i * L + i];
+}
+
+__global__ void precond_diag_kernel(const double* dK, const double* dV, int64_t n, int r,
+                                    double gamma, double lam, double rho, double* D) {
+  const int64_t len = n * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / r;
+    const int c = (int)(e % r);
+    const double d = fmax(dK[s], 0.0);
+    D[e] = 1.0 / (gamma * dV[c] * d * d + lam * d + rho);
+  }
+}
+
+__global__ void clamp_kernel(const double* src, double* dst, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = fmax(src[e], 0.0);
+}
+
+template <typename T>
+__global__ void convert_kernel(const double* src, int64_t ld_src, int64_t n, T* dst,
+                               int64_t ld_dst) {
+  const int64_t len = n * ld_dst;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ld_dst, k = e % ld_dst;
+    dst[e] = (T)(k < n ? src[i * ld_src + k] : 0.0);
+  }
+}
+
+// Tiled transpose-convert: dst[i][k] = src[k][i] (i, k < n), zero for k >= n.
+template <typename T>
+__global__ __launch_bounds__(256) void convert_t_kernel(const double* src, int64_t ld_src,
+                                                        int64_t n, T* dst, int64_t ld_dst) {
+  __shared__ double tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.y * 32;  // dst row block
+  const int64_t k0 = (int64_t)blockIdx.x * 32;  // dst column block
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t k = k0 + yy, i = i0 + tx;
+    tile[yy][tx] = (k < n && i < n) ? src[k * ld_src + i] : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t i = i0 + yy, k = k0 + tx;
+    if (i < n && k < ld_dst) dst[i * ld_dst + k] = (T)tile[tx][yy];
+  }
+}
+
+}  // namespace
+
+int vec_blocks(int64_t len) {
+  int64_t b = (len + 1023) / 1024;
+  if (b < 1) b = 1;
+  if (b > kMaxVecBlocks) b = kMaxVecBlocks;
+  return (int)b;
+}
+
+static int grid_for(int64_t len) {
+  int64_t b = (len + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 8192) b = 8192;
+  return (int)b;
+}
+
+int launch_reduce_partials(const void* part, bool is_float, int ksplit, int ldp, int64_t n,
+                           int r, double* out, const double* dotwith, double* red,
+                           int* nblk_out, const int32_t* done, hipStream_t st) {
+  const int nb = vec_blocks(n * r);
+  if (is_float)
+    hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(nb), dim3(256), 0, st,
+                       (const float*)part, ksplit, ldp, n, r, out, dotwith, red, done);
+  else
+    hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(nb), dim3(256), 0, st,
+                       (const double*)part, ksplit, ldp, n, r, out, dotwith, red, done);
+  CPHIFI_CHECK_LAUNCH();
+  if (nblk_out) *nblk_out = nb;
+  return CPHIFI_OK;
+}
+
+int launch_apply_finish(const void* part, bool is_float, int ksplit, int ldp, int64_t n, int r,
+                        const double* xhat, const double* p, const double* dscale, double lam,
+                        double rho, double* q, double* red, int* nblk_out, const int32_t* done,
+                        hipStream_t st) {
+  const int nb = vec_blocks(n * r);
+  if (is_float)
+    hipLaunchKernelGGL(apply_finish_kernel<float>, dim3(nb), dim3(256), 0, st, (const float*)part,
+                       ksplit, ldp, n, r, xhat, p, dscale, lam, rho, q, red, done);
+  else
+    hipLaunchKernelGGL(apply_finish_kernel<double>, dim3(nb), dim3(256), 0, st,
+                       (const double*)part, ksplit, ldp, n, r, xhat, p, dscale, lam, rho, q, red,
+                       done);
+  CPHIFI_CHECK_LAUNCH();
+  if (nblk_out) *nblk_out = nb;
+  return CPHIFI_OK;
+}
+
+int launch_dot(const double* a, const double* b, int64_t len, double* red, int* nblk_out,
+               const int32_t* done, hipStream_t st) {
+  const int nb = vec_blocks(len);
+  hipLaunchKernelGGL(dot_kernel, dim3(nb), dim3(256), 0, st, a, b, len, red, done);
+  CPHIFI_CHECK_LAUNCH();
+  if (nblk_out) *nblk_out = nb;
+  return CPHIFI_OK;
+}
+
+int launch_update_xr(double* x, double* r, const double* p, const double* q, int64_t len,
+                     const double* red_pq, int nblk_pq, double* red_rr, int* nblk_out,
+                     DevScalars* sc, int it, hipStream_t st) {
+  const int nb = vec_blocks(len);
+  hipLaunchKernelGGL(update_xr_kernel, dim3(nb), dim3(256), 0, st, x, r, p, q, len, red_pq,
+                     nblk_pq, red_rr, sc, it);
+  CPHIFI_CHECK_LAUNCH();
+  if (nblk_out) *nblk_out = nb;
+  return CPHIFI_OK;
+}
+
+int launch_check_conv(const double* red_rr, int nblk, DevScalars* sc, int it, double* hist,
+                      int hist_len, hipStream_t st) {
+  hipLaunchKernelGGL(check_conv_kernel, dim3(1), dim3(256), 0, st, red_rr, nblk, sc, it, hist,
+                     hist_len);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_prec_mid(const void* part, bool is_float, int ksplit, int ldp, const double* in,
+                    int64_t n, int r, const double* UV, const double* D, double* out,
+                    const double* dotwith, double* red, int* nblk_out, const int32_t* done,
+                    hipStream_t st) {
+  const int nb = (int)std::min<int64_t>(kMaxVecBlocks, (n + 3) / 4);
+  if (is_float)
+    hipLaunchKernelGGL(prec_mid_kernel<float>, dim3(nb), dim3(256), 0, st, (const float*)part,
+                       ksplit, ldp, in, n, r, UV, D, out, dotwith, red, done);
+  else
+    hipLaunchKernelGGL(prec_mid_kernel<double>, dim3(nb), dim3(256), 0, st, (const double*)part,
+                       ksplit, ldp, in, n, r, UV, D, out, dotwith, red, done);
+  CPHIFI_CHECK_LAUNCH();
+  if (nblk_out) *nblk_out = nb;
+  return CPHIFI_OK;
+}
+
+int launch_update_p(double* p, const double* z, int64_t len, const double* red_rz, int nblk,
+                    DevScalars* sc, int it, hipStream_t st) {
+  hipLaunchKernelGGL(update_p_kernel, dim3(vec_blocks(len)), dim3(256), 0, st, p, z, len, red_rz,
+                     nblk, sc, it);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_pcg_init(DevScalars* sc, const double* red_bb, int nblk_bb, const double* red_rr,
+                    int nblk_rr, const double* red_rz, int nblk_rz, double tol, double* hist,
+                    int hist_len, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(256), 0, st, sc, red_bb, nblk_bb, red_rr,
+                     nblk_rr, red_rz, nblk_rz, tol, hist, hist_len);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_store_sum(const double* red, int nblk, DevScalars* sc, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(store_sum_kernel, dim3(1), dim3(256), 0, st, red, nblk, sc, slot);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_axpby(double* y, double a, const double* x, double b, int64_t len,
+                 const int32_t* done, hipStream_t st) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(len)), dim3(256), 0, st, y, a, x, b, len, done);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_copy(double* dst, const double* src, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(len)), dim3(256), 0, st, dst, src, len);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_fill(double* dst, double v, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(len)), dim3(256), 0, st, dst, v, len);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_fill_i32(int32_t* dst, int32_t v, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(len)), dim3(256), 0, st, dst, v, len);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_gram(const double* A, int64_t I, const double* B, int64_t J, int r, double* V,
+                hipStream_t st) {
+  hipLaunchKernelGGL(gram_kernel, dim3(1), dim3(256), 0, st, A, I, B, J, r, V);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_jacobi_eig(const double* V, int r, double* UV, double* dV, hipStream_t st) {
+  if (r < 1 || r > kMaxRank) {
+    set_error("jacobi: bad rank %d", r);
+    return CPHIFI_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(256), 0, st, V, r, UV, dV);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_precond_diag(const double* dK, const double* dV, int64_t n, int r, double gamma,
+                        double lam, double rho, double* D, hipStream_t st) {
+  hipLaunchKernelGGL(precond_diag_kernel, dim3(grid_for(n * r)), dim3(256), 0, st, dK, dV, n, r,
+                     gamma, lam, rho, D);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_clamp_nonneg(const double* src, double* dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(clamp_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_convert_lowp(Elt elt, bool transpose, const double* src, int64_t ld_src, int64_t n,
+                        void* dst, int64_t ld_dst, hipStream_t st) {
+  if (ld_dst < n) {
+    set_error("convert: ld_dst < n");
+    return CPHIFI_INVALID_ARG;
+  }
+  if (!transpose) {
+    const int g = grid_for(n * ld_dst);
+    if (elt == Elt::F32)
+      hipLaunchKernelGGL(convert_kernel<float>, dim3(g), dim3(256), 0, st, src, ld_src, n,
+                         (float*)dst, ld_dst);
+    else if (elt == Elt::BF16)
+      hipLaunchKernelGGL(convert_kernel<__bf16>, dim3(g), dim3(256), 0, st, src, ld_src, n,
+                         (__bf16*)dst, ld_dst);
+    else
+      hipLaunchKernelGGL(convert_kernel<double>, dim3(g), dim3(256), 0, st, src, ld_src, n,
+                         (double*)dst, ld_dst);
+  } else {
+    dim3 grid((unsigned)((ld_dst + 31) / 32), (unsigned)((n + 31) / 32));
+    if (elt == Elt::F32)
+      hipLaunchKernelGGL(convert_t_kernel<float>, grid, dim3(256), 0, st, src, ld_src, n,
+                         (float*)dst, ld_dst);
+    else if (elt == Elt::BF16)
+      hipLaunchKernelGGL(convert_t_kernel<__bf16>, grid, dim3(256), 0, st, src, ld_src, n,
+                         (__bf16*)dst, ld_dst);
+    else
+      hipLaunchKernelGGL(convert_t_kernel<double>, grid, dim3(256), 0, st, src, ld_src, n,
+                         (double*)dst, ld_dst);
+  }
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+}  // namespace cphifi

@@ -1,0 +1,185 @@
+"""Torch-tensor convenience layer over the C ABI (argument marshalling only).
+
+torch supplies device memory and the current HIP stream; every computation is
+a call into libcphifi.so.  Inputs must already be CUDA (HIP) tensors of the
+documented dtype and layout; nothing is converted or computed here.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import cphifi as _c
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _need(t: torch.Tensor, dtype, shape, name: str):
+    if not t.is_cuda or t.dtype != dtype or tuple(t.shape) != tuple(shape) or \
+            not t.is_contiguous():
+        raise ValueError(f"{name}: expected contiguous device {dtype} of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+def kernel_eig(K: torch.Tensor):
+    """One-time eigendecomposition of K on the device (library call).
+
+    Returns (UK, dK) with UK holding eigenvector k in row k (the LAPACK
+    column-major order the ABI expects) and dK ascending.
+    """
+    n = K.shape[0]
+    _need(K, torch.float64, (n, n), "K")
+    UK = torch.empty_like(K)
+    dK = torch.empty(n, dtype=torch.float64, device=K.device)
+    _c.cphifi_kernel_eig(n, K.data_ptr(), n, UK.data_ptr(), dK.data_ptr(), _stream())
+    return UK, dK
+
+
+@dataclass
+class DeviceProblem:
+    n: int
+    r: int
+    q: int
+    I: int
+    J: int
+    K: torch.Tensor
+    UK: torch.Tensor
+    dK: torch.Tensor
+    obs_ptr: torch.Tensor
+    obs_i: torch.Tensor
+    obs_j: torch.Tensor
+    y: torch.Tensor
+    A: Optional[torch.Tensor] = None
+    B: Optional[torch.Tensor] = None
+    Zhat: Optional[torch.Tensor] = None
+    V: Optional[torch.Tensor] = None
+
+
+class UISolver:
+    """A plan plus its workspace; methods mirror the C ABI calls."""
+
+    def __init__(self, prob: DeviceProblem, lam: float, rho: float, tol: float,
+                 precision: str = "fp64", gamma: float = 0.0, flags: int = 0, maxit: int = 0,
+                 max_refine: int = 0, inner_tol: float = 0.0, check_every: int = 0):
+        self.prob = prob
+        n, r, q = prob.n, prob.r, prob.q
+        _need(prob.K, torch.float64, (n, n), "K")
+        _need(prob.UK, torch.float64, (n, n), "UK")
+        _need(prob.dK, torch.float64, (n,), "dK")
+        _need(prob.obs_ptr, torch.int32, (n + 1,), "obs_ptr")
+        _need(prob.y, torch.float64, (q,), "y")
+        if prob.Zhat is None:
+            _need(prob.A, torch.float64, (prob.I, r), "A")
+            _need(prob.B, torch.float64, (prob.J, r), "B")
+            _need(prob.obs_i, torch.int32, (q,), "obs_i")
+            _need(prob.obs_j, torch.int32, (q,), "obs_j")
+        else:
+            _need(prob.Zhat, torch.float64, (q, r), "Zhat")
+        if prob.V is not None:
+            _need(prob.V, torch.float64, (r, r), "V")
+        self.desc = _c.make_desc(n, r, q, prob.I, prob.J, lam, rho, gamma, tol,
+                                 _c.PRECISIONS[precision], flags, maxit, max_refine, inner_tol,
+                                 check_every)
+        self.inputs = _c.make_inputs(K=_ptr(prob.K), UK=_ptr(prob.UK), dK=_ptr(prob.dK),
+                                     obs_ptr=_ptr(prob.obs_ptr), obs_i=_ptr(prob.obs_i),
+                                     obs_j=_ptr(prob.obs_j), A=_ptr(prob.A), B=_ptr(prob.B),
+                                     Zhat=_ptr(prob.Zhat), V=_ptr(prob.V))
+        self.ws_bytes = _c.cphifi_ui_workspace_bytes(self.desc)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,
+                                     device=prob.K.device)
+        base = self.workspace.data_ptr()
+        self._ws = (base + 255) // 256 * 256
+        self.plan = _c.cphifi_ui_plan_create(self.desc, self.inputs, self._ws, self.ws_bytes,
+                                             _stream())
+
+    def _vec(self):
+        return torch.empty(self.prob.n, self.prob.r, dtype=torch.float64,
+                           device=self.prob.K.device)
+
+    def setup(self):
+        _c.cphifi_ui_setup(self.plan)
+
+    def rhs(self, y: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
+        y = self.prob.y if y is None else y
+        out = self._vec() if out is None else out
+        _c.cphifi_ui_rhs(self.plan, y.data_ptr(), out.data_ptr())
+        return out
+
+    def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None):
+        out = self._vec() if out is None else out
+        _c.cphifi_ui_apply(self.plan, x.data_ptr(), out.data_ptr())
+        return out
+
+    def precond(self, x: torch.Tensor, out: Optional[torch.Tensor] = None):
+        out = self._vec() if out is None else out
+        _c.cphifi_ui_precond(self.plan, x.data_ptr(), out.data_ptr())
+        return out
+
+    def apply_lowp(self, xbar: torch.Tensor, out: Optional[torch.Tensor] = None):
+        out = self._vec() if out is None else out
+        _c.cphifi_ui_apply_lowp(self.plan, xbar.data_ptr(), out.data_ptr())
+        return out
+
+    def solve(self, b: torch.Tensor, W: Optional[torch.Tensor] = None, history=None):
+        W = self._vec() if W is None else W
+        info = _c.cphifi_ui_solve(self.plan, b.data_ptr(), W.data_ptr(), history)
+        return W, info
+
+    def solve_subproblem(self, y: Optional[torch.Tensor] = None,
+                         W: Optional[torch.Tensor] = None, history=None):
+        y = self.prob.y if y is None else y
+        W = self._vec() if W is None else W
+        info = _c.cphifi_ui_solve_subproblem(self.plan, y.data_ptr(), W.data_ptr(), history)
+        return W, info
+
+    def close(self):
+        if getattr(self, "plan", 0):
+            _c.cphifi_ui_plan_destroy(self.plan)
+            self.plan = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def upload(p, device="cuda", explicit=None, eig=None) -> DeviceProblem:
+    """Copy a synth.Problem's arrays to the device (host-to-device copies only).
+
+    explicit: optional (Zhat, V) host arrays for the explicit per-observation
+    form; otherwise the implicit (A, B) form is used.  eig: optional host
+    (UK, dK) in the ABI's layout; by default the library computes the
+    eigendecomposition of K on the device.
+    """
+    import numpy as np
+
+    def dev(a, dtype):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+
+    K = dev(p.K, torch.float64)
+    if eig is not None:
+        UK = dev(eig[0], torch.float64)
+        dK = dev(eig[1], torch.float64)
+    else:
+        UK, dK = kernel_eig(K)
+    obs_ptr = dev(p.obs_ptr, torch.int32)
+    obs_i = dev(p.obs_i, torch.int32)
+    obs_j = dev(p.obs_j, torch.int32)
+    y = dev(p.y, torch.float64)
+    if explicit is not None:
+        return DeviceProblem(p.n, p.r, p.q, p.I, p.J, K, UK, dK, obs_ptr, obs_i, obs_j, y,
+                             Zhat=dev(explicit[0], torch.float64),
+                             V=dev(explicit[1], torch.float64))
+    A = dev(p.A, torch.float64)
+    B = dev(p.B, torch.float64)
+    return DeviceProblem(p.n, p.r, p.q, p.I, p.J, K, UK, dK, obs_ptr, obs_i, obs_j, y, A=A, B=B)

@@ -1,0 +1,86 @@
+"""Host-only checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad descriptions before touching a GPU."""
+
+import ctypes
+
+import pytest
+
+from paper_2603_25691_amd import cphifi as c
+
+
+def test_library_exports_every_declared_function():
+    names = c.declared_functions()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(c.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in cphifi.h but not exported"
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in c.version()
+    assert c.status_string(c.OK) == "CPHIFI_OK"
+    assert c.status_string(c.NOT_CONVERGED) == "CPHIFI_NOT_CONVERGED"
+    assert c.status_string(999) == "CPHIFI_UNKNOWN"
+
+
+def test_struct_layout_matches_header():
+    # int64 x6 + double x5 + int32 x6 = 112 bytes; 10 pointers; info 48 bytes
+    assert ctypes.sizeof(c.cphifi_ui_desc) == 112
+    assert ctypes.sizeof(c.cphifi_ui_inputs) == 80
+    assert ctypes.sizeof(c.cphifi_solve_info) == 48
+
+
+def test_workspace_grows_with_problem_and_precision():
+    small = c.cphifi_ui_workspace_bytes(c.make_desc(200, 5, 2000, 20, 10))
+    big = c.cphifi_ui_workspace_bytes(c.make_desc(3000, 40, 600000, 100, 200))
+    assert 0 < small < big
+    fp64 = c.cphifi_ui_workspace_bytes(c.make_desc(3000, 40, 600000, 100, 200))
+    bf16 = c.cphifi_ui_workspace_bytes(c.make_desc(3000, 40, 600000, 100, 200,
+                                                   precision=c.MIXED_BF16))
+    fp32 = c.cphifi_ui_workspace_bytes(c.make_desc(3000, 40, 600000, 100, 200,
+                                                   precision=c.MIXED_FP32))
+    # the low-precision copies of U_K: 2 bf16 copies, or 1 fp32 copy
+    ldl = (3000 + 255) // 256 * 256
+    assert bf16 - fp64 >= 2 * 2 * 3000 * ldl
+    assert fp32 - fp64 >= 4 * 3000 * ldl
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 0), ("r", 0), ("r", 65), ("q", -1), ("lambda_", 0.0), ("rho", -1.0),
+    ("tol", 0.0), ("precision", 7), ("ldk", 5),
+])
+def test_invalid_descriptions_are_rejected(field, value):
+    d = c.make_desc(200, 5, 2000, 20, 10)
+    setattr(d, field, value)
+    with pytest.raises(c.CphifiError) as ei:
+        c.cphifi_ui_workspace_bytes(d)
+    assert ei.value.status == c.INVALID_ARG
+    assert c.last_error() != ""
+
+
+def test_no_precond_flag_is_fp64_only():
+    d = c.make_desc(200, 5, 2000, 20, 10, precision=c.MIXED_BF16, flags=c.FLAG_NO_PRECOND)
+    with pytest.raises(c.CphifiError):
+        c.cphifi_ui_workspace_bytes(d)
+
+
+def test_plan_create_rejects_missing_pointers_without_gpu():
+    d = c.make_desc(200, 5, 2000, 20, 10)
+    inp = c.make_inputs()  # all NULL
+    with pytest.raises(c.CphifiError) as ei:
+        c.cphifi_ui_plan_create(d, inp, 0, 0, 0)
+    assert ei.value.status == c.INVALID_ARG
+
+
+def test_oracle_and_library_share_no_code():
+    """The product package never imports the oracle, and vice versa."""
+    import pathlib
+
+    root = pathlib.Path(c.__file__).resolve().parents[1]
+    for f in (root / "paper_2603_25691_amd").rglob("*.py"):
+        txt = f.read_text()
+        assert "import oracle" not in txt and "from oracle" not in txt, f
+    for f in (root / "oracle").rglob("*.py"):
+        txt = f.read_text()
+        assert "import paper_2603_25691_amd" not in txt, f
+        assert "from paper_2603_25691_amd" not in txt, f

@@ -1,0 +1,381 @@
+"""GPU parity: every call goes through the C ABI (libcphifi.so) and is compared
+with the FP64 CPU oracle on the same seeded inputs.
+
+Tolerances
+* single products (rhs, apply) in FP64: 1e-12 relative (Frobenius), from
+  n * u with u = 1.1e-16 and n <= 3000 at these sizes, plus headroom for the
+  different summation order;
+* preconditioner: 1e-8 relative -- the library and the oracle diagonalise K
+  with different eigensolvers, and eq. (fx) amplifies the eigenvector
+  differences of the tiny eigenvalues of K by up to 1/rho;  applied to M x
+  (M dense, formed in FP64) the round-off of M x itself is amplified by
+  cond(M), so that check is gated at 100 u cond(M);
+* FP64 solves at tol = 1e-12: e_KW <= max(1e-10, 3 delta), where delta is the
+  dense reference's own forward error in K W estimated by one step of FP64
+  iterative refinement (it exceeds 1e-10 only for the largest n r instance);
+  at a looser tol the GPU must agree with the oracle's PCG run to the same
+  tol (same algorithm) to within a tenth of that run's own distance from the
+  tight solution, since e_KW / tol depends on the problem;
+* mixed-precision solves refined to relres 1e-7: e_KW <= 1e-6.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from synth import (config_c1, config_c3, drop_observations, make_aligned,  # noqa: E402
+                   make_small)
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2603_25691_amd import cphifi as C  # noqa: E402
+    from paper_2603_25691_amd.torch_api import UISolver, kernel_eig, upload  # noqa: E402
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def small_cases():
+    return {
+        "c1": config_c1(),
+        "ragged-r3": make_small(31, n=77, I=5, J=7, r=3, q=400, kernel_param=0.2),
+        "ragged-r17": make_small(32, n=301, I=9, J=11, r=17, q=6000, kernel_param=0.1),
+        "r40": make_small(33, n=650, I=20, J=30, r=40, q=12000, kernel="matern32",
+                          kernel_param=0.1),
+        "r64": make_small(34, n=300, I=12, J=10, r=64, q=9000, kernel_param=0.2),
+        "c1-drop": drop_observations(config_c1(), 0.5, 7),
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module")
+def uploaded():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            p = CASES[name]
+            cache[name] = (p, upload(p))
+        return cache[name]
+
+    return get
+
+
+# ----------------------------------------------------------------- eig(K)
+
+@pytest.mark.parametrize("name", ["c1", "r40"])
+def test_kernel_eig_decomposes_K(name, uploaded):
+    p, dp = uploaded(name)
+    U = host(dp.UK).T       # columns = eigenvectors
+    d = host(dp.dK)
+    K = p.K
+    nK = np.linalg.norm(K, 2)
+    assert np.linalg.norm(K @ U - U * d) <= 1e-12 * nK * np.sqrt(p.n)
+    assert np.linalg.norm(U.T @ U - np.eye(p.n)) <= 1e-12 * p.n
+    assert np.max(np.abs(np.sort(d) - np.linalg.eigvalsh(K))) <= 1e-12 * nK
+
+
+# ----------------------------------------------------------- single calls
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rhs_matches_oracle(name, uploaded):
+    p, dp = uploaded(name)
+    s = UISolver(dp, p.lam, p.rho, p.tol)
+    b = host(s.rhs())
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    want = O.rhs_matrix(p.K, O.mttkrp_observed(p.y, Zhat, p.obs_t, p.n))
+    assert rel(b, want) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_matches_oracle(name, uploaded):
+    p, dp = uploaded(name)
+    s = UISolver(dp, p.lam, p.rho, p.tol)
+    X = np.random.default_rng(5).standard_normal((p.n, p.r))
+    y = host(s.apply(dev(X)))
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    want = O.matvec_twostep(p.K, Zhat, p.obs_t, p.lam, p.rho, X)
+    assert rel(y, want) <= 1e-12
+    assert np.max(np.abs(y - want)) <= 1e-12 * np.max(np.abs(want)) * 10
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged-r17", "r40"])
+def test_explicit_zhat_apply_matches_implicit(name, uploaded):
+    p, dp = uploaded(name)
+    Zhat = p.A[p.obs_i] * p.B[p.obs_j]
+    V = (p.A.T @ p.A) * (p.B.T @ p.B)
+    dpe = upload(p, explicit=(Zhat, V), eig=(host(dp.UK), host(dp.dK)))
+    s = UISolver(dpe, p.lam, p.rho, p.tol, gamma=p.gamma)
+    X = np.random.default_rng(6).standard_normal((p.n, p.r))
+    y = host(s.apply(dev(X)))
+    want = O.matvec_twostep(p.K, O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j), p.obs_t,
+                            p.lam, p.rho, X)
+    assert rel(y, want) <= 1e-12
+
+
+def test_operator_symmetric_positive_definite_on_gpu(uploaded):
+    p, dp = uploaded("r40")
+    s = UISolver(dp, p.lam, p.rho, p.tol)
+    rng = np.random.default_rng(8)
+    X, Y = rng.standard_normal((p.n, p.r)), rng.standard_normal((p.n, p.r))
+    AX, AY = host(s.apply(dev(X))), host(s.apply(dev(Y)))
+    assert abs(np.sum(AX * Y) - np.sum(X * AY)) <= 1e-12 * np.linalg.norm(AX) * np.linalg.norm(Y)
+    assert np.sum(X * AX) >= p.rho * np.sum(X * X)
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged-r3", "ragged-r17", "r40", "r64"])
+def test_precond_matches_oracle(name, uploaded):
+    p, dp = uploaded(name)
+    s = UISolver(dp, p.lam, p.rho, p.tol)
+    s.setup()
+    X = np.random.default_rng(9).standard_normal((p.n, p.r))
+    z = host(s.precond(dev(X)))
+    dK, UK = O.kernel_eig(p.K)
+    dV, UV = np.linalg.eigh(O.gram_V(p.A, p.B))
+    want = O.precond_apply(UK, dK, UV, dV, p.gamma, p.lam, p.rho, X)
+    assert rel(z, want) <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["ragged-r3", "c1"])
+def test_precond_inverts_dense_preconditioner(name, uploaded):
+    p, dp = uploaded(name)
+    s = UISolver(dp, p.lam, p.rho, p.tol)
+    s.setup()
+    M = O.precond_matrix(p.K, O.gram_V(p.A, p.B), p.gamma, p.lam, p.rho)
+    X = np.random.default_rng(10).standard_normal((p.n, p.r))
+    MX = O.unvec(M @ O.vec(X), p.n, p.r)
+    back = host(s.precond(dev(MX)))
+    assert rel(back, X) <= 100 * np.finfo(float).eps * np.linalg.cond(M)
+
+
+# ---------------------------------------------------------------- solves
+
+def _dense(p):
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    return O.solve_dense(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho)
+
+
+def _dense_gate(p):
+    """Dense reference and the FP64 gate max(1e-10, 3 delta)."""
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    W, delta = O.solve_dense_with_error(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho)
+    return W, max(1e-10, 3 * delta)
+
+
+@pytest.mark.parametrize("tol,gate", [(1e-10, 1e-9), (1e-12, 1e-10)])
+def test_fp64_solve_c1(tol, gate, uploaded):
+    p, dp = uploaded("c1")
+    s = UISolver(dp, p.lam, p.rho, tol)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK, info.as_dict()
+    Wo = _dense(p)
+    assert O.e_kw(p.K, host(W), Wo) <= gate
+    assert info.relres_true <= 10 * tol
+    Zhat, V = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j), O.gram_V(p.A, p.B)
+    ref = O.solve_pcg(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, p.gamma, V, tol, 500)
+    assert abs(info.iters - ref.iters) <= 2
+
+
+@pytest.mark.parametrize("name", ["ragged-r3", "ragged-r17", "c1-drop", "r64"])
+def test_fp64_solve_ragged(name, uploaded):
+    p, dp = uploaded(name)
+    s = UISolver(dp, p.lam, p.rho, 1e-12)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK, info.as_dict()
+    Wo, gate = _dense_gate(p)
+    assert O.e_kw(p.K, host(W), Wo) <= gate
+
+
+def test_fp64_history_is_monotone_tail_and_matches_oracle(uploaded):
+    p, dp = uploaded("c1")
+    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    hist = np.zeros(502)
+    W, info = s.solve_subproblem(history=hist)
+    Zhat, V = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j), O.gram_V(p.A, p.B)
+    ref = O.solve_pcg(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, p.gamma, V, 1e-10, 500)
+    k = min(info.iters, ref.iters)
+    got = hist[: k + 1]
+    want = np.array(ref.relres_hist[: k + 1])
+    # the early residual history is insensitive to rounding
+    assert np.allclose(got[:10], want[:10], rtol=1e-6)
+    assert got[info.iters] <= 1e-10
+
+
+def test_eigenbasis_fp64_form_same_solution(uploaded):
+    p, dp = uploaded("c1")
+    s = UISolver(dp, p.lam, p.rho, 1e-12, flags=C.FLAG_EIGENBASIS)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK, info.as_dict()
+    assert O.e_kw(p.K, host(W), _dense(p)) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp32", "mixed_bf16"])
+@pytest.mark.parametrize("name", ["c1", "r40"])
+def test_mixed_precision_solve_reaches_1e6(precision, name, uploaded):
+    p, dp = uploaded(name)
+    s = UISolver(dp, p.lam, p.rho, 1e-7, precision=precision)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK, info.as_dict()
+    assert info.relres_true <= 1e-7
+    assert O.e_kw(p.K, host(W), _dense(p)) <= 1e-6
+
+
+def test_explicit_zhat_solve(uploaded):
+    p, dp = uploaded("ragged-r17")
+    Zhat = p.A[p.obs_i] * p.B[p.obs_j]
+    V = (p.A.T @ p.A) * (p.B.T @ p.B)
+    dpe = upload(p, explicit=(Zhat, V), eig=(host(dp.UK), host(dp.dK)))
+    s = UISolver(dpe, p.lam, p.rho, 1e-12, gamma=p.gamma)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK
+    assert O.e_kw(p.K, host(W), _dense(p)) <= 1e-10
+
+
+def test_aligned_case_converges_in_one_iteration():
+    p = make_aligned(3, I=6, J=5, n=40, r=4, sigma=0.1, lam=1e-3, rho=1e-6, tol=1e-10)
+    dp = upload(p)
+    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK
+    assert info.iters == 1
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    KB = p.K @ O.mttkrp_observed(p.y, Zhat, p.obs_t, p.n)
+    Wk = O.solve_aligned_rho_kron(p.K, O.gram_V(p.A, p.B), KB, p.lam, p.rho)
+    assert O.e_kw(p.K, host(W), Wk) <= 1e-10
+
+
+def test_warm_start_from_solution_needs_no_iteration(uploaded):
+    p, dp = uploaded("c1")
+    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    W, info = s.solve_subproblem()
+    s2 = UISolver(dp, p.lam, p.rho, 1e-8, flags=C.FLAG_WARM_START)
+    W2, info2 = s2.solve_subproblem(W=W.clone())
+    assert info2.status == C.OK and info2.iters == 0
+
+
+def test_iteration_cap_reports_not_converged(uploaded):
+    p, dp = uploaded("c1")
+    s = UISolver(dp, p.lam, p.rho, 1e-12, maxit=1)
+    W, info = s.solve_subproblem()
+    assert info.status == C.NOT_CONVERGED
+    assert info.iters == 1
+    assert 0 < info.relres_true < 1
+
+
+def test_nan_observation_reports_numeric(uploaded):
+    p, dp = uploaded("c1")
+    y = dp.y.clone()
+    y[5] = float("nan")
+    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    with pytest.raises(C.CphifiError) as ei:
+        s.solve_subproblem(y=y)
+    assert ei.value.status == C.NUMERIC
+
+
+def test_zero_data_gives_zero_solution(uploaded):
+    p, dp = uploaded("c1")
+    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    W, info = s.solve_subproblem(y=torch.zeros_like(dp.y))
+    assert info.status == C.OK and info.iters == 0
+    assert float(torch.count_nonzero(W)) == 0
+
+
+def test_no_observations_at_all():
+    p = make_small(40, n=30, I=3, J=3, r=2, q=0)
+    dp = upload(p)
+    s = UISolver(dp, p.lam, p.rho, 1e-10, gamma=1e-3)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK and float(torch.count_nonzero(W)) == 0
+
+
+def test_validate_flag_rejects_bad_index(uploaded):
+    p, dp = uploaded("c1")
+    bad = dp.obs_i.clone()
+    bad[3] = p.I + 5
+    from paper_2603_25691_amd.torch_api import DeviceProblem
+    dpb = DeviceProblem(**{**dp.__dict__, "obs_i": bad})
+    with pytest.raises(C.CphifiError) as ei:
+        UISolver(dpb, p.lam, p.rho, 1e-10, flags=C.FLAG_VALIDATE)
+    assert ei.value.status == C.INVALID_ARG
+
+
+def test_lowp_operator_matches_rounded_eigenbasis_definition(uploaded):
+    """apply_lowp against the eigenbasis operator with U_K rounded the same way
+    (round-to-nearest-even) and the skinny operand carried as hi+lo bf16 parts."""
+    p, _ = uploaded("r40")
+    dK, U = np.linalg.eigh(p.K)
+    dp = upload(p, eig=(np.ascontiguousarray(U.T), dK))
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    dc = np.maximum(dK, 0.0)
+    Xb = np.random.default_rng(12).standard_normal((p.n, p.r))
+
+    def rnd(a, dt):
+        return torch.from_numpy(a).to(dt).to(torch.float64).numpy()
+
+    def split(a):
+        h = rnd(rnd(a, torch.float32), torch.bfloat16)
+        lo = rnd(rnd(a - h, torch.float32), torch.bfloat16)
+        return h + lo
+
+    for prec, gate in (("fp64", 1e-12), ("mixed_fp32", 2e-5), ("mixed_bf16", 2e-4)):
+        s = UISolver(dp, p.lam, p.rho, 1e-8, precision=prec)
+        got = host(s.apply_lowp(dev(Xb)))
+        if prec == "fp64":
+            Ut, opx = U, (lambda a: a)
+        elif prec == "mixed_fp32":
+            Ut, opx = rnd(U, torch.float32), (lambda a: rnd(a, torch.float32))
+        else:
+            Ut, opx = rnd(U, torch.bfloat16), split
+        Xh = Ut @ opx(dc[:, None] * Xb)
+        xbar = np.sum(Xh[p.obs_t] * Zhat, axis=1)
+        Y1 = np.zeros_like(Xb)
+        np.add.at(Y1, p.obs_t, xbar[:, None] * Zhat)
+        want = dc[:, None] * (Ut.T @ opx(Y1) + p.lam * Xb) + p.rho * Xb
+        assert rel(got, want) <= gate, prec
+
+
+def test_c3_recipe_at_reduced_size():
+    """The large-case recipe (Matern-3/2, r = 40, m_i ~ U{10..50}) at I = 100
+    (n ~ 3000, q ~ 6e5): no dense solve fits, so the references are the oracle's
+    own PCG runs (tol 1e-12, and the config tol 1e-8)."""
+    p = config_c3(I=100)
+    dp = upload(p)
+    Zhat, V = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j), O.gram_V(p.A, p.B)
+    eig = O.kernel_eig(p.K)
+    tight = O.solve_pcg(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, p.gamma, V, 1e-12, 1000,
+                        eigK=eig)
+    same = O.solve_pcg(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, p.gamma, V, p.tol, 1000,
+                       eigK=eig)
+    assert tight.converged and same.converged
+    s = UISolver(dp, p.lam, p.rho, p.tol)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK, info.as_dict()
+    assert abs(info.iters - same.iters) <= 2
+    # two runs of the same PCG with different rounding agree far more closely
+    # than either is to the tight solution (the method error at this tol)
+    method_err = O.e_kw(p.K, same.X, tight.X)
+    assert O.e_kw(p.K, host(W), same.X) <= 0.1 * method_err
+    assert O.e_kw(p.K, host(W), tight.X) <= 1.1 * method_err
+    st = UISolver(dp, p.lam, p.rho, 1e-12)
+    Wt, infot = st.solve_subproblem()
+    assert infot.status == C.OK, infot.as_dict()
+    assert O.e_kw(p.K, host(Wt), tight.X) <= 1e-10
+    sb = UISolver(dp, p.lam, p.rho, 1e-7, precision="mixed_bf16")
+    Wb, infob = sb.solve_subproblem()
+    assert infob.status == C.OK, infob.as_dict()
+    assert O.e_kw(p.K, host(Wb), tight.X) <= 1e-6
