@@ -196,6 +196,28 @@ CPHIFI_API int cphifi_ui_plan_destroy(cphifi_plan* p);
 CPHIFI_API int cphifi_kernel_eig(int64_t n, const double* K, int64_t ldk, double* UK,
                       double* dK, void* stream);
 
+/* ------------------------------------------------ products (tuning, tests)
+ * The n x n by n x r products behind every step above (K X in Section 4.4.1,
+ * U_K^T X and U_K X in eq. fx), exposed for tile tuning and per-variant
+ * tests:  Y = op(U) diag(xscale) X.
+ *   elt:    0 = FP64 U, 1 = FP32 U, 2 = BF16 U (bf16 needs trans = 0, a row
+ *           stride ldu that is a multiple of 8 and >= round_up(n, 128), and
+ *           zeros in columns n .. ldu-1);  FP32 and BF16 accumulate in FP32.
+ *   trans:  0: op(U) = U (row-major, stride ldu);  1: op(U) = U^T.
+ *   mw, s:  tile (16-row MFMA blocks per wave, MFMA steps per k chunk); see
+ *           cphifi_product_tile_ok().  ksplit <= 0 chooses the split-K depth.
+ *   X:      n x r row-major doubles (device), 1 <= r <= 64;  xscale: n doubles
+ *           or NULL;  Y: n x r row-major doubles (device).
+ *   workspace: device, >= cphifi_product_workspace_bytes(n, r, elt), 256-byte
+ *           aligned (split-K partials and the BF16 split of X).
+ * async.  Errors: INVALID_ARG (shape, tile, alignment), HIP_ERROR. */
+CPHIFI_API int cphifi_product_workspace_bytes(int64_t n, int64_t r, int elt, size_t* bytes);
+CPHIFI_API int cphifi_product_tile_ok(int elt, int mw, int s);
+CPHIFI_API int cphifi_product(int elt, int trans, int mw, int s, int ksplit, int64_t n,
+                              const void* U, int64_t ldu, const double* X, int64_t r,
+                              const double* xscale, double* Y, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
 /* Human-readable name of a status code (static string). */
 CPHIFI_API const char* cphifi_status_string(int status);
 

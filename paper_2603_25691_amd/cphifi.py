@@ -112,6 +112,11 @@ def _load() -> C.CDLL:
         "cphifi_ui_solve_subproblem": (C.c_int, [P, P, P, C.POINTER(cphifi_solve_info)]),
         "cphifi_ui_plan_destroy": (C.c_int, [P]),
         "cphifi_kernel_eig": (C.c_int, [C.c_int64, P, C.c_int64, P, P, P]),
+        "cphifi_product_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int,
+                                                     C.POINTER(C.c_size_t)]),
+        "cphifi_product_tile_ok": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+        "cphifi_product": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, P,
+                                     C.c_int64, P, C.c_int64, P, P, P, C.c_size_t, P]),
         "cphifi_status_string": (C.c_char_p, [C.c_int]),
         "cphifi_last_error": (C.c_char_p, []),
         "cphifi_version": (C.c_char_p, []),
@@ -238,3 +243,29 @@ def make_inputs(**ptrs: Optional[int]) -> cphifi_ui_inputs:
     for k, v in ptrs.items():
         setattr(inp, k, None if v is None else int(v))
     return inp
+
+
+ELT_F64 = 0
+ELT_F32 = 1
+ELT_BF16 = 2
+
+
+def cphifi_product_workspace_bytes(n: int, r: int, elt: int) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.cphifi_product_workspace_bytes(n, r, elt, C.byref(out)),
+           "cphifi_product_workspace_bytes")
+    return int(out.value)
+
+
+def cphifi_product_tile_ok(elt: int, mw: int, s: int) -> bool:
+    return bool(_lib.cphifi_product_tile_ok(elt, mw, s))
+
+
+def cphifi_product(elt: int, trans: int, mw: int, s: int, ksplit: int, n: int, U: int, ldu: int,
+                   X: int, r: int, xscale: Optional[int], Y: int, workspace: int,
+                   workspace_bytes: int, stream: int) -> None:
+    _check(_lib.cphifi_product(elt, trans, mw, s, ksplit, n, C.c_void_p(U), ldu, C.c_void_p(X),
+                               r, C.c_void_p(xscale) if xscale else None, C.c_void_p(Y),
+                               C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+                               C.c_void_p(stream)), "cphifi_product")
+

@@ -77,8 +77,11 @@ struct GemmPlan {
   int s = 8;    // MFMA steps per k chunk (chunk = 4*s rows of X; 32*s for BF16)
 };
 GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu);
-// Plan with an explicit tile; ksplit_req <= 0 picks the split from the CU count.
-GemmPlan make_gemm_plan(Elt elt, int64_t n, int mw, int s, int ksplit_req, int num_cu);
+// Plan with an explicit tile; ksplit_req <= 0 picks the split from the CU count
+// and the kernel's occupancy.
+GemmPlan make_gemm_plan(Elt elt, bool trans, int64_t n, int r, int mw, int s, int ksplit_req,
+                        int num_cu);
+int gemm_occupancy(Elt elt, bool trans, int mw, int s, int r);  // workgroups per CU
 bool gemm_cfg_valid(Elt elt, int mw, int s);
 int gemm_bk(Elt elt, int s);  // k-chunk of the kernel (kper is a multiple of it)
 int launch_gemm(Elt elt, bool trans, const GemmPlan& gp, const void* U, int64_t ldu,

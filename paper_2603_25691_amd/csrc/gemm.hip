@@ -16,6 +16,9 @@
 //    consumer kernel adds in a fixed order (no atomics).
 #include "cphifi_internal.h"
 
+#include <cstdlib>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 namespace cphifi {
@@ -60,9 +63,13 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
 }
 
 // ------------------------------------------------- FP64 / FP32 (16x16x4) kernel
-template <typename TA, int NB, int MW, int S, bool TRANS>
+// VW: elements per vector load of the n x n operand along k (NN form only;
+// requires ldu % VW == 0 and a 16-byte aligned U).
+template <typename TA, int NB, int MW, int S, bool TRANS, int VW>
 __global__ __launch_bounds__(256) void gemm_k4_kernel(GArgs g) {
   using AccT = typename std::conditional<std::is_same<TA, double>::value, d4, f4>::type;
+  typedef TA VecT __attribute__((ext_vector_type(VW)));
+  static_assert(S % VW == 0, "S must be a multiple of the vector width");
   if (g.done != nullptr && *g.done) return;
   constexpr int BK = 4 * S;
   constexpr int NC = NB * 16;
@@ -75,16 +82,33 @@ __global__ __launch_bounds__(256) void gemm_k4_kernel(GArgs g) {
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, kk = lane >> 4;
   const int64_t n = g.n;
+  const int64_t ldu = g.ldu;
   const int64_t mbase = (int64_t)blockIdx.x * (4 * MW * 16) + (int64_t)wave * (MW * 16);
   const int64_t kbeg = (int64_t)blockIdx.y * g.kper;
   const int64_t kend = min(n, kbeg + g.kper);
   const TA* __restrict__ U = (const TA*)g.U;
-  const double* __restrict__ X = g.X;
-  const int64_t ldu = g.ldu;
 
-  int64_t rowc[MW];
+  // Lane-invariant parts of the addresses, computed once.
+  const TA* abase[MW];
 #pragma unroll
-  for (int mb = 0; mb < MW; ++mb) rowc[mb] = min(mbase + mb * 16 + li, n - 1);
+  for (int mb = 0; mb < MW; ++mb) {
+    const int64_t rc = min(mbase + mb * 16 + li, n - 1);
+    abase[mb] = TRANS ? U + (int64_t)(kk * S) * ldu + rc : U + rc * ldu + kk * S;
+  }
+  const double* __restrict__ X = g.X;
+  int xoff[XPT];   // offset of the staged element inside a chunk of X rows
+  int xlds[XPT];   // its LDS slot
+  int xkid[XPT];   // its row inside the chunk
+  bool xon[XPT];   // inside the staged tile and a real column of X
+#pragma unroll
+  for (int j = 0; j < XPT; ++j) {
+    const int e = tid + j * 256;
+    const int kidx = e / NC, c = e % NC;
+    xkid[j] = kidx;
+    xoff[j] = kidx * (int)g.ldx + c;
+    xlds[j] = kidx * LDX + c;
+    xon[j] = e < XE && c < g.r;
+  }
 
   AccT acc[MW][NB];
 #pragma unroll
@@ -93,44 +117,56 @@ __global__ __launch_bounds__(256) void gemm_k4_kernel(GArgs g) {
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = AccT{0, 0, 0, 0};
 
   const int64_t span = kend - kbeg;
-  const int64_t nchunk = span > 0 ? (span + BK - 1) / BK : 0;
-  const bool tail = (span % BK) != 0;
+  const int64_t nfull = span > 0 ? span / BK : 0;
+  const bool has_tail = span > 0 && (span % BK) != 0;
+  const int64_t nchunk = nfull + (has_tail ? 1 : 0);
 
-  auto loadA = [&](TA (&dst)[MW][S], int64_t k0, bool check) {
+  auto loadA = [&](TA (&dst)[MW][S], int64_t k0) {
+#pragma unroll
+    for (int mb = 0; mb < MW; ++mb) {
+      if (TRANS) {
+        const TA* p = abase[mb] + k0 * ldu;
+#pragma unroll
+        for (int s = 0; s < S; ++s) dst[mb][s] = p[(int64_t)s * ldu];
+      } else {
+        const TA* p = abase[mb] + k0;
+#pragma unroll
+        for (int v = 0; v < S / VW; ++v) {
+          const VecT t = *(const VecT*)(p + v * VW);
+#pragma unroll
+          for (int w = 0; w < VW; ++w) dst[mb][v * VW + w] = t[w];
+        }
+      }
+    }
+  };
+  auto loadA_tail = [&](TA (&dst)[MW][S], int64_t k0) {
 #pragma unroll
     for (int mb = 0; mb < MW; ++mb)
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        int64_t k = k0 + kk * S + s;
-        if (check) {
-          const int64_t kc = min(k, n - 1);
-          const TA v = TRANS ? U[kc * ldu + rowc[mb]] : U[rowc[mb] * ldu + kc];
-          dst[mb][s] = (k < kend) ? v : TA(0);
-        } else {
-          dst[mb][s] = TRANS ? U[k * ldu + rowc[mb]] : U[rowc[mb] * ldu + k];
-        }
+        const int64_t k = k0 + kk * S + s;
+        const int64_t dk = min(k, n - 1) - kk * S;  // relative to abase's k offset
+        const TA v = TRANS ? abase[mb][dk * ldu] : abase[mb][dk];
+        dst[mb][s] = (k < kend) ? v : TA(0);
       }
   };
-  auto stageX = [&](TA (&xr)[XPT], int64_t k0) {
+  auto stageX = [&](TA (&xr)[XPT], int64_t k0, bool tail) {
+    const double* xp = X + k0 * g.ldx;
 #pragma unroll
     for (int j = 0; j < XPT; ++j) {
-      const int e = tid + j * 256;
-      const int kidx = e / NC, c = e % NC;
-      const int64_t k = k0 + kidx;
       double v = 0.0;
-      if (e < XE && k < kend && c < g.r) {
-        v = X[k * g.ldx + c];
-        if (g.xscale != nullptr) v *= g.xscale[k];
+      const bool on = xon[j] && (!tail || k0 + xkid[j] < kend);
+      if (on) {
+        v = xp[xoff[j]];
+        if (g.xscale != nullptr) v *= g.xscale[k0 + xkid[j]];
       }
       xr[j] = (TA)v;
     }
   };
   auto storeX = [&](int buf, const TA (&xr)[XPT]) {
 #pragma unroll
-    for (int j = 0; j < XPT; ++j) {
-      const int e = tid + j * 256;
-      if (e < XE) xs[buf][(e / NC) * LDX + (e % NC)] = xr[j];
-    }
+    for (int j = 0; j < XPT; ++j)
+      if (tid + j * 256 < XE) xs[buf][xlds[j]] = xr[j];
   };
   auto compute = [&](const TA (&a)[MW][S], int buf) {
 #pragma unroll
@@ -144,34 +180,36 @@ __global__ __launch_bounds__(256) void gemm_k4_kernel(GArgs g) {
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma4(a[mb][s], b[nb], acc[mb][nb]);
     }
   };
+  // Next chunk: X rows first, then the n x n operand.  vmcnt retires in
+  // order, so waiting for the X rows (to fill LDS) leaves the larger A
+  // prefetch in flight across the barrier and into the next compute.
+  auto fetch = [&](TA (&xr)[XPT], TA (&dst)[MW][S], int64_t c) {
+    const int64_t k0 = kbeg + c * BK;
+    const bool tail = c == nfull;
+    stageX(xr, k0, tail);
+    if (tail)
+      loadA_tail(dst, k0);
+    else
+      loadA(dst, k0);
+  };
 
   if (nchunk > 0) {
-    TA a0[MW][S], a1[MW][S];
+    TA acur[MW][S], anext[MW][S];
     TA xr[XPT];
-    loadA(a0, kbeg, tail && nchunk == 1);
-    stageX(xr, kbeg);
+    fetch(xr, acur, 0);
     storeX(0, xr);
     __syncthreads();
-    for (int64_t c = 0; c < nchunk; c += 2) {
-      const bool has1 = c + 1 < nchunk;
-      if (has1) {
-        const int64_t k1 = kbeg + (c + 1) * BK;
-        loadA(a1, k1, tail && (c + 1 == nchunk - 1));
-        stageX(xr, k1);
-      }
-      compute(a0, 0);
-      if (has1) storeX(1, xr);
+    for (int64_t c = 0; c < nchunk; ++c) {
+      const int buf = (int)(c & 1);
+      const bool more = c + 1 < nchunk;
+      if (more) fetch(xr, anext, c + 1);
+      compute(acur, buf);
+      if (more) storeX(buf ^ 1, xr);
       __syncthreads();
-      if (!has1) break;
-      const bool has2 = c + 2 < nchunk;
-      if (has2) {
-        const int64_t k2 = kbeg + (c + 2) * BK;
-        loadA(a0, k2, tail && (c + 2 == nchunk - 1));
-        stageX(xr, k2);
-      }
-      compute(a1, 1);
-      if (has2) storeX(0, xr);
-      __syncthreads();
+#pragma unroll
+      for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+        for (int q = 0; q < S; ++q) acur[mb][q] = anext[mb][q];
     }
   }
 
@@ -275,30 +313,28 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GArgs g) {
   };
 
   if (nchunk > 0) {
-    u32x4 a0[MW][S], a1[MW][S];
+    // X rows of the next chunk are fetched before its U rows: vmcnt retires in
+    // order, so filling LDS does not wait for the larger U prefetch.
+    u32x4 acur[MW][S], anext[MW][S];
     u32x4 xr[2][XPT];
-    loadA(a0, kbeg);
     stageX(xr, kbeg);
+    loadA(acur, kbeg);
     storeX(0, xr);
     __syncthreads();
-    for (int64_t c = 0; c < nchunk; c += 2) {
-      const bool has1 = c + 1 < nchunk;
-      if (has1) {
-        loadA(a1, kbeg + (c + 1) * BK);
+    for (int64_t c = 0; c < nchunk; ++c) {
+      const int buf = (int)(c & 1);
+      const bool more = c + 1 < nchunk;
+      if (more) {
         stageX(xr, kbeg + (c + 1) * BK);
+        loadA(anext, kbeg + (c + 1) * BK);
       }
-      compute(a0, 0);
-      if (has1) storeX(1, xr);
+      compute(acur, buf);
+      if (more) storeX(buf ^ 1, xr);
       __syncthreads();
-      if (!has1) break;
-      const bool has2 = c + 2 < nchunk;
-      if (has2) {
-        loadA(a0, kbeg + (c + 2) * BK);
-        stageX(xr, kbeg + (c + 2) * BK);
-      }
-      compute(a1, 1);
-      if (has2) storeX(0, xr);
-      __syncthreads();
+#pragma unroll
+      for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+        for (int q = 0; q < S; ++q) acur[mb][q] = anext[mb][q];
     }
   }
 
@@ -342,7 +378,13 @@ template <typename TA, int NB, int MW, int S, bool TRANS>
 int launch_k4(const GArgs& g, int ksplit, hipStream_t st) {
   const int64_t rows = 4 * MW * 16;
   dim3 grid((unsigned)((g.n + rows - 1) / rows), (unsigned)ksplit);
-  hipLaunchKernelGGL((gemm_k4_kernel<TA, NB, MW, S, TRANS>), grid, dim3(256), 0, st, g);
+  constexpr int VW = TRANS ? 1 : (std::is_same<TA, double>::value ? 2 : 4);
+  const bool vec_ok = !TRANS && g.ldu % VW == 0 &&
+                      (reinterpret_cast<uintptr_t>(g.U) % 16) == 0;
+  if (vec_ok)
+    hipLaunchKernelGGL((gemm_k4_kernel<TA, NB, MW, S, TRANS, VW>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_k4_kernel<TA, NB, MW, S, TRANS, 1>), grid, dim3(256), 0, st, g);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }
@@ -400,7 +442,62 @@ int dispatch_cfg_bf16(int mw, int s, int nb, const GArgs& g, int ksplit, hipStre
   return CPHIFI_INVALID_ARG;
 }
 
+template <typename TA, int MW, int S, bool TRANS>
+int occ_k4(int nb) {
+  constexpr int VW = TRANS ? 1 : (std::is_same<TA, double>::value ? 2 : 4);
+  int blocks = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (nb) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_k4_kernel<TA, 1, MW, S, TRANS, VW>, 256, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_k4_kernel<TA, 2, MW, S, TRANS, VW>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_k4_kernel<TA, 3, MW, S, TRANS, VW>, 256, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_k4_kernel<TA, 4, MW, S, TRANS, VW>, 256, 0); break;
+  }
+  return e == hipSuccess && blocks > 0 ? blocks : 1;
+}
+
+template <int MW, int S>
+int occ_bf16(int nb) {
+  int blocks = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (nb) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<1, MW, S>, 256, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<2, MW, S>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<3, MW, S>, 256, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<4, MW, S>, 256, 0); break;
+  }
+  return e == hipSuccess && blocks > 0 ? blocks : 1;
+}
+
+template <typename TA, bool TRANS>
+int occ_cfg_k4(int mw, int s, int nb) {
+  if (mw == 1 && s == 4) return occ_k4<TA, 1, 4, TRANS>(nb);
+  if (mw == 1 && s == 8) return occ_k4<TA, 1, 8, TRANS>(nb);
+  if (mw == 2 && s == 4) return occ_k4<TA, 2, 4, TRANS>(nb);
+  if (mw == 2 && s == 8) return occ_k4<TA, 2, 8, TRANS>(nb);
+  if (mw == 4 && s == 4) return occ_k4<TA, 4, 4, TRANS>(nb);
+  return 1;
+}
+
+int occ_cfg_bf16(int mw, int s, int nb) {
+  if (mw == 1 && s == 4) return occ_bf16<1, 4>(nb);
+  if (mw == 2 && s == 2) return occ_bf16<2, 2>(nb);
+  if (mw == 2 && s == 4) return occ_bf16<2, 4>(nb);
+  if (mw == 4 && s == 2) return occ_bf16<4, 2>(nb);
+  return 1;
+}
+
 }  // namespace
+
+int gemm_occupancy(Elt elt, bool trans, int mw, int s, int r) {
+  const int nb = (r + 15) / 16;
+  switch (elt) {
+    case Elt::F64: return trans ? occ_cfg_k4<double, true>(mw, s, nb) : occ_cfg_k4<double, false>(mw, s, nb);
+    case Elt::F32: return trans ? occ_cfg_k4<float, true>(mw, s, nb) : occ_cfg_k4<float, false>(mw, s, nb);
+    case Elt::BF16: return occ_cfg_bf16(mw, s, nb);
+  }
+  return 1;
+}
 
 int gemm_bk(Elt elt, int s) { return (elt == Elt::BF16 ? 32 : 4) * s; }
 
@@ -412,7 +509,8 @@ bool gemm_cfg_valid(Elt elt, int mw, int s) {
          (mw == 4 && s == 4);
 }
 
-GemmPlan make_gemm_plan(Elt elt, int64_t n, int mw, int s, int ksplit_req, int num_cu) {
+GemmPlan make_gemm_plan(Elt elt, bool trans, int64_t n, int r, int mw, int s, int ksplit_req,
+                        int num_cu) {
   GemmPlan gp;
   gp.mw = mw;
   gp.s = s;
@@ -421,10 +519,13 @@ GemmPlan make_gemm_plan(Elt elt, int64_t n, int mw, int s, int ksplit_req, int n
   const int64_t bk = gemm_bk(elt, s);
   int64_t ks = ksplit_req;
   if (ks <= 0) {
-    // about three resident workgroups per CU, k ranges of at least 8 chunks
-    const int64_t target = 3LL * (num_cu > 0 ? num_cu : 256);
-    ks = (target + nrowblk - 1) / nrowblk;
-    ks = std::min<int64_t>(ks, std::max<int64_t>(1, n / (8 * bk)));
+    // One round of resident workgroups: split K until the grid fills the
+    // co-resident slots (CUs x workgroups per CU) without spilling into a
+    // second, partial round; keep at least 4 chunks per split.
+    const int64_t slots =
+        (int64_t)(num_cu > 0 ? num_cu : 256) * gemm_occupancy(elt, trans, mw, s, r);
+    ks = std::max<int64_t>(1, slots / nrowblk);
+    ks = std::min<int64_t>(ks, std::max<int64_t>(1, n / (4 * bk)));
   }
   ks = std::max<int64_t>(1, std::min<int64_t>(ks, kMaxSplit));
   int64_t kper = (n + ks - 1) / ks;
@@ -434,9 +535,72 @@ GemmPlan make_gemm_plan(Elt elt, int64_t n, int mw, int s, int ksplit_req, int n
   return gp;
 }
 
-GemmPlan choose_gemm(Elt elt, bool /*trans*/, int64_t n, int /*r*/, int num_cu) {
-  if (elt == Elt::BF16) return make_gemm_plan(elt, n, 2, 4, 0, num_cu);
-  return make_gemm_plan(elt, n, 2, 8, 0, num_cu);
+namespace {
+
+struct TileRule {
+  int elt, trans, r_lo, r_hi;
+  int64_t n_lo, n_hi;
+  int mw, s, ksplit;
+};
+
+// Tile table written by the autotuner (paper_2603_25691_amd/tune.py), read
+// once per process from the file named by CPHIFI_TILE_TABLE.
+const std::vector<TileRule>& tile_table() {
+  static std::once_flag once;
+  static std::vector<TileRule> rules;
+  std::call_once(once, [] {
+    const char* path = std::getenv("CPHIFI_TILE_TABLE");
+    if (path == nullptr) return;
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return;
+    char line[256];
+    while (std::fgets(line, sizeof(line), f)) {
+      if (line[0] == '#') continue;
+      char tag[16];
+      TileRule t{};
+      long long nlo = 0, nhi = 0;
+      if (std::sscanf(line, "%15s %d %d %d %lld %lld %d %d %d", tag, &t.trans, &t.r_lo, &t.r_hi,
+                      &nlo, &nhi, &t.mw, &t.s, &t.ksplit) != 9)
+        continue;
+      const std::string e(tag);
+      t.elt = e == "f64" ? 0 : e == "f32" ? 1 : e == "bf16" ? 2 : -1;
+      t.n_lo = nlo;
+      t.n_hi = nhi;
+      if (t.elt >= 0 && gemm_cfg_valid((Elt)t.elt, t.mw, t.s)) rules.push_back(t);
+    }
+    std::fclose(f);
+  });
+  return rules;
+}
+
+bool table_tile(Elt elt, bool trans, int64_t n, int r, int* mw, int* s, int* ks) {
+  for (const TileRule& t : tile_table())
+    if (t.elt == (int)elt && t.trans == (int)trans && r >= t.r_lo && r <= t.r_hi &&
+        n >= t.n_lo && n <= t.n_hi) {
+      *mw = t.mw;
+      *s = t.s;
+      *ks = t.ksplit;
+      return true;
+    }
+  return false;
+}
+
+}  // namespace
+
+// Tile for a product: the autotuner's table when one is loaded and covers
+// (n, r), else defaults measured at n = 30658, r = 40 on MI355X.
+GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu) {
+  int mw = 0, s = 0, ks = 0;
+  if (table_tile(elt, trans && elt != Elt::BF16, n, r, &mw, &s, &ks))
+    return make_gemm_plan(elt, trans && elt != Elt::BF16, n, r, mw, s, ks, num_cu);
+  switch (elt) {
+    case Elt::BF16: return make_gemm_plan(elt, false, n, r, 4, 2, 0, num_cu);
+    case Elt::F32: return trans ? make_gemm_plan(elt, true, n, r, 4, 4, 0, num_cu)
+                                : make_gemm_plan(elt, false, n, r, 2, 4, 0, num_cu);
+    case Elt::F64: return trans ? make_gemm_plan(elt, true, n, r, 4, 4, 0, num_cu)
+                                : make_gemm_plan(elt, false, n, r, 2, 8, 0, num_cu);
+  }
+  return make_gemm_plan(elt, trans, n, r, 2, 8, 0, num_cu);
 }
 
 static bool plan_ok(Elt elt, const GemmPlan& gp, int64_t n, int r) {

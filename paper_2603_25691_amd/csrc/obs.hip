@@ -6,12 +6,17 @@
 // or formed on the fly as A(i_l,:) * B(j_l,:) (3-way Khatri-Rao rows, eq. zhat).
 //
 // Work unit: one wave per task = (segment s, contiguous observation range).
-// Lanes form 64/G groups of G >= r lanes; a group handles one observation per
-// step, lane c of the group holding column c.  The dot product of eq. vl is
-// a butterfly over the G lanes of the group; the scatter of eq. yhat1 keeps a
-// per-lane running sum that is folded across groups once at the end.  Segments
-// longer than one task write partial rows that a second kernel adds in order,
-// so results are deterministic (no atomics).  xbar never leaves registers.
+// Lane layout: the wave is 64/L rows of L lanes (L in {4, 8, 16}, chosen from
+// r so that each lane holds CPL = ceil(r/L) <= 5 columns c0, c0+L, ...).  Row
+// g takes one observation of a group of 64/L.  For each observation:
+//  * Zhat(l, :) is formed from coalesced row reads of A and B (or of Zhat);
+//  * xbar_l (eq. vl) is an L-lane row sum done with log2(L) DPP steps (no LDS,
+//    no barrier), every lane of the row receiving the total;
+//  * the scatter of eq. (yhat1) is a per-lane multiply-add into CPL running sums.
+// Four groups are unrolled so their index and row loads are in flight together;
+// the rows' running sums are folded once per task.  Segments longer than one
+// task write partial rows that a second kernel adds in a fixed order, so
+// results are deterministic (no atomics); xbar never leaves registers.
 #include "cphifi_internal.h"
 
 namespace cphifi {
@@ -31,65 +36,150 @@ struct ObsDev {
   int64_t I, J;
 };
 
-template <int G>
+// v from lane (dpp permutation of) within each 16-lane row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of L lanes (L = 4, 8, 16), result in every lane of the
+// group: xor 1 and xor 2 (quad permutations), then the half-row mirror (pairs
+// the two quads of an 8-lane half) and the row mirror (pairs the two halves).
+template <int L>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  v += dpp_d<0xB1>(v);                      // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);                      // quad_perm [2,3,0,1]
+  if (L >= 8) v += dpp_d<0x141>(v);         // row_half_mirror
+  if (L >= 16) v += dpp_d<0x140>(v);        // row_mirror
   return v;
 }
 
-template <int G, bool EXPL, int MODE, typename PT>
+constexpr int kGroups = 4;  // observation groups unrolled per step
+
+template <int L, int CPL, bool EXPL, int MODE, typename PT>
 __global__ __launch_bounds__(256) void obs_kernel(TaskView t, ObsDev d) {
+  constexpr int ROWS = 64 / L;  // observations per group
   const ObsArgs& a = d.a;
   if (a.done != nullptr && *a.done) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t task = (int64_t)blockIdx.x * 4 + wave;
   if (task >= t.ntask) return;
-  constexpr int P = 64 / G;
-  const int g = lane / G, c = lane % G;
   const int r = a.r;
-  const bool col = c < r;
+  const int g = lane / L, cl = lane % L;
   const int64_t s = t.seg[task];
   const int64_t beg = t.beg[task], end = t.end[task];
   const int32_t slot = t.slot[task];
 
-  double xh = 0.0;
-  if (MODE == 0) {
-    if (col) {
-      const PT* part = (const PT*)a.part;
-      for (int sp = 0; sp < a.ksplit; ++sp)
-        xh += (double)part[((int64_t)sp * a.n + s) * a.ldp + c];
-    }
-    if (a.Xhat != nullptr && t.first[task] && g == 0 && col) a.Xhat[s * r + c] = xh;
+  uint32_t cidx[CPL];  // in-bounds column index used for loads
+  bool con[CPL];       // real column
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int c = cl + L * j;
+    con[j] = c < r;
+    cidx[j] = (uint32_t)min(c, r - 1);
   }
 
-  double acc = 0.0;
-  for (int64_t base = beg; base < end; base += P) {
-    const int64_t l = base + g;
-    const bool act = l < end;
-    double z = 0.0;
-    if (act && col) {
-      if (EXPL) {
-        z = a.Zhat[l * r + c];
-      } else {
-        const int64_t ii = min<int64_t>(max(a.obs_i[l], 0), d.I - 1);
-        const int64_t jj = min<int64_t>(max(a.obs_j[l], 0), d.J - 1);
-        z = a.A[ii * r + c] * a.B[jj * r + c];
+  const uint32_t Imax = (uint32_t)(d.I - 1), Jmax = (uint32_t)(d.J - 1), ur = (uint32_t)r;
+  const char* __restrict__ Abytes = (const char*)a.A;
+  const char* __restrict__ Bbytes = (const char*)a.B;
+  uint32_t cbyte[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) cbyte[j] = cidx[j] * 8u;
+  constexpr int STEP = ROWS * kGroups;
+
+  // Observation indices are software-pipelined one step ahead: the next step's
+  // (HBM) index loads are in flight while this step's rows are read and used.
+  auto fetch_idx = [&](int64_t base_, int32_t (&ii_)[kGroups], int32_t (&jj_)[kGroups]) {
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) {
+      const int64_t l = base_ + ROWS * u + g;
+      const int64_t o = l < end ? l : end - 1;
+      if (!EXPL) {
+        ii_[u] = a.obs_i[o];
+        jj_[u] = a.obs_j[o];
       }
     }
-    double w;
-    if (MODE == 0) {
-      w = group_sum<G>(z * xh);  // xbar_l, eq. vl
-    } else {
-      w = act ? a.y[l] : 0.0;
-    }
-    acc += w * z;  // eq. yhat1 (or the MTTKRP)
-  }
+  };
+  int32_t ii_cur[kGroups] = {}, jj_cur[kGroups] = {};
+  if (beg < end) fetch_idx(beg, ii_cur, jj_cur);
+
+  // Xhat(s, :); zero in padding columns, so they drop out of the dot products.
+  double xh[CPL];
 #pragma unroll
-  for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
-  if (g == 0 && col) {
+  for (int j = 0; j < CPL; ++j) xh[j] = 0.0;
+  if (MODE == 0) {
+    const PT* part = (const PT*)a.part;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      double v = 0.0;
+      for (int sp = 0; sp < a.ksplit; ++sp)
+        v += (double)part[((int64_t)sp * a.n + s) * a.ldp + cidx[j]];
+      xh[j] = con[j] ? v : 0.0;
+      if (a.Xhat != nullptr && t.first[task] && g == 0 && con[j]) a.Xhat[s * r + cidx[j]] = v;
+    }
+  }
+
+  double acc[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) acc[j] = 0.0;
+  for (int64_t base = beg; base < end; base += STEP) {
+    int32_t ii_nxt[kGroups] = {}, jj_nxt[kGroups] = {};
+    if (base + STEP < end) fetch_idx(base + STEP, ii_nxt, jj_nxt);
+    double z[kGroups][CPL];
+    double w[kGroups];
+    bool on[kGroups];
+    // Branch-free loads: clamp to an in-bounds observation, mask the result.
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) {
+      const int64_t l = base + ROWS * u + g;
+      on[u] = l < end;
+      const int64_t o = on[u] ? l : end - 1;
+      if (EXPL) {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) z[u][j] = a.Zhat[o * r + cidx[j]];
+      } else {
+        // byte offsets in 32 bits (I r and J r doubles fit, checked on the host)
+        const uint32_t ib = min((uint32_t)max(ii_cur[u], 0), Imax) * ur * 8u;
+        const uint32_t jb = min((uint32_t)max(jj_cur[u], 0), Jmax) * ur * 8u;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j)
+          z[u][j] = *(const double*)(Abytes + (ib + cbyte[j])) *
+                    *(const double*)(Bbytes + (jb + cbyte[j]));
+      }
+      if (MODE == 1) w[u] = on[u] ? a.y[o] : 0.0;
+    }
+    if (MODE == 0) {
+#pragma unroll
+      for (int u = 0; u < kGroups; ++u) {
+        double part = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) part += z[u][j] * xh[j];
+        const double xb = group_sum<L>(part);  // xbar_l, eq. vl
+        w[u] = on[u] ? xb : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u)
+#pragma unroll
+      for (int j = 0; j < CPL; ++j) acc[j] += w[u] * z[u][j];  // eq. yhat1 / MTTKRP
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) {
+      ii_cur[u] = ii_nxt[u];
+      jj_cur[u] = jj_nxt[u];
+    }
+  }
+  // fold the observation rows of the wave
+#pragma unroll
+  for (int j = 0; j < CPL; ++j)
+#pragma unroll
+    for (int off = L; off < 64; off <<= 1) acc[j] += __shfl_xor(acc[j], off, 64);
+  if (g == 0) {
     double* dst = slot < 0 ? a.out + s * r : a.tpart + (int64_t)slot * r;
-    dst[c] = acc;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j)
+      if (con[j]) dst[cidx[j]] = acc[j];
   }
 }
 
@@ -107,26 +197,34 @@ __global__ void segment_reduce_kernel(const int32_t* __restrict__ mseg,
   out[(int64_t)mseg[m] * r + lane] = acc;
 }
 
-template <int G, bool EXPL, int MODE>
-int launch_g(bool pf, const TaskView& tv, const ObsDev& d, hipStream_t st) {
+template <int L, int CPL, bool EXPL, int MODE>
+int launch_c(bool pf, const TaskView& tv, const ObsDev& d, hipStream_t st) {
   const int blocks = (tv.ntask + 3) / 4;
   if (blocks == 0) return CPHIFI_OK;
   if (pf)
-    hipLaunchKernelGGL((obs_kernel<G, EXPL, MODE, float>), dim3(blocks), dim3(256), 0, st, tv, d);
-  else
-    hipLaunchKernelGGL((obs_kernel<G, EXPL, MODE, double>), dim3(blocks), dim3(256), 0, st, tv,
+    hipLaunchKernelGGL((obs_kernel<L, CPL, EXPL, MODE, float>), dim3(blocks), dim3(256), 0, st, tv,
                        d);
+  else
+    hipLaunchKernelGGL((obs_kernel<L, CPL, EXPL, MODE, double>), dim3(blocks), dim3(256), 0, st,
+                       tv, d);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }
 
+// Lanes per observation: L = 4 up to r = 20, 8 up to r = 40, 16 beyond; each
+// lane then holds ceil(r / L) <= 5 columns.
 template <bool EXPL, int MODE>
 int launch_m(int r, bool pf, const TaskView& tv, const ObsDev& d, hipStream_t st) {
-  if (r <= 4) return launch_g<4, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 8) return launch_g<8, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 16) return launch_g<16, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 32) return launch_g<32, EXPL, MODE>(pf, tv, d, st);
-  return launch_g<64, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 4) return launch_c<4, 1, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 8) return launch_c<4, 2, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 12) return launch_c<4, 3, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 16) return launch_c<4, 4, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 20) return launch_c<4, 5, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 24) return launch_c<8, 3, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 32) return launch_c<8, 4, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 40) return launch_c<8, 5, EXPL, MODE>(pf, tv, d, st);
+  if (r <= 48) return launch_c<16, 3, EXPL, MODE>(pf, tv, d, st);
+  return launch_c<16, 4, EXPL, MODE>(pf, tv, d, st);
 }
 
 }  // namespace
@@ -141,6 +239,10 @@ int launch_obs(ObsMode mode, bool part_is_float, const ObsTasks& t, const ObsArg
   if (!expl && (a.A == nullptr || a.B == nullptr || I < 1 || J < 1)) {
     set_error("launch_obs: implicit factor form needs A, B, I, J");
     return CPHIFI_INVALID_ARG;
+  }
+  if (!expl && (I * a.r * 8 > (int64_t)UINT32_MAX || J * a.r * 8 > (int64_t)UINT32_MAX)) {
+    set_error("launch_obs: factor matrices beyond 4 GiB need the explicit Zhat form");
+    return CPHIFI_UNSUPPORTED;
   }
   TaskView tv{t.seg, t.beg, t.end, t.slot, t.first, t.ntask};
   ObsDev d{a, I, J};

@@ -142,7 +142,8 @@ struct cphifi_plan {
   void* ulp = nullptr;   // U_K rounded, row-major U (BF16 form only)
   void* utlp = nullptr;  // U_K rounded, row-major U^T (eigenvector k = row k)
   __bf16 *xthi = nullptr, *xtlo = nullptr;
-  GemmPlan gp64{}, gplp{};
+  GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
+  int last_ksplit = 1;  // split-K depth of the partials the last product wrote
   DevScalars* h_sc = nullptr;  // pinned host mirror
   bool timing = false;
   Elt timed_elt = Elt::F64;  // product type whose launches are timed ...
@@ -202,8 +203,9 @@ int timing_collect(cphifi_plan* p, double* ms, int* count) {
 int prod_K(cphifi_plan* p, const double* X, const int32_t* done) {
   hipEvent_t e0;
   TRY(timed_begin(p, Elt::F64, false, &e0));
-  TRY(launch_gemm(Elt::F64, false, p->gp64, p->in.K, p->ldk, p->n, X, p->r, (int)p->r, nullptr,
+  TRY(launch_gemm(Elt::F64, false, p->gp64n, p->in.K, p->ldk, p->n, X, p->r, (int)p->r, nullptr,
                   p->part, done, p->st));
+  p->last_ksplit = p->gp64n.ksplit;
   return timed_end(p, e0);
 }
 
@@ -218,16 +220,19 @@ int prod_U(cphifi_plan* p, Elt elt, const double* X, const double* xscale,
   TRY(timed_begin(p, elt, elt != Elt::BF16, &e0));
   switch (elt) {
     case Elt::F64:
-      TRY(launch_gemm(Elt::F64, true, p->gp64, p->in.UK, p->ldk, p->n, X, p->r, (int)p->r,
+      TRY(launch_gemm(Elt::F64, true, p->gp64t, p->in.UK, p->ldk, p->n, X, p->r, (int)p->r,
                       xscale, p->part, done, p->st));
+      p->last_ksplit = p->gp64t.ksplit;
       break;
     case Elt::F32:
-      TRY(launch_gemm(Elt::F32, true, p->gplp, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
+      TRY(launch_gemm(Elt::F32, true, p->gplpt, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
                       xscale, p->part, done, p->st));
+      p->last_ksplit = p->gplpt.ksplit;
       break;
     case Elt::BF16:
-      TRY(launch_gemm_bf16(p->gplp, (const __bf16*)p->ulp, p->L.ldl, p->n, X, p->r, (int)p->r,
+      TRY(launch_gemm_bf16(p->gplpn, (const __bf16*)p->ulp, p->L.ldl, p->n, X, p->r, (int)p->r,
                            xscale, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st));
+      p->last_ksplit = p->gplpn.ksplit;
       break;
   }
   return timed_end(p, e0);
@@ -242,24 +247,26 @@ int prod_Ut(cphifi_plan* p, Elt elt, const double* X, const int32_t* done) {
   TRY(timed_begin(p, elt, false, &e0));
   switch (elt) {
     case Elt::F64:
-      TRY(launch_gemm(Elt::F64, false, p->gp64, p->in.UK, p->ldk, p->n, X, p->r, (int)p->r,
+      TRY(launch_gemm(Elt::F64, false, p->gp64n, p->in.UK, p->ldk, p->n, X, p->r, (int)p->r,
                       nullptr, p->part, done, p->st));
+      p->last_ksplit = p->gp64n.ksplit;
       break;
     case Elt::F32:
-      TRY(launch_gemm(Elt::F32, false, p->gplp, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
+      TRY(launch_gemm(Elt::F32, false, p->gplpn, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
                       nullptr, p->part, done, p->st));
+      p->last_ksplit = p->gplpn.ksplit;
       break;
     case Elt::BF16:
-      TRY(launch_gemm_bf16(p->gplp, (const __bf16*)p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
+      TRY(launch_gemm_bf16(p->gplpn, (const __bf16*)p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
                            nullptr, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st));
+      p->last_ksplit = p->gplpn.ksplit;
       break;
   }
   return timed_end(p, e0);
 }
 
-int ksplit_of(const cphifi_plan* p, Elt elt) {
-  return elt == Elt::F64 ? p->gp64.ksplit : p->gplp.ksplit;
-}
+// Split-K depth of the partials in p->part (set by the product that wrote them).
+int ksplit_of(const cphifi_plan* p, Elt /*elt*/) { return p->last_ksplit; }
 
 // Gather-dot-scatter over the observations: out <- G applied to the product
 // held in part (gather mode), optionally storing Xhat.
@@ -290,7 +297,7 @@ int op_apply_paper(cphifi_plan* p, const double* x, double* y, double* red, int*
   TRY(prod_K(p, x, done));
   TRY(obs_gather(p, Elt::F64, p->vec[V_XHAT], p->vec[V_Y1], done));
   TRY(prod_K(p, p->vec[V_Y1], done));
-  return launch_apply_finish(p->part, false, p->gp64.ksplit, p->ldp, p->n, (int)p->r,
+  return launch_apply_finish(p->part, false, p->last_ksplit, p->ldp, p->n, (int)p->r,
                              p->vec[V_XHAT], x, nullptr, p->d.lambda, p->d.rho, y, red, nblk,
                              done, p->st);
 }
@@ -303,10 +310,10 @@ int op_precond_paper(cphifi_plan* p, const double* x, double* z, double* red, in
     return red ? launch_dot(x, z, p->n * p->r, red, nblk, done, p->st) : CPHIFI_OK;
   }
   TRY(prod_Ut(p, Elt::F64, x, done));
-  TRY(launch_prec_mid(p->part, false, p->gp64.ksplit, p->ldp, nullptr, p->n, (int)p->r, p->UV,
+  TRY(launch_prec_mid(p->part, false, p->last_ksplit, p->ldp, nullptr, p->n, (int)p->r, p->UV,
                       p->D, p->vec[V_T2], nullptr, nullptr, nullptr, done, p->st));
   TRY(prod_U(p, Elt::F64, p->vec[V_T2], nullptr, done));
-  return launch_reduce_partials(p->part, false, p->gp64.ksplit, p->ldp, p->n, (int)p->r, z, x,
+  return launch_reduce_partials(p->part, false, p->last_ksplit, p->ldp, p->n, (int)p->r, z, x,
                                 red, nblk, done, p->st);
 }
 
@@ -591,12 +598,13 @@ int validate_desc(const cphifi_ui_desc* d) {
 }
 
 // Optional tile override "mw,s,ksplit" from the environment (tuning sweeps).
-GemmPlan plan_from_env(const char* var, Elt elt, int64_t n, const GemmPlan& dflt, int num_cu) {
+GemmPlan plan_from_env(const char* var, Elt elt, bool trans, int64_t n, int r,
+                       const GemmPlan& dflt, int num_cu) {
   const char* s = std::getenv(var);
   if (s == nullptr) return dflt;
   int mw = 0, ss = 0, ks = 0;
   if (std::sscanf(s, "%d,%d,%d", &mw, &ss, &ks) < 2 || !gemm_cfg_valid(elt, mw, ss)) return dflt;
-  return make_gemm_plan(elt, n, mw, ss, ks, num_cu);
+  return make_gemm_plan(elt, trans, n, r, mw, ss, ks, num_cu);
 }
 
 }  // namespace
@@ -811,8 +819,11 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
       (rc = up(p->tasks.mptr, mptr)))
     return fail(rc);
 
-  p->gp64 = plan_from_env("CPHIFI_TILE_F64", Elt::F64, n,
-                          choose_gemm(Elt::F64, false, n, (int)d->r, p->num_cu), p->num_cu);
+  const int rr = (int)d->r;
+  p->gp64n = plan_from_env("CPHIFI_TILE_F64", Elt::F64, false, n, rr,
+                           choose_gemm(Elt::F64, false, n, rr, p->num_cu), p->num_cu);
+  p->gp64t = plan_from_env("CPHIFI_TILE_F64T", Elt::F64, true, n, rr,
+                           choose_gemm(Elt::F64, true, n, rr, p->num_cu), p->num_cu);
   if (d->precision == CPHIFI_MIXED_BF16) {
     p->lp = Elt::BF16;
     p->timed_elt = Elt::BF16;
@@ -820,8 +831,8 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     p->utlp = ws + L.utlp;
     p->xthi = (__bf16*)(ws + L.xthi);
     p->xtlo = (__bf16*)(ws + L.xtlo);
-    p->gplp = plan_from_env("CPHIFI_TILE_BF16", Elt::BF16, n,
-                            choose_gemm(Elt::BF16, false, n, (int)d->r, p->num_cu), p->num_cu);
+    p->gplpn = plan_from_env("CPHIFI_TILE_BF16", Elt::BF16, false, n, rr,
+                             choose_gemm(Elt::BF16, false, n, rr, p->num_cu), p->num_cu);
     if ((rc = launch_convert_lowp(Elt::BF16, false, in->UK, p->ldk, n, p->utlp, L.ldl, st)) ||
         (rc = launch_convert_lowp(Elt::BF16, true, in->UK, p->ldk, n, p->ulp, L.ldl, st)))
       return fail(rc);
@@ -829,8 +840,10 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     p->lp = Elt::F32;
     p->timed_elt = Elt::F32;
     p->utlp = ws + L.utlp;
-    p->gplp = plan_from_env("CPHIFI_TILE_F32", Elt::F32, n,
-                            choose_gemm(Elt::F32, false, n, (int)d->r, p->num_cu), p->num_cu);
+    p->gplpn = plan_from_env("CPHIFI_TILE_F32", Elt::F32, false, n, rr,
+                             choose_gemm(Elt::F32, false, n, rr, p->num_cu), p->num_cu);
+    p->gplpt = plan_from_env("CPHIFI_TILE_F32T", Elt::F32, true, n, rr,
+                             choose_gemm(Elt::F32, true, n, rr, p->num_cu), p->num_cu);
     if ((rc = launch_convert_lowp(Elt::F32, false, in->UK, p->ldk, n, p->utlp, L.ldl, st)))
       return fail(rc);
   }
@@ -890,7 +903,7 @@ int cphifi_ui_rhs(cphifi_plan* p, const double* y, double* b) {
   const int rc = prod_K(p, p->vec[V_Y1], nullptr);
   p->timing = t;
   TRY(rc);
-  return launch_reduce_partials(p->part, false, p->gp64.ksplit, p->ldp, p->n, (int)p->r, b,
+  return launch_reduce_partials(p->part, false, p->last_ksplit, p->ldp, p->n, (int)p->r, b,
                                 nullptr, nullptr, nullptr, nullptr, p->st);
 }
 

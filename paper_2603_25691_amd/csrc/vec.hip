@@ -292,15 +292,23 @@ __global__ void fill_i32_kernel(int32_t* dst, int32_t v, int64_t len) {
 }
 
 // V = (A^T A) had (B^T B): the Gram of the Khatri-Rao product of the other
-// modes' factors (Section 3, reused in Section 4.4.2).  One block.
+// modes' factors (Section 3, reused in Section 4.4.2).  One block per entry of
+// the upper triangle, each a deterministic block reduction over I and J.
 __global__ __launch_bounds__(256) void gram_kernel(const double* A, int64_t I, const double* B,
                                                    int64_t J, int r, double* V) {
-  for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
-    const int a = e / r, b = e % r;
-    if (b < a) continue;
-    double ga = 0.0, gb = 0.0;
-    for (int64_t i = 0; i < I; ++i) ga += A[i * r + a] * A[i * r + b];
-    for (int64_t j = 0; j < J; ++j) gb += B[j * r + a] * B[j * r + b];
+  // block -> (a, b) with a <= b, row-major over the upper triangle
+  int idx = blockIdx.x, a = 0;
+  while (idx >= r - a) {
+    idx -= r - a;
+    ++a;
+  }
+  const int b = a + idx;
+  double ga = 0.0, gb = 0.0;
+  for (int64_t i = threadIdx.x; i < I; i += blockDim.x) ga += A[i * r + a] * A[i * r + b];
+  for (int64_t j = threadIdx.x; j < J; j += blockDim.x) gb += B[j * r + a] * B[j * r + b];
+  ga = block_sum(ga);
+  gb = block_sum(gb);
+  if (threadIdx.x == 0) {
     V[a * r + b] = ga * gb;
     V[b * r + a] = ga * gb;
   }
@@ -585,7 +593,7 @@ int launch_fill_i32(int32_t* dst, int32_t v, int64_t len, hipStream_t st) {
 
 int launch_gram(const double* A, int64_t I, const double* B, int64_t J, int r, double* V,
                 hipStream_t st) {
-  hipLaunchKernelGGL(gram_kernel, dim3(1), dim3(256), 0, st, A, I, B, J, r, V);
+  hipLaunchKernelGGL(gram_kernel, dim3(r * (r + 1) / 2), dim3(256), 0, st, A, I, B, J, r, V);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }

@@ -183,3 +183,26 @@ def upload(p, device="cuda", explicit=None, eig=None) -> DeviceProblem:
     A = dev(p.A, torch.float64)
     B = dev(p.B, torch.float64)
     return DeviceProblem(p.n, p.r, p.q, p.I, p.J, K, UK, dK, obs_ptr, obs_i, obs_j, y, A=A, B=B)
+
+
+def product(U: torch.Tensor, X: torch.Tensor, elt: str = "fp64", trans: bool = False,
+            tile=(0, 0), ksplit: int = 0, xscale: Optional[torch.Tensor] = None,
+            out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None):
+    """Y = op(U) diag(xscale) X through cphifi_product (U already in the element
+    type's storage: float64, float32, or bfloat16 zero-padded to a row stride
+    that is a multiple of 8 and >= round_up(n, 128))."""
+    e = {"fp64": _c.ELT_F64, "fp32": _c.ELT_F32, "bf16": _c.ELT_BF16}[elt]
+    n, r = X.shape
+    mw, s = tile
+    if mw == 0:
+        mw, s = (2, 4) if e == _c.ELT_BF16 else (2, 8)
+    ws_bytes = _c.cphifi_product_workspace_bytes(n, r, e)
+    if workspace is None or workspace.numel() < ws_bytes + 256:
+        workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=X.device)
+    base = (workspace.data_ptr() + 255) // 256 * 256
+    out = torch.empty(n, r, dtype=torch.float64, device=X.device) if out is None else out
+    _c.cphifi_product(e, int(trans), mw, s, ksplit, n, U.data_ptr(), U.stride(0), X.data_ptr(),
+                      r, None if xscale is None else xscale.data_ptr(), out.data_ptr(), base,
+                      ws_bytes, _stream())
+    return out
+

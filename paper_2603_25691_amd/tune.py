@@ -1,0 +1,152 @@
+"""Tile autotuner for the n x n by n x r product kernels.
+
+  python -m paper_2603_25691_amd.tune sweep --n 500 2000 8000 30658 --r 5 10 20 40 \
+      --elt fp64 bf16 --out tiles.txt
+  python -m paper_2603_25691_amd.tune measure --n 30658 --r 40 --elt bf16 --reps 4 \
+      --calib-mb 1024
+
+`sweep` times every (mw, s, ksplit) tile of cphifi_product for each size and
+writes the fastest per (element type, orientation, r, n) to a plain-text table
+that plans read when CPHIFI_TILE_TABLE names it.  Table line format:
+
+    <elt> <trans> <r_lo> <r_hi> <n_lo> <n_hi> <mw> <s> <ksplit>
+
+with elt in {f64, f32, bf16}; the first line whose ranges contain (r, n) wins.
+
+`measure` runs the chosen product `reps` times after a plain device copy of
+known size, so a hardware-counter run (e.g. rocprofv3 --pmc FETCH_SIZE) can scale
+the product's HBM bytes by what the counter reads for the copy.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import torch
+
+from . import cphifi as C
+from .torch_api import product
+
+TILES = {"fp64": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
+         "fp32": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
+         "bf16": [(1, 4), (2, 2), (2, 4), (4, 2)]}
+TAG = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+ESIZE = {"fp64": 8, "fp32": 4, "bf16": 2}
+
+
+def _operand(elt: str, n: int, gen: torch.Generator) -> torch.Tensor:
+    U = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=gen)
+    if elt == "fp64":
+        return U
+    if elt == "fp32":
+        return U.float()
+    ld = (n + 255) // 256 * 256
+    Ub = torch.zeros(n, ld, dtype=torch.bfloat16, device="cuda")
+    Ub[:, :n] = U.to(torch.bfloat16)
+    return Ub
+
+
+def _time(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def sweep(ns, rs, elts, out_path: str, reps: int = 5) -> None:
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    lines = []
+    for elt in elts:
+        transes = (False,) if elt == "bf16" else (False, True)
+        for n in sorted(ns):
+            U = _operand(elt, n, gen)
+            for r in sorted(rs):
+                X = torch.rand(n, r, dtype=torch.float64, device="cuda", generator=gen)
+                Y = torch.empty_like(X)
+                ws = torch.empty(C.cphifi_product_workspace_bytes(n, r, C.ELT_BF16) + 256,
+                                 dtype=torch.uint8, device="cuda")
+                for trans in transes:
+                    best = None
+                    for tile in TILES[elt]:
+                        for ks in (0, 1, 2, 4, 8):
+                            ms = _time(lambda: product(U, X, elt, trans, tile, ks, out=Y,
+                                                       workspace=ws), reps)
+                            rec = {"elt": elt, "trans": trans, "n": n, "r": r, "tile": tile,
+                                   "ksplit": ks, "ms": ms,
+                                   "GBps": (ESIZE[elt] * n * n + 16 * n * r) / ms / 1e6}
+                            print(json.dumps(rec), flush=True)
+                            if best is None or ms < best["ms"]:
+                                best = rec
+                    lines.append((elt, trans, n, r, best))
+            del U
+            torch.cuda.empty_cache()
+    # ranges: each measured n covers up to the next measured n; each r up to the next r
+    ns_s, rs_s = sorted(ns), sorted(rs)
+    with open(out_path, "w") as f:
+        f.write("# elt trans r_lo r_hi n_lo n_hi mw s ksplit  (tile table, MI355X)\n")
+        for elt, trans, n, r, b in lines:
+            i, k = ns_s.index(n), rs_s.index(r)
+            n_lo = 1 if i == 0 else ns_s[i - 1] + 1
+            n_hi = n if i + 1 < len(ns_s) else 1 << 31
+            r_lo = 1 if k == 0 else rs_s[k - 1] + 1
+            r_hi = r if k + 1 < len(rs_s) else 64
+            f.write(f"{TAG[elt]} {int(trans)} {r_lo} {r_hi} {n_lo} {n_hi} {b['tile'][0]} "
+                    f"{b['tile'][1]} {b['ksplit']}\n")
+    print(f"wrote {out_path}", file=sys.stderr)
+
+
+def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False) -> None:
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    if calib_mb > 0:
+        src = torch.ones(calib_mb * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": calib_mb * 2 ** 20}), flush=True)
+    for elt in elts:
+        U = _operand(elt, n, gen)
+        X = torch.rand(n, r, dtype=torch.float64, device="cuda", generator=gen)
+        Y = torch.empty_like(X)
+        ws = torch.empty(C.cphifi_product_workspace_bytes(n, r, C.ELT_BF16) + 256,
+                         dtype=torch.uint8, device="cuda")
+        ms = _time(lambda: product(U, X, elt, trans and elt != "bf16", (0, 0), 0, out=Y,
+                                   workspace=ws), reps)
+        print(json.dumps({"elt": elt, "n": n, "r": r, "ms": ms, "reps": reps,
+                          "algorithmic_bytes": ESIZE[elt] * n * n + 16 * n * r}), flush=True)
+        del U
+        torch.cuda.empty_cache()
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("sweep")
+    s.add_argument("--n", type=int, nargs="+", required=True)
+    s.add_argument("--r", type=int, nargs="+", required=True)
+    s.add_argument("--elt", nargs="+", default=["fp64", "bf16"])
+    s.add_argument("--out", default="tiles.txt")
+    s.add_argument("--reps", type=int, default=5)
+    m = sub.add_parser("measure")
+    m.add_argument("--n", type=int, required=True)
+    m.add_argument("--r", type=int, required=True)
+    m.add_argument("--elt", nargs="+", default=["bf16", "fp64"])
+    m.add_argument("--reps", type=int, default=4)
+    m.add_argument("--calib-mb", type=int, default=1024)
+    a = ap.parse_args(argv)
+    if a.cmd == "sweep":
+        sweep(a.n, a.r, a.elt, a.out, a.reps)
+    else:
+        measure(a.n, a.r, a.elt, a.reps, a.calib_mb)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,78 @@
+"""Every tile variant of the n x n by n x r product kernels against numpy.
+
+FP64: 1e-13 relative (Frobenius).  FP32 and BF16 operands are rounded on the
+host exactly as the library stores them (round to nearest even), the skinny
+operand as the kernels carry it (FP32: one rounding; BF16: a hi + lo pair of
+bf16), and the reference product is then taken in FP64: what remains is FP32
+accumulation, bounded here by 1e-5 relative.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2603_25691_amd import cphifi as C  # noqa: E402
+    from paper_2603_25691_amd.torch_api import product  # noqa: E402
+
+TILES = {"fp64": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
+         "fp32": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
+         "bf16": [(1, 4), (2, 2), (2, 4), (4, 2)]}
+
+
+def _rnd(a, dt):
+    return torch.from_numpy(a).to(dt).to(torch.float64).numpy()
+
+
+def _split_bf16(a):
+    hi = _rnd(_rnd(a, torch.float32), torch.bfloat16)
+    return hi + _rnd(_rnd(a - hi, torch.float32), torch.bfloat16)
+
+
+def _case(n, r, seed):
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((n, n))
+    X = rng.standard_normal((n, r))
+    scale = rng.uniform(0.5, 2.0, n)
+    return U, X, scale
+
+
+@pytest.mark.parametrize("elt", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,r", [(37, 5), (300, 17), (1000, 40), (777, 64), (129, 33)])
+def test_product_all_tiles(elt, n, r):
+    U, X, scale = _case(n, r, n + r)
+    Xd = torch.from_numpy(X).cuda()
+    sd = torch.from_numpy(scale).cuda()
+    if elt == "fp64":
+        Ud = torch.from_numpy(U).cuda()
+        Ur, opx, gate, transes = U, (lambda a: a), 1e-13, (False, True)
+    elif elt == "fp32":
+        Ud = torch.from_numpy(U).cuda().float()
+        Ur, opx, gate, transes = _rnd(U, torch.float32), (lambda a: _rnd(a, torch.float32)), \
+            1e-5, (False, True)
+    else:
+        ld = (n + 255) // 256 * 256
+        Ud = torch.zeros(n, ld, dtype=torch.bfloat16, device="cuda")
+        Ud[:, :n] = torch.from_numpy(U).cuda().to(torch.bfloat16)
+        Ur, opx, gate, transes = _rnd(U, torch.bfloat16), _split_bf16, 1e-5, (False,)
+    for trans in transes:
+        A = Ur.T if trans else Ur
+        want = A @ opx(scale[:, None] * X)
+        for tile in TILES[elt]:
+            for ks in (0, 1, 3):
+                got = product(Ud, Xd, elt, trans, tile, ks, sd).cpu().numpy()
+                err = np.linalg.norm(got - want) / np.linalg.norm(want)
+                assert err <= gate, (elt, trans, tile, ks, err)
+
+
+def test_product_rejects_bad_tiles_and_shapes():
+    X = torch.zeros(40, 8, dtype=torch.float64, device="cuda")
+    U = torch.zeros(40, 40, dtype=torch.float64, device="cuda")
+    with pytest.raises(C.CphifiError):
+        product(U, X, "fp64", False, (3, 4))
+    Ub = torch.zeros(40, 40, dtype=torch.bfloat16, device="cuda")  # stride < 128
+    with pytest.raises(C.CphifiError):
+        product(Ub, X, "bf16", False, (2, 4))
