@@ -1,0 +1,80 @@
+// Plan state shared by the translation units of the solver: the workspace
+// layout of one subproblem and the plan object behind cphifi_plan*.
+#pragma once
+
+#include "cphifi_internal.h"
+
+namespace cphifi {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+enum VecSlot {
+  V_R = 0, V_Z, V_P, V_Q,           // outer / FP64 PCG vectors
+  V_XHAT, V_Y1, V_T2, V_B,          // product intermediates, internal right-hand side
+  V_RF, V_RB, V_XB,                 // refinement residual, its eigenbasis image, correction
+  V_R2, V_Z2, V_P2, V_Q2,           // eigenbasis PCG vectors
+  V_TMP,
+  NVEC
+};
+
+struct Layout {
+  size_t vec[NVEC];
+  size_t part, tpart;
+  size_t tseg, tbeg, tend, tslot, tfirst, mseg, mptr, rowm;
+  size_t red[3];
+  size_t sc, sc2, hist;
+  size_t V, UV, dV, D, dKc;
+  size_t ulp, utlp, xthi, xtlo;
+  size_t total;
+  int64_t ldl;
+  int64_t ntask_max, nslot_max, nmulti_max;
+  int hist_len;
+};
+
+inline int64_t eff_ldk(const cphifi_ui_desc& d) { return d.ldk > 0 ? d.ldk : d.n; }
+inline int eff_maxit(const cphifi_ui_desc& d) { return d.maxit > 0 ? d.maxit : 500; }
+
+// Workspace layout of one subproblem (offsets into the caller's buffer).
+Layout make_layout(const cphifi_ui_desc& d);
+
+}  // namespace cphifi
+
+using namespace cphifi;  // the plan is a global type behind the C ABI
+
+struct cphifi_plan {
+  cphifi_ui_desc d{};
+  cphifi_ui_inputs in{};
+  hipStream_t st = nullptr;
+  int64_t n = 0, r = 0, q = 0, ldk = 0, I = 0, J = 0;
+  int ldp = 16;
+  double gamma = 0.0;
+  int num_cu = 256;
+  Layout L{};
+  char* ws = nullptr;
+  double* vec[NVEC]{};
+  void* part = nullptr;
+  double* tpart = nullptr;
+  ObsTasks tasks{};
+  int32_t* rowm = nullptr;  // [n] multi-task segment index of each row, or -1
+  double* red[3]{};
+  DevScalars* sc = nullptr;
+  DevScalars* sc2 = nullptr;
+  double* hist = nullptr;
+  double *V = nullptr, *UV = nullptr, *dV = nullptr, *D = nullptr, *dKc = nullptr;
+  Elt lp = Elt::F64;
+  void* ulp = nullptr;   // U_K rounded, row-major U (BF16 form only)
+  void* utlp = nullptr;  // U_K rounded, row-major U^T (eigenvector k = row k)
+  __bf16 *xthi = nullptr, *xtlo = nullptr;
+  GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
+  int last_ksplit = 1;  // split-K depth of the partials the last product wrote
+  DevScalars* h_sc = nullptr;  // pinned host mirror
+  bool timing = false;
+  Elt timed_elt = Elt::F64;  // product type whose launches are timed ...
+  bool timed_trans = false;  // ... and orientation (one kernel symbol)
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  bool setup_done = false;
+};

@@ -10,6 +10,7 @@
 // which stays symmetric positive definite when U is rounded to FP32 or BF16,
 // and the preconditioner of eq. (fx) reduces to its r x r middle step.
 #include "cphifi_internal.h"
+#include "plan.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -36,38 +37,7 @@ void clear_error() { g_last_error.clear(); }
 
 using namespace cphifi;
 
-namespace {
-
-constexpr size_t kAlign = 256;
-
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
-enum VecSlot {
-  V_R = 0, V_Z, V_P, V_Q,           // outer / FP64 PCG vectors
-  V_XHAT, V_Y1, V_T2, V_B,          // product intermediates, internal right-hand side
-  V_RF, V_RB, V_XB,                 // refinement residual, its eigenbasis image, correction
-  V_R2, V_Z2, V_P2, V_Q2,           // eigenbasis PCG vectors
-  V_TMP,
-  NVEC
-};
-
-struct Layout {
-  size_t vec[NVEC];
-  size_t part, tpart;
-  size_t tseg, tbeg, tend, tslot, tfirst, mseg, mptr;
-  size_t red[3];
-  size_t sc, sc2, hist;
-  size_t V, UV, dV, D, dKc;
-  size_t ulp, utlp, xthi, xtlo;
-  size_t total;
-  int64_t ldl;
-  int64_t ntask_max, nslot_max, nmulti_max;
-  int hist_len;
-};
-
-int64_t eff_ldk(const cphifi_ui_desc& d) { return d.ldk > 0 ? d.ldk : d.n; }
-int eff_maxit(const cphifi_ui_desc& d) { return d.maxit > 0 ? d.maxit : 500; }
+namespace cphifi {
 
 Layout make_layout(const cphifi_ui_desc& d) {
   Layout L{};
@@ -94,6 +64,7 @@ Layout make_layout(const cphifi_ui_desc& d) {
   L.tfirst = take(sizeof(int32_t) * L.ntask_max);
   L.mseg = take(sizeof(int32_t) * L.nmulti_max);
   L.mptr = take(sizeof(int32_t) * (L.nmulti_max + 1));
+  L.rowm = take(sizeof(int32_t) * n);
   for (int i = 0; i < 3; ++i) L.red[i] = take(sizeof(double) * kMaxVecBlocks);
   L.sc = take(sizeof(DevScalars));
   L.sc2 = take(sizeof(DevScalars));
@@ -117,41 +88,7 @@ Layout make_layout(const cphifi_ui_desc& d) {
   return L;
 }
 
-}  // namespace
-
-struct cphifi_plan {
-  cphifi_ui_desc d{};
-  cphifi_ui_inputs in{};
-  hipStream_t st = nullptr;
-  int64_t n = 0, r = 0, q = 0, ldk = 0, I = 0, J = 0;
-  int ldp = 16;
-  double gamma = 0.0;
-  int num_cu = 256;
-  Layout L{};
-  char* ws = nullptr;
-  double* vec[NVEC]{};
-  void* part = nullptr;
-  double* tpart = nullptr;
-  ObsTasks tasks{};
-  double* red[3]{};
-  DevScalars* sc = nullptr;
-  DevScalars* sc2 = nullptr;
-  double* hist = nullptr;
-  double *V = nullptr, *UV = nullptr, *dV = nullptr, *D = nullptr, *dKc = nullptr;
-  Elt lp = Elt::F64;
-  void* ulp = nullptr;   // U_K rounded, row-major U (BF16 form only)
-  void* utlp = nullptr;  // U_K rounded, row-major U^T (eigenvector k = row k)
-  __bf16 *xthi = nullptr, *xtlo = nullptr;
-  GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
-  int last_ksplit = 1;  // split-K depth of the partials the last product wrote
-  DevScalars* h_sc = nullptr;  // pinned host mirror
-  bool timing = false;
-  Elt timed_elt = Elt::F64;  // product type whose launches are timed ...
-  bool timed_trans = false;  // ... and orientation (one kernel symbol)
-  std::vector<hipEvent_t> ev;
-  size_t ev_used = 0;
-  bool setup_done = false;
-};
+}  // namespace cphifi
 
 namespace {
 
@@ -712,12 +649,13 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
         return CPHIFI_INVALID_ARG;
       }
   }
-  std::vector<int32_t> tseg, tbeg, tend, tslot, tfirst, mseg, mptr;
+  std::vector<int32_t> tseg, tbeg, tend, tslot, tfirst, mseg, mptr, rowm(n, -1);
   int32_t nslot = 0;
   for (int64_t s = 0; s < n; ++s) {
     const int32_t b0 = ptr[s], e0 = ptr[s + 1];
     const int32_t cnt = e0 - b0;
     const int32_t nt = std::max<int32_t>(1, (cnt + kObsChunk - 1) / kObsChunk);
+    if (nt > 1) rowm[s] = (int32_t)mseg.size();
     if (nt == 1) {
       tseg.push_back((int32_t)s);
       tbeg.push_back(b0);
@@ -795,6 +733,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   p->tasks.first = (int32_t*)(ws + L.tfirst);
   p->tasks.mseg = (int32_t*)(ws + L.mseg);
   p->tasks.mptr = (int32_t*)(ws + L.mptr);
+  p->rowm = (int32_t*)(ws + L.rowm);
 
   auto fail = [&](int code) {
     if (p->h_sc) (void)hipHostFree(p->h_sc);
@@ -816,7 +755,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   if ((rc = up(p->tasks.seg, tseg)) || (rc = up(p->tasks.beg, tbeg)) ||
       (rc = up(p->tasks.end, tend)) || (rc = up(p->tasks.slot, tslot)) ||
       (rc = up(p->tasks.first, tfirst)) || (rc = up(p->tasks.mseg, mseg)) ||
-      (rc = up(p->tasks.mptr, mptr)))
+      (rc = up(p->tasks.mptr, mptr)) || (rc = up(p->rowm, rowm)))
     return fail(rc);
 
   const int rr = (int)d->r;
