@@ -218,6 +218,71 @@ CPHIFI_API int cphifi_product(int elt, int trans, int mw, int s, int ksplit, int
                               const double* xscale, double* Y, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------------- batched solver
+ * Many independent UI subproblems (Section 4.4) of uneven n and r solved by
+ * the mixed-precision method of cphifi_ui_solve (precision MIXED_BF16: FP64
+ * iterative refinement of the system of eq. unaligned-infinite-1 around inner
+ * PCG solves in the eigenbasis of K with BF16 eigenvectors and the r x r step
+ * of eq. fx), all members together in ONE persistent kernel launch that is
+ * captured with its reset kernel in a HIP graph.  Members: implicit (A, B)
+ * form, n <= 65536, r <= 48, up to 256 per batch; each member's desc and
+ * inputs follow cphifi_ui_plan_create (tol: FP64 relres target; inner_tol,
+ * maxit, max_refine, FLAG_WARM_START honoured per member).
+ *
+ * Workspace: device, >= cphifi_batch_workspace_bytes(), 256-byte aligned; it
+ * holds every member's plan workspace plus the batch's scalars.  Product tiles
+ * per member come from the autotuner's table at `tile_table` (NULL: the file
+ * named by CPHIFI_TILE_TABLE, else built-in sizes).  create runs the per-member
+ * setup (Section 4.4.2) and synchronizes `stream`.
+ * Errors: INVALID_ARG, UNSUPPORTED (other precision, explicit Zhat, n too
+ * large), HIP_ERROR, and any member's plan-creation error (member named in
+ * cphifi_last_error). */
+typedef struct cphifi_batch cphifi_batch;
+
+CPHIFI_API int cphifi_batch_workspace_bytes(int count, const cphifi_ui_desc* descs,
+                                            size_t* bytes);
+CPHIFI_API int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* descs,
+                                   const cphifi_ui_inputs* inputs, void* workspace,
+                                   size_t workspace_bytes, void* stream,
+                                   const char* tile_table);
+
+/* The plan of member `member` (owned by the batch, valid until destroy): every
+ * cphifi_ui_* call works on it; it shares device buffers with the batched
+ * solve, so do not run both at once. */
+CPHIFI_API int cphifi_batch_plan(cphifi_batch* bt, int member, cphifi_plan** out);
+
+/* Right-hand sides b_i = K_i B_i of all members (cphifi_ui_rhs per member).
+ * y, b: host arrays of `count` device pointers.  async. */
+CPHIFI_API int cphifi_batch_rhs(cphifi_batch* bt, const double* const* y, double* const* b);
+
+/* Bind the right-hand sides b_i (n_i x r_i, device) and solutions W_i (device;
+ * x0 on entry for members with FLAG_WARM_START) that the graph reads and
+ * writes.  b, W: host arrays of `count` device pointers.  stream-ordered. */
+CPHIFI_API int cphifi_batch_bind(cphifi_batch* bt, const double* const* b, double* const* W);
+
+/* Solve all members: binds b / W when given (else the last binding), launches
+ * the graph on the batch's stream.  With infos (host array of `count`) it
+ * waits and fills them (iters = total inner iterations, refine_steps,
+ * relres_true = FP64 ||b - A w|| / ||b||, status); the return value is then
+ * OK, NOT_CONVERGED, NUMERIC or HIP_ERROR (the worst member; HIP_ERROR also
+ * when a bounded grid wait timed out).  With infos NULL it returns after the
+ * launch (async); read the results with cphifi_batch_info. */
+CPHIFI_API int cphifi_batch_solve(cphifi_batch* bt, const double* const* b, double* const* W,
+                                  cphifi_solve_info* infos);
+CPHIFI_API int cphifi_batch_info(cphifi_batch* bt, cphifi_solve_info* infos);
+
+/* The instantiated graph (hipGraphExec_t) of one batched solve: launching it
+ * on any stream solves the bound batch.  Owned by the batch. */
+CPHIFI_API int cphifi_batch_graph(cphifi_batch* bt, void** graph_exec);
+
+/* Rounds run by the last launch (one PCG iteration or one refinement stage of
+ * every active member per round) and the persistent grid size.  sync. */
+CPHIFI_API int cphifi_batch_rounds(cphifi_batch* bt, int* rounds, int* grid);
+
+/* Release the batch's host state and member plans (the workspace belongs to
+ * the caller).  Waits for the batch's stream. */
+CPHIFI_API int cphifi_batch_destroy(cphifi_batch* bt);
+
 /* Human-readable name of a status code (static string). */
 CPHIFI_API const char* cphifi_status_string(int status);
 

@@ -117,6 +117,20 @@ def _load() -> C.CDLL:
         "cphifi_product_tile_ok": (C.c_int, [C.c_int, C.c_int, C.c_int]),
         "cphifi_product": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, P,
                                      C.c_int64, P, C.c_int64, P, P, P, C.c_size_t, P]),
+        "cphifi_batch_workspace_bytes": (C.c_int, [C.c_int, C.POINTER(cphifi_ui_desc),
+                                                   C.POINTER(C.c_size_t)]),
+        "cphifi_batch_create": (C.c_int, [C.POINTER(P), C.c_int, C.POINTER(cphifi_ui_desc),
+                                          C.POINTER(cphifi_ui_inputs), P, C.c_size_t, P,
+                                          C.c_char_p]),
+        "cphifi_batch_plan": (C.c_int, [P, C.c_int, C.POINTER(P)]),
+        "cphifi_batch_rhs": (C.c_int, [P, C.POINTER(P), C.POINTER(P)]),
+        "cphifi_batch_bind": (C.c_int, [P, C.POINTER(P), C.POINTER(P)]),
+        "cphifi_batch_solve": (C.c_int, [P, C.POINTER(P), C.POINTER(P),
+                                         C.POINTER(cphifi_solve_info)]),
+        "cphifi_batch_info": (C.c_int, [P, C.POINTER(cphifi_solve_info)]),
+        "cphifi_batch_graph": (C.c_int, [P, C.POINTER(P)]),
+        "cphifi_batch_rounds": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "cphifi_batch_destroy": (C.c_int, [P]),
         "cphifi_status_string": (C.c_char_p, [C.c_int]),
         "cphifi_last_error": (C.c_char_p, []),
         "cphifi_version": (C.c_char_p, []),
@@ -269,3 +283,86 @@ def cphifi_product(elt: int, trans: int, mw: int, s: int, ksplit: int, n: int, U
                                C.c_void_p(workspace), C.c_size_t(workspace_bytes),
                                C.c_void_p(stream)), "cphifi_product")
 
+
+
+# ------------------------------------------------------------- batched solver
+def _ptr_array(ptrs):
+    arr = (C.c_void_p * len(ptrs))()
+    for i, v in enumerate(ptrs):
+        arr[i] = int(v)
+    return arr
+
+
+def cphifi_batch_workspace_bytes(descs) -> int:
+    arr = (cphifi_ui_desc * len(descs))(*descs)
+    out = C.c_size_t(0)
+    _check(_lib.cphifi_batch_workspace_bytes(len(descs), arr, C.byref(out)),
+           "cphifi_batch_workspace_bytes")
+    return int(out.value)
+
+
+def cphifi_batch_create(descs, inputs, workspace: int, workspace_bytes: int, stream: int,
+                        tile_table: Optional[str] = None) -> int:
+    darr = (cphifi_ui_desc * len(descs))(*descs)
+    iarr = (cphifi_ui_inputs * len(inputs))(*inputs)
+    bt = C.c_void_p(0)
+    _check(_lib.cphifi_batch_create(C.byref(bt), len(descs), darr, iarr, C.c_void_p(workspace),
+                                    C.c_size_t(workspace_bytes), C.c_void_p(stream),
+                                    tile_table.encode() if tile_table else None),
+           "cphifi_batch_create")
+    return int(bt.value)
+
+
+def cphifi_batch_plan(batch: int, member: int) -> int:
+    out = C.c_void_p(0)
+    _check(_lib.cphifi_batch_plan(C.c_void_p(batch), member, C.byref(out)), "cphifi_batch_plan")
+    return int(out.value)
+
+
+def cphifi_batch_rhs(batch: int, y_ptrs, b_ptrs) -> None:
+    _check(_lib.cphifi_batch_rhs(C.c_void_p(batch), _ptr_array(y_ptrs), _ptr_array(b_ptrs)),
+           "cphifi_batch_rhs")
+
+
+def cphifi_batch_bind(batch: int, b_ptrs, W_ptrs) -> None:
+    _check(_lib.cphifi_batch_bind(C.c_void_p(batch), _ptr_array(b_ptrs), _ptr_array(W_ptrs)),
+           "cphifi_batch_bind")
+
+
+def cphifi_batch_solve(batch: int, count: int, b_ptrs=None, W_ptrs=None, wait: bool = True):
+    """Returns (status, [cphifi_solve_info]) when wait, else None (async launch)."""
+    infos = (cphifi_solve_info * count)() if wait else None
+    st = _lib.cphifi_batch_solve(C.c_void_p(batch),
+                                 _ptr_array(b_ptrs) if b_ptrs is not None else None,
+                                 _ptr_array(W_ptrs) if W_ptrs is not None else None, infos)
+    if not wait:
+        _check(st, "cphifi_batch_solve")
+        return None
+    if st not in (OK, NOT_CONVERGED, NUMERIC, BREAKDOWN):
+        raise CphifiError(st, "cphifi_batch_solve", last_error())
+    return st, list(infos)
+
+
+def cphifi_batch_info(batch: int, count: int):
+    infos = (cphifi_solve_info * count)()
+    st = _lib.cphifi_batch_info(C.c_void_p(batch), infos)
+    if st not in (OK, NOT_CONVERGED, NUMERIC, BREAKDOWN):
+        raise CphifiError(st, "cphifi_batch_info", last_error())
+    return st, list(infos)
+
+
+def cphifi_batch_graph(batch: int) -> int:
+    out = C.c_void_p(0)
+    _check(_lib.cphifi_batch_graph(C.c_void_p(batch), C.byref(out)), "cphifi_batch_graph")
+    return int(out.value)
+
+
+def cphifi_batch_rounds(batch: int):
+    rounds, grid = C.c_int(0), C.c_int(0)
+    _check(_lib.cphifi_batch_rounds(C.c_void_p(batch), C.byref(rounds), C.byref(grid)),
+           "cphifi_batch_rounds")
+    return int(rounds.value), int(grid.value)
+
+
+def cphifi_batch_destroy(batch: int) -> None:
+    _check(_lib.cphifi_batch_destroy(C.c_void_p(batch)), "cphifi_batch_destroy")

@@ -1,0 +1,1294 @@
+// Batched mixed-precision solver: many independent unaligned RKHS-mode
+// subproblems (Section 4.4) of uneven n and r, solved together by ONE
+// persistent kernel launch that is captured, with its reset kernel, in a HIP
+// graph.
+//
+// Method per member (the same as cphifi_ui_solve at MIXED_BF16): FP64 iterative
+// refinement on (F^T F + lambda I kron K + rho I) w = b, whose corrections come
+// from inner PCG solves in the eigenbasis of K (x = U_K xbar, the rotation of
+// Section 3.3) with the BF16-rounded eigenvectors, and the r x r middle step of
+// eq. (fx) as preconditioner.  The residual and both rotations use FP64 K and
+// U_K.
+//
+// Execution model.  Each member runs a small state machine (mode):
+//   INIT -> ROT_IN -> INNER ... INNER -> ROT_OUT -> RES -> ROT_IN -> ... -> DONE
+// and the kernel advances every member by one step per *round*.  A round has
+// eight phases; in each phase every active member contributes work items
+// according to its mode:
+//
+//   phase   INNER (one PCG iteration)         RES (FP64 residual)  ROT_IN / ROT_OUT / INIT
+//   A       BF16 U (D_K p)          product   FP64 K w             FP64 U^T rf / U xbar / -
+//   OBS     gather-dot-scatter (eqs. vl, yhat1, both forms)        -
+//   ROWS    split segments + hi/lo BF16 split of Yhat1             -
+//   B       BF16 U^T Yhat1          product   FP64 K Yhat1         -
+//   FIN     q = D_K(Y + lambda p) + rho p     rf = b - A w         rbar = U^T rf / w += U xbar / rf = b
+//   UPD     alpha; x, r update                -                    -
+//   PREC    z = ((r U_V) had D) U_V^T         -                    (ROT_IN) z
+//   CTRL    beta; p update + split; state     relres test; state   state
+//
+// Work items of a phase (product tiles, wave tasks of the gather, row chunks
+// of the vector steps) are handed out by an atomic counter; phases are
+// separated by a bounded grid barrier; reductions write one partial per item
+// and every consumer adds them in a fixed order, so results do not depend on
+// the schedule.  Per-member scalars stay on the device.  Every wait is bounded:
+// a barrier that times out raises an error flag on which every workgroup
+// leaves, so the launch always drains.
+#include "cphifi_internal.h"
+#include "gemm_tiles.h"
+#include "obs_tile.h"
+#include "plan.h"
+
+#include <cmath>
+#include <cstdlib>
+#include <cstddef>
+#include <cstring>
+#include <vector>
+
+using namespace cphifi;
+
+#define TRY_RC(x)                    \
+  do {                               \
+    const int s_ = (x);              \
+    if (s_ != CPHIFI_OK) return s_;  \
+  } while (0)
+
+namespace {
+
+constexpr int kMaxBatch = 256;     // members per batch (one thread each in the round setup)
+constexpr int kRC = 64;            // rows per vector work item
+constexpr int kSlots = 8;          // phases per round
+constexpr int64_t kMaxN = (int64_t)kRC * kMaxVecBlocks;  // partials of a vector phase fit red[]
+// Members have r <= 48 (three 16-column MFMA blocks): the largest tiles then
+// fit the register budget of two workgroups per CU.
+constexpr int kBatchRank = 48;
+constexpr int kSmemBytes = 27648;  // LDS shared by the phases (largest: BF16 tile, NB = 3)
+
+static_assert(tiles::bf16_lds_elems<3, 2>() * 2 <= kSmemBytes, "bf16 tile LDS");
+static_assert(tiles::k4_lds_elems<double, 3, 8>() * 8 <= kSmemBytes, "f64 NN tile LDS");
+static_assert(tiles::k4_lds_elems<double, 3, 4>() * 8 <= kSmemBytes, "f64 T tile LDS");
+static_assert((kBatchRank * kBatchRank + 4 * kWave) * 8 <= kSmemBytes, "preconditioner LDS");
+static_assert(2 * kBatchRank * kRC * 2 <= kSmemBytes, "split transpose LDS");
+
+enum : int32_t { M_INIT = 0, M_RES = 1, M_ROT_IN = 2, M_INNER = 3, M_ROT_OUT = 4, M_DONE = 5 };
+enum : int { S_A = 0, S_OBS = 1, S_ROWS = 2, S_B = 3, S_FIN = 4, S_UPD = 5, S_PREC = 6, S_CTRL = 7 };
+
+// Constants of one member (device copy; never written by the kernel).
+struct BSub {
+  int64_t n, ldk, ldl, I, J;
+  int32_t r, ldp, nb, ocls;  // ocls: lane layout class of the gather (from r)
+  int32_t nrc, ntask, ntask4, nmulti;
+  const double* K;
+  const double* UK;
+  const double* b;
+  double* W;
+  const int32_t* obs_i;
+  const int32_t* obs_j;
+  const double* A;
+  const double* B;
+  const int32_t *tseg, *tbeg, *tend, *tslot, *tfirst, *mptr, *rowm;
+  void* part;
+  double* tpart;
+  const double *UV, *D, *dKc;
+  const __bf16 *ulp, *utlp;
+  __bf16 *xthi, *xtlo;
+  double *X, *R, *Z, *P, *Q, *XH, *Y1, *RF;
+  double *red0, *red1, *red2;
+  int32_t bf_mw, bf_ks, bf_nrb, fn_ks, fn_nrb, fn_vw, ft_mw, ft_ks, ft_nrb, pad0;
+  int64_t bf_kper, fn_kper, ft_kper;
+  double lam, rho, tol, inner_tol2;
+  int32_t maxit, max_refine, warm, pad1;
+};
+
+template <typename P>
+__device__ __forceinline__ P global_word(uint64_t w) {
+  return (P)(__attribute__((address_space(1))) char*)(uintptr_t)w;
+}
+
+// A member's constants, read through the constant address space: the kernel
+// never writes them, and scalar loads keep them out of vector registers.
+__device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
+  static_assert(sizeof(BSub) % 8 == 0, "BSub is copied in 8-byte words");
+  typedef __attribute__((address_space(4))) const uint64_t cword;
+  const cword* src = (const cword*)(sub + b);
+  uint64_t w[sizeof(BSub) / 8];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(BSub) / 8); ++k) w[k] = src[k];
+  BSub s;
+  __builtin_memcpy(&s, w, sizeof(BSub));
+  // Every pointer refers to global memory; rebuilding it as a global-space
+  // pointer lets the compiler use global (not flat) loads and stores.
+  s.K = global_word<decltype(s.K)>(w[offsetof(BSub, K) / 8]);
+  s.UK = global_word<decltype(s.UK)>(w[offsetof(BSub, UK) / 8]);
+  s.b = global_word<decltype(s.b)>(w[offsetof(BSub, b) / 8]);
+  s.W = global_word<decltype(s.W)>(w[offsetof(BSub, W) / 8]);
+  s.obs_i = global_word<decltype(s.obs_i)>(w[offsetof(BSub, obs_i) / 8]);
+  s.obs_j = global_word<decltype(s.obs_j)>(w[offsetof(BSub, obs_j) / 8]);
+  s.A = global_word<decltype(s.A)>(w[offsetof(BSub, A) / 8]);
+  s.B = global_word<decltype(s.B)>(w[offsetof(BSub, B) / 8]);
+  s.tseg = global_word<decltype(s.tseg)>(w[offsetof(BSub, tseg) / 8]);
+  s.tbeg = global_word<decltype(s.tbeg)>(w[offsetof(BSub, tbeg) / 8]);
+  s.tend = global_word<decltype(s.tend)>(w[offsetof(BSub, tend) / 8]);
+  s.tslot = global_word<decltype(s.tslot)>(w[offsetof(BSub, tslot) / 8]);
+  s.tfirst = global_word<decltype(s.tfirst)>(w[offsetof(BSub, tfirst) / 8]);
+  s.mptr = global_word<decltype(s.mptr)>(w[offsetof(BSub, mptr) / 8]);
+  s.rowm = global_word<decltype(s.rowm)>(w[offsetof(BSub, rowm) / 8]);
+  s.part = global_word<decltype(s.part)>(w[offsetof(BSub, part) / 8]);
+  s.tpart = global_word<decltype(s.tpart)>(w[offsetof(BSub, tpart) / 8]);
+  s.UV = global_word<decltype(s.UV)>(w[offsetof(BSub, UV) / 8]);
+  s.D = global_word<decltype(s.D)>(w[offsetof(BSub, D) / 8]);
+  s.dKc = global_word<decltype(s.dKc)>(w[offsetof(BSub, dKc) / 8]);
+  s.ulp = global_word<decltype(s.ulp)>(w[offsetof(BSub, ulp) / 8]);
+  s.utlp = global_word<decltype(s.utlp)>(w[offsetof(BSub, utlp) / 8]);
+  s.xthi = global_word<decltype(s.xthi)>(w[offsetof(BSub, xthi) / 8]);
+  s.xtlo = global_word<decltype(s.xtlo)>(w[offsetof(BSub, xtlo) / 8]);
+  s.X = global_word<decltype(s.X)>(w[offsetof(BSub, X) / 8]);
+  s.R = global_word<decltype(s.R)>(w[offsetof(BSub, R) / 8]);
+  s.Z = global_word<decltype(s.Z)>(w[offsetof(BSub, Z) / 8]);
+  s.P = global_word<decltype(s.P)>(w[offsetof(BSub, P) / 8]);
+  s.Q = global_word<decltype(s.Q)>(w[offsetof(BSub, Q) / 8]);
+  s.XH = global_word<decltype(s.XH)>(w[offsetof(BSub, XH) / 8]);
+  s.Y1 = global_word<decltype(s.Y1)>(w[offsetof(BSub, Y1) / 8]);
+  s.RF = global_word<decltype(s.RF)>(w[offsetof(BSub, RF) / 8]);
+  s.red0 = global_word<decltype(s.red0)>(w[offsetof(BSub, red0) / 8]);
+  s.red1 = global_word<decltype(s.red1)>(w[offsetof(BSub, red1) / 8]);
+  s.red2 = global_word<decltype(s.red2)>(w[offsetof(BSub, red2) / 8]);
+  return s;
+}
+
+// Mutable scalars of one member.
+struct BState {
+  int32_t mode, k, it, total_inner, status, pad;
+  double bb, rel, tol2, rz[2];
+};
+
+// Batch-wide control words.
+struct BCtl {
+  uint32_t bar;    // grid barrier arrivals (monotonic within a launch)
+  uint32_t fc[4];  // work-item counters of the last four phases
+  int32_t err;     // a wait timed out: every workgroup leaves
+  int32_t rounds;  // rounds executed by the last launch
+  int32_t pad;
+};
+
+struct BArgs {
+  const BSub* sub;
+  BState* st;
+  BCtl* ctl;
+  int32_t count;
+  int32_t max_rounds;
+  int64_t spin_limit;
+};
+
+// ------------------------------------------------------------ small helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic sum over the 256 threads; result in every thread.
+__device__ __forceinline__ double block_sum(double v, double* s_red) {
+  v = wave_sum(v);
+  const int wave = item_tid() >> 6, lane = item_tid() & 63;
+  __syncthreads();
+  if (lane == 0) s_red[wave] = v;
+  __syncthreads();
+  if (item_tid() == 0) s_red[4] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+  __syncthreads();
+  return s_red[4];
+}
+
+// Sum of red[0..cnt) in one fixed order (the same in every caller).
+__device__ __forceinline__ double sum_partials(const double* red, int cnt, double* s_red) {
+  double v = 0.0;
+  for (int i = item_tid(); i < cnt; i += blockDim.x) v += red[i];
+  return block_sum(v, s_red);
+}
+
+template <typename PT>
+__device__ __forceinline__ double part_sum(const void* part, int ks, int64_t n, int ldp, int64_t s,
+                                           int c) {
+  const PT* p = (const PT*)part;
+  double v = 0.0;
+  for (int sp = 0; sp < ks; ++sp) v += (double)p[((int64_t)sp * n + s) * ldp + c];
+  return v;
+}
+
+// hi + lo BF16 pair carrying ~16 significant bits of v (as the plain split).
+__device__ __forceinline__ void split_pair(double v, __bf16* hi, __bf16* lo) {
+  const __bf16 hb = (__bf16)(float)v;
+  const float h = (float)hb;
+  const float l = (float)(v - (double)h);
+  *hi = (__bf16)h;
+  *lo = (__bf16)l;
+}
+
+// Writes the transposed split tile th/tl ([c][row], kRC rows) of rows
+// [s0, s0 + rows) into the c-major hi/lo operand of the BF16 product.
+__device__ __forceinline__ void store_split(const BSub& S, int64_t s0, int rows, const __bf16* th,
+                            const __bf16* tl) {
+  __syncthreads();
+  for (int e = item_tid(); e < S.r * kRC; e += blockDim.x) {
+    const int c = e / kRC, sr = e % kRC;
+    if (sr < rows) {
+      const int64_t o = (int64_t)c * S.ldl + s0 + sr;
+      S.xthi[o] = th[c * kRC + sr];
+      S.xtlo[o] = tl[c * kRC + sr];
+    }
+  }
+}
+
+// ------------------------------------------------------------- work counts
+__device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
+  const int fn = S.fn_nrb * S.fn_ks, ft = S.ft_nrb * S.ft_ks, bf = S.bf_nrb * S.bf_ks;
+  switch (mode) {
+    case M_INIT:
+      return slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
+    case M_RES:
+      switch (slot) {
+        case S_A:
+        case S_B: return fn;
+        case S_OBS: return S.ntask4;
+        case S_ROWS: return S.nmulti > 0 ? S.nrc : 0;
+        case S_FIN: return S.nrc;
+        case S_CTRL: return 1;
+        default: return 0;
+      }
+    case M_ROT_IN:
+      switch (slot) {
+        case S_A: return fn;
+        case S_FIN:
+        case S_PREC:
+        case S_CTRL: return S.nrc;
+        default: return 0;
+      }
+    case M_INNER:
+      switch (slot) {
+        case S_A:
+        case S_B: return bf;
+        case S_OBS: return S.ntask4;
+        default: return S.nrc;
+      }
+    case M_ROT_OUT:
+      return slot == S_A ? ft : slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------- products
+enum : int { G_BF_U = 0, G_BF_UT = 1, G_K = 2, G_UKN = 3, G_UKT = 4 };
+
+template <int NB>
+__device__ __forceinline__ void gemm_item_nb(const BSub& S, int kind, const double* X, int64_t i, char* smem) {
+  tiles::GArgs g{};
+  g.n = S.n;
+  g.r = S.r;
+  g.ldp = S.ldp;
+  g.part = S.part;
+  g.X = X;
+  g.ldx = S.r;
+  if (kind == G_BF_U || kind == G_BF_UT) {
+    g.U = kind == G_BF_U ? (const void*)S.ulp : (const void*)S.utlp;
+    g.ldu = S.ldl;
+    g.kper = S.bf_kper;
+    g.xt_hi = S.xthi;
+    g.xt_lo = S.xtlo;
+    g.ldxt = S.ldl;
+    const int64_t bx = i % S.bf_nrb, by = i / S.bf_nrb;
+    if (S.bf_mw == 4)
+      tiles::gemm_bf16_tile<NB, 4, 2>(g, bx, by, (__bf16*)smem);
+    else
+      tiles::gemm_bf16_tile<NB, 2, 2>(g, bx, by, (__bf16*)smem);
+  } else if (kind == G_UKT) {
+    g.U = S.UK;
+    g.ldu = S.ldk;
+    g.kper = S.ft_kper;
+    const int64_t bx = i % S.ft_nrb, by = i / S.ft_nrb;
+    tiles::gemm_k4_tile<double, NB, 2, 4, true, 1>(g, bx, by, (double*)smem);
+  } else {
+    g.U = kind == G_K ? S.K : S.UK;
+    g.ldu = S.ldk;
+    g.kper = S.fn_kper;
+    const int64_t bx = i % S.fn_nrb, by = i / S.fn_nrb;
+    if (S.fn_vw == 2)
+      tiles::gemm_k4_tile<double, NB, 2, 8, false, 2>(g, bx, by, (double*)smem);
+    else
+      tiles::gemm_k4_tile<double, NB, 2, 8, false, 1>(g, bx, by, (double*)smem);
+  }
+}
+
+__device__ __forceinline__ void gemm_item(const BSub& S, int kind, const double* X, int64_t i, char* smem) {
+  switch (S.nb) {
+    case 1: gemm_item_nb<1>(S, kind, X, i, smem); break;
+    case 2: gemm_item_nb<2>(S, kind, X, i, smem); break;
+    default: gemm_item_nb<3>(S, kind, X, i, smem); break;
+  }
+}
+
+// ------------------------------------------------------ gather-dot-scatter
+template <int L, int CPL, typename PT>
+__device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, bool res) {
+  const int64_t task = 4 * i + (item_tid() >> 6);
+  if (task >= S.ntask) return;
+  tiles::TaskView tv{S.tseg, S.tbeg, S.tend, S.tslot, S.tfirst, S.ntask};
+  tiles::ObsDev d{};
+  d.a.n = S.n;
+  d.a.r = S.r;
+  d.a.obs_i = S.obs_i;
+  d.a.obs_j = S.obs_j;
+  d.a.A = S.A;
+  d.a.B = S.B;
+  d.a.Zhat = nullptr;
+  d.a.y = nullptr;
+  d.a.part = S.part;
+  d.a.ksplit = res ? S.fn_ks : S.bf_ks;
+  d.a.ldp = S.ldp;
+  d.a.Xhat = res ? S.XH : nullptr;
+  d.a.out = S.Y1;
+  d.a.tpart = S.tpart;
+  d.a.done = nullptr;
+  d.I = S.I;
+  d.J = S.J;
+  tiles::obs_task<L, CPL, false, 0, PT>(tv, d, task);
+}
+
+template <int L, int CPL>
+__device__ __forceinline__ void obs_item_l(const BSub& S, int64_t i, bool res) {
+  if (res)
+    obs_item_c<L, CPL, double>(S, i, true);
+  else
+    obs_item_c<L, CPL, float>(S, i, false);
+}
+
+__device__ __forceinline__ void obs_item(const BSub& S, int64_t i, bool res) {
+  switch (S.ocls) {
+    case 0: obs_item_l<4, 2>(S, i, res); break;
+    case 1: obs_item_l<4, 3>(S, i, res); break;
+    case 2: obs_item_l<4, 5>(S, i, res); break;
+    case 3: obs_item_l<8, 5>(S, i, res); break;
+    default: obs_item_l<16, 4>(S, i, res); break;
+  }
+}
+
+// Rows of segments split over several gather tasks: Yhat1 = sum of their
+// partial rows (fixed order).  With `split`, also the hi/lo BF16 operand of
+// the U^T Yhat1 product for the chunk's rows.
+__device__ __forceinline__ void rows_item(const BSub& S, int64_t i, bool split, char* smem) {
+  const int64_t s0 = i * kRC;
+  const int rows = (int)min((int64_t)kRC, S.n - s0);
+  const int r = S.r;
+  __bf16* th = (__bf16*)smem;
+  __bf16* tl = th + kBatchRank * kRC;
+  for (int e = item_tid(); e < rows * r; e += blockDim.x) {
+    const int sr = e / r, c = e % r;
+    const int64_t s = s0 + sr;
+    const int32_t m = S.rowm[s];
+    double v;
+    if (m >= 0) {
+      v = 0.0;
+      for (int32_t k = S.mptr[m]; k < S.mptr[m + 1]; ++k) v += S.tpart[(int64_t)k * r + c];
+      if (!split) S.Y1[s * r + c] = v;
+    } else {
+      if (!split) continue;
+      v = S.Y1[s * r + c];
+    }
+    split_pair(v, &th[c * kRC + sr], &tl[c * kRC + sr]);
+  }
+  if (split) store_split(S, s0, rows, th, tl);
+}
+
+// ------------------------------------------------------------ vector steps
+__device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, double* s_red) {
+  const int r = S.r;
+  const int64_t e0 = i * kRC * r, e1 = min(S.n, (i + 1) * kRC) * r;
+  double loc = 0.0;
+  double* red = nullptr;
+  for (int64_t e = e0 + item_tid(); e < e1; e += blockDim.x) {
+    const int64_t s = e / r;
+    const int c = (int)(e % r);
+    switch (mode) {
+      case M_INNER: {
+        const double y = part_sum<float>(S.part, S.bf_ks, S.n, S.ldp, s, c);
+        const double pe = S.P[e];
+        const double v = S.dKc[s] * (y + S.lam * pe) + S.rho * pe;
+        S.Q[e] = v;
+        loc += pe * v;
+        break;
+      }
+      case M_RES: {
+        const double y = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
+        const double q = y + S.lam * S.XH[e] + S.rho * S.W[e];
+        const double v = S.b[e] - q;
+        S.RF[e] = v;
+        loc += v * v;
+        break;
+      }
+      case M_ROT_IN: {
+        const double v = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
+        S.R[e] = v;
+        S.X[e] = 0.0;
+        loc += v * v;
+        break;
+      }
+      case M_ROT_OUT:
+        S.W[e] += part_sum<double>(S.part, S.ft_ks, S.n, S.ldp, s, c);
+        break;
+      default: {  // M_INIT
+        const double v = S.b[e];
+        S.RF[e] = v;
+        if (!S.warm) S.W[e] = 0.0;
+        loc += v * v;
+        break;
+      }
+    }
+  }
+  switch (mode) {
+    case M_INNER: red = S.red0; break;
+    case M_RES:
+    case M_ROT_IN: red = S.red1; break;
+    case M_INIT: red = S.red2; break;
+    default: break;
+  }
+  if (red != nullptr) {
+    const double t = block_sum(loc, s_red);
+    if (item_tid() == 0) red[i] = t;
+  }
+}
+
+// Inner stopping test of iteration `it`, identical in every caller: p^T A p
+// not positive or not finite, ||r||^2 <= tol2, or the iteration cap.
+__device__ __forceinline__ bool inner_stop(const BSub& S, const BState* st, int it, double* s_red, bool* finite) {
+  const double pq = sum_partials(S.red0, S.nrc, s_red);
+  const double rr = sum_partials(S.red1, S.nrc, s_red);
+  *finite = isfinite(pq) && isfinite(rr);
+  return !(pq > 0.0) || !*finite || rr <= st->tol2 || it + 1 >= S.maxit;
+}
+
+__device__ __forceinline__ void upd_item(const BSub& S, const BState* st, int it, int64_t i, double* s_red) {
+  const double pq = sum_partials(S.red0, S.nrc, s_red);
+  const double rz = st->rz[it & 1];
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) return;  // CTRL ends the inner solve
+  const double alpha = rz / pq;
+  const int r = S.r;
+  const int64_t e0 = i * kRC * r, e1 = min(S.n, (i + 1) * kRC) * r;
+  double loc = 0.0;
+  for (int64_t e = e0 + item_tid(); e < e1; e += blockDim.x) {
+    S.X[e] += alpha * S.P[e];
+    const double rv = S.R[e] - alpha * S.Q[e];
+    S.R[e] = rv;
+    loc += rv * rv;
+  }
+  const double t = block_sum(loc, s_red);
+  if (item_tid() == 0) S.red1[i] = t;
+}
+
+// z = ((r U_V) had D) U_V^T for the chunk's rows (eq. fx in the eigenbasis of
+// K), one wave per row; partial r^T z.
+__device__ __forceinline__ void prec_rows(const BSub& S, int64_t i, char* smem, double* s_red) {
+  const int r = S.r;
+  double* uv = (double*)smem;
+  double* buf = uv + kBatchRank * kBatchRank;
+  for (int e = item_tid(); e < r * r; e += blockDim.x) uv[e] = S.UV[e];
+  __syncthreads();
+  const int wave = item_tid() >> 6, c = item_tid() & 63;
+  double* wb = buf + wave * kWave;
+  const int64_t s0 = i * kRC, s1 = min(S.n, s0 + kRC);
+  double loc = 0.0;
+  for (int64_t s = s0 + wave; s < s1; s += 4) {
+    const double t = c < r ? S.R[s * r + c] : 0.0;
+    wb[c] = t;
+    __builtin_amdgcn_wave_barrier();
+    double u = 0.0;
+    if (c < r) {
+      for (int j = 0; j < r; ++j) u += wb[j] * uv[j * r + c];
+      u *= S.D[s * r + c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    wb[c] = u;
+    __builtin_amdgcn_wave_barrier();
+    if (c < r) {
+      double o = 0.0;
+      for (int j = 0; j < r; ++j) o += wb[j] * uv[c * r + j];
+      S.Z[s * r + c] = o;
+      loc += t * o;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  const double tot = block_sum(loc, s_red);
+  if (item_tid() == 0) S.red2[i] = tot;
+}
+
+// p = z + beta p for the chunk's rows and the hi/lo split of D_K p.
+__device__ __forceinline__ void p_rows(const BSub& S, int64_t i, double beta, char* smem) {
+  const int r = S.r;
+  const int64_t s0 = i * kRC;
+  const int rows = (int)min((int64_t)kRC, S.n - s0);
+  __bf16* th = (__bf16*)smem;
+  __bf16* tl = th + kBatchRank * kRC;
+  for (int e = item_tid(); e < rows * r; e += blockDim.x) {
+    const int sr = e / r, c = e % r;
+    const int64_t s = s0 + sr, o = s * r + c;
+    const double pv = S.Z[o] + beta * S.P[o];
+    S.P[o] = pv;
+    split_pair(S.dKc[s] * pv, &th[c * kRC + sr], &tl[c * kRC + sr]);
+  }
+  store_split(S, s0, rows, th, tl);
+}
+
+__device__ __forceinline__ void finish_member(BState* st, int32_t mode, int32_t status) {
+  st->mode = mode;
+  if (mode == M_DONE) st->status = status;
+}
+
+__device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, int it, int64_t i, char* smem,
+                          double* s_red) {
+  const bool lead = i == 0 && item_tid() == 0;
+  switch (mode) {
+    case M_INNER: {
+      bool finite = true;
+      bool stop = inner_stop(S, st, it, s_red, &finite);
+      double rz_new = 0.0;
+      if (!stop) {
+        rz_new = sum_partials(S.red2, S.nrc, s_red);
+        if (!(rz_new > 0.0) || !isfinite(rz_new)) {
+          stop = true;
+          finite = isfinite(rz_new);
+        }
+      }
+      if (stop) {
+        if (lead) {
+          st->total_inner += it + 1;
+          if (finite)
+            finish_member(st, M_ROT_OUT, 0);
+          else
+            finish_member(st, M_DONE, CPHIFI_NUMERIC);
+        }
+        return;
+      }
+      p_rows(S, i, rz_new / st->rz[it & 1], smem);
+      if (lead) {
+        st->rz[(it + 1) & 1] = rz_new;
+        st->it = it + 1;
+      }
+      return;
+    }
+    case M_ROT_IN: {
+      const double bb_in = sum_partials(S.red1, S.nrc, s_red);
+      const double rz0 = sum_partials(S.red2, S.nrc, s_red);
+      const bool ok = bb_in > 0.0 && isfinite(bb_in) && rz0 > 0.0 && isfinite(rz0);
+      if (!ok) {
+        if (lead) {
+          if (isfinite(bb_in) && isfinite(rz0))
+            finish_member(st, M_ROT_OUT, 0);
+          else
+            finish_member(st, M_DONE, CPHIFI_NUMERIC);
+        }
+        return;
+      }
+      p_rows(S, i, 0.0, smem);
+      if (lead) {
+        st->tol2 = S.inner_tol2 * bb_in;
+        st->rz[0] = rz0;
+        st->it = 0;
+        finish_member(st, M_INNER, 0);
+      }
+      return;
+    }
+    case M_RES: {
+      const double rr = sum_partials(S.red1, S.nrc, s_red);
+      if (lead) {
+        const double bb = st->bb;
+        const double rel = bb > 0.0 ? sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+        st->rel = rel;
+        if (!isfinite(rel))
+          finish_member(st, M_DONE, CPHIFI_NUMERIC);
+        else if (rel <= S.tol)
+          finish_member(st, M_DONE, CPHIFI_OK);
+        else if (st->k >= S.max_refine)
+          finish_member(st, M_DONE, CPHIFI_NOT_CONVERGED);
+        else
+          finish_member(st, M_ROT_IN, 0);
+      }
+      return;
+    }
+    case M_ROT_OUT:
+      if (lead) {
+        st->k += 1;
+        finish_member(st, M_RES, 0);
+      }
+      return;
+    default: {  // M_INIT
+      const double bb = sum_partials(S.red2, S.nrc, s_red);
+      if (lead) {
+        st->bb = bb;
+        if (!isfinite(bb)) {
+          finish_member(st, M_DONE, CPHIFI_NUMERIC);
+        } else if (S.warm) {
+          finish_member(st, M_RES, 0);
+        } else if (bb == 0.0) {
+          st->rel = 0.0;  // b = 0: w = 0 is exact
+          finish_member(st, M_DONE, CPHIFI_OK);
+        } else {
+          st->rel = 1.0;
+          finish_member(st, M_ROT_IN, 0);
+        }
+      }
+      return;
+    }
+  }
+}
+
+__device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, int mode, int it, int64_t i,
+                         char* smem, double* s_red) {
+  switch (slot) {
+    case S_A:
+      switch (mode) {
+        case M_INNER: gemm_item(S, G_BF_U, nullptr, i, smem); break;
+        case M_RES: gemm_item(S, G_K, S.W, i, smem); break;
+        case M_ROT_IN: gemm_item(S, G_UKN, S.RF, i, smem); break;
+        case M_ROT_OUT: gemm_item(S, G_UKT, S.X, i, smem); break;
+      }
+      break;
+    case S_OBS: obs_item(S, i, mode == M_RES); break;
+    case S_ROWS: rows_item(S, i, mode == M_INNER, smem); break;
+    case S_B:
+      if (mode == M_INNER)
+        gemm_item(S, G_BF_UT, nullptr, i, smem);
+      else
+        gemm_item(S, G_K, S.Y1, i, smem);
+      break;
+    case S_FIN: fin_item(S, mode, i, s_red); break;
+    case S_UPD: upd_item(S, st, it, i, s_red); break;
+    case S_PREC: {
+      if (mode == M_INNER) {
+        bool finite = true;
+        if (inner_stop(S, st, it, s_red, &finite)) break;
+      }
+      prec_rows(S, i, smem, s_red);
+      break;
+    }
+    default: ctrl_item(S, st, mode, it, i, smem, s_red); break;
+  }
+}
+
+// Bounded grid barrier: returns false when a wait timed out (here or in any
+// other workgroup); the caller then leaves the kernel.
+__device__ __forceinline__ bool grid_sync(BCtl* ctl, uint32_t target, int64_t spin_limit, int* s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();  // release this workgroup's writes device-wide
+    __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int64_t spin = 0;; ++spin) {
+      const uint32_t v = __hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v >= target) break;
+      if ((spin & 63) == 63 &&
+          __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 0;
+        break;
+      }
+      if (spin >= spin_limit) {
+        __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();  // acquire the other workgroups' writes
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel(
+    BArgs a) {
+  __shared__ __attribute__((aligned(16))) char smem[kSmemBytes];
+  __shared__ int s_pref[kSlots][kMaxBatch + 1];
+  __shared__ int s_mode[kMaxBatch];
+  __shared__ int s_it[kMaxBatch];
+  __shared__ int s_wtot[kSlots][4];
+  __shared__ double s_red[8];
+  __shared__ int s_item;
+  __shared__ int s_ok;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int count = a.count;
+  uint32_t nbar = 0;  // barriers passed
+  uint32_t pi = 0;    // phases run
+  int round = 0;
+  for (; round < a.max_rounds; ++round) {
+    if (__hip_atomic_load(&a.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    // Snapshot of the members' modes and the item prefix sums of each phase.
+    int cnt[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) cnt[s] = 0;
+    if (tid < count) {
+      const int m = a.st[tid].mode;
+      s_mode[tid] = m;
+      s_it[tid] = a.st[tid].it;
+      if (m != M_DONE) {
+        const BSub& S = a.sub[tid];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) cnt[s] = item_count(S, m, s);
+      }
+    }
+    int incl[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      int v = cnt[s];
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+      }
+      incl[s] = v;
+      if (lane == 63) s_wtot[s][wave] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      int base = 0;
+      for (int w = 0; w < wave; ++w) base += s_wtot[s][w];
+      if (tid < count) s_pref[s][tid] = base + incl[s] - cnt[s];
+      if (tid == count - 1) s_pref[s][count] = base + incl[s];
+    }
+    __syncthreads();
+    if (s_pref[S_CTRL][count] == 0) break;  // every member is done
+
+    for (int slot = 0; slot < kSlots; ++slot) {
+      const int total = s_pref[slot][count];
+      if (total == 0) continue;
+      if (blockIdx.x == 0 && tid == 0)
+        __hip_atomic_store(&a.ctl->fc[(pi + 2) & 3], 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      int item = blockIdx.x;
+      while (item < total) {
+        // member b: last one whose range starts at or before the item
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pref[slot][mid] <= item)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        // uniform member index
+        const int b = __builtin_amdgcn_readfirstlane(lo);
+        const BSub S = load_sub(a.sub, b);
+        run_item(S, &a.st[b], slot, __builtin_amdgcn_readfirstlane(s_mode[b]),
+                 __builtin_amdgcn_readfirstlane(s_it[b]),
+                 __builtin_amdgcn_readfirstlane(item - s_pref[slot][b]), smem, s_red);
+        __syncthreads();
+        if (tid == 0)
+          s_item = (int)gridDim.x + (int)__hip_atomic_fetch_add(&a.ctl->fc[pi & 3], 1u,
+                                                                 __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        item = s_item;
+      }
+      ++pi;
+      ++nbar;
+      if (!grid_sync(a.ctl, nbar * gridDim.x, a.spin_limit, &s_ok)) return;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) a.ctl->rounds = round;
+}
+
+// Start state of a launch: control words cleared, every member at INIT.
+__global__ void batch_reset_kernel(BArgs a) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl->bar = 0;
+    for (int j = 0; j < 4; ++j) a.ctl->fc[j] = 0;
+    a.ctl->err = 0;
+    a.ctl->rounds = 0;
+  }
+  for (int b = threadIdx.x; b < a.count; b += blockDim.x) {
+    BState s{};
+    s.mode = M_INIT;
+    s.status = CPHIFI_NOT_CONVERGED;
+    a.st[b] = s;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- host
+struct cphifi_batch {
+  int count = 0;
+  hipStream_t st = nullptr;
+  std::vector<cphifi_plan*> plans;
+  BSub* d_sub = nullptr;
+  BState* d_st = nullptr;
+  BCtl* d_ctl = nullptr;
+  BSub* h_sub = nullptr;    // pinned mirrors
+  BState* h_st = nullptr;
+  BCtl* h_ctl = nullptr;
+  int grid = 0;
+  int max_rounds = 0;
+  int64_t spin_limit = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t sub, st, ctl, head;
+  std::vector<size_t> member, member_bytes;
+  size_t total;
+};
+
+int batch_layout(int count, const cphifi_ui_desc* descs, BatchLayout* L) {
+  if (count < 1 || count > kMaxBatch) {
+    set_error("batch count %d outside 1..%d", count, kMaxBatch);
+    return CPHIFI_INVALID_ARG;
+  }
+  if (descs == nullptr) {
+    set_error("descs is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align_up(off, kAlign);
+    const size_t o = off;
+    off += std::max<size_t>(bytes, 1);
+    return o;
+  };
+  L->sub = take(sizeof(BSub) * count);
+  L->st = take(sizeof(BState) * count);
+  L->ctl = take(sizeof(BCtl));
+  L->head = align_up(off, kAlign);
+  L->member.resize(count);
+  L->member_bytes.resize(count);
+  for (int b = 0; b < count; ++b) {
+    size_t bytes = 0;
+    const int rc = cphifi_ui_workspace_bytes(&descs[b], &bytes);
+    if (rc != CPHIFI_OK) return rc;
+    L->member[b] = take(bytes);
+    L->member_bytes[b] = bytes;
+  }
+  L->total = align_up(off, kAlign);
+  return CPHIFI_OK;
+}
+
+// Tile of one product kind for the batch: the tile table (when it covers
+// (n, r)) gives the split-K depth and, for BF16, the rows per wave; else the
+// k-range of an item is about 2048.
+void batch_tile(const char* table, Elt elt, bool trans, int64_t n, int r, int* mw, int* ks,
+                int64_t* kper, int* nrb) {
+  int tmw = 0, ts = 0, tks = 0;
+  const bool hit = gemm_table_lookup(table, elt, trans, n, r, &tmw, &ts, &tks);
+  const int nb = (r + 15) / 16;
+  int64_t bk;
+  if (elt == Elt::BF16) {
+    *mw = (hit && tmw < 4) ? 2 : 4;
+    bk = gemm_bk(Elt::BF16, 2);
+  } else if (trans) {
+    *mw = 2;
+    bk = gemm_bk(Elt::F64, 4);
+  } else {
+    *mw = 2;
+    bk = gemm_bk(Elt::F64, 8);
+  }
+  int64_t want = hit && tks > 0 ? tks : (n + 2047) / 2048;
+  want = std::max<int64_t>(1, std::min<int64_t>(want, kMaxSplit));
+  int64_t kp = (n + want - 1) / want;
+  kp = (kp + bk - 1) / bk * bk;
+  *kper = kp;
+  *ks = (int)((n + kp - 1) / kp);
+  const int64_t rows = tiles::tile_rows(*mw);
+  *nrb = (int)((n + rows - 1) / rows);
+}
+
+int obs_class(int r) {
+  if (r <= 8) return 0;
+  if (r <= 12) return 1;
+  if (r <= 20) return 2;
+  if (r <= 40) return 3;
+  return 4;
+}
+
+void destroy_batch(cphifi_batch* bt) {
+  if (bt == nullptr) return;
+  for (cphifi_plan* p : bt->plans)
+    if (p) (void)cphifi_ui_plan_destroy(p);
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  if (bt->h_sub) (void)hipHostFree(bt->h_sub);
+  if (bt->h_st) (void)hipHostFree(bt->h_st);
+  if (bt->h_ctl) (void)hipHostFree(bt->h_ctl);
+  delete bt;
+}
+
+BArgs make_args(const cphifi_batch* bt) {
+  BArgs a{};
+  a.sub = bt->d_sub;
+  a.st = bt->d_st;
+  a.ctl = bt->d_ctl;
+  a.count = bt->count;
+  a.max_rounds = bt->max_rounds;
+  a.spin_limit = bt->spin_limit;
+  return a;
+}
+
+// The graph of one batched solve: the reset kernel, then the persistent
+// kernel.  It is captured on a private stream (the caller's may be the null
+// stream, which cannot be captured) and launched on the batch's stream.
+int build_graph(cphifi_batch* bt) {
+  if (bt->exec != nullptr) return CPHIFI_OK;
+  const BArgs a = make_args(bt);
+  hipStream_t cs = nullptr;
+  CPHIFI_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, cs, a);
+    hipLaunchKernelGGL(batch_kernel, dim3(bt->grid), dim3(256), 0, cs, a);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess && g == nullptr) e = hipErrorInvalidValue;
+    if (e == hipSuccess) {
+      bt->graph = g;
+      e = hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    bt->exec = nullptr;
+    set_error("graph capture of the batched solve failed: %s", hipGetErrorString(e));
+    return CPHIFI_HIP_ERROR;
+  }
+  return CPHIFI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cphifi_batch_workspace_bytes(int count, const cphifi_ui_desc* descs, size_t* bytes) {
+  clear_error();
+  if (bytes == nullptr) {
+    set_error("bytes is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  BatchLayout L;
+  const int rc = batch_layout(count, descs, &L);
+  if (rc != CPHIFI_OK) return rc;
+  *bytes = L.total;
+  return CPHIFI_OK;
+}
+
+int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* descs,
+                        const cphifi_ui_inputs* inputs, void* workspace, size_t workspace_bytes,
+                        void* stream, const char* tile_table) {
+  clear_error();
+  if (out == nullptr || inputs == nullptr) {
+    set_error("out / inputs is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  *out = nullptr;
+  BatchLayout L;
+  TRY_RC(batch_layout(count, descs, &L));
+  if (workspace == nullptr || workspace_bytes < L.total ||
+      (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) {
+    set_error("workspace must be >= %zu bytes and 256-byte aligned (got %zu)", L.total,
+              workspace_bytes);
+    return CPHIFI_INVALID_ARG;
+  }
+  for (int b = 0; b < count; ++b) {
+    const cphifi_ui_desc& d = descs[b];
+    if (d.precision != CPHIFI_MIXED_BF16) {
+      set_error("member %d: the batched solver runs the MIXED_BF16 form only", b);
+      return CPHIFI_UNSUPPORTED;
+    }
+    if (inputs[b].Zhat != nullptr) {
+      set_error("member %d: the batched solver takes the implicit (A, B) form only", b);
+      return CPHIFI_UNSUPPORTED;
+    }
+    if (d.r > kBatchRank) {
+      set_error("member %d: r = %lld exceeds the batched limit %d", b, (long long)d.r,
+                kBatchRank);
+      return CPHIFI_UNSUPPORTED;
+    }
+    if (d.n > kMaxN) {
+      set_error("member %d: n = %lld exceeds the batched limit %lld", b, (long long)d.n,
+                (long long)kMaxN);
+      return CPHIFI_UNSUPPORTED;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  cphifi_batch* bt = new cphifi_batch();
+  bt->count = count;
+  bt->st = st;
+  bt->plans.assign(count, nullptr);
+  char* ws = (char*)workspace;
+  bt->d_sub = (BSub*)(ws + L.sub);
+  bt->d_st = (BState*)(ws + L.st);
+  bt->d_ctl = (BCtl*)(ws + L.ctl);
+  auto fail = [&](int code) {
+    destroy_batch(bt);
+    return code;
+  };
+  if (hipHostMalloc((void**)&bt->h_sub, sizeof(BSub) * count, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&bt->h_st, sizeof(BState) * count, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&bt->h_ctl, sizeof(BCtl), hipHostMallocDefault) != hipSuccess) {
+    set_error("hipHostMalloc of the batch mirrors failed");
+    return fail(CPHIFI_HIP_ERROR);
+  }
+  std::memset(bt->h_sub, 0, sizeof(BSub) * count);
+  int num_cu = 256;
+  {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cu > 0)
+      num_cu = cu;
+  }
+  int max_rounds = 0;
+  for (int b = 0; b < count; ++b) {
+    const cphifi_ui_desc& d = descs[b];
+    const cphifi_ui_inputs& in = inputs[b];
+    int rc = cphifi_ui_plan_create(&bt->plans[b], &d, &in, ws + L.member[b], L.member_bytes[b],
+                                   stream);
+    if (rc == CPHIFI_OK) rc = cphifi_ui_setup(bt->plans[b]);
+    if (rc != CPHIFI_OK) {
+      const std::string msg = cphifi_last_error();
+      destroy_batch(bt);
+      set_error("member %d: %s", b, msg.c_str());
+      return rc;
+    }
+    cphifi_plan* p = bt->plans[b];
+    // zero padding rows / columns of the BF16 split operand once
+    const size_t xt_bytes = sizeof(__bf16) * (size_t)p->ldp * p->L.ldl;
+    if (hipMemsetAsync(p->xthi, 0, xt_bytes, st) != hipSuccess ||
+        hipMemsetAsync(p->xtlo, 0, xt_bytes, st) != hipSuccess) {
+      set_error("clearing the split operand failed");
+      return fail(CPHIFI_HIP_ERROR);
+    }
+    BSub& S = bt->h_sub[b];
+    S.n = p->n;
+    S.ldk = p->ldk;
+    S.ldl = p->L.ldl;
+    S.I = p->I;
+    S.J = p->J;
+    S.r = (int32_t)p->r;
+    S.ldp = p->ldp;
+    S.nb = (int32_t)((p->r + 15) / 16);
+    S.ocls = obs_class((int)p->r);
+    S.nrc = (int32_t)((p->n + kRC - 1) / kRC);
+    S.ntask = p->tasks.ntask;
+    S.ntask4 = (p->tasks.ntask + 3) / 4;
+    S.nmulti = p->tasks.nmulti;
+    S.K = in.K;
+    S.UK = in.UK;
+    S.obs_i = in.obs_i;
+    S.obs_j = in.obs_j;
+    S.A = in.A;
+    S.B = in.B;
+    S.tseg = p->tasks.seg;
+    S.tbeg = p->tasks.beg;
+    S.tend = p->tasks.end;
+    S.tslot = p->tasks.slot;
+    S.tfirst = p->tasks.first;
+    S.mptr = p->tasks.mptr;
+    S.rowm = p->rowm;
+    S.part = p->part;
+    S.tpart = p->tpart;
+    S.UV = p->UV;
+    S.D = p->D;
+    S.dKc = p->dKc;
+    S.ulp = (const __bf16*)p->ulp;
+    S.utlp = (const __bf16*)p->utlp;
+    S.xthi = p->xthi;
+    S.xtlo = p->xtlo;
+    S.X = p->vec[V_XB];
+    S.R = p->vec[V_R2];
+    S.Z = p->vec[V_Z2];
+    S.P = p->vec[V_P2];
+    S.Q = p->vec[V_Q2];
+    S.XH = p->vec[V_XHAT];
+    S.Y1 = p->vec[V_Y1];
+    S.RF = p->vec[V_RF];
+    S.red0 = p->red[0];
+    S.red1 = p->red[1];
+    S.red2 = p->red[2];
+    int mw = 0;
+    batch_tile(tile_table, Elt::BF16, false, p->n, (int)p->r, &S.bf_mw, &S.bf_ks, &S.bf_kper,
+               &S.bf_nrb);
+    batch_tile(tile_table, Elt::F64, false, p->n, (int)p->r, &mw, &S.fn_ks, &S.fn_kper,
+               &S.fn_nrb);
+    batch_tile(tile_table, Elt::F64, true, p->n, (int)p->r, &S.ft_mw, &S.ft_ks, &S.ft_kper,
+               &S.ft_nrb);
+    const bool aligned = (reinterpret_cast<uintptr_t>(in.K) % 16) == 0 &&
+                         (reinterpret_cast<uintptr_t>(in.UK) % 16) == 0;
+    S.fn_vw = (p->ldk % 2 == 0 && aligned) ? 2 : 1;
+    S.lam = d.lambda;
+    S.rho = d.rho;
+    S.tol = d.tol;
+    const double itol = d.inner_tol > 0.0 ? d.inner_tol : 1e-3;
+    S.inner_tol2 = itol * itol;
+    S.maxit = eff_maxit(d);
+    S.max_refine = d.max_refine > 0 ? d.max_refine : 30;
+    S.warm = (d.flags & CPHIFI_FLAG_WARM_START) ? 1 : 0;
+    max_rounds = std::max(max_rounds, (S.max_refine + 1) * (S.maxit + 3) + 8);
+  }
+  bt->max_rounds = max_rounds;
+  {
+    const char* e = std::getenv("CPHIFI_BATCH_SPIN_LIMIT");
+    bt->spin_limit = (e != nullptr && std::atoll(e) > 0) ? std::atoll(e) : (1LL << 23);
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel, 256, 0) !=
+          hipSuccess ||
+      per_cu < 1) {
+    set_error("occupancy query of the batched kernel failed");
+    return fail(CPHIFI_HIP_ERROR);
+  }
+  bt->grid = num_cu * per_cu;
+  {
+    const char* e = std::getenv("CPHIFI_BATCH_GRID");
+    if (e != nullptr && std::atoi(e) > 0) bt->grid = std::min(bt->grid, std::atoi(e));
+  }
+  if (hipMemcpyAsync(bt->d_sub, bt->h_sub, sizeof(BSub) * count, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    set_error("uploading the batch description failed");
+    return fail(CPHIFI_HIP_ERROR);
+  }
+  *out = bt;
+  return CPHIFI_OK;
+}
+
+int cphifi_batch_plan(cphifi_batch* bt, int member, cphifi_plan** out) {
+  clear_error();
+  if (bt == nullptr || out == nullptr || member < 0 || member >= bt->count) {
+    set_error("bad batch, member or out");
+    return CPHIFI_INVALID_ARG;
+  }
+  *out = bt->plans[member];
+  return CPHIFI_OK;
+}
+
+int cphifi_batch_rhs(cphifi_batch* bt, const double* const* y, double* const* b) {
+  clear_error();
+  if (bt == nullptr || y == nullptr || b == nullptr) {
+    set_error("bad batch, y or b");
+    return CPHIFI_INVALID_ARG;
+  }
+  for (int i = 0; i < bt->count; ++i) {
+    const int rc = cphifi_ui_rhs(bt->plans[i], y[i], b[i]);
+    if (rc != CPHIFI_OK) return rc;
+  }
+  return CPHIFI_OK;
+}
+
+int cphifi_batch_bind(cphifi_batch* bt, const double* const* b, double* const* W) {
+  clear_error();
+  if (bt == nullptr || b == nullptr || W == nullptr) {
+    set_error("bad batch, b or W");
+    return CPHIFI_INVALID_ARG;
+  }
+  for (int i = 0; i < bt->count; ++i)
+    if (b[i] == nullptr || W[i] == nullptr) {
+      set_error("member %d: b / W is NULL", i);
+      return CPHIFI_INVALID_ARG;
+    }
+  CPHIFI_HIP(hipStreamSynchronize(bt->st));  // the mirror may still be in flight
+  for (int i = 0; i < bt->count; ++i) {
+    bt->h_sub[i].b = b[i];
+    bt->h_sub[i].W = W[i];
+  }
+  CPHIFI_HIP(hipMemcpyAsync(bt->d_sub, bt->h_sub, sizeof(BSub) * bt->count,
+                            hipMemcpyHostToDevice, bt->st));
+  return CPHIFI_OK;
+}
+
+int cphifi_batch_graph(cphifi_batch* bt, void** graph_exec) {
+  clear_error();
+  if (bt == nullptr || graph_exec == nullptr) {
+    set_error("bad batch or graph_exec");
+    return CPHIFI_INVALID_ARG;
+  }
+  TRY_RC(build_graph(bt));
+  *graph_exec = (void*)bt->exec;
+  return CPHIFI_OK;
+}
+
+int cphifi_batch_info(cphifi_batch* bt, cphifi_solve_info* infos) {
+  clear_error();
+  if (bt == nullptr || infos == nullptr) {
+    set_error("bad batch or infos");
+    return CPHIFI_INVALID_ARG;
+  }
+  CPHIFI_HIP(hipMemcpyAsync(bt->h_st, bt->d_st, sizeof(BState) * bt->count,
+                            hipMemcpyDeviceToHost, bt->st));
+  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, sizeof(BCtl), hipMemcpyDeviceToHost, bt->st));
+  CPHIFI_HIP(hipStreamSynchronize(bt->st));
+  const bool timed_out = bt->h_ctl->err != 0;
+  int worst = CPHIFI_OK;
+  for (int i = 0; i < bt->count; ++i) {
+    const BState& s = bt->h_st[i];
+    cphifi_solve_info& f = infos[i];
+    f.iters = s.total_inner;
+    f.refine_steps = s.k;
+    f.relres_true = s.rel;
+    f.relres_recursive = s.rel;
+    f.gemm_ms = 0.0;
+    f.gemm_launches = 0;
+    int status = s.mode == M_DONE ? s.status : CPHIFI_NOT_CONVERGED;
+    if (timed_out) status = CPHIFI_HIP_ERROR;
+    f.status = status;
+    if (status == CPHIFI_HIP_ERROR)
+      worst = CPHIFI_HIP_ERROR;
+    else if (status == CPHIFI_NUMERIC && worst != CPHIFI_HIP_ERROR)
+      worst = CPHIFI_NUMERIC;
+    else if (status != CPHIFI_OK && worst == CPHIFI_OK)
+      worst = status;
+  }
+  if (timed_out) set_error("a grid barrier of the batched kernel timed out");
+  return worst;
+}
+
+int cphifi_batch_solve(cphifi_batch* bt, const double* const* b, double* const* W,
+                       cphifi_solve_info* infos) {
+  clear_error();
+  if (bt == nullptr) {
+    set_error("batch is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  if (b != nullptr || W != nullptr) TRY_RC(cphifi_batch_bind(bt, b, W));
+  for (int i = 0; i < bt->count; ++i)
+    if (bt->h_sub[i].b == nullptr || bt->h_sub[i].W == nullptr) {
+      set_error("member %d has no bound b / W", i);
+      return CPHIFI_INVALID_ARG;
+    }
+  TRY_RC(build_graph(bt));
+  CPHIFI_HIP(hipGraphLaunch(bt->exec, bt->st));
+  if (infos == nullptr) return CPHIFI_OK;
+  return cphifi_batch_info(bt, infos);
+}
+
+int cphifi_batch_rounds(cphifi_batch* bt, int* rounds, int* grid) {
+  clear_error();
+  if (bt == nullptr || rounds == nullptr || grid == nullptr) {
+    set_error("bad arguments");
+    return CPHIFI_INVALID_ARG;
+  }
+  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, sizeof(BCtl), hipMemcpyDeviceToHost, bt->st));
+  CPHIFI_HIP(hipStreamSynchronize(bt->st));
+  *rounds = bt->h_ctl->rounds;
+  *grid = bt->grid;
+  return CPHIFI_OK;
+}
+
+int cphifi_batch_destroy(cphifi_batch* bt) {
+  clear_error();
+  if (bt == nullptr) return CPHIFI_OK;
+  (void)hipStreamSynchronize(bt->st);
+  destroy_batch(bt);
+  return CPHIFI_OK;
+}
+
+}  // extern "C"

@@ -46,6 +46,16 @@ constexpr int kMaxSplit = 16;        // upper bound on split-K of the n x n prod
 constexpr int kObsChunk = 1024;      // max observations per gather-scatter task
 constexpr int kLowpAlign = 256;      // row stride alignment (elements) of the low-precision copies
 
+// Thread index behind an opaque register move.  The tiles also run as work
+// items inside the loop of a persistent kernel; there the compiler would hoist
+// every index computation derived from threadIdx.x out of the item loop and
+// keep all of them live across every item kind, costing occupancy.
+__device__ __forceinline__ int item_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
 // Scalars of one PCG run, resident in device memory so the whole iteration is
 // enqueued without host round trips.  rz is double-buffered by iteration
 // parity: iteration `it` reads rz[it & 1] and writes rz[(it + 1) & 1].
@@ -84,6 +94,10 @@ GemmPlan make_gemm_plan(Elt elt, bool trans, int64_t n, int r, int mw, int s, in
 int gemm_occupancy(Elt elt, bool trans, int mw, int s, int r);  // workgroups per CU
 bool gemm_cfg_valid(Elt elt, int mw, int s);
 int gemm_bk(Elt elt, int s);  // k-chunk of the kernel (kper is a multiple of it)
+// First rule of the tile table at `path` (NULL: the file named by
+// CPHIFI_TILE_TABLE) covering (elt, trans, n, r).
+bool gemm_table_lookup(const char* path, Elt elt, bool trans, int64_t n, int r, int* mw, int* s,
+                       int* ks);
 int launch_gemm(Elt elt, bool trans, const GemmPlan& gp, const void* U, int64_t ldu,
                 int64_t n, const double* X, int64_t ldx, int r, const double* xscale,
                 void* part, const int32_t* done, hipStream_t st);

@@ -6,6 +6,7 @@
 #include "gemm_tiles.h"
 
 #include <cstdlib>
+#include <map>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -222,38 +223,52 @@ struct TileRule {
   int mw, s, ksplit;
 };
 
-// Tile table written by the autotuner (paper_2603_25691_amd/tune.py), read
-// once per process from the file named by CPHIFI_TILE_TABLE.
-const std::vector<TileRule>& tile_table() {
-  static std::once_flag once;
-  static std::vector<TileRule> rules;
-  std::call_once(once, [] {
-    const char* path = std::getenv("CPHIFI_TILE_TABLE");
-    if (path == nullptr) return;
-    FILE* f = std::fopen(path, "r");
-    if (f == nullptr) return;
-    char line[256];
-    while (std::fgets(line, sizeof(line), f)) {
-      if (line[0] == '#') continue;
-      char tag[16];
-      TileRule t{};
-      long long nlo = 0, nhi = 0;
-      if (std::sscanf(line, "%15s %d %d %d %lld %lld %d %d %d", tag, &t.trans, &t.r_lo, &t.r_hi,
-                      &nlo, &nhi, &t.mw, &t.s, &t.ksplit) != 9)
-        continue;
-      const std::string e(tag);
-      t.elt = e == "f64" ? 0 : e == "f32" ? 1 : e == "bf16" ? 2 : -1;
-      t.n_lo = nlo;
-      t.n_hi = nhi;
-      if (t.elt >= 0 && gemm_cfg_valid((Elt)t.elt, t.mw, t.s)) rules.push_back(t);
-    }
-    std::fclose(f);
-  });
+// Tile tables written by the autotuner (paper_2603_25691_amd/tune.py): each
+// file is parsed once per process; the default table is the file named by
+// CPHIFI_TILE_TABLE.
+std::vector<TileRule> read_table(const char* path) {
+  std::vector<TileRule> rules;
+  FILE* f = path != nullptr ? std::fopen(path, "r") : nullptr;
+  if (f == nullptr) return rules;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    char tag[16];
+    TileRule t{};
+    long long nlo = 0, nhi = 0;
+    if (std::sscanf(line, "%15s %d %d %d %lld %lld %d %d %d", tag, &t.trans, &t.r_lo, &t.r_hi,
+                    &nlo, &nhi, &t.mw, &t.s, &t.ksplit) != 9)
+      continue;
+    const std::string e(tag);
+    t.elt = e == "f64" ? 0 : e == "f32" ? 1 : e == "bf16" ? 2 : -1;
+    t.n_lo = nlo;
+    t.n_hi = nhi;
+    if (t.elt >= 0 && gemm_cfg_valid((Elt)t.elt, t.mw, t.s)) rules.push_back(t);
+  }
+  std::fclose(f);
   return rules;
 }
 
+const std::vector<TileRule>& tile_table(const char* path) {
+  static std::mutex mu;
+  static std::map<std::string, std::vector<TileRule>> cache;
+  const char* p = path != nullptr ? path : std::getenv("CPHIFI_TILE_TABLE");
+  const std::string key = p != nullptr ? p : "";
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it == cache.end()) it = cache.emplace(key, read_table(p)).first;
+  return it->second;
+}
+
 bool table_tile(Elt elt, bool trans, int64_t n, int r, int* mw, int* s, int* ks) {
-  for (const TileRule& t : tile_table())
+  return gemm_table_lookup(nullptr, elt, trans, n, r, mw, s, ks);
+}
+
+}  // namespace
+
+bool gemm_table_lookup(const char* path, Elt elt, bool trans, int64_t n, int r, int* mw, int* s,
+                       int* ks) {
+  for (const TileRule& t : tile_table(path))
     if (t.elt == (int)elt && t.trans == (int)trans && r >= t.r_lo && r <= t.r_hi &&
         n >= t.n_lo && n <= t.n_hi) {
       *mw = t.mw;
@@ -263,8 +278,6 @@ bool table_tile(Elt elt, bool trans, int64_t n, int r, int* mw, int* s, int* ks)
     }
   return false;
 }
-
-}  // namespace
 
 // Tile for a product: the autotuner's table when one is loaded and covers
 // (n, r), else defaults measured at n = 30658, r = 40 on MI355X.

@@ -94,7 +94,7 @@ __device__ __forceinline__ void gemm_k4_tile(const GArgs& g, int64_t bx, int64_t
   constexpr int XB = BK * LDX;      // LDS elements per buffer
   constexpr int XPT = (XE + 255) / 256;
 
-  const int tid = threadIdx.x;
+  const int tid = item_tid();
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, kk = lane >> 4;
   const int64_t n = g.n;
@@ -258,7 +258,7 @@ __device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64
   constexpr int XP = NC * LDK;          // LDS elements per part
   constexpr int XB = 2 * XP;            // LDS elements per buffer (hi, lo)
 
-  const int tid = threadIdx.x;
+  const int tid = item_tid();
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, kk = lane >> 4;
   const int64_t n = g.n;

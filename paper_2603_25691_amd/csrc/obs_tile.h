@@ -67,7 +67,7 @@ template <int L, int CPL, bool EXPL, int MODE, typename PT>
 __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int64_t task) {
   constexpr int ROWS = 64 / L;  // observations per group
   const ObsArgs& a = d.a;
-  const int lane = threadIdx.x & 63;
+  const int lane = item_tid() & 63;
   const int r = a.r;
   const int g = lane / L, cl = lane % L;
   const int64_t s = t.seg[task];

@@ -153,6 +153,84 @@ class UISolver:
             pass
 
 
+class BatchSolver:
+    """Many subproblems solved by one persistent, graph-captured launch
+    (cphifi_batch_*).  probs: DeviceProblems in the implicit (A, B) form;
+    per-member parameters are given as scalars or lists."""
+
+    def __init__(self, probs, lam, rho, tol, inner_tol: float = 0.0, maxit: int = 0,
+                 max_refine: int = 0, flags: int = 0, tile_table: Optional[str] = None):
+        self.probs = list(probs)
+        m = len(self.probs)
+
+        def per(v):
+            return list(v) if isinstance(v, (list, tuple)) else [v] * m
+        lam, rho, tol, inner_tol = per(lam), per(rho), per(tol), per(inner_tol)
+        maxit, max_refine, flags = per(maxit), per(max_refine), per(flags)
+        self.descs, self.inputs = [], []
+        for k, pr in enumerate(self.probs):
+            n, r, q = pr.n, pr.r, pr.q
+            _need(pr.K, torch.float64, (n, n), "K")
+            _need(pr.UK, torch.float64, (n, n), "UK")
+            _need(pr.dK, torch.float64, (n,), "dK")
+            _need(pr.obs_ptr, torch.int32, (n + 1,), "obs_ptr")
+            _need(pr.A, torch.float64, (pr.I, r), "A")
+            _need(pr.B, torch.float64, (pr.J, r), "B")
+            _need(pr.obs_i, torch.int32, (q,), "obs_i")
+            _need(pr.obs_j, torch.int32, (q,), "obs_j")
+            self.descs.append(_c.make_desc(n, r, q, pr.I, pr.J, lam[k], rho[k], 0.0, tol[k],
+                                           _c.MIXED_BF16, flags[k], maxit[k], max_refine[k],
+                                           inner_tol[k]))
+            self.inputs.append(_c.make_inputs(K=_ptr(pr.K), UK=_ptr(pr.UK), dK=_ptr(pr.dK),
+                                              obs_ptr=_ptr(pr.obs_ptr), obs_i=_ptr(pr.obs_i),
+                                              obs_j=_ptr(pr.obs_j), A=_ptr(pr.A),
+                                              B=_ptr(pr.B)))
+        self.ws_bytes = _c.cphifi_batch_workspace_bytes(self.descs)
+        dev = self.probs[0].K.device
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self._ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.batch = _c.cphifi_batch_create(self.descs, self.inputs, self._ws, self.ws_bytes,
+                                            _stream(), tile_table)
+
+    def plan(self, k: int) -> int:
+        return _c.cphifi_batch_plan(self.batch, k)
+
+    def rhs(self):
+        bs = [torch.empty(p.n, p.r, dtype=torch.float64, device=p.K.device) for p in self.probs]
+        _c.cphifi_batch_rhs(self.batch, [p.y.data_ptr() for p in self.probs],
+                            [b.data_ptr() for b in bs])
+        return bs
+
+    def bind(self, bs, Ws):
+        _c.cphifi_batch_bind(self.batch, [b.data_ptr() for b in bs], [W.data_ptr() for W in Ws])
+
+    def solve(self, bs=None, Ws=None, wait: bool = True):
+        """Returns (status, infos) when wait, else None."""
+        return _c.cphifi_batch_solve(self.batch, len(self.probs),
+                                     None if bs is None else [b.data_ptr() for b in bs],
+                                     None if Ws is None else [W.data_ptr() for W in Ws], wait)
+
+    def info(self):
+        return _c.cphifi_batch_info(self.batch, len(self.probs))
+
+    def graph(self) -> int:
+        return _c.cphifi_batch_graph(self.batch)
+
+    def rounds(self):
+        return _c.cphifi_batch_rounds(self.batch)
+
+    def close(self):
+        if getattr(self, "batch", 0):
+            _c.cphifi_batch_destroy(self.batch)
+            self.batch = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def upload(p, device="cuda", explicit=None, eig=None) -> DeviceProblem:
     """Copy a synth.Problem's arrays to the device (host-to-device copies only).
 

@@ -84,3 +84,49 @@ def test_oracle_and_library_share_no_code():
         txt = f.read_text()
         assert "import paper_2603_25691_amd" not in txt, f
         assert "from paper_2603_25691_amd" not in txt, f
+
+
+def _bf16_desc(n=600, r=10, **kw):
+    return c.make_desc(n, r, n * 20, 20, 20, lam=1e-4, tol=1e-8, precision=c.MIXED_BF16, **kw)
+
+
+def test_batch_workspace_is_members_plus_scalars():
+    descs = [_bf16_desc(600, 10), _bf16_desc(1500, 40), _bf16_desc(77, 3)]
+    total = c.cphifi_batch_workspace_bytes(descs)
+    members = sum(c.cphifi_ui_workspace_bytes(d) for d in descs)
+    assert members < total < members + 64 * 1024
+
+
+@pytest.mark.parametrize("case,status", [
+    ("rank49", c.UNSUPPORTED), ("fp64", c.UNSUPPORTED), ("fp32", c.UNSUPPORTED),
+    ("explicit", c.UNSUPPORTED), ("n_too_large", c.UNSUPPORTED),
+])
+def test_batch_create_rejects_unsupported_members_without_gpu(case, status):
+    d = _bf16_desc()
+    good = c.make_inputs(K=256, UK=256, dK=256, obs_ptr=256, obs_i=256, obs_j=256, A=256, B=256)
+    inp = good
+    if case == "rank49":
+        d.r = 49
+    elif case == "fp64":
+        d.precision = c.FP64
+    elif case == "fp32":
+        d.precision = c.MIXED_FP32
+    elif case == "explicit":
+        inp = c.make_inputs(K=256, UK=256, dK=256, obs_ptr=256, Zhat=256, V=256)
+        d.gamma = 1.0
+    elif case == "n_too_large":
+        d.n, d.q = 70000, 70000
+    descs = [_bf16_desc(), d]
+    inputs = [good, inp]
+    nbytes = c.cphifi_batch_workspace_bytes(descs)
+    with pytest.raises(c.CphifiError) as ei:  # fails validation before any device call
+        c.cphifi_batch_create(descs, inputs, 1 << 20, nbytes, 0)
+    assert ei.value.status == status
+    assert "member 1" in c.last_error()
+
+
+@pytest.mark.parametrize("count", [0, 257])
+def test_batch_count_is_bounded(count):
+    with pytest.raises(c.CphifiError) as ei:
+        c.cphifi_batch_workspace_bytes([_bf16_desc()] * count)
+    assert ei.value.status == c.INVALID_ARG
