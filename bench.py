@@ -9,8 +9,14 @@ residual certificate) with every input already resident in HBM.
 
 The headline form is the mixed-precision solver (BF16 MFMA inner solves in the
 eigenbasis of K, FP64 refinement to relative residual 1e-7, i.e. K W within
-1e-6); the plain FP64 PCG of the paper is timed beside it.  One JSON line goes
-to stdout.
+1e-6); the plain FP64 PCG of the paper is timed beside it.
+
+The "batched" field measures the batched form: 64 independent subproblems of
+uneven size (n_b ~ U{500..8000}, r_b in {5, 10, 20, 40}, Gaussian kernels of
+bandwidth ~U[0.05, 0.2), J_b = 20, lambda = 1e-4) solved by one persistent,
+graph-captured launch in mixed precision, against the FP64 PCG solving the
+same members one after another.  Both start from right-hand sides already in
+HBM.  One JSON line goes to stdout.
 """
 
 from __future__ import annotations
@@ -47,7 +53,112 @@ def parse():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--batch-count", type=int, default=64,
+                    help="members of the batched workload (0: skip it)")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="measure only the batched workload (prints its JSON object)")
     return ap.parse_args()
+
+
+def bench_batch(a, torch, C):
+    """The batched workload: one persistent graph launch for all members
+    (mixed BF16) against the FP64 PCG over the members in turn."""
+    from paper_2603_25691_amd.torch_api import BatchSolver, UISolver, upload
+    from synth import batch_members
+
+    t0 = time.time()
+    probs, dps = [], []
+    for bm in batch_members(seed=0, count=a.batch_count):
+        p = bm.problem
+        dps.append(upload(p, ldk_align=8))
+        # keep only what the accuracy check needs on the host
+        probs.append(p)
+    torch.cuda.synchronize()
+    ns = np.array([p.n for p in probs])
+    rs = np.array([p.r for p in probs])
+    log(f"batch: {len(probs)} members, n {ns.min()}..{ns.max()} (sum n^2 = {np.sum(ns**2.0):.3e}),"
+        f" r {sorted(set(rs.tolist()))}; generated, uploaded, eig(K) in {time.time() - t0:.1f} s")
+    tol = 1e-7
+    t0 = time.time()
+    bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], tol)
+    rhs = bs.rhs()
+    Ws = [torch.empty_like(b) for b in rhs]
+    bs.bind(rhs, Ws)
+    status, infos = bs.solve()
+    torch.cuda.synchronize()
+    log(f"batch: created + first solve in {time.time() - t0:.1f} s, status {status}")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(a.batch_steps):
+        bs.solve(wait=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_batch = ev0.elapsed_time(ev1) / a.batch_steps
+    status, infos = bs.info()
+    rounds, grid = bs.rounds()
+    phase = bs.phase_ms()
+    log("batch phases (ms, last launch): " + ", ".join(f"{k} {v:.2f}" for k, v in phase.items()))
+    log(f"batch mixed: {ms_batch:.2f} ms per batch ({len(probs) * 1e3 / ms_batch:.1f} "
+        f"subproblem solves/s), {rounds} rounds, grid {grid}, status {C.status_string(status)}")
+
+    # FP64 PCG (paper form), members one after another
+    tol64 = 1e-8
+    solvers = [UISolver(dp, p.lam, p.rho, tol64, precision="fp64") for p, dp in zip(probs, dps)]
+    for s_ in solvers:
+        s_.setup()
+    W64 = [torch.empty_like(b) for b in rhs]
+    for s_, b, W in zip(solvers, rhs, W64):  # warm-up
+        s_.solve(b, W)
+    torch.cuda.synchronize()
+    ev0.record()
+    it64 = []
+    for s_, b, W in zip(solvers, rhs, W64):
+        _, info = s_.solve(b, W)
+        it64.append(info.iters)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms64 = ev0.elapsed_time(ev1)
+    log(f"batch fp64 (members in turn): {ms64:.1f} ms ({len(probs) * 1e3 / ms64:.1f} solves/s)")
+
+    # accuracy: every member's mixed result against its FP64 result
+    ekw = []
+    for p, W, Wd in zip(probs, Ws, W64):
+        Wh, Wdh = W.cpu().numpy(), Wd.cpu().numpy()
+        KW = p.K @ Wdh
+        ekw.append(float(np.linalg.norm(p.K @ Wh - KW) / np.linalg.norm(KW)))
+    # algorithmic bytes of the n x n passes of one batched solve: per inner
+    # iteration 2 BF16 passes; per refinement step 2 FP64 passes of K (the
+    # residual) and 2 of U_K (rotations in and out); plus the final residual.
+    byts = 0.0
+    for p, inf in zip(probs, infos):
+        n2 = float(p.n) ** 2
+        byts += inf.iters * 2 * 2 * n2 + inf.refine_steps * 4 * 8 * n2 + 2 * 8 * n2
+    gbps = byts / (ms_batch * 1e6)
+    for s_ in solvers:
+        s_.close()
+    out = {
+        "workload": (f"{len(probs)} subproblems, n_b~U{{500..8000}}, r_b in {{5,10,20,40}}, "
+                     "RBF sigma_b~U[0.05,0.2), J_b=20, I_b=ceil(n_b/30), lambda=1e-4, "
+                     "rho=1e-6, seed=0"),
+        "members": len(probs), "sum_n2": float(np.sum(ns ** 2.0)),
+        "ms_per_batch": ms_batch, "solves_per_s": len(probs) * 1e3 / ms_batch,
+        "status": C.status_string(status), "rounds": rounds, "grid": grid,
+        "phase_ms": phase,
+        "inner_iters_max": max(i.iters for i in infos),
+        "refine_steps_max": max(i.refine_steps for i in infos),
+        "relres_max": max(i.relres_true for i in infos),
+        "fp64_ms_per_batch": ms64, "fp64_solves_per_s": len(probs) * 1e3 / ms64,
+        "fp64_iters_max": max(it64),
+        "mixed_vs_fp64_speedup": ms64 / ms_batch,
+        "e_KW_vs_fp64_max": max(ekw),
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "batch_kernel (whole batched solve, n x n passes only)",
+                     "algorithmic_bytes": byts},
+    }
+    bs.close()
+    return out
 
 
 def cpu_baseline(p, iters: int, budget_s: float = 20.0):
@@ -108,6 +219,9 @@ def main():
     from synth import config_c3
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.batch_only:
+        print(json.dumps(bench_batch(a, torch, C)), flush=True)
+        return
     t0 = time.time()
     p = config_c3(I=a.I, J=a.J)
     log(f"generated n={p.n} q={p.q} r={p.r} in {time.time() - t0:.1f} s")
@@ -258,6 +372,10 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, fp64["iters"])
         log(f"cpu baseline {out['cpu_baseline']}")
+    if a.batch_count > 0:
+        del sf, sf64, sm, dp
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batch(a, torch, C)
     print(json.dumps(out), flush=True)
 
 

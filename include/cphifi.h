@@ -279,6 +279,13 @@ CPHIFI_API int cphifi_batch_graph(cphifi_batch* bt, void** graph_exec);
  * every active member per round) and the persistent grid size.  sync. */
 CPHIFI_API int cphifi_batch_rounds(cphifi_batch* bt, int* rounds, int* grid);
 
+/* Where the last launch spent its time, from the device real-time clock as
+ * seen by one workgroup: ms[0..7] the eight phases of a round (products A,
+ * gather-scatter, segment rows + split, products B, finish, x/r update,
+ * preconditioner, control + p update), each including its closing grid
+ * barrier; ms[8] the per-round setup.  ms: host array of 9.  sync. */
+CPHIFI_API int cphifi_batch_phase_ms(cphifi_batch* bt, double* ms);
+
 /* Release the batch's host state and member plans (the workspace belongs to
  * the caller).  Waits for the batch's stream. */
 CPHIFI_API int cphifi_batch_destroy(cphifi_batch* bt);

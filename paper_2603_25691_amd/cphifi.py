@@ -130,6 +130,7 @@ def _load() -> C.CDLL:
         "cphifi_batch_info": (C.c_int, [P, C.POINTER(cphifi_solve_info)]),
         "cphifi_batch_graph": (C.c_int, [P, C.POINTER(P)]),
         "cphifi_batch_rounds": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "cphifi_batch_phase_ms": (C.c_int, [P, C.POINTER(C.c_double)]),
         "cphifi_batch_destroy": (C.c_int, [P]),
         "cphifi_status_string": (C.c_char_p, [C.c_int]),
         "cphifi_last_error": (C.c_char_p, []),
@@ -366,3 +367,13 @@ def cphifi_batch_rounds(batch: int):
 
 def cphifi_batch_destroy(batch: int) -> None:
     _check(_lib.cphifi_batch_destroy(C.c_void_p(batch)), "cphifi_batch_destroy")
+
+
+BATCH_PHASES = ("products_a", "gather", "rows_split", "products_b", "finish", "update_xr",
+                "precond", "control", "round_setup")
+
+
+def cphifi_batch_phase_ms(batch: int) -> dict:
+    arr = (C.c_double * 9)()
+    _check(_lib.cphifi_batch_phase_ms(C.c_void_p(batch), arr), "cphifi_batch_phase_ms")
+    return dict(zip(BATCH_PHASES, list(arr)))

@@ -55,9 +55,11 @@ using namespace cphifi;
 namespace {
 
 constexpr int kMaxBatch = 256;     // members per batch (one thread each in the round setup)
-constexpr int kRC = 64;            // rows per vector work item
+constexpr int kRC = 128;           // rows per vector work item
+constexpr int kTPW = 8;            // gather tasks per wave in one work item
 constexpr int kSlots = 8;          // phases per round
-constexpr int64_t kMaxN = (int64_t)kRC * kMaxVecBlocks;  // partials of a vector phase fit red[]
+constexpr int64_t kMaxN = 65536;   // also keeps a vector phase's partials within red[]
+static_assert(kMaxN <= (int64_t)kRC * kMaxVecBlocks, "partials of a vector phase fit red[]");
 // Members have r <= 48 (three 16-column MFMA blocks): the largest tiles then
 // fit the register budget of two workgroups per CU.
 constexpr int kBatchRank = 48;
@@ -76,7 +78,8 @@ enum : int { S_A = 0, S_OBS = 1, S_ROWS = 2, S_B = 3, S_FIN = 4, S_UPD = 5, S_PR
 struct BSub {
   int64_t n, ldk, ldl, I, J;
   int32_t r, ldp, nb, ocls;  // ocls: lane layout class of the gather (from r)
-  int32_t nrc, ntask, ntask4, nmulti;
+  int32_t nrc, ntask, ntaskw, nmulti;  // ntaskw: gather work items
+  int32_t orow, pad2;                  // gather by lane rows (short segments)
   const double* K;
   const double* UK;
   const double* b;
@@ -85,7 +88,7 @@ struct BSub {
   const int32_t* obs_j;
   const double* A;
   const double* B;
-  const int32_t *tseg, *tbeg, *tend, *tslot, *tfirst, *mptr, *rowm;
+  const int32_t *tseg, *tbeg, *tend, *tslot, *tfirst, *mptr, *rowm, *obs_ptr;
   void* part;
   double* tpart;
   const double *UV, *D, *dKc;
@@ -132,6 +135,7 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
   s.tfirst = global_word<decltype(s.tfirst)>(w[offsetof(BSub, tfirst) / 8]);
   s.mptr = global_word<decltype(s.mptr)>(w[offsetof(BSub, mptr) / 8]);
   s.rowm = global_word<decltype(s.rowm)>(w[offsetof(BSub, rowm) / 8]);
+  s.obs_ptr = global_word<decltype(s.obs_ptr)>(w[offsetof(BSub, obs_ptr) / 8]);
   s.part = global_word<decltype(s.part)>(w[offsetof(BSub, part) / 8]);
   s.tpart = global_word<decltype(s.tpart)>(w[offsetof(BSub, tpart) / 8]);
   s.UV = global_word<decltype(s.UV)>(w[offsetof(BSub, UV) / 8]);
@@ -168,6 +172,9 @@ struct BCtl {
   int32_t err;     // a wait timed out: every workgroup leaves
   int32_t rounds;  // rounds executed by the last launch
   int32_t pad;
+  // Real-time clock ticks (100 MHz) spent in each phase, seen by workgroup 0
+  // from one barrier exit to the next: [kSlots] phases, then the round setup.
+  uint64_t ticks[kSlots + 1];
 };
 
 struct BArgs {
@@ -248,7 +255,7 @@ __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
       switch (slot) {
         case S_A:
         case S_B: return fn;
-        case S_OBS: return S.ntask4;
+        case S_OBS: return S.ntaskw;
         case S_ROWS: return S.nmulti > 0 ? S.nrc : 0;
         case S_FIN: return S.nrc;
         case S_CTRL: return 1;
@@ -266,7 +273,7 @@ __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
       switch (slot) {
         case S_A:
         case S_B: return bf;
-        case S_OBS: return S.ntask4;
+        case S_OBS: return S.ntaskw;
         default: return S.nrc;
       }
     case M_ROT_OUT:
@@ -326,10 +333,13 @@ __device__ __forceinline__ void gemm_item(const BSub& S, int kind, const double*
 }
 
 // ------------------------------------------------------ gather-dot-scatter
+// Work item i: wave w takes tasks [(4 i + w) kTPW, ...) of the member's list,
+// or, for short segments, segments [(4 i + w) kSegPerWave, ...) by lane rows.
 template <int L, int CPL, typename PT>
 __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, bool res) {
-  const int64_t task = 4 * i + (item_tid() >> 6);
-  if (task >= S.ntask) return;
+  const int64_t wv = 4 * i + (item_tid() >> 6);
+  const int64_t t0 = wv * kTPW;
+  const int64_t t1 = min((int64_t)S.ntask, t0 + kTPW);
   tiles::TaskView tv{S.tseg, S.tbeg, S.tend, S.tslot, S.tfirst, S.ntask};
   tiles::ObsDev d{};
   d.a.n = S.n;
@@ -349,7 +359,16 @@ __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, bool res) {
   d.a.done = nullptr;
   d.I = S.I;
   d.J = S.J;
-  tiles::obs_task<L, CPL, false, 0, PT>(tv, d, task);
+  if (S.orow) {
+    constexpr int ROWS = 64 / L;
+    for (int k = 0; k < kSegPerWave; k += ROWS) {
+      const int64_t s0 = wv * kSegPerWave + k;
+      if (s0 >= S.n) break;
+      tiles::obs_rows<L, CPL, false, 0, PT>(d, S.obs_ptr, s0, (int)min((int64_t)ROWS, S.n - s0));
+    }
+    return;
+  }
+  for (int64_t task = t0; task < t1; ++task) tiles::obs_task<L, CPL, false, 0, PT>(tv, d, task);
 }
 
 template <int L, int CPL>
@@ -483,7 +502,12 @@ __device__ __forceinline__ void upd_item(const BSub& S, const BState* st, int it
 }
 
 // z = ((r U_V) had D) U_V^T for the chunk's rows (eq. fx in the eigenbasis of
-// K), one wave per row; partial r^T z.
+// K); partial r^T z.  Lane c of a wave owns column c; a wave takes kPR rows at
+// a time, so every U_V element read from LDS feeds kPR multiply-adds and the
+// rows' global loads are in flight together.
+constexpr int kPR = 4;
+static_assert((kBatchRank * kBatchRank + 4 * kPR * kWave) * 8 <= kSmemBytes, "precond LDS");
+
 __device__ __forceinline__ void prec_rows(const BSub& S, int64_t i, char* smem, double* s_red) {
   const int r = S.r;
   double* uv = (double*)smem;
@@ -491,26 +515,48 @@ __device__ __forceinline__ void prec_rows(const BSub& S, int64_t i, char* smem, 
   for (int e = item_tid(); e < r * r; e += blockDim.x) uv[e] = S.UV[e];
   __syncthreads();
   const int wave = item_tid() >> 6, c = item_tid() & 63;
-  double* wb = buf + wave * kWave;
+  double* wb = buf + wave * (kPR * kWave);
   const int64_t s0 = i * kRC, s1 = min(S.n, s0 + kRC);
+  const bool col = c < r;
   double loc = 0.0;
-  for (int64_t s = s0 + wave; s < s1; s += 4) {
-    const double t = c < r ? S.R[s * r + c] : 0.0;
-    wb[c] = t;
-    __builtin_amdgcn_wave_barrier();
-    double u = 0.0;
-    if (c < r) {
-      for (int j = 0; j < r; ++j) u += wb[j] * uv[j * r + c];
-      u *= S.D[s * r + c];
+  for (int64_t sb = s0 + wave * kPR; sb < s1; sb += 4 * kPR) {
+    double t[kPR], u[kPR], dd[kPR];
+#pragma unroll
+    for (int k = 0; k < kPR; ++k) {
+      const bool on = col && sb + k < s1;
+      t[k] = on ? S.R[(sb + k) * r + c] : 0.0;
+      dd[k] = on ? S.D[(sb + k) * r + c] : 0.0;
+      wb[k * kWave + c] = t[k];
     }
     __builtin_amdgcn_wave_barrier();
-    wb[c] = u;
+#pragma unroll
+    for (int k = 0; k < kPR; ++k) u[k] = 0.0;
+    if (col) {
+      for (int j = 0; j < r; ++j) {
+        const double w = uv[j * r + c];
+#pragma unroll
+        for (int k = 0; k < kPR; ++k) u[k] += wb[k * kWave + j] * w;
+      }
+    }
     __builtin_amdgcn_wave_barrier();
-    if (c < r) {
-      double o = 0.0;
-      for (int j = 0; j < r; ++j) o += wb[j] * uv[c * r + j];
-      S.Z[s * r + c] = o;
-      loc += t * o;
+#pragma unroll
+    for (int k = 0; k < kPR; ++k) wb[k * kWave + c] = u[k] * dd[k];
+    __builtin_amdgcn_wave_barrier();
+    if (col) {
+      double o[kPR];
+#pragma unroll
+      for (int k = 0; k < kPR; ++k) o[k] = 0.0;
+      for (int j = 0; j < r; ++j) {
+        const double w = uv[c * r + j];
+#pragma unroll
+        for (int k = 0; k < kPR; ++k) o[k] += wb[k * kWave + j] * w;
+      }
+#pragma unroll
+      for (int k = 0; k < kPR; ++k)
+        if (sb + k < s1) {
+          S.Z[(sb + k) * r + c] = o[k];
+          loc += t[k] * o[k];
+        }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -711,9 +757,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   __shared__ double s_red[8];
   __shared__ int s_item;
   __shared__ int s_ok;
+  __shared__ uint64_t s_tick[kSlots + 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int count = a.count;
+  const bool clock0 = blockIdx.x == 0 && tid == 0;  // keeps the phase clock
+  if (tid <= kSlots) s_tick[tid] = 0;
+  uint64_t t_last = clock0 ? __builtin_amdgcn_s_memrealtime() : 0;
   uint32_t nbar = 0;  // barriers passed
   uint32_t pi = 0;    // phases run
   int round = 0;
@@ -754,6 +804,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
       if (tid == count - 1) s_pref[s][count] = base + incl[s];
     }
     __syncthreads();
+    if (clock0) {
+      const uint64_t t = __builtin_amdgcn_s_memrealtime();
+      s_tick[kSlots] += t - t_last;
+      t_last = t;
+    }
     if (s_pref[S_CTRL][count] == 0) break;  // every member is done
 
     for (int slot = 0; slot < kSlots; ++slot) {
@@ -790,9 +845,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
       ++pi;
       ++nbar;
       if (!grid_sync(a.ctl, nbar * gridDim.x, a.spin_limit, &s_ok)) return;
+      if (clock0) {
+        const uint64_t t = __builtin_amdgcn_s_memrealtime();
+        s_tick[slot] += t - t_last;
+        t_last = t;
+      }
     }
   }
-  if (blockIdx.x == 0 && tid == 0) a.ctl->rounds = round;
+  if (clock0) {
+    a.ctl->rounds = round;
+    for (int j = 0; j <= kSlots; ++j) a.ctl->ticks[j] = s_tick[j];
+  }
 }
 
 // Start state of a launch: control words cleared, every member at INIT.
@@ -802,6 +865,7 @@ __global__ void batch_reset_kernel(BArgs a) {
     for (int j = 0; j < 4; ++j) a.ctl->fc[j] = 0;
     a.ctl->err = 0;
     a.ctl->rounds = 0;
+    for (int j = 0; j <= kSlots; ++j) a.ctl->ticks[j] = 0;
   }
   for (int b = threadIdx.x; b < a.count; b += blockDim.x) {
     BState s{};
@@ -1079,7 +1143,10 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.ocls = obs_class((int)p->r);
     S.nrc = (int32_t)((p->n + kRC - 1) / kRC);
     S.ntask = p->tasks.ntask;
-    S.ntask4 = (p->tasks.ntask + 3) / 4;
+    S.orow = p->tasks.rows ? 1 : 0;
+    S.ntaskw = S.orow ? (int32_t)((p->n + 4 * kSegPerWave - 1) / (4 * kSegPerWave))
+                      : (p->tasks.ntask + 4 * kTPW - 1) / (4 * kTPW);
+    S.obs_ptr = in.obs_ptr;
     S.nmulti = p->tasks.nmulti;
     S.K = in.K;
     S.UK = in.UK;
@@ -1280,6 +1347,18 @@ int cphifi_batch_rounds(cphifi_batch* bt, int* rounds, int* grid) {
   CPHIFI_HIP(hipStreamSynchronize(bt->st));
   *rounds = bt->h_ctl->rounds;
   *grid = bt->grid;
+  return CPHIFI_OK;
+}
+
+int cphifi_batch_phase_ms(cphifi_batch* bt, double* ms) {
+  clear_error();
+  if (bt == nullptr || ms == nullptr) {
+    set_error("bad arguments");
+    return CPHIFI_INVALID_ARG;
+  }
+  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, sizeof(BCtl), hipMemcpyDeviceToHost, bt->st));
+  CPHIFI_HIP(hipStreamSynchronize(bt->st));
+  for (int j = 0; j <= kSlots; ++j) ms[j] = 1e-5 * (double)bt->h_ctl->ticks[j];  // 100 MHz
   return CPHIFI_OK;
 }
 

@@ -123,7 +123,14 @@ struct ObsTasks {
   int32_t* first = nullptr;    // [ntask] 1 if first task of its segment
   int32_t* mseg = nullptr;     // [nmulti] segments with several tasks
   int32_t* mptr = nullptr;     // [nmulti+1] their task-slot ranges
+  // Short segments (no split ones, few observations each): one L-lane row of
+  // a wave per segment, read straight from the CSR (no task list).
+  bool rows = false;
+  const int32_t* obs_ptr = nullptr;
+  int64_t nseg = 0;
 };
+constexpr int kSegPerWave = 32;  // segments per wave in the short-segment form
+constexpr int kShortSegment = 32;  // mean observations per segment for that form
 
 struct ObsArgs {
   int64_t n;

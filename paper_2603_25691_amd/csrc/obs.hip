@@ -18,6 +18,20 @@ __global__ __launch_bounds__(256) void obs_kernel(TaskView t, ObsDev d) {
   obs_task<L, CPL, EXPL, MODE, PT>(t, d, task);
 }
 
+// Short segments: wave w takes segments [w kSegPerWave, ...), 64/L at a time.
+template <int L, int CPL, bool EXPL, int MODE, typename PT>
+__global__ __launch_bounds__(256) void obs_rows_kernel(ObsDev d, const int32_t* obs_ptr,
+                                                       int64_t n) {
+  if (d.a.done != nullptr && *d.a.done) return;
+  constexpr int ROWS = 64 / L;
+  const int64_t sb = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kSegPerWave;
+  for (int k = 0; k < kSegPerWave; k += ROWS) {
+    const int64_t s0 = sb + k;
+    if (s0 >= n) break;
+    tiles::obs_rows<L, CPL, EXPL, MODE, PT>(d, obs_ptr, s0, (int)min((int64_t)ROWS, n - s0));
+  }
+}
+
 // Adds the partial rows of segments that were split over several tasks.
 __global__ void segment_reduce_kernel(const int32_t* __restrict__ mseg,
                                       const int32_t* __restrict__ mptr, int32_t nmulti,
@@ -33,7 +47,19 @@ __global__ void segment_reduce_kernel(const int32_t* __restrict__ mseg,
 }
 
 template <int L, int CPL, bool EXPL, int MODE>
-int launch_c(bool pf, const TaskView& tv, const ObsDev& d, hipStream_t st) {
+int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hipStream_t st) {
+  if (t.rows) {
+    const int64_t blocks = (t.nseg + 4 * kSegPerWave - 1) / (4 * kSegPerWave);
+    if (blocks == 0) return CPHIFI_OK;
+    if (pf)
+      hipLaunchKernelGGL((obs_rows_kernel<L, CPL, EXPL, MODE, float>), dim3((unsigned)blocks),
+                         dim3(256), 0, st, d, t.obs_ptr, t.nseg);
+    else
+      hipLaunchKernelGGL((obs_rows_kernel<L, CPL, EXPL, MODE, double>), dim3((unsigned)blocks),
+                         dim3(256), 0, st, d, t.obs_ptr, t.nseg);
+    CPHIFI_CHECK_LAUNCH();
+    return CPHIFI_OK;
+  }
   const int blocks = (tv.ntask + 3) / 4;
   if (blocks == 0) return CPHIFI_OK;
   if (pf)
@@ -49,17 +75,18 @@ int launch_c(bool pf, const TaskView& tv, const ObsDev& d, hipStream_t st) {
 // Lanes per observation: L = 4 up to r = 20, 8 up to r = 40, 16 beyond; each
 // lane then holds ceil(r / L) <= 5 columns.
 template <bool EXPL, int MODE>
-int launch_m(int r, bool pf, const TaskView& tv, const ObsDev& d, hipStream_t st) {
-  if (r <= 4) return launch_c<4, 1, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 8) return launch_c<4, 2, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 12) return launch_c<4, 3, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 16) return launch_c<4, 4, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 20) return launch_c<4, 5, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 24) return launch_c<8, 3, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 32) return launch_c<8, 4, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 40) return launch_c<8, 5, EXPL, MODE>(pf, tv, d, st);
-  if (r <= 48) return launch_c<16, 3, EXPL, MODE>(pf, tv, d, st);
-  return launch_c<16, 4, EXPL, MODE>(pf, tv, d, st);
+int launch_m(int r, bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t,
+             hipStream_t st) {
+  if (r <= 4) return launch_c<4, 1, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 8) return launch_c<4, 2, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 12) return launch_c<4, 3, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 16) return launch_c<4, 4, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 20) return launch_c<4, 5, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 24) return launch_c<8, 3, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 32) return launch_c<8, 4, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 40) return launch_c<8, 5, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 48) return launch_c<16, 3, EXPL, MODE>(pf, tv, d, t, st);
+  return launch_c<16, 4, EXPL, MODE>(pf, tv, d, t, st);
 }
 
 }  // namespace
@@ -82,14 +109,18 @@ int launch_obs(ObsMode mode, bool part_is_float, const ObsTasks& t, const ObsArg
   TaskView tv{t.seg, t.beg, t.end, t.slot, t.first, t.ntask};
   ObsDev d{a, I, J};
   int st_ = CPHIFI_OK;
+  if (t.rows && (t.nmulti > 0 || t.obs_ptr == nullptr)) {
+    set_error("launch_obs: the short-segment form needs the CSR and no split segments");
+    return CPHIFI_INVALID_ARG;
+  }
   if (mode == ObsMode::Gather)
-    st_ = expl ? launch_m<true, 0>(a.r, part_is_float, tv, d, st)
-               : launch_m<false, 0>(a.r, part_is_float, tv, d, st);
+    st_ = expl ? launch_m<true, 0>(a.r, part_is_float, tv, d, t, st)
+               : launch_m<false, 0>(a.r, part_is_float, tv, d, t, st);
   else
-    st_ = expl ? launch_m<true, 1>(a.r, part_is_float, tv, d, st)
-               : launch_m<false, 1>(a.r, part_is_float, tv, d, st);
+    st_ = expl ? launch_m<true, 1>(a.r, part_is_float, tv, d, t, st)
+               : launch_m<false, 1>(a.r, part_is_float, tv, d, t, st);
   if (st_ != CPHIFI_OK) return st_;
-  if (t.nmulti > 0) {
+  if (!t.rows && t.nmulti > 0) {
     hipLaunchKernelGGL(segment_reduce_kernel, dim3((t.nmulti + 3) / 4), dim3(256), 0, st, t.mseg,
                        t.mptr, t.nmulti, a.tpart, a.r, a.out, a.done);
     CPHIFI_CHECK_LAUNCH();

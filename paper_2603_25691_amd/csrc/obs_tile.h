@@ -185,5 +185,133 @@ __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int
   }
 }
 
+// Short segments: each L-lane row of the wave takes one whole segment, so a
+// wave works on 64/L segments at once, each row accumulating its segment's
+// observations kGroups at a time and writing its own output row (no fold
+// across rows).  Segments [s0, s0 + nseg), nseg <= 64/L, read from the CSR
+// obs_ptr; for segments without a split over several tasks (the caller
+// checks), this gives the same Yhat1 / MTTKRP rows as obs_task.
+template <int L, int CPL, bool EXPL, int MODE, typename PT>
+__device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr, int64_t s0,
+                                         int nseg) {
+  const ObsArgs& a = d.a;
+  const int lane = item_tid() & 63;
+  const int r = a.r;
+  const int g = lane / L, cl = lane % L;
+  const bool row_on = g < nseg;
+  const int64_t s = s0 + (row_on ? g : 0);
+  const int64_t beg = obs_ptr[s];
+  const int64_t end = row_on ? (int64_t)obs_ptr[s + 1] : beg;
+  const int64_t last = end > beg ? end - 1 : -1;  // clamp target of masked loads
+
+  uint32_t cidx[CPL];
+  bool con[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int c = cl + L * j;
+    con[j] = c < r;
+    cidx[j] = (uint32_t)min(c, r - 1);
+  }
+  const uint32_t Imax = (uint32_t)(d.I - 1), Jmax = (uint32_t)(d.J - 1), ur = (uint32_t)r;
+  const char* __restrict__ Abytes = (const char*)a.A;
+  const char* __restrict__ Bbytes = (const char*)a.B;
+  uint32_t cbyte[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) cbyte[j] = cidx[j] * 8u;
+
+  // wave-uniform step count: the longest segment of the wave
+  int maxlen = (int)(end - beg);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, 64));
+  const int nstep = (maxlen + kGroups - 1) / kGroups;
+
+  auto obs_at = [&](int step, int u) -> int64_t {
+    const int64_t l = beg + (int64_t)step * kGroups + u;
+    return l < end ? l : last;
+  };
+  auto fetch_idx = [&](int step, int32_t (&ii_)[kGroups], int32_t (&jj_)[kGroups]) {
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) {
+      const int64_t o = obs_at(step, u);
+      ii_[u] = 0;
+      jj_[u] = 0;
+      if (!EXPL && o >= 0) {
+        ii_[u] = a.obs_i[o];
+        jj_[u] = a.obs_j[o];
+      }
+    }
+  };
+  int32_t ii_cur[kGroups] = {}, jj_cur[kGroups] = {};
+  if (nstep > 0) fetch_idx(0, ii_cur, jj_cur);
+
+  double xh[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) xh[j] = 0.0;
+  if (MODE == 0) {
+    const PT* part = (const PT*)a.part;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      double v = 0.0;
+      for (int sp = 0; sp < a.ksplit; ++sp)
+        v += (double)part[((int64_t)sp * a.n + s) * a.ldp + cidx[j]];
+      xh[j] = con[j] ? v : 0.0;
+      if (a.Xhat != nullptr && row_on && con[j]) a.Xhat[s * r + cidx[j]] = v;
+    }
+  }
+
+  double acc[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) acc[j] = 0.0;
+  for (int step = 0; step < nstep; ++step) {
+    int32_t ii_nxt[kGroups] = {}, jj_nxt[kGroups] = {};
+    if (step + 1 < nstep) fetch_idx(step + 1, ii_nxt, jj_nxt);
+    double z[kGroups][CPL];
+    double w[kGroups];
+    bool on[kGroups];
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) {
+      const int64_t l = beg + (int64_t)step * kGroups + u;
+      on[u] = l < end;
+      const int64_t o = on[u] ? l : last;
+      if (EXPL) {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) z[u][j] = o >= 0 ? a.Zhat[o * r + cidx[j]] : 0.0;
+      } else {
+        const uint32_t ib = min((uint32_t)max(ii_cur[u], 0), Imax) * ur * 8u;
+        const uint32_t jb = min((uint32_t)max(jj_cur[u], 0), Jmax) * ur * 8u;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j)
+          z[u][j] = *(const double*)(Abytes + (ib + cbyte[j])) *
+                    *(const double*)(Bbytes + (jb + cbyte[j]));
+      }
+      if (MODE == 1) w[u] = on[u] ? a.y[o] : 0.0;
+    }
+    if (MODE == 0) {
+#pragma unroll
+      for (int u = 0; u < kGroups; ++u) {
+        double part = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) part += z[u][j] * xh[j];
+        const double xb = group_sum<L>(part);  // xbar_l, eq. vl
+        w[u] = on[u] ? xb : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u)
+#pragma unroll
+      for (int j = 0; j < CPL; ++j) acc[j] += w[u] * z[u][j];  // eq. yhat1 / MTTKRP
+#pragma unroll
+    for (int u = 0; u < kGroups; ++u) {
+      ii_cur[u] = ii_nxt[u];
+      jj_cur[u] = jj_nxt[u];
+    }
+  }
+  if (row_on) {
+#pragma unroll
+    for (int j = 0; j < CPL; ++j)
+      if (con[j]) a.out[s * r + cidx[j]] = acc[j];
+  }
+}
+
 }  // namespace tiles
 }  // namespace cphifi

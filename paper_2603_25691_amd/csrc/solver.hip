@@ -733,6 +733,11 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   p->tasks.first = (int32_t*)(ws + L.tfirst);
   p->tasks.mseg = (int32_t*)(ws + L.mseg);
   p->tasks.mptr = (int32_t*)(ws + L.mptr);
+  // Short segments (at most kShortSegment observations on average, none split):
+  // one lane row per segment instead of one wave per segment.
+  p->tasks.rows = mseg.empty() && q <= kShortSegment * n;
+  p->tasks.obs_ptr = in->obs_ptr;
+  p->tasks.nseg = n;
   p->rowm = (int32_t*)(ws + L.rowm);
 
   auto fail = [&](int code) {

@@ -33,15 +33,22 @@ def _need(t: torch.Tensor, dtype, shape, name: str):
 def kernel_eig(K: torch.Tensor):
     """One-time eigendecomposition of K on the device (library call).
 
-    Returns (UK, dK) with UK holding eigenvector k in row k (the LAPACK
+    K: (n, ldk) storage with ldk >= n (row stride ldk).  Returns (UK, dK) with
+    UK of the same storage shape holding eigenvector k in row k (the LAPACK
     column-major order the ABI expects) and dK ascending.
     """
-    n = K.shape[0]
-    _need(K, torch.float64, (n, n), "K")
+    n, ldk = K.shape[0], K.shape[1]
+    if ldk < n:
+        raise ValueError("K: row stride below n")
+    _need(K, torch.float64, (n, ldk), "K")
     UK = torch.empty_like(K)
     dK = torch.empty(n, dtype=torch.float64, device=K.device)
-    _c.cphifi_kernel_eig(n, K.data_ptr(), n, UK.data_ptr(), dK.data_ptr(), _stream())
+    _c.cphifi_kernel_eig(n, K.data_ptr(), ldk, UK.data_ptr(), dK.data_ptr(), _stream())
     return UK, dK
+
+
+def _ldk(prob) -> int:
+    return prob.K.shape[1]
 
 
 @dataclass
@@ -72,8 +79,8 @@ class UISolver:
                  max_refine: int = 0, inner_tol: float = 0.0, check_every: int = 0):
         self.prob = prob
         n, r, q = prob.n, prob.r, prob.q
-        _need(prob.K, torch.float64, (n, n), "K")
-        _need(prob.UK, torch.float64, (n, n), "UK")
+        _need(prob.K, torch.float64, (n, _ldk(prob)), "K")
+        _need(prob.UK, torch.float64, (n, _ldk(prob)), "UK")
         _need(prob.dK, torch.float64, (n,), "dK")
         _need(prob.obs_ptr, torch.int32, (n + 1,), "obs_ptr")
         _need(prob.y, torch.float64, (q,), "y")
@@ -88,7 +95,7 @@ class UISolver:
             _need(prob.V, torch.float64, (r, r), "V")
         self.desc = _c.make_desc(n, r, q, prob.I, prob.J, lam, rho, gamma, tol,
                                  _c.PRECISIONS[precision], flags, maxit, max_refine, inner_tol,
-                                 check_every)
+                                 check_every, ldk=_ldk(prob))
         self.inputs = _c.make_inputs(K=_ptr(prob.K), UK=_ptr(prob.UK), dK=_ptr(prob.dK),
                                      obs_ptr=_ptr(prob.obs_ptr), obs_i=_ptr(prob.obs_i),
                                      obs_j=_ptr(prob.obs_j), A=_ptr(prob.A), B=_ptr(prob.B),
@@ -170,8 +177,8 @@ class BatchSolver:
         self.descs, self.inputs = [], []
         for k, pr in enumerate(self.probs):
             n, r, q = pr.n, pr.r, pr.q
-            _need(pr.K, torch.float64, (n, n), "K")
-            _need(pr.UK, torch.float64, (n, n), "UK")
+            _need(pr.K, torch.float64, (n, _ldk(pr)), "K")
+            _need(pr.UK, torch.float64, (n, _ldk(pr)), "UK")
             _need(pr.dK, torch.float64, (n,), "dK")
             _need(pr.obs_ptr, torch.int32, (n + 1,), "obs_ptr")
             _need(pr.A, torch.float64, (pr.I, r), "A")
@@ -180,7 +187,7 @@ class BatchSolver:
             _need(pr.obs_j, torch.int32, (q,), "obs_j")
             self.descs.append(_c.make_desc(n, r, q, pr.I, pr.J, lam[k], rho[k], 0.0, tol[k],
                                            _c.MIXED_BF16, flags[k], maxit[k], max_refine[k],
-                                           inner_tol[k]))
+                                           inner_tol[k], ldk=_ldk(pr)))
             self.inputs.append(_c.make_inputs(K=_ptr(pr.K), UK=_ptr(pr.UK), dK=_ptr(pr.dK),
                                               obs_ptr=_ptr(pr.obs_ptr), obs_i=_ptr(pr.obs_i),
                                               obs_j=_ptr(pr.obs_j), A=_ptr(pr.A),
@@ -219,6 +226,9 @@ class BatchSolver:
     def rounds(self):
         return _c.cphifi_batch_rounds(self.batch)
 
+    def phase_ms(self):
+        return _c.cphifi_batch_phase_ms(self.batch)
+
     def close(self):
         if getattr(self, "batch", 0):
             _c.cphifi_batch_destroy(self.batch)
@@ -231,21 +241,30 @@ class BatchSolver:
             pass
 
 
-def upload(p, device="cuda", explicit=None, eig=None) -> DeviceProblem:
+def upload(p, device="cuda", explicit=None, eig=None, ldk_align: int = 1) -> DeviceProblem:
     """Copy a synth.Problem's arrays to the device (host-to-device copies only).
 
     explicit: optional (Zhat, V) host arrays for the explicit per-observation
     form; otherwise the implicit (A, B) form is used.  eig: optional host
     (UK, dK) in the ABI's layout; by default the library computes the
-    eigendecomposition of K on the device.
+    eigendecomposition of K on the device.  ldk_align: K and U_K are stored
+    with row stride round_up(n, ldk_align) (an even stride keeps every row
+    16-byte aligned for the FP64 products' vector loads).
     """
     import numpy as np
 
     def dev(a, dtype):
         return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
 
-    K = dev(p.K, torch.float64)
+    ldk = (p.n + ldk_align - 1) // ldk_align * ldk_align
+    if ldk == p.n:
+        K = dev(p.K, torch.float64)
+    else:
+        K = torch.zeros(p.n, ldk, dtype=torch.float64, device=device)
+        K[:, :p.n] = dev(p.K, torch.float64)
     if eig is not None:
+        if ldk != p.n:
+            raise ValueError("eig= takes the unpadded layout")
         UK = dev(eig[0], torch.float64)
         dK = dev(eig[1], torch.float64)
     else:

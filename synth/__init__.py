@@ -16,6 +16,7 @@ from .generator import (  # noqa: F401
     make_aligned,
     make_small,
     make_batch,
+    batch_members,
     make_paper_standin,
     config_c1,
     config_c2,

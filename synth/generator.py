@@ -322,17 +322,17 @@ class BatchMember:
     sigma: float
 
 
-def make_batch(seed: int = 0, count: int = 64, n_lo: int = 500, n_hi: int = 8000,
-               ranks=(5, 10, 20, 40), J: int = 20, lam: float = 1e-4,
-               rho: float = 1e-6, tol: float = 1e-7) -> List[BatchMember]:
-    """Batched recipe: `count` independent subproblems of uneven size.
+def batch_members(seed: int = 0, count: int = 64, n_lo: int = 500, n_hi: int = 8000,
+                  ranks=(5, 10, 20, 40), J: int = 20, lam: float = 1e-4,
+                  rho: float = 1e-6, tol: float = 1e-7):
+    """Batched recipe, one member at a time (a generator, so a large batch
+    never holds every kernel matrix in host memory at once).
 
-    Per member b (own child seed from SeedSequence(seed).spawn(count)), draw in
-    order: n_b ~ U{n_lo..n_hi}; r_b uniform over `ranks`; RBF bandwidth
+    Member b draws from its own child seed of SeedSequence(seed).spawn(count),
+    in order: n_b ~ U{n_lo..n_hi}; r_b uniform over `ranks`; RBF bandwidth
     sigma_b ~ U[0.05, 0.2); the n_b times U[0,1); the owner sample of each time
     ~ U{0..I_b-1} with I_b = ceil(n_b/30); A; B; Wstar; noise.  J_b = J.
     """
-    out: List[BatchMember] = []
     for b, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
         rng = np.random.default_rng(child)
         n = int(rng.integers(n_lo, n_hi + 1))
@@ -363,8 +363,12 @@ def make_batch(seed: int = 0, count: int = 64, n_lo: int = 500, n_hi: int = 8000
             gamma=q / (n * I * J), tol=tol, kernel="rbf", kernel_param=sigma,
             meta={"seed": seed, "member": b, "owner": owner},
         )
-        out.append(BatchMember(problem=p, sigma=sigma))
-    return out
+        yield BatchMember(problem=p, sigma=sigma)
+
+
+def make_batch(seed: int = 0, count: int = 64, **kw) -> List[BatchMember]:
+    """All members of the batched recipe (see batch_members)."""
+    return list(batch_members(seed=seed, count=count, **kw))
 
 
 def config_c5(seed: int = 0, count: int = 64, **kw) -> List[BatchMember]:

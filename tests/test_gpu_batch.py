@@ -198,3 +198,25 @@ def test_batch_barrier_timeout_is_reported_and_drains(batch):
 
 def test_batch_graph_handle(batch):
     assert batch["bs"].graph() != 0
+
+
+def test_batch_with_padded_kernel_stride(batch):
+    """K and U_K stored with a row stride above n (16-byte aligned rows for
+    odd n): same solutions as the unpadded layout."""
+    idx = [k for k, p in enumerate(batch["probs"]) if p.n % 2 == 1][:3]
+    assert idx, "need members of odd n"
+    probs = [batch["probs"][k] for k in idx]
+    dps = [upload(p, ldk_align=64) for p in probs]
+    assert all(dp.K.shape[1] % 64 == 0 and dp.K.shape[1] > dp.n for dp in dps)
+    bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], TOL, **CAPS)
+    try:
+        rhs = bs.rhs()
+        Ws = [torch.empty_like(b) for b in rhs]
+        status, infos = bs.solve(rhs, Ws)
+        assert status == C.OK
+        for j, k in enumerate(idx):
+            p = batch["probs"][k]
+            assert infos[j].relres_true <= TOL
+            assert O.e_kw(p.K, host(Ws[j]), batch["W"][k]) <= 1e-6
+    finally:
+        bs.close()
