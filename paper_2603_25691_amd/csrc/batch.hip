@@ -79,7 +79,8 @@ struct BSub {
   int64_t n, ldk, ldl, I, J;
   int32_t r, ldp, nb, ocls;  // ocls: lane layout class of the gather (from r)
   int32_t nrc, ntask, ntaskw, nmulti;  // ntaskw: gather work items
-  int32_t orow, pad2;                  // gather by lane rows (short segments)
+  int32_t orow, own;                   // gather by lane rows (short segments); one
+                                       // sample per time point (A read per segment)
   const double* K;
   const double* UK;
   const double* b;
@@ -303,24 +304,24 @@ __device__ __forceinline__ void gemm_item_nb(const BSub& S, int kind, const doub
     g.ldxt = S.ldl;
     const int64_t bx = i % S.bf_nrb, by = i / S.bf_nrb;
     if (S.bf_mw == 4)
-      tiles::gemm_bf16_tile<NB, 4, 2>(g, bx, by, (__bf16*)smem);
+      tiles::gemm_bf16_tile<NB, 4, 2>(g, bx, by, (__bf16*)smem, item_tid());
     else
-      tiles::gemm_bf16_tile<NB, 2, 2>(g, bx, by, (__bf16*)smem);
+      tiles::gemm_bf16_tile<NB, 2, 2>(g, bx, by, (__bf16*)smem, item_tid());
   } else if (kind == G_UKT) {
     g.U = S.UK;
     g.ldu = S.ldk;
     g.kper = S.ft_kper;
     const int64_t bx = i % S.ft_nrb, by = i / S.ft_nrb;
-    tiles::gemm_k4_tile<double, NB, 2, 4, true, 1>(g, bx, by, (double*)smem);
+    tiles::gemm_k4_tile<double, NB, 2, 4, true, 1>(g, bx, by, (double*)smem, item_tid());
   } else {
     g.U = kind == G_K ? S.K : S.UK;
     g.ldu = S.ldk;
     g.kper = S.fn_kper;
     const int64_t bx = i % S.fn_nrb, by = i / S.fn_nrb;
     if (S.fn_vw == 2)
-      tiles::gemm_k4_tile<double, NB, 2, 8, false, 2>(g, bx, by, (double*)smem);
+      tiles::gemm_k4_tile<double, NB, 2, 8, false, 2>(g, bx, by, (double*)smem, item_tid());
     else
-      tiles::gemm_k4_tile<double, NB, 2, 8, false, 1>(g, bx, by, (double*)smem);
+      tiles::gemm_k4_tile<double, NB, 2, 8, false, 1>(g, bx, by, (double*)smem, item_tid());
   }
 }
 
@@ -335,7 +336,7 @@ __device__ __forceinline__ void gemm_item(const BSub& S, int kind, const double*
 // ------------------------------------------------------ gather-dot-scatter
 // Work item i: wave w takes tasks [(4 i + w) kTPW, ...) of the member's list,
 // or, for short segments, segments [(4 i + w) kSegPerWave, ...) by lane rows.
-template <int L, int CPL, typename PT>
+template <int L, int CPL, int FORM, typename PT>
 __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, bool res) {
   const int64_t wv = 4 * i + (item_tid() >> 6);
   const int64_t t0 = wv * kTPW;
@@ -364,19 +365,28 @@ __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, bool res) {
     for (int k = 0; k < kSegPerWave; k += ROWS) {
       const int64_t s0 = wv * kSegPerWave + k;
       if (s0 >= S.n) break;
-      tiles::obs_rows<L, CPL, false, 0, PT>(d, S.obs_ptr, s0, (int)min((int64_t)ROWS, S.n - s0));
+      tiles::obs_rows<L, CPL, FORM, 0, PT>(d, S.obs_ptr, s0, (int)min((int64_t)ROWS, S.n - s0),
+                                           item_tid() & 63);
     }
     return;
   }
-  for (int64_t task = t0; task < t1; ++task) tiles::obs_task<L, CPL, false, 0, PT>(tv, d, task);
+  for (int64_t task = t0; task < t1; ++task)
+    tiles::obs_task<L, CPL, FORM, 0, PT>(tv, d, task, item_tid() & 63);
 }
 
 template <int L, int CPL>
 __device__ __forceinline__ void obs_item_l(const BSub& S, int64_t i, bool res) {
-  if (res)
-    obs_item_c<L, CPL, double>(S, i, true);
-  else
-    obs_item_c<L, CPL, float>(S, i, false);
+  if (S.own) {
+    if (res)
+      obs_item_c<L, CPL, tiles::kOwner, double>(S, i, true);
+    else
+      obs_item_c<L, CPL, tiles::kOwner, float>(S, i, false);
+  } else {
+    if (res)
+      obs_item_c<L, CPL, tiles::kImplicit, double>(S, i, true);
+    else
+      obs_item_c<L, CPL, tiles::kImplicit, float>(S, i, false);
+  }
 }
 
 __device__ __forceinline__ void obs_item(const BSub& S, int64_t i, bool res) {
@@ -1144,6 +1154,7 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.nrc = (int32_t)((p->n + kRC - 1) / kRC);
     S.ntask = p->tasks.ntask;
     S.orow = p->tasks.rows ? 1 : 0;
+    S.own = p->tasks.owner ? 1 : 0;
     S.ntaskw = S.orow ? (int32_t)((p->n + 4 * kSegPerWave - 1) / (4 * kSegPerWave))
                       : (p->tasks.ntask + 4 * kTPW - 1) / (4 * kTPW);
     S.obs_ptr = in.obs_ptr;

@@ -128,6 +128,10 @@ struct ObsTasks {
   bool rows = false;
   const int32_t* obs_ptr = nullptr;
   int64_t nseg = 0;
+  // Every observation of a segment has the same obs_i (each time point
+  // belongs to one sample, as in the unaligned setting): the implicit-form
+  // tiles then read A once per segment.
+  bool owner = false;
 };
 constexpr int kSegPerWave = 32;  // segments per wave in the short-segment form
 constexpr int kShortSegment = 32;  // mean observations per segment for that form

@@ -20,14 +20,14 @@ template <typename TA, int NB, int MW, int S, bool TRANS, int VW>
 __global__ __launch_bounds__(256) void gemm_k4_kernel(GArgs g) {
   if (g.done != nullptr && *g.done) return;
   __shared__ TA xs[tiles::k4_lds_elems<TA, NB, S>()];
-  tiles::gemm_k4_tile<TA, NB, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs);
+  tiles::gemm_k4_tile<TA, NB, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
 }
 
 template <int NB, int MW, int S>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GArgs g) {
   if (g.done != nullptr && *g.done) return;
   __shared__ __attribute__((aligned(16))) __bf16 xs[tiles::bf16_lds_elems<NB, S>()];
-  tiles::gemm_bf16_tile<NB, MW, S>(g, blockIdx.x, blockIdx.y, xs);
+  tiles::gemm_bf16_tile<NB, MW, S>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
 }
 
 // X (n x r, row-major, optionally row-scaled) -> hi/lo bf16, c-major rows of

@@ -79,11 +79,13 @@ constexpr int tile_rows(int mw) { return 4 * mw * 16; }
 
 // ------------------------------------------------- FP64 / FP32 (16x16x4) tile
 // Rows [bx*tile_rows(MW), ...) over k in [by*kper, (by+1)*kper) into partial
-// slab `by`.  VW: elements per vector load of the n x n operand along k (NN
+// slab `by`; tid is the thread index (threadIdx.x, or item_tid() inside a
+// persistent kernel).  VW: elements per vector load of the n x n operand along k (NN
 // form only; requires ldu % VW == 0 and a 16-byte aligned U).  xs: LDS of
 // k4_lds_elems<TA, NB, S>() elements.
 template <typename TA, int NB, int MW, int S, bool TRANS, int VW>
-__device__ __forceinline__ void gemm_k4_tile(const GArgs& g, int64_t bx, int64_t by, TA* xs) {
+__device__ __forceinline__ void gemm_k4_tile(const GArgs& g, int64_t bx, int64_t by, TA* xs,
+                                             int tid) {
   using AccT = typename std::conditional<std::is_same<TA, double>::value, d4, f4>::type;
   typedef TA VecT __attribute__((ext_vector_type(VW)));
   static_assert(S % VW == 0, "S must be a multiple of the vector width");
@@ -94,7 +96,6 @@ __device__ __forceinline__ void gemm_k4_tile(const GArgs& g, int64_t bx, int64_t
   constexpr int XB = BK * LDX;      // LDS elements per buffer
   constexpr int XPT = (XE + 255) / 256;
 
-  const int tid = item_tid();
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, kk = lane >> 4;
   const int64_t n = g.n;
@@ -248,7 +249,7 @@ __device__ __forceinline__ void gemm_k4_tile(const GArgs& g, int64_t bx, int64_t
 // stays at bf16.  Accumulation is FP32.  xs: LDS of bf16_lds_elems<NB, S>().
 template <int NB, int MW, int S>
 __device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64_t by,
-                                               __bf16* xs) {
+                                               __bf16* xs, int tid) {
   constexpr int BK = 32 * S;
   constexpr int NC = NB * 16;
   constexpr int LDK = BK + 8;           // bf16 elements per LDS row (bank spread)
@@ -258,7 +259,6 @@ __device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64
   constexpr int XP = NC * LDK;          // LDS elements per part
   constexpr int XB = 2 * XP;            // LDS elements per buffer (hi, lo)
 
-  const int tid = item_tid();
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, kk = lane >> 4;
   const int64_t n = g.n;

@@ -10,16 +10,16 @@ using tiles::ObsDev;
 using tiles::TaskView;
 using tiles::obs_task;
 
-template <int L, int CPL, bool EXPL, int MODE, typename PT>
+template <int L, int CPL, int FORM, int MODE, typename PT>
 __global__ __launch_bounds__(256) void obs_kernel(TaskView t, ObsDev d) {
   if (d.a.done != nullptr && *d.a.done) return;
   const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= t.ntask) return;
-  obs_task<L, CPL, EXPL, MODE, PT>(t, d, task);
+  obs_task<L, CPL, FORM, MODE, PT>(t, d, task, threadIdx.x & 63);
 }
 
 // Short segments: wave w takes segments [w kSegPerWave, ...), 64/L at a time.
-template <int L, int CPL, bool EXPL, int MODE, typename PT>
+template <int L, int CPL, int FORM, int MODE, typename PT>
 __global__ __launch_bounds__(256) void obs_rows_kernel(ObsDev d, const int32_t* obs_ptr,
                                                        int64_t n) {
   if (d.a.done != nullptr && *d.a.done) return;
@@ -28,7 +28,8 @@ __global__ __launch_bounds__(256) void obs_rows_kernel(ObsDev d, const int32_t* 
   for (int k = 0; k < kSegPerWave; k += ROWS) {
     const int64_t s0 = sb + k;
     if (s0 >= n) break;
-    tiles::obs_rows<L, CPL, EXPL, MODE, PT>(d, obs_ptr, s0, (int)min((int64_t)ROWS, n - s0));
+    tiles::obs_rows<L, CPL, FORM, MODE, PT>(d, obs_ptr, s0, (int)min((int64_t)ROWS, n - s0),
+                                            threadIdx.x & 63);
   }
 }
 
@@ -46,16 +47,16 @@ __global__ void segment_reduce_kernel(const int32_t* __restrict__ mseg,
   out[(int64_t)mseg[m] * r + lane] = acc;
 }
 
-template <int L, int CPL, bool EXPL, int MODE>
+template <int L, int CPL, int FORM, int MODE>
 int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hipStream_t st) {
   if (t.rows) {
     const int64_t blocks = (t.nseg + 4 * kSegPerWave - 1) / (4 * kSegPerWave);
     if (blocks == 0) return CPHIFI_OK;
     if (pf)
-      hipLaunchKernelGGL((obs_rows_kernel<L, CPL, EXPL, MODE, float>), dim3((unsigned)blocks),
+      hipLaunchKernelGGL((obs_rows_kernel<L, CPL, FORM, MODE, float>), dim3((unsigned)blocks),
                          dim3(256), 0, st, d, t.obs_ptr, t.nseg);
     else
-      hipLaunchKernelGGL((obs_rows_kernel<L, CPL, EXPL, MODE, double>), dim3((unsigned)blocks),
+      hipLaunchKernelGGL((obs_rows_kernel<L, CPL, FORM, MODE, double>), dim3((unsigned)blocks),
                          dim3(256), 0, st, d, t.obs_ptr, t.nseg);
     CPHIFI_CHECK_LAUNCH();
     return CPHIFI_OK;
@@ -63,10 +64,10 @@ int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hi
   const int blocks = (tv.ntask + 3) / 4;
   if (blocks == 0) return CPHIFI_OK;
   if (pf)
-    hipLaunchKernelGGL((obs_kernel<L, CPL, EXPL, MODE, float>), dim3(blocks), dim3(256), 0, st, tv,
+    hipLaunchKernelGGL((obs_kernel<L, CPL, FORM, MODE, float>), dim3(blocks), dim3(256), 0, st, tv,
                        d);
   else
-    hipLaunchKernelGGL((obs_kernel<L, CPL, EXPL, MODE, double>), dim3(blocks), dim3(256), 0, st,
+    hipLaunchKernelGGL((obs_kernel<L, CPL, FORM, MODE, double>), dim3(blocks), dim3(256), 0, st,
                        tv, d);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
@@ -74,19 +75,19 @@ int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hi
 
 // Lanes per observation: L = 4 up to r = 20, 8 up to r = 40, 16 beyond; each
 // lane then holds ceil(r / L) <= 5 columns.
-template <bool EXPL, int MODE>
+template <int FORM, int MODE>
 int launch_m(int r, bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t,
              hipStream_t st) {
-  if (r <= 4) return launch_c<4, 1, EXPL, MODE>(pf, tv, d, t, st);
-  if (r <= 8) return launch_c<4, 2, EXPL, MODE>(pf, tv, d, t, st);
-  if (r <= 12) return launch_c<4, 3, EXPL, MODE>(pf, tv, d, t, st);
-  if (r <= 16) return launch_c<4, 4, EXPL, MODE>(pf, tv, d, t, st);
-  if (r <= 20) return launch_c<4, 5, EXPL, MODE>(pf, tv, d, t, st);
-  if (r <= 24) return launch_c<8, 3, EXPL, MODE>(pf, tv, d, t, st);
-  if (r <= 32) return launch_c<8, 4, EXPL, MODE>(pf, tv, d, t, st);
-  if (r <= 40) return launch_c<8, 5, EXPL, MODE>(pf, tv, d, t, st);
-  if (r <= 48) return launch_c<16, 3, EXPL, MODE>(pf, tv, d, t, st);
-  return launch_c<16, 4, EXPL, MODE>(pf, tv, d, t, st);
+  if (r <= 4) return launch_c<4, 1, FORM, MODE>(pf, tv, d, t, st);
+  if (r <= 8) return launch_c<4, 2, FORM, MODE>(pf, tv, d, t, st);
+  if (r <= 12) return launch_c<4, 3, FORM, MODE>(pf, tv, d, t, st);
+  if (r <= 16) return launch_c<4, 4, FORM, MODE>(pf, tv, d, t, st);
+  if (r <= 20) return launch_c<4, 5, FORM, MODE>(pf, tv, d, t, st);
+  if (r <= 24) return launch_c<8, 3, FORM, MODE>(pf, tv, d, t, st);
+  if (r <= 32) return launch_c<8, 4, FORM, MODE>(pf, tv, d, t, st);
+  if (r <= 40) return launch_c<8, 5, FORM, MODE>(pf, tv, d, t, st);
+  if (r <= 48) return launch_c<16, 3, FORM, MODE>(pf, tv, d, t, st);
+  return launch_c<16, 4, FORM, MODE>(pf, tv, d, t, st);
 }
 
 }  // namespace
@@ -113,12 +114,18 @@ int launch_obs(ObsMode mode, bool part_is_float, const ObsTasks& t, const ObsArg
     set_error("launch_obs: the short-segment form needs the CSR and no split segments");
     return CPHIFI_INVALID_ARG;
   }
+  using tiles::kExplicit;
+  using tiles::kImplicit;
+  using tiles::kOwner;
+  const bool own = !expl && t.owner;
   if (mode == ObsMode::Gather)
-    st_ = expl ? launch_m<true, 0>(a.r, part_is_float, tv, d, t, st)
-               : launch_m<false, 0>(a.r, part_is_float, tv, d, t, st);
+    st_ = expl  ? launch_m<kExplicit, 0>(a.r, part_is_float, tv, d, t, st)
+          : own ? launch_m<kOwner, 0>(a.r, part_is_float, tv, d, t, st)
+                : launch_m<kImplicit, 0>(a.r, part_is_float, tv, d, t, st);
   else
-    st_ = expl ? launch_m<true, 1>(a.r, part_is_float, tv, d, t, st)
-               : launch_m<false, 1>(a.r, part_is_float, tv, d, t, st);
+    st_ = expl  ? launch_m<kExplicit, 1>(a.r, part_is_float, tv, d, t, st)
+          : own ? launch_m<kOwner, 1>(a.r, part_is_float, tv, d, t, st)
+                : launch_m<kImplicit, 1>(a.r, part_is_float, tv, d, t, st);
   if (st_ != CPHIFI_OK) return st_;
   if (!t.rows && t.nmulti > 0) {
     hipLaunchKernelGGL(segment_reduce_kernel, dim3((t.nmulti + 3) / 4), dim3(256), 0, st, t.mseg,

@@ -635,19 +635,32 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
       set_error("obs_ptr decreases at %lld", (long long)s);
       return CPHIFI_INVALID_ARG;
     }
-  if ((d->flags & CPHIFI_FLAG_VALIDATE) && !expl && q > 0) {
-    std::vector<int32_t> oi(q), oj(q);
+  bool owner = false;
+  if (!expl && q > 0) {
+    std::vector<int32_t> oi(q);
     CPHIFI_HIP(hipMemcpyAsync(oi.data(), in->obs_i, sizeof(int32_t) * q, hipMemcpyDeviceToHost,
                               st));
-    CPHIFI_HIP(hipMemcpyAsync(oj.data(), in->obs_j, sizeof(int32_t) * q, hipMemcpyDeviceToHost,
-                              st));
     CPHIFI_HIP(hipStreamSynchronize(st));
-    for (int64_t l = 0; l < q; ++l)
-      if (oi[l] < 0 || oi[l] >= d->I || oj[l] < 0 || oj[l] >= d->J) {
-        set_error("observation %lld has index (%d, %d) outside I=%lld, J=%lld", (long long)l,
-                  oi[l], oj[l], (long long)d->I, (long long)d->J);
-        return CPHIFI_INVALID_ARG;
-      }
+    if (d->flags & CPHIFI_FLAG_VALIDATE) {
+      std::vector<int32_t> oj(q);
+      CPHIFI_HIP(hipMemcpyAsync(oj.data(), in->obs_j, sizeof(int32_t) * q,
+                                hipMemcpyDeviceToHost, st));
+      CPHIFI_HIP(hipStreamSynchronize(st));
+      for (int64_t l = 0; l < q; ++l)
+        if (oi[l] < 0 || oi[l] >= d->I || oj[l] < 0 || oj[l] >= d->J) {
+          set_error("observation %lld has index (%d, %d) outside I=%lld, J=%lld", (long long)l,
+                    oi[l], oj[l], (long long)d->I, (long long)d->J);
+          return CPHIFI_INVALID_ARG;
+        }
+    }
+    // one sample per time point (the unaligned setting)?
+    owner = true;
+    for (int64_t s = 0; s < n && owner; ++s)
+      for (int32_t l = ptr[s] + 1; l < ptr[s + 1]; ++l)
+        if (oi[l] != oi[ptr[s]]) {
+          owner = false;
+          break;
+        }
   }
   std::vector<int32_t> tseg, tbeg, tend, tslot, tfirst, mseg, mptr, rowm(n, -1);
   int32_t nslot = 0;
@@ -738,6 +751,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   p->tasks.rows = mseg.empty() && q <= kShortSegment * n;
   p->tasks.obs_ptr = in->obs_ptr;
   p->tasks.nseg = n;
+  p->tasks.owner = owner;
   p->rowm = (int32_t*)(ws + L.rowm);
 
   auto fail = [&](int code) {
