@@ -4,27 +4,32 @@
 // graph.
 //
 // Method per member (the same as cphifi_ui_solve at MIXED_BF16): FP64 iterative
-// refinement on (F^T F + lambda I kron K + rho I) w = b, whose corrections come
-// from inner PCG solves in the eigenbasis of K (x = U_K xbar, the rotation of
-// Section 3.3) with the BF16-rounded eigenvectors, and the r x r middle step of
-// eq. (fx) as preconditioner.  The residual and both rotations use FP64 K and
-// U_K.
+// refinement of (F^T F + lambda I kron K + rho I) w = b carried out in the
+// eigenbasis of K (w = U_K xbar, the rotation of Section 3.3): the FP64
+// residual of the rotated system rbar = U^T b - Abar xbar, inner PCG solves of
+// Abar_lp dbar = rbar with the BF16-rounded eigenvectors and the r x r middle
+// step of eq. (fx) as preconditioner, xbar += dbar; at the end W = U xbar and
+// its FP64 residual in the original form certifies it.
 //
 // Execution model.  Each member runs a small state machine (mode):
-//   INIT -> ROT_IN -> INNER ... INNER -> ROT_OUT -> RES -> ROT_IN -> ... -> DONE
+//   INIT -> ROT_B [-> ROT_W] -> RES0 -> INNER ... INNER -> RES -> INNER ...
+//        -> RES -> FINAL -> CERT -> DONE   (or back to RES if CERT misses tol)
 // and the kernel advances every member by one step per *round*.  A round has
 // eight phases; in each phase every active member contributes work items
 // according to its mode:
 //
-//   phase   INNER (one PCG iteration)         RES (FP64 residual)  ROT_IN / ROT_OUT / INIT
-//   A       BF16 U (D_K p)          product   FP64 K w             FP64 U^T rf / U xbar / -
-//   OBS     gather-dot-scatter (eqs. vl, yhat1, both forms)        -
-//   ROWS    split segments + hi/lo BF16 split of Yhat1             -
-//   B       BF16 U^T Yhat1          product   FP64 K Yhat1         -
-//   FIN     q = D_K(Y + lambda p) + rho p     rf = b - A w         rbar = U^T rf / w += U xbar / rf = b
-//   UPD     alpha; x, r update                -                    -
-//   PREC    z = ((r U_V) had D) U_V^T         -                    (ROT_IN) z
-//   CTRL    beta; p update + split; state     relres test; state   state
+//   phase  INNER (one PCG iteration)     RES (rotated FP64 residual)   CERT (FP64 residual of W)
+//   A      BF16 U (D_K p)                FP64 U (D_K xbar)             FP64 K W
+//   OBS    gather-dot-scatter (eqs. vl, yhat1)                         (with Xhat)
+//   ROWS   split segments + hi/lo BF16 split of Yhat1; elsewhere split segments only
+//   B      BF16 U^T Yhat1                FP64 U^T Yhat1                FP64 K Yhat1
+//   FIN    q = D_K(Y + lambda p) + rho p rbar = bbar - Abar xbar       rf = b - A W
+//   UPD    alpha; dbar, r update         -                             -
+//   PREC   z = ((r U_V) had D) U_V^T     z (when refining on)          -
+//   CTRL   beta; p update + split;       relres test; p = z + split    certificate test
+//          at the stop xbar += dbar
+// ROT_B / ROT_W (U^T b, U^T W0 for a warm start) and FINAL (W = U xbar) use
+// phases A and FIN; INIT (||b||) and RES0 (rbar = bbar) have no products.
 //
 // Work items of a phase (product tiles, wave tasks of the gather, row chunks
 // of the vector steps) are handed out by an atomic counter; phases are
@@ -71,7 +76,17 @@ static_assert(tiles::k4_lds_elems<double, 3, 4>() * 8 <= kSmemBytes, "f64 T tile
 static_assert((kBatchRank * kBatchRank + 4 * kWave) * 8 <= kSmemBytes, "preconditioner LDS");
 static_assert(2 * kBatchRank * kRC * 2 <= kSmemBytes, "split transpose LDS");
 
-enum : int32_t { M_INIT = 0, M_RES = 1, M_ROT_IN = 2, M_INNER = 3, M_ROT_OUT = 4, M_DONE = 5 };
+enum : int32_t {
+  M_INIT = 0,   // ||b||^2; W = 0 unless warm
+  M_ROT_B = 1,  // bbar = U^T b
+  M_ROT_W = 2,  // xbar = U^T W (warm start)
+  M_RES0 = 3,   // rbar = bbar (xbar = 0)
+  M_RES = 4,    // rbar = bbar - Abar xbar (FP64)
+  M_INNER = 5,  // one inner PCG iteration
+  M_FINAL = 6,  // W = U xbar
+  M_CERT = 7,   // FP64 residual of W
+  M_DONE = 8
+};
 enum : int { S_A = 0, S_OBS = 1, S_ROWS = 2, S_B = 3, S_FIN = 4, S_UPD = 5, S_PREC = 6, S_CTRL = 7 };
 
 // Constants of one member (device copy; never written by the kernel).
@@ -96,6 +111,7 @@ struct BSub {
   const __bf16 *ulp, *utlp;
   __bf16 *xthi, *xtlo;
   double *X, *R, *Z, *P, *Q, *XH, *Y1, *RF;
+  double *BB, *XA;  // bbar = U^T b, accumulated xbar
   double *red0, *red1, *red2;
   int32_t bf_mw, bf_ks, bf_nrb, fn_ks, fn_nrb, fn_vw, ft_mw, ft_ks, ft_nrb, pad0;
   int64_t bf_kper, fn_kper, ft_kper;
@@ -154,6 +170,8 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
   s.XH = global_word<decltype(s.XH)>(w[offsetof(BSub, XH) / 8]);
   s.Y1 = global_word<decltype(s.Y1)>(w[offsetof(BSub, Y1) / 8]);
   s.RF = global_word<decltype(s.RF)>(w[offsetof(BSub, RF) / 8]);
+  s.BB = global_word<decltype(s.BB)>(w[offsetof(BSub, BB) / 8]);
+  s.XA = global_word<decltype(s.XA)>(w[offsetof(BSub, XA) / 8]);
   s.red0 = global_word<decltype(s.red0)>(w[offsetof(BSub, red0) / 8]);
   s.red1 = global_word<decltype(s.red1)>(w[offsetof(BSub, red1) / 8]);
   s.red2 = global_word<decltype(s.red2)>(w[offsetof(BSub, red2) / 8]);
@@ -162,8 +180,8 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
 
 // Mutable scalars of one member.
 struct BState {
-  int32_t mode, k, it, total_inner, status, pad;
-  double bb, rel, tol2, rz[2];
+  int32_t mode, k, it, total_inner, status, force;  // force: refine although rel <= tol
+  double bb, bbar, rel, cert, tol2, rz[2];           // ||b||^2, ||bbar||^2, relres, ...
 };
 
 // Batch-wide control words.
@@ -249,25 +267,34 @@ __device__ __forceinline__ void store_split(const BSub& S, int64_t s0, int rows,
 // ------------------------------------------------------------- work counts
 __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
   const int fn = S.fn_nrb * S.fn_ks, ft = S.ft_nrb * S.ft_ks, bf = S.bf_nrb * S.bf_ks;
+  const int rows = (S.nmulti > 0 && !S.orow) ? S.nrc : 0;  // split segments to add
   switch (mode) {
     case M_INIT:
       return slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
+    case M_ROT_B:
+    case M_ROT_W:
+      return slot == S_A ? fn : slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
+    case M_FINAL:
+      return slot == S_A ? ft : slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
+    case M_RES0:
+      return (slot == S_FIN || slot == S_PREC || slot == S_CTRL) ? S.nrc : 0;
     case M_RES:
+      switch (slot) {
+        case S_A: return ft;
+        case S_OBS: return S.ntaskw;
+        case S_ROWS: return rows;
+        case S_B: return fn;
+        case S_UPD: return 0;
+        default: return S.nrc;  // FIN, PREC, CTRL
+      }
+    case M_CERT:
       switch (slot) {
         case S_A:
         case S_B: return fn;
         case S_OBS: return S.ntaskw;
-        case S_ROWS: return S.nmulti > 0 ? S.nrc : 0;
+        case S_ROWS: return rows;
         case S_FIN: return S.nrc;
         case S_CTRL: return 1;
-        default: return 0;
-      }
-    case M_ROT_IN:
-      switch (slot) {
-        case S_A: return fn;
-        case S_FIN:
-        case S_PREC:
-        case S_CTRL: return S.nrc;
         default: return 0;
       }
     case M_INNER:
@@ -277,14 +304,14 @@ __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
         case S_OBS: return S.ntaskw;
         default: return S.nrc;
       }
-    case M_ROT_OUT:
-      return slot == S_A ? ft : slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
   }
   return 0;
 }
 
 // ---------------------------------------------------------------- products
-enum : int { G_BF_U = 0, G_BF_UT = 1, G_K = 2, G_UKN = 3, G_UKT = 4 };
+// Products: BF16 U (D_K p) / U^T Y (inner), FP64 K X, FP64 U^T X (NN on the
+// stored U^T), FP64 U X and U (D_K X) (transposed form).
+enum : int { G_BF_U = 0, G_BF_UT = 1, G_K = 2, G_UKN = 3, G_UKT = 4, G_UKT_D = 5 };
 
 template <int NB>
 __device__ __forceinline__ void gemm_item_nb(const BSub& S, int kind, const double* X, int64_t i, char* smem) {
@@ -307,10 +334,11 @@ __device__ __forceinline__ void gemm_item_nb(const BSub& S, int kind, const doub
       tiles::gemm_bf16_tile<NB, 4, 2>(g, bx, by, (__bf16*)smem, item_tid());
     else
       tiles::gemm_bf16_tile<NB, 2, 2>(g, bx, by, (__bf16*)smem, item_tid());
-  } else if (kind == G_UKT) {
+  } else if (kind == G_UKT || kind == G_UKT_D) {
     g.U = S.UK;
     g.ldu = S.ldk;
     g.kper = S.ft_kper;
+    g.xscale = kind == G_UKT_D ? S.dKc : nullptr;
     const int64_t bx = i % S.ft_nrb, by = i / S.ft_nrb;
     tiles::gemm_k4_tile<double, NB, 2, 4, true, 1>(g, bx, by, (double*)smem, item_tid());
   } else {
@@ -337,7 +365,7 @@ __device__ __forceinline__ void gemm_item(const BSub& S, int kind, const double*
 // Work item i: wave w takes tasks [(4 i + w) kTPW, ...) of the member's list,
 // or, for short segments, segments [(4 i + w) kSegPerWave, ...) by lane rows.
 template <int L, int CPL, int FORM, typename PT>
-__device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, bool res) {
+__device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, int mode) {
   const int64_t wv = 4 * i + (item_tid() >> 6);
   const int64_t t0 = wv * kTPW;
   const int64_t t1 = min((int64_t)S.ntask, t0 + kTPW);
@@ -352,9 +380,10 @@ __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, bool res) {
   d.a.Zhat = nullptr;
   d.a.y = nullptr;
   d.a.part = S.part;
-  d.a.ksplit = res ? S.fn_ks : S.bf_ks;
+  // split-K depth of the product A that made Xhat
+  d.a.ksplit = mode == M_INNER ? S.bf_ks : mode == M_RES ? S.ft_ks : S.fn_ks;
   d.a.ldp = S.ldp;
-  d.a.Xhat = res ? S.XH : nullptr;
+  d.a.Xhat = mode == M_CERT ? S.XH : nullptr;
   d.a.out = S.Y1;
   d.a.tpart = S.tpart;
   d.a.done = nullptr;
@@ -375,27 +404,28 @@ __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, bool res) {
 }
 
 template <int L, int CPL>
-__device__ __forceinline__ void obs_item_l(const BSub& S, int64_t i, bool res) {
+__device__ __forceinline__ void obs_item_l(const BSub& S, int64_t i, int mode) {
+  const bool f = mode == M_INNER;  // BF16 products leave float partials
   if (S.own) {
-    if (res)
-      obs_item_c<L, CPL, tiles::kOwner, double>(S, i, true);
+    if (f)
+      obs_item_c<L, CPL, tiles::kOwner, float>(S, i, mode);
     else
-      obs_item_c<L, CPL, tiles::kOwner, float>(S, i, false);
+      obs_item_c<L, CPL, tiles::kOwner, double>(S, i, mode);
   } else {
-    if (res)
-      obs_item_c<L, CPL, tiles::kImplicit, double>(S, i, true);
+    if (f)
+      obs_item_c<L, CPL, tiles::kImplicit, float>(S, i, mode);
     else
-      obs_item_c<L, CPL, tiles::kImplicit, float>(S, i, false);
+      obs_item_c<L, CPL, tiles::kImplicit, double>(S, i, mode);
   }
 }
 
-__device__ __forceinline__ void obs_item(const BSub& S, int64_t i, bool res) {
+__device__ __forceinline__ void obs_item(const BSub& S, int64_t i, int mode) {
   switch (S.ocls) {
-    case 0: obs_item_l<4, 2>(S, i, res); break;
-    case 1: obs_item_l<4, 3>(S, i, res); break;
-    case 2: obs_item_l<4, 5>(S, i, res); break;
-    case 3: obs_item_l<8, 5>(S, i, res); break;
-    default: obs_item_l<16, 4>(S, i, res); break;
+    case 0: obs_item_l<4, 2>(S, i, mode); break;
+    case 1: obs_item_l<4, 3>(S, i, mode); break;
+    case 2: obs_item_l<4, 5>(S, i, mode); break;
+    case 3: obs_item_l<8, 5>(S, i, mode); break;
+    default: obs_item_l<16, 4>(S, i, mode); break;
   }
 }
 
@@ -431,12 +461,11 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
   const int r = S.r;
   const int64_t e0 = i * kRC * r, e1 = min(S.n, (i + 1) * kRC) * r;
   double loc = 0.0;
-  double* red = nullptr;
   for (int64_t e = e0 + item_tid(); e < e1; e += blockDim.x) {
     const int64_t s = e / r;
     const int c = (int)(e % r);
     switch (mode) {
-      case M_INNER: {
+      case M_INNER: {  // q = D_K (Y + lambda p) + rho p
         const double y = part_sum<float>(S.part, S.bf_ks, S.n, S.ldp, s, c);
         const double pe = S.P[e];
         const double v = S.dKc[s] * (y + S.lam * pe) + S.rho * pe;
@@ -444,7 +473,24 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
         loc += pe * v;
         break;
       }
-      case M_RES: {
+      case M_RES: {  // rbar = bbar - (D_K (Y + lambda xbar) + rho xbar)
+        const double y = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
+        const double xa = S.XA[e];
+        const double q = S.dKc[s] * (y + S.lam * xa) + S.rho * xa;
+        const double v = S.BB[e] - q;
+        S.R[e] = v;
+        S.X[e] = 0.0;
+        loc += v * v;
+        break;
+      }
+      case M_RES0: {  // rbar = bbar
+        const double v = S.BB[e];
+        S.R[e] = v;
+        S.X[e] = 0.0;
+        loc += v * v;
+        break;
+      }
+      case M_CERT: {  // rf = b - (Y + lambda Xhat + rho W)
         const double y = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
         const double q = y + S.lam * S.XH[e] + S.rho * S.W[e];
         const double v = S.b[e] - q;
@@ -452,29 +498,34 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
         loc += v * v;
         break;
       }
-      case M_ROT_IN: {
+      case M_ROT_B: {  // bbar = U^T b
         const double v = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
-        S.R[e] = v;
-        S.X[e] = 0.0;
+        S.BB[e] = v;
+        if (!S.warm) S.XA[e] = 0.0;
         loc += v * v;
         break;
       }
-      case M_ROT_OUT:
-        S.W[e] += part_sum<double>(S.part, S.ft_ks, S.n, S.ldp, s, c);
+      case M_ROT_W:  // xbar = U^T W
+        S.XA[e] = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
         break;
-      default: {  // M_INIT
+      case M_FINAL:  // W = U xbar
+        S.W[e] = part_sum<double>(S.part, S.ft_ks, S.n, S.ldp, s, c);
+        break;
+      default: {  // M_INIT: ||b||^2
         const double v = S.b[e];
-        S.RF[e] = v;
         if (!S.warm) S.W[e] = 0.0;
         loc += v * v;
         break;
       }
     }
   }
+  double* red = nullptr;
   switch (mode) {
     case M_INNER: red = S.red0; break;
     case M_RES:
-    case M_ROT_IN: red = S.red1; break;
+    case M_RES0:
+    case M_CERT:
+    case M_ROT_B: red = S.red1; break;
     case M_INIT: red = S.red2; break;
     default: break;
   }
@@ -482,6 +533,18 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
     const double t = block_sum(loc, s_red);
     if (item_tid() == 0) red[i] = t;
   }
+}
+
+// Refinement decision after a rotated residual (RES, RES0), identical in every
+// caller: refine on while the residual misses tol (or a certificate asked for
+// one more step) and steps remain.
+__device__ __forceinline__ bool refine_on(const BSub& S, const BState* st, double* s_red,
+                                          double* rel_out) {
+  const double rr = sum_partials(S.red1, S.nrc, s_red);
+  const double bb = st->bbar;
+  const double rel = bb > 0.0 ? sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+  *rel_out = rel;
+  return isfinite(rel) && (rel > S.tol || st->force) && st->k < S.max_refine;
 }
 
 // Inner stopping test of iteration `it`, identical in every caller: p^T A p
@@ -596,8 +659,15 @@ __device__ __forceinline__ void finish_member(BState* st, int32_t mode, int32_t 
   if (mode == M_DONE) st->status = status;
 }
 
-__device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, int it, int64_t i, char* smem,
-                          double* s_red) {
+// xbar += dbar for the chunk's rows (the inner solve's correction).
+__device__ __forceinline__ void accumulate_rows(const BSub& S, int64_t i) {
+  const int r = S.r;
+  const int64_t e0 = i * kRC * r, e1 = min(S.n, (i + 1) * kRC) * r;
+  for (int64_t e = e0 + item_tid(); e < e1; e += blockDim.x) S.XA[e] += S.X[e];
+}
+
+__device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, int it, int64_t i,
+                                          char* smem, double* s_red) {
   const bool lead = i == 0 && item_tid() == 0;
   switch (mode) {
     case M_INNER: {
@@ -612,10 +682,13 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
         }
       }
       if (stop) {
+        if (finite) accumulate_rows(S, i);
         if (lead) {
           st->total_inner += it + 1;
+          st->k += 1;
+          st->force = 0;
           if (finite)
-            finish_member(st, M_ROT_OUT, 0);
+            finish_member(st, M_RES, 0);
           else
             finish_member(st, M_DONE, CPHIFI_NUMERIC);
         }
@@ -628,50 +701,65 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
       }
       return;
     }
-    case M_ROT_IN: {
-      const double bb_in = sum_partials(S.red1, S.nrc, s_red);
-      const double rz0 = sum_partials(S.red2, S.nrc, s_red);
-      const bool ok = bb_in > 0.0 && isfinite(bb_in) && rz0 > 0.0 && isfinite(rz0);
-      if (!ok) {
-        if (lead) {
-          if (isfinite(bb_in) && isfinite(rz0))
-            finish_member(st, M_ROT_OUT, 0);
-          else
-            finish_member(st, M_DONE, CPHIFI_NUMERIC);
-        }
-        return;
+    case M_RES:
+    case M_RES0: {
+      double rel = 0.0;
+      const bool on = refine_on(S, st, s_red, &rel);
+      double rz0 = 0.0;
+      if (on) {
+        rz0 = sum_partials(S.red2, S.nrc, s_red);
+        if (rz0 > 0.0 && isfinite(rz0)) p_rows(S, i, 0.0, smem);
       }
-      p_rows(S, i, 0.0, smem);
       if (lead) {
-        st->tol2 = S.inner_tol2 * bb_in;
-        st->rz[0] = rz0;
-        st->it = 0;
-        finish_member(st, M_INNER, 0);
+        st->rel = rel;
+        if (!isfinite(rel) || (on && !isfinite(rz0))) {
+          finish_member(st, M_DONE, CPHIFI_NUMERIC);
+        } else if (on && rz0 > 0.0) {
+          const double rr = rel * rel * st->bbar;
+          st->tol2 = S.inner_tol2 * rr;
+          st->rz[0] = rz0;
+          st->it = 0;
+          finish_member(st, M_INNER, 0);
+        } else if (on) {
+          finish_member(st, M_DONE, CPHIFI_BREAKDOWN);  // r^T M^{-1} r <= 0
+        } else {
+          finish_member(st, M_FINAL, 0);
+        }
       }
       return;
     }
-    case M_RES: {
+    case M_CERT: {
       const double rr = sum_partials(S.red1, S.nrc, s_red);
       if (lead) {
         const double bb = st->bb;
-        const double rel = bb > 0.0 ? sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
-        st->rel = rel;
-        if (!isfinite(rel))
+        const double cert = bb > 0.0 ? sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+        st->cert = cert;
+        if (!isfinite(cert)) {
           finish_member(st, M_DONE, CPHIFI_NUMERIC);
-        else if (rel <= S.tol)
+        } else if (cert <= S.tol) {
           finish_member(st, M_DONE, CPHIFI_OK);
-        else if (st->k >= S.max_refine)
+        } else if (st->k >= S.max_refine) {
           finish_member(st, M_DONE, CPHIFI_NOT_CONVERGED);
-        else
-          finish_member(st, M_ROT_IN, 0);
+        } else {
+          st->force = 1;  // the rotated residual met tol, the certificate did not
+          finish_member(st, M_RES, 0);
+        }
       }
       return;
     }
-    case M_ROT_OUT:
+    case M_ROT_B: {
+      const double bb = sum_partials(S.red1, S.nrc, s_red);
       if (lead) {
-        st->k += 1;
-        finish_member(st, M_RES, 0);
+        st->bbar = bb;
+        finish_member(st, S.warm ? M_ROT_W : M_RES0, 0);
       }
+      return;
+    }
+    case M_ROT_W:
+      if (lead) finish_member(st, M_RES, 0);
+      return;
+    case M_FINAL:
+      if (lead) finish_member(st, M_CERT, 0);
       return;
     default: {  // M_INIT
       const double bb = sum_partials(S.red2, S.nrc, s_red);
@@ -679,14 +767,11 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
         st->bb = bb;
         if (!isfinite(bb)) {
           finish_member(st, M_DONE, CPHIFI_NUMERIC);
-        } else if (S.warm) {
-          finish_member(st, M_RES, 0);
-        } else if (bb == 0.0) {
-          st->rel = 0.0;  // b = 0: w = 0 is exact
+        } else if (bb == 0.0 && !S.warm) {
+          st->rel = st->cert = 0.0;  // b = 0: w = 0 is exact
           finish_member(st, M_DONE, CPHIFI_OK);
         } else {
-          st->rel = 1.0;
-          finish_member(st, M_ROT_IN, 0);
+          finish_member(st, M_ROT_B, 0);
         }
       }
       return;
@@ -694,24 +779,27 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
   }
 }
 
-__device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, int mode, int it, int64_t i,
-                         char* smem, double* s_red) {
+__device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, int mode, int it,
+                                         int64_t i, char* smem, double* s_red) {
   switch (slot) {
     case S_A:
       switch (mode) {
         case M_INNER: gemm_item(S, G_BF_U, nullptr, i, smem); break;
-        case M_RES: gemm_item(S, G_K, S.W, i, smem); break;
-        case M_ROT_IN: gemm_item(S, G_UKN, S.RF, i, smem); break;
-        case M_ROT_OUT: gemm_item(S, G_UKT, S.X, i, smem); break;
+        case M_RES: gemm_item(S, G_UKT_D, S.XA, i, smem); break;
+        case M_CERT: gemm_item(S, G_K, S.W, i, smem); break;
+        case M_ROT_B: gemm_item(S, G_UKN, S.b, i, smem); break;
+        case M_ROT_W: gemm_item(S, G_UKN, S.W, i, smem); break;
+        case M_FINAL: gemm_item(S, G_UKT, S.XA, i, smem); break;
       }
       break;
-    case S_OBS: obs_item(S, i, mode == M_RES); break;
+    case S_OBS: obs_item(S, i, mode); break;
     case S_ROWS: rows_item(S, i, mode == M_INNER, smem); break;
     case S_B:
-      if (mode == M_INNER)
-        gemm_item(S, G_BF_UT, nullptr, i, smem);
-      else
-        gemm_item(S, G_K, S.Y1, i, smem);
+      switch (mode) {
+        case M_INNER: gemm_item(S, G_BF_UT, nullptr, i, smem); break;
+        case M_RES: gemm_item(S, G_UKN, S.Y1, i, smem); break;
+        default: gemm_item(S, G_K, S.Y1, i, smem); break;  // M_CERT
+      }
       break;
     case S_FIN: fin_item(S, mode, i, s_red); break;
     case S_UPD: upd_item(S, st, it, i, s_red); break;
@@ -719,6 +807,9 @@ __device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, in
       if (mode == M_INNER) {
         bool finite = true;
         if (inner_stop(S, st, it, s_red, &finite)) break;
+      } else {  // M_RES, M_RES0
+        double rel = 0.0;
+        if (!refine_on(S, st, s_red, &rel)) break;
       }
       prec_rows(S, i, smem, s_red);
       break;
@@ -1189,6 +1280,8 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.XH = p->vec[V_XHAT];
     S.Y1 = p->vec[V_Y1];
     S.RF = p->vec[V_RF];
+    S.BB = p->vec[V_T2];
+    S.XA = p->vec[V_TMP];
     S.red0 = p->red[0];
     S.red1 = p->red[1];
     S.red2 = p->red[2];
@@ -1311,7 +1404,7 @@ int cphifi_batch_info(cphifi_batch* bt, cphifi_solve_info* infos) {
     cphifi_solve_info& f = infos[i];
     f.iters = s.total_inner;
     f.refine_steps = s.k;
-    f.relres_true = s.rel;
+    f.relres_true = s.cert;
     f.relres_recursive = s.rel;
     f.gemm_ms = 0.0;
     f.gemm_launches = 0;

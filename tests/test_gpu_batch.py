@@ -160,7 +160,11 @@ def test_batch_warm_start_from_solution(batch):
         for k, info in enumerate(infos):
             assert info.status == C.OK
             assert info.refine_steps == 0 and info.iters == 0
-            assert np.array_equal(host(Ws[k]), batch["W"][k])
+            assert info.relres_true <= TOL
+            # W = U (U^T W0): the start point back, up to the rounding of two
+            # orthogonal FP64 rotations
+            p = probs[k]
+            assert O.e_kw(p.K, host(Ws[k]), batch["W"][k]) <= 1e-12
     finally:
         bs.close()
 

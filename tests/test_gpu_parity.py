@@ -268,6 +268,20 @@ def test_warm_start_from_solution_needs_no_iteration(uploaded):
     assert info2.status == C.OK and info2.iters == 0
 
 
+def test_mixed_warm_start_from_solution_needs_no_correction(uploaded):
+    p, dp = uploaded("r40")
+    s = UISolver(dp, p.lam, p.rho, 1e-8, precision="mixed_bf16")
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK and info.refine_steps > 0
+    s2 = UISolver(dp, p.lam, p.rho, 1e-8, precision="mixed_bf16", flags=C.FLAG_WARM_START)
+    W2, info2 = s2.solve_subproblem(W=W.clone())
+    assert info2.status == C.OK
+    assert info2.iters == 0 and info2.refine_steps == 0
+    assert info2.relres_true <= 1e-8
+    # W = U (U^T W0): the start point back up to the rounding of the rotations
+    assert O.e_kw(p.K, host(W2), host(W)) <= 1e-12
+
+
 def test_iteration_cap_reports_not_converged(uploaded):
     p, dp = uploaded("c1")
     s = UISolver(dp, p.lam, p.rho, 1e-12, maxit=1)
