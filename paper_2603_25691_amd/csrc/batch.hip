@@ -71,7 +71,7 @@ constexpr int kBatchRank = 48;
 constexpr int kSmemBytes = 27648;  // LDS shared by the phases (largest: BF16 tile, NB = 3)
 
 static_assert(tiles::bf16_lds_elems<3, 2>() * 2 <= kSmemBytes, "bf16 tile LDS");
-static_assert(tiles::k4_lds_elems<double, 3, 8>() * 8 <= kSmemBytes, "f64 NN tile LDS");
+static_assert(tiles::k4_lds_elems<double, 3, 4>() * 8 <= kSmemBytes, "f64 NN tile LDS");
 static_assert(tiles::k4_lds_elems<double, 3, 4>() * 8 <= kSmemBytes, "f64 T tile LDS");
 static_assert((kBatchRank * kBatchRank + 4 * kWave) * 8 <= kSmemBytes, "preconditioner LDS");
 static_assert(2 * kBatchRank * kRC * 2 <= kSmemBytes, "split transpose LDS");
@@ -347,9 +347,9 @@ __device__ __forceinline__ void gemm_item_nb(const BSub& S, int kind, const doub
     g.kper = S.fn_kper;
     const int64_t bx = i % S.fn_nrb, by = i / S.fn_nrb;
     if (S.fn_vw == 2)
-      tiles::gemm_k4_tile<double, NB, 2, 8, false, 2>(g, bx, by, (double*)smem, item_tid());
+      tiles::gemm_k4_tile<double, NB, 2, 4, false, 2>(g, bx, by, (double*)smem, item_tid());
     else
-      tiles::gemm_k4_tile<double, NB, 2, 8, false, 1>(g, bx, by, (double*)smem, item_tid());
+      tiles::gemm_k4_tile<double, NB, 2, 4, false, 1>(g, bx, by, (double*)smem, item_tid());
   }
 }
 
@@ -1054,7 +1054,7 @@ void batch_tile(const char* table, Elt elt, bool trans, int64_t n, int r, int* m
     bk = gemm_bk(Elt::F64, 4);
   } else {
     *mw = 2;
-    bk = gemm_bk(Elt::F64, 8);
+    bk = gemm_bk(Elt::F64, 4);
   }
   int64_t want = hit && tks > 0 ? tks : (n + 2047) / 2048;
   want = std::max<int64_t>(1, std::min<int64_t>(want, kMaxSplit));

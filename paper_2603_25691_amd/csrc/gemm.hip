@@ -16,15 +16,18 @@ namespace {
 
 using tiles::GArgs;
 
+// Two workgroups per CU (occupancy target of the register allocator).
 template <typename TA, int NB, int MW, int S, bool TRANS, int VW>
-__global__ __launch_bounds__(256) void gemm_k4_kernel(GArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_k4_kernel(
+    GArgs g) {
   if (g.done != nullptr && *g.done) return;
   __shared__ TA xs[tiles::k4_lds_elems<TA, NB, S>()];
   tiles::gemm_k4_tile<TA, NB, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
 }
 
 template <int NB, int MW, int S>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_kernel(
+    GArgs g) {
   if (g.done != nullptr && *g.done) return;
   __shared__ __attribute__((aligned(16))) __bf16 xs[tiles::bf16_lds_elems<NB, S>()];
   tiles::gemm_bf16_tile<NB, MW, S>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
@@ -285,12 +288,14 @@ GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu) {
   int mw = 0, s = 0, ks = 0;
   if (table_tile(elt, trans && elt != Elt::BF16, n, r, &mw, &s, &ks))
     return make_gemm_plan(elt, trans && elt != Elt::BF16, n, r, mw, s, ks, num_cu);
+  // (tiles that fit two workgroups per CU without spilling at this r)
+  const bool nb4 = r > 48;
   switch (elt) {
     case Elt::BF16: return make_gemm_plan(elt, false, n, r, 4, 2, 0, num_cu);
     case Elt::F32: return trans ? make_gemm_plan(elt, true, n, r, 4, 4, 0, num_cu)
                                 : make_gemm_plan(elt, false, n, r, 2, 4, 0, num_cu);
-    case Elt::F64: return trans ? make_gemm_plan(elt, true, n, r, 4, 4, 0, num_cu)
-                                : make_gemm_plan(elt, false, n, r, 2, 8, 0, num_cu);
+    case Elt::F64: return trans ? make_gemm_plan(elt, true, n, r, 2, 4, 0, num_cu)
+                                : make_gemm_plan(elt, false, n, r, nb4 ? 2 : 4, 4, 0, num_cu);
   }
   return make_gemm_plan(elt, trans, n, r, 2, 8, 0, num_cu);
 }

@@ -210,23 +210,54 @@ __device__ __forceinline__ void gemm_k4_tile(const GArgs& g, int64_t bx, int64_t
       loadA(dst, k0);
   };
 
+  // Chunk loop unrolled twice with ping-pong operand registers a0 / a1: the
+  // next chunk's loads go to the other set, so they stay in flight across
+  // this chunk's MFMAs (a register copy would let the compiler sink them).
+  // The steady state prefetches unconditionally (no branch for the waitcnt
+  // insertion to merge conservatively) and runs only while both chunks it
+  // prefetches are full ones; the remaining chunks, the k tail among them,
+  // go through the general fetch.
+  auto fetch_full = [&](TA (&xr)[XPT], TA (&dst)[MW][S], int64_t c) {
+    const int64_t k0 = kbeg + c * BK;
+    stageX(xr, k0, false);
+    loadA(dst, k0);
+  };
   if (nchunk > 0) {
-    TA acur[MW][S], anext[MW][S];
+    TA a0[MW][S], a1[MW][S];
     TA xr[XPT];
-    fetch(xr, acur, 0);
+    fetch(xr, a0, 0);
     storeX(0, xr);
     __syncthreads();
-    for (int64_t c = 0; c < nchunk; ++c) {
-      const int buf = (int)(c & 1);
-      const bool more = c + 1 < nchunk;
-      if (more) fetch(xr, anext, c + 1);
-      compute(acur, buf);
-      if (more) storeX(buf ^ 1, xr);
+    int64_t c = 0;
+    while (c + 2 < nfull) {  // chunks c + 1 and c + 2 are full ones
+      fetch_full(xr, a1, c + 1);
+      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+      compute(a0, (int)(c & 1));
+      storeX((int)((c + 1) & 1), xr);
       __syncthreads();
-#pragma unroll
-      for (int mb = 0; mb < MW; ++mb)
-#pragma unroll
-        for (int q = 0; q < S; ++q) acur[mb][q] = anext[mb][q];
+      ++c;
+      fetch_full(xr, a0, c + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, (int)(c & 1));
+      storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      ++c;
+    }
+    for (;;) {  // at most three chunks left; a0 holds chunk c
+      bool more = c + 1 < nchunk;
+      if (more) fetch(xr, a1, c + 1);
+      compute(a0, (int)(c & 1));
+      if (more) storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      if (!more) break;
+      ++c;
+      more = c + 1 < nchunk;
+      if (more) fetch(xr, a0, c + 1);
+      compute(a1, (int)(c & 1));
+      if (more) storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      if (!more) break;
+      ++c;
     }
   }
 
@@ -329,29 +360,45 @@ __device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64
     }
   };
 
+  // X rows of the next chunk are fetched before its U rows: vmcnt retires in
+  // order, so filling LDS does not wait for the larger U prefetch.  The chunk
+  // loop is unrolled twice with ping-pong U registers a0 / a1, so the next
+  // chunk's loads stay in flight across this chunk's MFMAs; the steady state
+  // prefetches unconditionally and the last one or two chunks are peeled.
+  auto fetch = [&](u32x4 (&xr)[2][XPT], u32x4 (&dst)[MW][S], int64_t c) {
+    stageX(xr, kbeg + c * BK);
+    loadA(dst, kbeg + c * BK);
+  };
   if (nchunk > 0) {
-    // X rows of the next chunk are fetched before its U rows: vmcnt retires in
-    // order, so filling LDS does not wait for the larger U prefetch.
-    u32x4 acur[MW][S], anext[MW][S];
+    u32x4 a0[MW][S], a1[MW][S];
     u32x4 xr[2][XPT];
-    stageX(xr, kbeg);
-    loadA(acur, kbeg);
+    fetch(xr, a0, 0);
     storeX(0, xr);
     __syncthreads();
-    for (int64_t c = 0; c < nchunk; ++c) {
-      const int buf = (int)(c & 1);
-      const bool more = c + 1 < nchunk;
-      if (more) {
-        stageX(xr, kbeg + (c + 1) * BK);
-        loadA(anext, kbeg + (c + 1) * BK);
-      }
-      compute(acur, buf);
-      if (more) storeX(buf ^ 1, xr);
+    int64_t c = 0;
+    while (c + 2 < nchunk) {
+      fetch(xr, a1, c + 1);
+      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+      compute(a0, (int)(c & 1));
+      storeX((int)((c + 1) & 1), xr);
       __syncthreads();
-#pragma unroll
-      for (int mb = 0; mb < MW; ++mb)
-#pragma unroll
-        for (int q = 0; q < S; ++q) acur[mb][q] = anext[mb][q];
+      ++c;
+      fetch(xr, a0, c + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, (int)(c & 1));
+      storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      ++c;
+    }
+    if (c + 1 < nchunk) {
+      fetch(xr, a1, c + 1);
+      compute(a0, (int)(c & 1));
+      storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      ++c;
+      compute(a1, (int)(c & 1));
+    } else {
+      compute(a0, (int)(c & 1));
     }
   }
 

@@ -291,8 +291,13 @@ def product(U: torch.Tensor, X: torch.Tensor, elt: str = "fp64", trans: bool = F
     e = {"fp64": _c.ELT_F64, "fp32": _c.ELT_F32, "bf16": _c.ELT_BF16}[elt]
     n, r = X.shape
     mw, s = tile
-    if mw == 0:
-        mw, s = (2, 4) if e == _c.ELT_BF16 else (2, 8)
+    if mw == 0:  # the solver's default tiles
+        if e == _c.ELT_BF16:
+            mw, s = 4, 2
+        elif trans:
+            mw, s = 4, 4
+        else:
+            mw, s = (2, 8) if e == _c.ELT_F64 else (2, 4)
     ws_bytes = _c.cphifi_product_workspace_bytes(n, r, e)
     if workspace is None or workspace.numel() < ws_bytes + 256:
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=X.device)
