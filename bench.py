@@ -34,6 +34,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 
+# HBM bytes per launch of the dominant kernel at the default workload, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled by a calibration copy
+# (profiles/products_n30658_r40_hbm_counters.md).  Keyed by kernel and shape;
+# clear an entry whenever that kernel changes.
+MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2>", 30658, 40): 1.9963e9}
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -282,7 +288,7 @@ def main():
               "peak": HBM_PEAK_GBPS, "unit": "GB/s"}
     roof64["frac"] = roof64["achieved"] / roof64["peak"]
     roof64["traffic"] = None
-    roof64["kernel"] = "gemm_k4_kernel<double, NB=3, NN> (K X and U_K^T R products)"
+    roof64["kernel"] = "gemm_k4_kernel<double, 3, 4, 4, false, 2> (K X and U_K^T R products)"
 
     # --------------------------------------------------- headline (mixed) form
     prec = a.precision
@@ -328,7 +334,7 @@ def main():
 
     if prec == "mixed_bf16":
         lp_bytes = 2 * n * n + 16 * n * r
-        kname = "gemm_bf16_kernel<NB=3> (U_K-rounded products of the inner solve)"
+        kname = "gemm_bf16_kernel<3, 4, 2> (U_K-rounded products of the inner solve)"
     elif prec == "mixed_fp32":
         lp_bytes = 4 * n * n + 16 * n * r
         kname = "gemm_k4_kernel<float, NB=3, NN> (U_K-rounded products of the inner solve)"
@@ -339,7 +345,7 @@ def main():
     roof = {"bound": "hbm", "achieved": lp_bytes / (avg_ms * 1e6), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = MEASURED_TRAFFIC.get((kname.split(" (")[0], n, r))
     roof["kernel"] = kname
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_solve"] = g_n / a.steps

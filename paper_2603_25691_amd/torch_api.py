@@ -294,10 +294,10 @@ def product(U: torch.Tensor, X: torch.Tensor, elt: str = "fp64", trans: bool = F
     if mw == 0:  # the solver's default tiles
         if e == _c.ELT_BF16:
             mw, s = 4, 2
-        elif trans:
-            mw, s = 4, 4
+        elif e == _c.ELT_F64:
+            mw, s = (2, 4) if trans or r > 48 else (4, 4)
         else:
-            mw, s = (2, 8) if e == _c.ELT_F64 else (2, 4)
+            mw, s = (4, 4) if trans else (2, 4)
     ws_bytes = _c.cphifi_product_workspace_bytes(n, r, e)
     if workspace is None or workspace.numel() < ws_bytes + 256:
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=X.device)
