@@ -38,6 +38,9 @@ HBM_PEAK_GBPS = 8000.0
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled by a calibration copy
 # (profiles/products_n30658_r40_hbm_counters.md).  Keyed by kernel and shape;
 # clear an entry whenever that kernel changes.
+# Tiles of the batched solver written by `python -m paper_2603_25691_amd.tune batch`
+# on MI355X (the defaults apply when the file is absent).
+BATCH_TILES = os.path.join(ROOT, "paper_2603_25691_amd", "tiles_batch_mi355x.txt")
 MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2>", 30658, 40): 1.9963e9}
 
 
@@ -87,7 +90,8 @@ def bench_batch(a, torch, C):
         f" r {sorted(set(rs.tolist()))}; generated, uploaded, eig(K) in {time.time() - t0:.1f} s")
     tol = 1e-7
     t0 = time.time()
-    bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], tol)
+    table = BATCH_TILES if os.path.exists(BATCH_TILES) else None
+    bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], tol, tile_table=table)
     rhs = bs.rhs()
     Ws = [torch.empty_like(b) for b in rhs]
     bs.bind(rhs, Ws)
@@ -134,12 +138,14 @@ def bench_batch(a, torch, C):
         KW = p.K @ Wdh
         ekw.append(float(np.linalg.norm(p.K @ Wh - KW) / np.linalg.norm(KW)))
     # algorithmic bytes of the n x n passes of one batched solve: per inner
-    # iteration 2 BF16 passes; per refinement step 2 FP64 passes of K (the
-    # residual) and 2 of U_K (rotations in and out); plus the final residual.
+    # iteration 2 BF16 passes over U_K; per refinement step the FP64 residual
+    # in the eigenbasis (2 passes over U_K); once per solve the rotation of b
+    # into the eigenbasis and of the solution out of it (2 passes over U_K) and
+    # the FP64 certificate (2 passes over K).
     byts = 0.0
     for p, inf in zip(probs, infos):
         n2 = float(p.n) ** 2
-        byts += inf.iters * 2 * 2 * n2 + inf.refine_steps * 4 * 8 * n2 + 2 * 8 * n2
+        byts += inf.iters * 2 * 2 * n2 + (2 * inf.refine_steps + 4) * 8 * n2
     gbps = byts / (ms_batch * 1e6)
     for s_ in solvers:
         s_.close()
@@ -148,6 +154,7 @@ def bench_batch(a, torch, C):
                      "RBF sigma_b~U[0.05,0.2), J_b=20, I_b=ceil(n_b/30), lambda=1e-4, "
                      "rho=1e-6, seed=0"),
         "members": len(probs), "sum_n2": float(np.sum(ns ** 2.0)),
+        "tile_table": os.path.basename(table) if table else "defaults",
         "ms_per_batch": ms_batch, "solves_per_s": len(probs) * 1e3 / ms_batch,
         "status": C.status_string(status), "rounds": rounds, "grid": grid,
         "phase_ms": phase,

@@ -164,10 +164,12 @@ int launch_obs(ObsMode mode, bool part_is_float, const ObsTasks& t, const ObsArg
 // partial per block into `red` (grid <= kMaxVecBlocks), and every consumer
 // sums those partials in the same fixed order.
 int vec_blocks(int64_t len);
-// out[s][c] = sum_sp part[sp][s][c]; with dotwith: red[blk] = sum dotwith . out
+// out[s][c] = rowscale[s] * sum_sp part[sp][s][c] (rowscale NULL: 1); with
+// dotwith: red[blk] = sum dotwith . out
 int launch_reduce_partials(const void* part, bool is_float, int ksplit, int ldp, int64_t n,
                            int r, double* out, const double* dotwith, double* red,
-                           int* nblk_out, const int32_t* done, hipStream_t st);
+                           int* nblk_out, const int32_t* done, hipStream_t st,
+                           const double* rowscale = nullptr);
 // q = Y + lam*xhat + rho*p (paper form), or q = d*(Y + lam*p) + rho*p when dscale
 // is given (eigenbasis form), Y = sum of partials; red[blk] = sum p . q.
 int launch_apply_finish(const void* part, bool is_float, int ksplit, int ldp, int64_t n,
@@ -180,7 +182,7 @@ int launch_update_xr(double* x, double* r, const double* p, const double* q, int
                      const double* red_pq, int nblk_pq, double* red_rr, int* nblk_out,
                      DevScalars* sc, int it, hipStream_t st);
 int launch_check_conv(const double* red_rr, int nblk, DevScalars* sc, int it, double* hist,
-                      int hist_len, hipStream_t st);
+                      int hist_len, int32_t* flag, hipStream_t st);
 // out[s,:] = ((in[s,:] U_V) * D[s,:]) U_V^T with in = sum of partials when part is
 // given; with dotwith: red[blk] = sum dotwith . out.
 int launch_prec_mid(const void* part, bool is_float, int ksplit, int ldp, const double* in,
@@ -193,6 +195,8 @@ int launch_pcg_init(DevScalars* sc, const double* red_bb, int nblk_bb, const dou
                     int nblk_rr, const double* red_rz, int nblk_rz, double tol, double* hist,
                     int hist_len, hipStream_t st);
 // sc->scratch[slot] = sum of partials (single block)
+// *dst <- *src by a kernel (dst: host-mapped memory; no copy engine involved).
+int launch_mirror(const DevScalars* src, DevScalars* dst, hipStream_t st);
 int launch_store_sum(const double* red, int nblk, DevScalars* sc, int slot, hipStream_t st);
 int launch_axpby(double* y, double a, const double* x, double b, int64_t len,
                  const int32_t* done, hipStream_t st);

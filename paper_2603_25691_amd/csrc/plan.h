@@ -44,6 +44,9 @@ Layout make_layout(const cphifi_ui_desc& d);
 
 using namespace cphifi;  // the plan is a global type behind the C ABI
 
+constexpr int kPollRing = 16;  // PCG iterations the host may enqueue ahead
+constexpr int kNoWork = -2;    // timing tag of a launch issued after convergence
+
 struct cphifi_plan {
   cphifi_ui_desc d{};
   cphifi_ui_inputs in{};
@@ -70,11 +73,25 @@ struct cphifi_plan {
   __bf16 *xthi = nullptr, *xtlo = nullptr;
   GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
   int last_ksplit = 1;  // split-K depth of the partials the last product wrote
-  DevScalars* h_sc = nullptr;  // pinned host mirror
+  DevScalars* h_sc = nullptr;  // host mirror (mapped, coherent) ...
+  DevScalars* d_sc = nullptr;  // ... and its device address
+  // Convergence flag that the device writes into host memory every PCG
+  // iteration, and one event per in-flight iteration: the host waits for an
+  // iteration some steps behind the one it enqueues, so the stream never runs
+  // dry while the host decides whether to stop.
+  int32_t* h_flag = nullptr;  // host-mapped, coherent
+  int32_t* d_flag = nullptr;  // its device address
+  hipEvent_t pev[kPollRing]{};
   bool timing = false;
   Elt timed_elt = Elt::F64;  // product type whose launches are timed ...
   bool timed_trans = false;  // ... and orientation (one kernel symbol)
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
+  // Per timed launch (event pair): the PCG step that issued it, 2 it for the
+  // operator and 2 it + 1 for the preconditioner of iteration it, -1 outside
+  // the iteration, kNoWork once known to have run after convergence (its
+  // kernels returned at once, so it is left out of the timing).
+  std::vector<int> ev_tag;
+  int cur_tag = -1;
   bool setup_done = false;
 };

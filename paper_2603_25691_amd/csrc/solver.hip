@@ -102,7 +102,9 @@ int timed_begin(cphifi_plan* p, Elt elt, bool trans, hipEvent_t* out) {
       CPHIFI_HIP(hipEventCreate(&e));
       p->ev.push_back(e);
     }
+    p->ev_tag.resize(p->ev.size() / 2);
   }
+  p->ev_tag[p->ev_used / 2] = p->cur_tag;
   *out = p->ev[p->ev_used];
   CPHIFI_HIP(hipEventRecord(*out, p->st));
   return CPHIFI_OK;
@@ -120,6 +122,7 @@ int timing_collect(cphifi_plan* p, double* ms, int* count) {
   *count = 0;
   if (!p->timing) return CPHIFI_OK;
   for (size_t i = 0; i + 1 < p->ev_used; i += 2) {
+    if (p->ev_tag[i / 2] == kNoWork) continue;
     float t = 0.f;
     CPHIFI_HIP(hipEventElapsedTime(&t, p->ev[i], p->ev[i + 1]));
     *ms += t;
@@ -298,19 +301,27 @@ struct PcgOut {
   double relres = 0.0;
 };
 
+// Host copy of *sc once the stream has drained (a kernel writes it into the
+// mapped mirror: cheaper than a device-to-host copy of a few words).
 int poll(cphifi_plan* p, DevScalars* sc) {
-  CPHIFI_HIP(hipMemcpyAsync(p->h_sc, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, p->st));
+  TRY(launch_mirror(sc, p->d_sc, p->st));
   CPHIFI_HIP(hipStreamSynchronize(p->st));
   return CPHIFI_OK;
 }
 
+// Iterations the host keeps enqueued beyond the newest one whose convergence
+// flag it has read (at most kPollRing - 1).
 int check_every(const cphifi_plan* p) {
-  if (p->d.check_every > 0) return p->d.check_every;
-  return p->n >= 4096 ? 1 : 8;
+  const int e = p->d.check_every > 0 ? p->d.check_every : (p->n >= 4096 ? 1 : 8);
+  return std::min(e, kPollRing - 1);
 }
 
 // Textbook PCG with device-resident scalars.  Every kernel of an iteration
-// checks sc->done, so iterations can be enqueued ahead of the host's poll.
+// checks sc->done, so iterations can be enqueued ahead of the host's check:
+// after enqueuing iteration it, the host waits for iteration it - every and
+// reads the convergence flag that iteration's check wrote to host memory.
+// The stream keeps `every` iterations of work queued meanwhile; those left
+// over after convergence return at once.
 int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double* b, double* x,
             bool have_x0, double tol, int maxit, const PcgVecs& v, DevScalars* sc,
             double* hist, int hist_len, PcgOut* out) {
@@ -334,25 +345,30 @@ int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double
   TRY(launch_copy(v.P, v.Z, len, st));
   TRY(launch_pcg_init(sc, red0, nb_bb, red1, nb_rr, red2, nb_rz, tol, hist, hist_len, st));
   const int every = check_every(p);
-  bool stopped = false;
+  *(volatile int32_t*)p->h_flag = 0;
+  const size_t first_pair = p->ev_used / 2;
   for (int it = 0; it < maxit; ++it) {
+    p->cur_tag = 2 * it;
     TRY(apply(v.P, v.Q, red0, &nb_pq, &sc->done));
     TRY(launch_update_xr(x, v.R, v.P, v.Q, len, red0, nb_pq, red1, &nb_rr, sc, it, st));
-    TRY(launch_check_conv(red1, nb_rr, sc, it, hist, hist_len, st));
-    if ((it + 1) % every == 0 || it + 1 == maxit) {
-      TRY(poll(p, sc));
-      if (p->h_sc->done) {
-        stopped = true;
-        break;
-      }
+    TRY(launch_check_conv(red1, nb_rr, sc, it, hist, hist_len, p->d_flag, st));
+    CPHIFI_HIP(hipEventRecord(p->pev[it % kPollRing], st));
+    if (it >= every) {
+      CPHIFI_HIP(hipEventSynchronize(p->pev[(it - every) % kPollRing]));
+      if (*(volatile int32_t*)p->h_flag) break;
     }
     if (it + 1 == maxit) break;
+    p->cur_tag = 2 * it + 1;
     TRY(precond(v.R, v.Z, red2, &nb_rz, &sc->done));
     TRY(launch_update_p(v.P, v.Z, len, red2, nb_rz, sc, it, st));
   }
-  if (!stopped) TRY(poll(p, sc));
+  p->cur_tag = -1;
+  TRY(poll(p, sc));
   const DevScalars& h = *p->h_sc;
   out->iters = h.done ? h.iters : maxit;
+  // Launches of the iterations enqueued past convergence did no work.
+  for (size_t i = first_pair; i < p->ev_used / 2; ++i)
+    if (p->ev_tag[i] >= 2 * out->iters - 1) p->ev_tag[i] = kNoWork;
   out->status = h.done ? h.status : CPHIFI_NOT_CONVERGED;
   out->relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
   return CPHIFI_OK;
@@ -371,6 +387,32 @@ int true_relres(cphifi_plan* p, const double* b, const double* x, double* rel) {
   TRY(launch_store_sum(p->red[1], nbb, p->sc2, 1, p->st));
   TRY(poll(p, p->sc2));
   const double rr = p->h_sc->scratch[0], bb = p->h_sc->scratch[1];
+  *rel = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+  return CPHIFI_OK;
+}
+
+// The same certificate for b = K Bm given through Bm (the observed MTTKRP):
+// b - A W = K (Bm - Yhat1 - lambda W) - rho W with Yhat1 = G(K W), two passes
+// over K as above; bb = ||b||^2 comes from the caller.
+int true_relres_from_B(cphifi_plan* p, const double* Bm, const double* W, double bb,
+                       double* rel) {
+  const int64_t len = p->n * p->r;
+  double* T = p->vec[V_Z];
+  double* RF = p->vec[V_RF];
+  int nb = 0;
+  TRY(prod_K(p, W, nullptr));
+  TRY(obs_gather(p, Elt::F64, nullptr, p->vec[V_Y1], nullptr));
+  TRY(launch_copy(T, Bm, len, p->st));
+  TRY(launch_axpby(T, -1.0, p->vec[V_Y1], 1.0, len, nullptr, p->st));
+  TRY(launch_axpby(T, -p->d.lambda, W, 1.0, len, nullptr, p->st));
+  TRY(prod_K(p, T, nullptr));
+  TRY(launch_reduce_partials(p->part, false, p->last_ksplit, p->ldp, p->n, (int)p->r, RF,
+                             nullptr, nullptr, nullptr, nullptr, p->st));
+  TRY(launch_axpby(RF, -p->d.rho, W, 1.0, len, nullptr, p->st));
+  TRY(launch_dot(RF, RF, len, p->red[0], &nb, nullptr, p->st));
+  TRY(launch_store_sum(p->red[0], nb, p->sc2, 0, p->st));
+  TRY(poll(p, p->sc2));
+  const double rr = p->h_sc->scratch[0];
   *rel = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
   return CPHIFI_OK;
 }
@@ -437,7 +479,13 @@ int solve_fp64(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* in
 // formed once at the end and certified by the FP64 residual of the original
 // system (two passes over K); should that certificate miss the target while
 // the rotated one met it, refinement continues.
-int solve_mixed(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* info) {
+//
+// The right-hand side comes either as b = K Bm or, from the whole-subproblem
+// entry, as Bm itself (the observed MTTKRP, eq. for B in Section 4.4): then
+// bbar = U^T K Bm = D_K U^T Bm takes one pass over U_K instead of a pass over
+// K followed by one over U_K, and the certificate forms b - A W without b.
+int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
+                cphifi_solve_info* info) {
   const bool warm = (p->d.flags & CPHIFI_FLAG_WARM_START) != 0;
   const int64_t len = p->n * p->r;
   const int maxit = eff_maxit(p->d);
@@ -452,7 +500,13 @@ int solve_mixed(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* i
   // a rounded U_K is not orthogonal, and its error, mapped through the
   // ill-conditioned system, makes the refinement diverge.  Only the inner
   // operator runs at low precision; the FP64 residual corrects its error.
-  TRY(rotate_in(p, Elt::F64, b, bbar));
+  if (Bm != nullptr) {
+    TRY(prod_Ut(p, Elt::F64, Bm, nullptr));
+    TRY(launch_reduce_partials(p->part, false, p->last_ksplit, p->ldp, p->n, (int)p->r, bbar,
+                               nullptr, nullptr, nullptr, nullptr, p->st, p->dKc));
+  } else {
+    TRY(rotate_in(p, Elt::F64, b, bbar));
+  }
   TRY(launch_dot(bbar, bbar, len, p->red[1], &nb, nullptr, p->st));
   TRY(launch_store_sum(p->red[1], nb, p->sc2, 1, p->st));
   if (warm)
@@ -466,7 +520,7 @@ int solve_mixed(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* i
     return op_precond_eig(p, x, z, red, nbk, done);
   };
   int total_inner = 0, k = 0, status = CPHIFI_NOT_CONVERGED;
-  double rel = INFINITY, cert = INFINITY;
+  double rel = INFINITY, cert = INFINITY, bb_bar = 0.0;
   bool force = false;  // one more correction although the rotated residual met tol
   bool fresh = !warm;  // xbar = 0: its residual is bbar
   for (;;) {
@@ -482,6 +536,7 @@ int solve_mixed(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* i
       TRY(launch_store_sum(p->red[0], nb, p->sc2, 0, p->st));
       TRY(poll(p, p->sc2));
       const double rr = p->h_sc->scratch[0], bb = p->h_sc->scratch[1];
+      bb_bar = bb;
       rel = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
       if (!std::isfinite(rel)) {
         status = CPHIFI_NUMERIC;
@@ -506,7 +561,9 @@ int solve_mixed(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* i
     // The certificate is not part of the kernel timing.
     const bool t = p->timing;
     p->timing = false;
-    const int rs = true_relres(p, b, W, &cert);
+    // ||b|| = ||U^T b|| (U_K orthogonal) when b is not formed
+    const int rs = Bm != nullptr ? true_relres_from_B(p, Bm, W, bb_bar, &cert)
+                                 : true_relres(p, b, W, &cert);
     p->timing = t;
     TRY(rs);
     if (!std::isfinite(cert)) {
@@ -576,6 +633,33 @@ GemmPlan plan_from_env(const char* var, Elt elt, bool trans, int64_t n, int r,
   int mw = 0, ss = 0, ks = 0;
   if (std::sscanf(s, "%d,%d,%d", &mw, &ss, &ks) < 2 || !gemm_cfg_valid(elt, mw, ss)) return dflt;
   return make_gemm_plan(elt, trans, n, r, mw, ss, ks, num_cu);
+}
+
+// out <- B(s,:) = sum_{l in seg(s)} y_l Zhat(l,:), the observed MTTKRP.
+int mttkrp(cphifi_plan* p, const double* y, double* out) {
+  ObsArgs a{};
+  a.n = p->n;
+  a.r = (int)p->r;
+  a.obs_i = p->in.obs_i;
+  a.obs_j = p->in.obs_j;
+  a.A = p->in.A;
+  a.B = p->in.B;
+  a.Zhat = p->in.Zhat;
+  a.y = y;
+  a.out = out;
+  a.tpart = p->tpart;
+  a.done = nullptr;
+  return launch_obs(ObsMode::Mttkrp, false, p->tasks, a, p->I, p->J, p->st);
+}
+
+// Pinned host memory and events of a plan.
+void release_host(cphifi_plan* p) {
+  for (hipEvent_t& e : p->pev)
+    if (e != nullptr) (void)hipEventDestroy(e), e = nullptr;
+  if (p->h_flag) (void)hipHostFree(p->h_flag);
+  if (p->h_sc) (void)hipHostFree(p->h_sc);
+  p->h_flag = p->d_flag = nullptr;
+  p->h_sc = p->d_sc = nullptr;
 }
 
 }  // namespace
@@ -789,7 +873,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   p->rowm = (int32_t*)(ws + L.rowm);
 
   auto fail = [&](int code) {
-    if (p->h_sc) (void)hipHostFree(p->h_sc);
+    release_host(p);
     delete p;
     return code;
   };
@@ -799,11 +883,33 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
                               st));
     return CPHIFI_OK;
   };
-  if (hipHostMalloc((void**)&p->h_sc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&p->h_sc, sizeof(DevScalars),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     p->h_sc = nullptr;
     set_error("hipHostMalloc of the scalar mirror failed");
     return fail(CPHIFI_HIP_ERROR);
   }
+  if (hipHostGetDevicePointer((void**)&p->d_sc, p->h_sc, 0) != hipSuccess) {
+    set_error("hipHostGetDevicePointer of the scalar mirror failed");
+    return fail(CPHIFI_HIP_ERROR);
+  }
+  if (hipHostMalloc((void**)&p->h_flag, 64, hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess) {
+    p->h_flag = nullptr;
+    set_error("hipHostMalloc of the convergence flag failed");
+    return fail(CPHIFI_HIP_ERROR);
+  }
+  if (hipHostGetDevicePointer((void**)&p->d_flag, p->h_flag, 0) != hipSuccess) {
+    set_error("hipHostGetDevicePointer of the convergence flag failed");
+    return fail(CPHIFI_HIP_ERROR);
+  }
+  *(volatile int32_t*)p->h_flag = 0;
+  for (int i = 0; i < kPollRing; ++i)
+    if (hipEventCreateWithFlags(&p->pev[i], hipEventDisableTiming) != hipSuccess) {
+      p->pev[i] = nullptr;
+      set_error("hipEventCreateWithFlags failed");
+      return fail(CPHIFI_HIP_ERROR);
+    }
   int rc = CPHIFI_OK;
   if ((rc = up(p->tasks.seg, tseg)) || (rc = up(p->tasks.beg, tbeg)) ||
       (rc = up(p->tasks.end, tend)) || (rc = up(p->tasks.slot, tslot)) ||
@@ -877,19 +983,7 @@ int cphifi_ui_rhs(cphifi_plan* p, const double* y, double* b) {
     set_error("rhs: NULL argument");
     return CPHIFI_INVALID_ARG;
   }
-  ObsArgs a{};
-  a.n = p->n;
-  a.r = (int)p->r;
-  a.obs_i = p->in.obs_i;
-  a.obs_j = p->in.obs_j;
-  a.A = p->in.A;
-  a.B = p->in.B;
-  a.Zhat = p->in.Zhat;
-  a.y = y;
-  a.out = p->vec[V_Y1];
-  a.tpart = p->tpart;
-  a.done = nullptr;
-  TRY(launch_obs(ObsMode::Mttkrp, false, p->tasks, a, p->I, p->J, p->st));
+  TRY(mttkrp(p, y, p->vec[V_Y1]));
   const bool t = p->timing;
   p->timing = false;
   const int rc = prod_K(p, p->vec[V_Y1], nullptr);
@@ -946,7 +1040,7 @@ int cphifi_ui_solve(cphifi_plan* p, const double* b, double* W, cphifi_solve_inf
   info->history = hist;
   p->ev_used = 0;
   if (p->d.precision == CPHIFI_FP64) return solve_fp64(p, b, W, info);
-  return solve_mixed(p, b, W, info);
+  return solve_mixed(p, b, nullptr, W, info);
 }
 
 int cphifi_ui_solve_subproblem(cphifi_plan* p, const double* y, double* W,
@@ -957,15 +1051,28 @@ int cphifi_ui_solve_subproblem(cphifi_plan* p, const double* y, double* W,
     return CPHIFI_INVALID_ARG;
   }
   TRY(cphifi_ui_setup(p));
-  TRY(cphifi_ui_rhs(p, y, p->vec[V_B]));
-  return cphifi_ui_solve(p, p->vec[V_B], W, info);
+  if (p->d.precision == CPHIFI_FP64) {
+    TRY(cphifi_ui_rhs(p, y, p->vec[V_B]));
+    return cphifi_ui_solve(p, p->vec[V_B], W, info);
+  }
+  // Mixed forms: the refinement starts from Bm (no pass over K for b).
+  if (y == nullptr && p->q > 0) {
+    set_error("solve_subproblem: y is NULL");
+    return CPHIFI_INVALID_ARG;
+  }
+  TRY(mttkrp(p, y, p->vec[V_B]));
+  double* hist = info->history;
+  std::memset(info, 0, sizeof(*info));
+  info->history = hist;
+  p->ev_used = 0;
+  return solve_mixed(p, nullptr, p->vec[V_B], W, info);
 }
 
 int cphifi_ui_plan_destroy(cphifi_plan* p) {
   clear_error();
   if (p == nullptr) return CPHIFI_OK;
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
-  if (p->h_sc) (void)hipHostFree(p->h_sc);
+  release_host(p);
   delete p;
   return CPHIFI_OK;
 }

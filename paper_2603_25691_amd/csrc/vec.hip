@@ -55,6 +55,7 @@ template <typename PT>
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const PT* part, int ksplit, int ldp,
                                                               int64_t n, int r, double* out,
                                                               const double* dotwith, double* red,
+                                                              const double* rowscale,
                                                               const int32_t* done) {
   if (is_done(done)) return;
   const int64_t len = n * r;
@@ -63,7 +64,8 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const PT* part, in
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = e / r;
     const int c = (int)(e % r);
-    const double v = part_sum(part, ksplit, n, ldp, s, c);
+    double v = part_sum(part, ksplit, n, ldp, s, c);
+    if (rowscale != nullptr) v *= rowscale[s];
     out[e] = v;
     if (dotwith != nullptr) loc += dotwith[e] * v;
   }
@@ -144,23 +146,29 @@ __global__ __launch_bounds__(256) void update_xr_kernel(double* x, double* r, co
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->pq = pq;
 }
 
+// flag (host memory, may be null) receives sc->done as of this iteration.
 __global__ __launch_bounds__(256) void check_conv_kernel(const double* red_rr, int nblk,
                                                          DevScalars* sc, int it, double* hist,
-                                                         int hist_len) {
-  if (sc->done) return;
+                                                         int hist_len, int32_t* flag) {
+  if (sc->done) {
+    if (flag != nullptr && threadIdx.x == 0) *(volatile int32_t*)flag = 1;
+    return;
+  }
   const double rr = sum_partials(red_rr, nblk);
   if (threadIdx.x == 0) {
     sc->rr = rr;
     if (hist != nullptr && it + 1 < hist_len) hist[it + 1] = sqrt(rr / sc->bb);
+    int32_t done = 0;
     if (!isfinite(rr)) {
       sc->status = CPHIFI_NUMERIC;
       sc->iters = it + 1;
-      sc->done = 1;
+      sc->done = done = 1;
     } else if (rr <= sc->tol2) {
       sc->status = CPHIFI_OK;
       sc->iters = it + 1;
-      sc->done = 1;
+      sc->done = done = 1;
     }
+    if (flag != nullptr) *(volatile int32_t*)flag = done;
   }
 }
 
@@ -221,6 +229,15 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(DevScalars* sc, const dou
 __global__ void store_sum_kernel(const double* red, int nblk, DevScalars* sc, int slot) {
   const double v = sum_partials(red, nblk);
   if (threadIdx.x == 0) sc->scratch[slot] = v;
+}
+
+// dst (host-mapped memory) <- *src, word by word.
+__global__ void mirror_kernel(const DevScalars* src, DevScalars* dst) {
+  constexpr int kWords = sizeof(DevScalars) / sizeof(int32_t);
+  static_assert(sizeof(DevScalars) % sizeof(int32_t) == 0, "DevScalars is whole words");
+  const int32_t* s = (const int32_t*)src;
+  volatile int32_t* d = (volatile int32_t*)dst;
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x) d[i] = s[i];
 }
 
 // out[s,:] = ((t U_V) * D[s,:]) U_V^T, t = in[s,:] or the sum of partials.
@@ -469,14 +486,16 @@ static int grid_for(int64_t len) {
 
 int launch_reduce_partials(const void* part, bool is_float, int ksplit, int ldp, int64_t n,
                            int r, double* out, const double* dotwith, double* red,
-                           int* nblk_out, const int32_t* done, hipStream_t st) {
+                           int* nblk_out, const int32_t* done, hipStream_t st,
+                           const double* rowscale) {
   const int nb = vec_blocks(n * r);
   if (is_float)
     hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(nb), dim3(256), 0, st,
-                       (const float*)part, ksplit, ldp, n, r, out, dotwith, red, done);
+                       (const float*)part, ksplit, ldp, n, r, out, dotwith, red, rowscale, done);
   else
     hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(nb), dim3(256), 0, st,
-                       (const double*)part, ksplit, ldp, n, r, out, dotwith, red, done);
+                       (const double*)part, ksplit, ldp, n, r, out, dotwith, red, rowscale,
+                       done);
   CPHIFI_CHECK_LAUNCH();
   if (nblk_out) *nblk_out = nb;
   return CPHIFI_OK;
@@ -520,9 +539,9 @@ int launch_update_xr(double* x, double* r, const double* p, const double* q, int
 }
 
 int launch_check_conv(const double* red_rr, int nblk, DevScalars* sc, int it, double* hist,
-                      int hist_len, hipStream_t st) {
+                      int hist_len, int32_t* flag, hipStream_t st) {
   hipLaunchKernelGGL(check_conv_kernel, dim3(1), dim3(256), 0, st, red_rr, nblk, sc, it, hist,
-                     hist_len);
+                     hist_len, flag);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }
@@ -562,6 +581,12 @@ int launch_pcg_init(DevScalars* sc, const double* red_bb, int nblk_bb, const dou
 
 int launch_store_sum(const double* red, int nblk, DevScalars* sc, int slot, hipStream_t st) {
   hipLaunchKernelGGL(store_sum_kernel, dim3(1), dim3(256), 0, st, red, nblk, sc, slot);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_mirror(const DevScalars* src, DevScalars* dst, hipStream_t st) {
+  hipLaunchKernelGGL(mirror_kernel, dim3(1), dim3(64), 0, st, src, dst);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }

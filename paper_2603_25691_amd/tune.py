@@ -4,6 +4,8 @@
       --elt fp64 bf16 --out tiles.txt
   python -m paper_2603_25691_amd.tune measure --n 30658 --r 40 --elt bf16 --reps 4 \
       --calib-mb 1024
+  python -m paper_2603_25691_amd.tune batch --count 64 \
+      --out paper_2603_25691_amd/tiles_batch_mi355x.txt
 
 `sweep` times every (mw, s, ksplit) tile of cphifi_product for each size and
 writes the fastest per (element type, orientation, r, n) to a plain-text table
@@ -12,6 +14,13 @@ that plans read when CPHIFI_TILE_TABLE names it.  Table line format:
     <elt> <trans> <r_lo> <r_hi> <n_lo> <n_hi> <mw> <s> <ksplit>
 
 with elt in {f64, f32, bf16}; the first line whose ranges contain (r, n) wins.
+
+`batch` tunes the tiles of the persistent batched solver on the synthetic
+batched workload itself (members of uneven n and r): inside one launch the
+members' product items share the grid, so the best split-K depth there is not
+the one of a product launched alone.  For each candidate -- a target k-range
+length per work item and the BF16 rows per wave -- it writes a table, times
+batched solves with it, and keeps the fastest table.
 
 `measure` runs the chosen product `reps` times after a plain device copy of
 known size, so a hardware-counter run (e.g. rocprofv3 --pmc FETCH_SIZE) can scale
@@ -126,6 +135,71 @@ def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False)
         torch.cuda.empty_cache()
 
 
+BATCH_KRANGE = (1024, 2048, 4096)
+BATCH_BF16_MW = (2, 4)
+BATCH_BIN = 512  # n bins of the batch table
+
+
+def _batch_table(path: str, krange: int, bf_mw: int, n_max: int) -> None:
+    """Split-K depth ~ n / krange per bin of n (midpoint), BF16 rows per wave
+    bf_mw; the FP64 tiles of the batched kernel are fixed, only their depth
+    comes from the table."""
+    with open(path, "w") as f:
+        f.write(f"# batched solver tiles (MI355X): k-range ~{krange}, bf16 mw {bf_mw}\n")
+        f.write("# elt trans r_lo r_hi n_lo n_hi mw s ksplit\n")
+        for lo in range(1, n_max + 1, BATCH_BIN):
+            hi = lo + BATCH_BIN - 1
+            ks = max(1, min(16, round((lo + hi) / 2 / krange)))
+            f.write(f"bf16 0 1 64 {lo} {hi} {bf_mw} 2 {ks}\n")
+            f.write(f"f64 0 1 64 {lo} {hi} 2 4 {ks}\n")
+            f.write(f"f64 1 1 64 {lo} {hi} 2 4 {ks}\n")
+
+
+def batch(count: int, seed: int, out_path: str, reps: int = 3) -> None:
+    import os
+    import tempfile
+
+    from synth import batch_members
+
+    from .torch_api import BatchSolver, upload
+
+    probs, dps = [], []
+    for bm in batch_members(seed=seed, count=count):
+        probs.append(bm.problem)
+        dps.append(upload(bm.problem, ldk_align=8))
+    torch.cuda.synchronize()
+    n_max = (max(p.n for p in probs) + BATCH_BIN - 1) // BATCH_BIN * BATCH_BIN
+    tmp = tempfile.mkdtemp(prefix="cphifi_tune_")
+    best = None
+    for kr in BATCH_KRANGE:
+        for mw in BATCH_BF16_MW:
+            # a fresh file name per candidate: plans cache tables by path
+            path = os.path.join(tmp, f"batch_k{kr}_mw{mw}.txt")
+            _batch_table(path, kr, mw, n_max)
+            bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], probs[0].tol,
+                             tile_table=path)
+            try:
+                rhs = bs.rhs()
+                Ws = [torch.empty_like(b) for b in rhs]
+                bs.bind(rhs, Ws)
+                status, _ = bs.solve()
+                ms = _time(lambda: bs.solve(wait=False), reps)
+                status, infos = bs.info()
+            finally:
+                bs.close()
+            rec = {"krange": kr, "bf16_mw": mw, "ms_per_batch": ms,
+                   "status": C.status_string(status),
+                   "relres_max": max(i.relres_true for i in infos)}
+            print(json.dumps(rec), flush=True)
+            if status == C.OK and (best is None or ms < best[0]):
+                best = (ms, kr, mw)
+    if best is None:
+        raise SystemExit("no candidate solved the batch")
+    _batch_table(out_path, best[1], best[2], max(n_max, 1 << 15))
+    print(f"wrote {out_path} (k-range {best[1]}, bf16 mw {best[2]}, {best[0]:.2f} ms)",
+          file=sys.stderr)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -141,9 +215,16 @@ def main(argv=None):
     m.add_argument("--elt", nargs="+", default=["bf16", "fp64"])
     m.add_argument("--reps", type=int, default=4)
     m.add_argument("--calib-mb", type=int, default=1024)
+    b = sub.add_parser("batch")
+    b.add_argument("--count", type=int, default=64)
+    b.add_argument("--seed", type=int, default=0)
+    b.add_argument("--reps", type=int, default=3)
+    b.add_argument("--out", default="tiles_batch.txt")
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
         sweep(a.n, a.r, a.elt, a.out, a.reps)
+    elif a.cmd == "batch":
+        batch(a.count, a.seed, a.out, a.reps)
     else:
         measure(a.n, a.r, a.elt, a.reps, a.calib_mb)
 

@@ -130,3 +130,42 @@ def test_batch_count_is_bounded(count):
     with pytest.raises(c.CphifiError) as ei:
         c.cphifi_batch_workspace_bytes([_bf16_desc()] * count)
     assert ei.value.status == c.INVALID_ARG
+
+
+def _parse_table(path):
+    rules = []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        tag, trans, r_lo, r_hi, n_lo, n_hi, mw, s, ks = line.split()
+        rules.append((tag, int(trans), int(r_lo), int(r_hi), int(n_lo), int(n_hi), int(mw),
+                      int(s), int(ks)))
+    return rules
+
+
+@pytest.mark.parametrize("krange,mw", [(1024, 2), (2048, 4), (4096, 4)])
+def test_batch_tile_table_is_complete_and_valid(tmp_path, krange, mw):
+    """The batch autotuner's table: for each product kind, bins that tile
+    1..n_max without gaps, tiles the library accepts, split-K depth in 1..16
+    and about n / krange."""
+    from paper_2603_25691_amd import tune
+
+    path = tmp_path / "t.txt"
+    tune._batch_table(str(path), krange, mw, 8192)
+    rules = _parse_table(path)
+    elts = {"bf16": c.ELT_BF16, "f64": c.ELT_F64}
+    kinds = sorted({(r[0], r[1]) for r in rules})
+    assert kinds == [("bf16", 0), ("f64", 0), ("f64", 1)]
+    for kind in kinds:
+        rs = [r for r in rules if (r[0], r[1]) == kind]
+        assert rs[0][4] == 1 and rs[-1][5] >= 8192
+        for a, b in zip(rs, rs[1:]):
+            assert b[4] == a[5] + 1
+        for tag, trans, r_lo, r_hi, n_lo, n_hi, tmw, s, ks in rs:
+            assert (r_lo, r_hi) == (1, 64)
+            assert c.cphifi_product_tile_ok(elts[tag], tmw, s)
+            assert 1 <= ks <= 16
+            mid = (n_lo + n_hi) / 2
+            assert ks == max(1, min(16, round(mid / krange)))
+        if kind[0] == "bf16":
+            assert all(r[6] == mw for r in rs)

@@ -224,3 +224,25 @@ def test_batch_with_padded_kernel_stride(batch):
             assert O.e_kw(p.K, host(Ws[j]), batch["W"][k]) <= 1e-6
     finally:
         bs.close()
+
+
+def test_batch_with_tuner_table(batch, tmp_path):
+    """Tiles from a table written by the batch autotuner (a k-range and BF16
+    rows per wave other than the defaults): the same solutions."""
+    from paper_2603_25691_amd import tune
+
+    probs, dps = batch["probs"], batch["dps"]
+    path = tmp_path / "tiles.txt"
+    tune._batch_table(str(path), 1024, 2, 8192)
+    bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], TOL,
+                     tile_table=str(path), **CAPS)
+    try:
+        rhs = bs.rhs()
+        Ws = [torch.empty_like(b) for b in rhs]
+        status, infos = bs.solve(rhs, Ws)
+        assert status == C.OK
+        for k, W in enumerate(Ws):
+            assert infos[k].relres_true <= TOL, MEMBERS[k][0]
+            assert O.e_kw(probs[k].K, host(W), batch["W"][k]) <= 1e-6, MEMBERS[k][0]
+    finally:
+        bs.close()

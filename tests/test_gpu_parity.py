@@ -235,6 +235,27 @@ def test_mixed_precision_solve_reaches_1e6(precision, name, uploaded):
     assert O.e_kw(p.K, host(W), _dense(p)) <= 1e-6
 
 
+@pytest.mark.parametrize("name", ["c1", "r40"])
+def test_mixed_subproblem_from_mttkrp_matches_solve_from_b(name, uploaded):
+    """The whole-subproblem entry starts the mixed refinement from the observed
+    MTTKRP B (bbar = D_K U^T B, no b = K B) and certifies W against K B formed
+    inside the residual; the solve from b = K B (cphifi_ui_rhs) must give the
+    same W, and both reported certificates must be the oracle's."""
+    p, dp = uploaded(name)
+    tol = 1e-8
+    s = UISolver(dp, p.lam, p.rho, tol, precision="mixed_bf16")
+    W1, i1 = s.solve_subproblem()
+    W1 = W1.clone()
+    W2, i2 = s.solve(s.rhs())
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    for W, info in ((W1, i1), (W2, i2)):
+        assert info.status == C.OK, info.as_dict()
+        cert = O.relres(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, host(W))
+        assert cert <= 2 * tol
+        assert abs(cert - info.relres_true) <= 0.05 * tol + 1e-3 * cert
+    assert O.e_kw(p.K, host(W1), host(W2)) <= 1e-6
+
+
 def test_explicit_zhat_solve(uploaded):
     p, dp = uploaded("ragged-r17")
     Zhat = p.A[p.obs_i] * p.B[p.obs_j]
