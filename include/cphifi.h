@@ -180,7 +180,12 @@ CPHIFI_API int cphifi_ui_solve(cphifi_plan* p, const double* b, double* W,
                     cphifi_solve_info* info);
 
 /* Whole subproblem from the observed values: setup, right-hand side, solve
- * and the FP64 true residual.  y: q doubles (device).  sync. */
+ * and the FP64 true residual.  y: q doubles (device).  In the mixed forms the
+ * refinement starts from the observed MTTKRP B itself (right-hand side
+ * b = K B, Section 4.4): U_K^T b = D_K U_K^T B takes one pass over U_K and b
+ * is never formed; relres_true is ||K (B - Yhat1 - lambda W) - rho W|| /
+ * ||b||, the same FP64 paper-form residual, with ||b|| = ||U_K^T b||.  The
+ * FP64 form forms b (cphifi_ui_rhs) and calls cphifi_ui_solve.  sync. */
 CPHIFI_API int cphifi_ui_solve_subproblem(cphifi_plan* p, const double* y, double* W,
                                cphifi_solve_info* info);
 
@@ -281,9 +286,10 @@ CPHIFI_API int cphifi_batch_rounds(cphifi_batch* bt, int* rounds, int* grid);
 
 /* Where the last launch spent its time, from the device real-time clock as
  * seen by one workgroup: ms[0..7] the eight phases of a round (products A,
- * gather-scatter, segment rows + split, products B, finish, x/r update,
- * preconditioner, control + p update), each including its closing grid
- * barrier; ms[8] the per-round setup.  ms: host array of 9.  sync. */
+ * gather-scatter, segment rows + split, products B, finish, x/r update (with
+ * the preconditioner in inner iterations), preconditioner (refinement steps),
+ * control + p update), each including its closing grid barrier; ms[8] the
+ * per-round setup.  ms: host array of 9.  sync. */
 CPHIFI_API int cphifi_batch_phase_ms(cphifi_batch* bt, double* ms);
 
 /* Release the batch's host state and member plans (the workspace belongs to

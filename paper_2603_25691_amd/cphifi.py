@@ -369,8 +369,8 @@ def cphifi_batch_destroy(batch: int) -> None:
     _check(_lib.cphifi_batch_destroy(C.c_void_p(batch)), "cphifi_batch_destroy")
 
 
-BATCH_PHASES = ("products_a", "gather", "rows_split", "products_b", "finish", "update_xr",
-                "precond", "control", "round_setup")
+BATCH_PHASES = ("products_a", "gather", "rows_split", "products_b", "finish",
+                "update_precond", "precond_refine", "control", "round_setup")
 
 
 def cphifi_batch_phase_ms(batch: int) -> dict:

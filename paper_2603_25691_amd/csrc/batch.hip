@@ -240,15 +240,6 @@ __device__ __forceinline__ double part_sum(const void* part, int ks, int64_t n, 
   return v;
 }
 
-// hi + lo BF16 pair carrying ~16 significant bits of v (as the plain split).
-__device__ __forceinline__ void split_pair(double v, __bf16* hi, __bf16* lo) {
-  const __bf16 hb = (__bf16)(float)v;
-  const float h = (float)hb;
-  const float l = (float)(v - (double)h);
-  *hi = (__bf16)h;
-  *lo = (__bf16)l;
-}
-
 // Writes the transposed split tile th/tl ([c][row], kRC rows) of rows
 // [s0, s0 + rows) into the c-major hi/lo operand of the BF16 product.
 __device__ __forceinline__ void store_split(const BSub& S, int64_t s0, int rows, const __bf16* th,
@@ -302,7 +293,9 @@ __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
         case S_A:
         case S_B: return bf;
         case S_OBS: return S.ntaskw;
-        default: return S.nrc;
+        case S_ROWS: return S.orow ? 0 : S.nrc;  // lane-row gathers split their own rows
+        case S_PREC: return 0;                   // fused into S_UPD
+        default: return S.nrc;                   // FIN, UPD, CTRL
       }
   }
   return 0;
@@ -390,6 +383,11 @@ __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, int mode) {
   d.I = S.I;
   d.J = S.J;
   if (S.orow) {
+    if (mode == M_INNER) {  // Yhat1 only feeds the BF16 U^T Yhat1 product
+      d.a.xt_hi = S.xthi;
+      d.a.xt_lo = S.xtlo;
+      d.a.ldxt = S.ldl;
+    }
     constexpr int ROWS = 64 / L;
     for (int k = 0; k < kSegPerWave; k += ROWS) {
       const int64_t s0 = wv * kSegPerWave + k;
@@ -556,32 +554,18 @@ __device__ __forceinline__ bool inner_stop(const BSub& S, const BState* st, int 
   return !(pq > 0.0) || !*finite || rr <= st->tol2 || it + 1 >= S.maxit;
 }
 
-__device__ __forceinline__ void upd_item(const BSub& S, const BState* st, int it, int64_t i, double* s_red) {
-  const double pq = sum_partials(S.red0, S.nrc, s_red);
-  const double rz = st->rz[it & 1];
-  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) return;  // CTRL ends the inner solve
-  const double alpha = rz / pq;
-  const int r = S.r;
-  const int64_t e0 = i * kRC * r, e1 = min(S.n, (i + 1) * kRC) * r;
-  double loc = 0.0;
-  for (int64_t e = e0 + item_tid(); e < e1; e += blockDim.x) {
-    S.X[e] += alpha * S.P[e];
-    const double rv = S.R[e] - alpha * S.Q[e];
-    S.R[e] = rv;
-    loc += rv * rv;
-  }
-  const double t = block_sum(loc, s_red);
-  if (item_tid() == 0) S.red1[i] = t;
-}
-
 // z = ((r U_V) had D) U_V^T for the chunk's rows (eq. fx in the eigenbasis of
 // K); partial r^T z.  Lane c of a wave owns column c; a wave takes kPR rows at
 // a time, so every U_V element read from LDS feeds kPR multiply-adds and the
-// rows' global loads are in flight together.
+// rows' global loads are in flight together.  With UPD (inner iteration) the
+// rows are first updated, x += alpha p and r -= alpha q, and r^T r is summed
+// as well: the update and the preconditioner share one pass over the rows.
 constexpr int kPR = 4;
 static_assert((kBatchRank * kBatchRank + 4 * kPR * kWave) * 8 <= kSmemBytes, "precond LDS");
 
-__device__ __forceinline__ void prec_rows(const BSub& S, int64_t i, char* smem, double* s_red) {
+template <bool UPD>
+__device__ __forceinline__ void prec_rows(const BSub& S, int64_t i, char* smem, double* s_red,
+                                          double alpha = 0.0) {
   const int r = S.r;
   double* uv = (double*)smem;
   double* buf = uv + kBatchRank * kBatchRank;
@@ -591,14 +575,26 @@ __device__ __forceinline__ void prec_rows(const BSub& S, int64_t i, char* smem, 
   double* wb = buf + wave * (kPR * kWave);
   const int64_t s0 = i * kRC, s1 = min(S.n, s0 + kRC);
   const bool col = c < r;
-  double loc = 0.0;
+  double loc = 0.0, loc_rr = 0.0;
   for (int64_t sb = s0 + wave * kPR; sb < s1; sb += 4 * kPR) {
     double t[kPR], u[kPR], dd[kPR];
 #pragma unroll
     for (int k = 0; k < kPR; ++k) {
       const bool on = col && sb + k < s1;
-      t[k] = on ? S.R[(sb + k) * r + c] : 0.0;
-      dd[k] = on ? S.D[(sb + k) * r + c] : 0.0;
+      const int64_t o = (sb + k) * r + c;
+      if (UPD) {
+        double rv = 0.0;
+        if (on) {
+          S.X[o] += alpha * S.P[o];
+          rv = S.R[o] - alpha * S.Q[o];
+          S.R[o] = rv;
+        }
+        t[k] = rv;
+        loc_rr += rv * rv;
+      } else {
+        t[k] = on ? S.R[o] : 0.0;
+      }
+      dd[k] = on ? S.D[o] : 0.0;
       wb[k * kWave + c] = t[k];
     }
     __builtin_amdgcn_wave_barrier();
@@ -633,8 +629,24 @@ __device__ __forceinline__ void prec_rows(const BSub& S, int64_t i, char* smem, 
     }
     __builtin_amdgcn_wave_barrier();
   }
+  if (UPD) {
+    const double rr = block_sum(loc_rr, s_red);
+    if (item_tid() == 0) S.red1[i] = rr;
+  }
   const double tot = block_sum(loc, s_red);
   if (item_tid() == 0) S.red2[i] = tot;
+}
+
+// Inner iteration, after the FIN phase: alpha = r^T z / p^T q, then the
+// fused row update and preconditioner apply (partials r^T r -> red1, r^T z ->
+// red2).  A step length that is not positive and finite leaves the rows as
+// they are; the control phase then ends the inner solve.
+__device__ __forceinline__ void upd_item(const BSub& S, const BState* st, int it, int64_t i,
+                                         char* smem, double* s_red) {
+  const double pq = sum_partials(S.red0, S.nrc, s_red);
+  const double rz = st->rz[it & 1];
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) return;
+  prec_rows<true>(S, i, smem, s_red, rz / pq);
 }
 
 // p = z + beta p for the chunk's rows and the hi/lo split of D_K p.
@@ -802,16 +814,10 @@ __device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, in
       }
       break;
     case S_FIN: fin_item(S, mode, i, s_red); break;
-    case S_UPD: upd_item(S, st, it, i, s_red); break;
-    case S_PREC: {
-      if (mode == M_INNER) {
-        bool finite = true;
-        if (inner_stop(S, st, it, s_red, &finite)) break;
-      } else {  // M_RES, M_RES0
-        double rel = 0.0;
-        if (!refine_on(S, st, s_red, &rel)) break;
-      }
-      prec_rows(S, i, smem, s_red);
+    case S_UPD: upd_item(S, st, it, i, smem, s_red); break;
+    case S_PREC: {  // M_RES, M_RES0 (the inner iteration's is fused into S_UPD)
+      double rel = 0.0;
+      if (refine_on(S, st, s_red, &rel)) prec_rows<false>(S, i, smem, s_red);
       break;
     }
     default: ctrl_item(S, st, mode, it, i, smem, s_red); break;

@@ -56,6 +56,16 @@ __device__ __forceinline__ int item_tid() {
   return t;
 }
 
+// hi + lo BF16 pair carrying ~16 significant bits of v: hi = bf16(v), lo =
+// bf16(v - hi) (round to nearest even, through FP32).
+__device__ __forceinline__ void split_pair(double v, __bf16* hi, __bf16* lo) {
+  const __bf16 hb = (__bf16)(float)v;
+  const float h = (float)hb;
+  const float l = (float)(v - (double)h);
+  *hi = (__bf16)h;
+  *lo = (__bf16)l;
+}
+
 // Scalars of one PCG run, resident in device memory so the whole iteration is
 // enqueued without host round trips.  rz is double-buffered by iteration
 // parity: iteration `it` reads rz[it & 1] and writes rz[(it + 1) & 1].
@@ -152,6 +162,12 @@ struct ObsArgs {
   double* out;              // n x r result (Yhat1 or the MTTKRP B)
   double* tpart;            // partial rows of split segments
   const int32_t* done;
+  // Short-segment gather only: when xt_hi is set, each result row goes out as
+  // its hi/lo BF16 split (split_pair) into the c-major operands xt_hi/xt_lo
+  // (element (s, c) at c * ldxt + s) of a following BF16 product, not to out.
+  __bf16* xt_hi;
+  __bf16* xt_lo;
+  int64_t ldxt;
 };
 enum class ObsMode { Gather = 0, Mttkrp = 1 };
 // I, J bound the implicit-form indices (clamped on the device; range errors are

@@ -44,16 +44,12 @@ __global__ void split_bf16_kernel(const double* __restrict__ X, int64_t ldx, int
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e / ldxt, k = e % ldxt;
-    float h = 0.f, l = 0.f;
+    double v = 0.0;
     if (k < n && c < r) {
-      double v = X[k * ldx + c];
+      v = X[k * ldx + c];
       if (xscale != nullptr) v *= xscale[k];
-      const __bf16 hb = (__bf16)(float)v;
-      h = (float)hb;
-      l = (float)(v - (double)h);
     }
-    hi[e] = (__bf16)h;
-    lo[e] = (__bf16)l;
+    split_pair(v, &hi[e], &lo[e]);
   }
 }
 

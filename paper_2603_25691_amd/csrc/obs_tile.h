@@ -316,7 +316,15 @@ __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr
   if (row_on) {
 #pragma unroll
     for (int j = 0; j < CPL; ++j)
-      if (R.con[j]) a.out[s * a.r + R.cidx[j]] = R.acc[j] * R.arow[j];
+      if (R.con[j]) {
+        const double v = R.acc[j] * R.arow[j];
+        if (a.xt_hi != nullptr) {
+          const int64_t o = (int64_t)R.cidx[j] * a.ldxt + s;
+          split_pair(v, &a.xt_hi[o], &a.xt_lo[o]);
+        } else {
+          a.out[s * a.r + R.cidx[j]] = v;
+        }
+      }
   }
 }
 
