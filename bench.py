@@ -38,6 +38,11 @@ HBM_PEAK_GBPS = 8000.0
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled by a calibration copy
 # (profiles/products_n30658_r40_hbm_counters.md).  Keyed by kernel and shape;
 # clear an entry whenever that kernel changes.
+# K and U_K are stored with row strides rounded up to 16 doubles: every row
+# then starts on a 128-byte line, so a product's 16-element chunk of a row is
+# one line (with the odd stride n = 30658 each chunk straddles two lines and
+# the FP64 product fetched 1.24x its algorithmic bytes instead of 1.01x).
+KROW_ALIGN = 16
 # Tiles of the batched solver written by `python -m paper_2603_25691_amd.tune batch`
 # on MI355X (the defaults apply when the file is absent).
 BATCH_TILES = os.path.join(ROOT, "paper_2603_25691_amd", "tiles_batch_mi355x.txt")
@@ -80,7 +85,7 @@ def bench_batch(a, torch, C):
     probs, dps = [], []
     for bm in batch_members(seed=0, count=a.batch_count):
         p = bm.problem
-        dps.append(upload(p, ldk_align=8))
+        dps.append(upload(p, ldk_align=KROW_ALIGN))
         # keep only what the accuracy check needs on the host
         probs.append(p)
     torch.cuda.synchronize()
@@ -239,7 +244,7 @@ def main():
     p = config_c3(I=a.I, J=a.J)
     log(f"generated n={p.n} q={p.q} r={p.r} in {time.time() - t0:.1f} s")
     t0 = time.time()
-    dp = upload(p)
+    dp = upload(p, ldk_align=KROW_ALIGN)
     torch.cuda.synchronize()
     log(f"uploaded + eig(K) on device in {time.time() - t0:.1f} s")
     n, r, q = p.n, p.r, p.q

@@ -230,7 +230,8 @@ CPHIFI_API int cphifi_product(int elt, int trans, int mw, int s, int ksplit, int
  * PCG solves in the eigenbasis of K with BF16 eigenvectors and the r x r step
  * of eq. fx), all members together in ONE persistent kernel launch that is
  * captured with its reset kernel in a HIP graph.  Members: implicit (A, B)
- * form, n <= 65536, r <= 48, up to 256 per batch; each member's desc and
+ * form, n <= 65536, r <= 48, J r <= 8192 (B is read from an LDS copy), up to
+ * 256 per batch; each member's desc and
  * inputs follow cphifi_ui_plan_create (tol: FP64 relres target; inner_tol,
  * maxit, max_refine, FLAG_WARM_START honoured per member).
  *

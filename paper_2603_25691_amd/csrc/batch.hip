@@ -68,7 +68,7 @@ static_assert(kMaxN <= (int64_t)kRC * kMaxVecBlocks, "partials of a vector phase
 // Members have r <= 48 (three 16-column MFMA blocks): the largest tiles then
 // fit the register budget of two workgroups per CU.
 constexpr int kBatchRank = 48;
-constexpr int kSmemBytes = 27648;  // LDS shared by the phases (largest: BF16 tile, NB = 3)
+constexpr int kSmemBytes = 65536;  // LDS shared by the phases (largest: B of a member, J r <= 8192)
 
 static_assert(tiles::bf16_lds_elems<3, 2>() * 2 <= kSmemBytes, "bf16 tile LDS");
 static_assert(tiles::k4_lds_elems<double, 3, 4>() * 8 <= kSmemBytes, "f64 NN tile LDS");
@@ -357,8 +357,8 @@ __device__ __forceinline__ void gemm_item(const BSub& S, int kind, const double*
 // ------------------------------------------------------ gather-dot-scatter
 // Work item i: wave w takes tasks [(4 i + w) kTPW, ...) of the member's list,
 // or, for short segments, segments [(4 i + w) kSegPerWave, ...) by lane rows.
-template <int L, int CPL, int FORM, typename PT>
-__device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, int mode) {
+template <int L, int CPL, int FORM, typename PT, bool BL>
+__device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, const double* Bl) {
   const int64_t wv = 4 * i + (item_tid() >> 6);
   const int64_t t0 = wv * kTPW;
   const int64_t t1 = min((int64_t)S.ntask, t0 + kTPW);
@@ -392,38 +392,52 @@ __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, int mode) {
     for (int k = 0; k < kSegPerWave; k += ROWS) {
       const int64_t s0 = wv * kSegPerWave + k;
       if (s0 >= S.n) break;
-      tiles::obs_rows<L, CPL, FORM, 0, PT>(d, S.obs_ptr, s0, (int)min((int64_t)ROWS, S.n - s0),
-                                           item_tid() & 63);
+      tiles::obs_rows<L, CPL, FORM, 0, PT, BL>(d, S.obs_ptr, s0,
+                                               (int)min((int64_t)ROWS, S.n - s0),
+                                               item_tid() & 63, Bl);
     }
     return;
   }
   for (int64_t task = t0; task < t1; ++task)
-    tiles::obs_task<L, CPL, FORM, 0, PT>(tv, d, task, item_tid() & 63);
+    tiles::obs_task<L, CPL, FORM, 0, PT, BL>(tv, d, task, item_tid() & 63, Bl);
 }
 
-template <int L, int CPL>
-__device__ __forceinline__ void obs_item_l(const BSub& S, int64_t i, int mode) {
-  const bool f = mode == M_INNER;  // BF16 products leave float partials
-  if (S.own) {
-    if (f)
-      obs_item_c<L, CPL, tiles::kOwner, float>(S, i, mode);
-    else
-      obs_item_c<L, CPL, tiles::kOwner, double>(S, i, mode);
-  } else {
-    if (f)
-      obs_item_c<L, CPL, tiles::kImplicit, float>(S, i, mode);
-    else
-      obs_item_c<L, CPL, tiles::kImplicit, double>(S, i, mode);
+// B (J x r, at most kSmemBytes; checked at batch creation) goes to LDS first,
+// so every observation reads its factor row from LDS instead of L2.
+template <int L, int CPL, int FORM, typename PT>
+__device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, int mode, char* smem) {
+  const int64_t len = (int64_t)S.J * S.r;
+  if (len * (int64_t)sizeof(double) <= kSmemBytes) {
+    double* Bl = (double*)smem;
+    for (int64_t e = item_tid(); e < len; e += blockDim.x) Bl[e] = S.B[e];
+    __syncthreads();
+    obs_item_b<L, CPL, FORM, PT, true>(S, i, mode, Bl);
   }
 }
 
-__device__ __forceinline__ void obs_item(const BSub& S, int64_t i, int mode) {
+template <int L, int CPL>
+__device__ __forceinline__ void obs_item_l(const BSub& S, int64_t i, int mode, char* smem) {
+  const bool f = mode == M_INNER;  // BF16 products leave float partials
+  if (S.own) {
+    if (f)
+      obs_item_c<L, CPL, tiles::kOwner, float>(S, i, mode, smem);
+    else
+      obs_item_c<L, CPL, tiles::kOwner, double>(S, i, mode, smem);
+  } else {
+    if (f)
+      obs_item_c<L, CPL, tiles::kImplicit, float>(S, i, mode, smem);
+    else
+      obs_item_c<L, CPL, tiles::kImplicit, double>(S, i, mode, smem);
+  }
+}
+
+__device__ __forceinline__ void obs_item(const BSub& S, int64_t i, int mode, char* smem) {
   switch (S.ocls) {
-    case 0: obs_item_l<4, 2>(S, i, mode); break;
-    case 1: obs_item_l<4, 3>(S, i, mode); break;
-    case 2: obs_item_l<4, 5>(S, i, mode); break;
-    case 3: obs_item_l<8, 5>(S, i, mode); break;
-    default: obs_item_l<16, 4>(S, i, mode); break;
+    case 0: obs_item_l<4, 2>(S, i, mode, smem); break;
+    case 1: obs_item_l<4, 3>(S, i, mode, smem); break;
+    case 2: obs_item_l<4, 5>(S, i, mode, smem); break;
+    case 3: obs_item_l<8, 5>(S, i, mode, smem); break;
+    default: obs_item_l<16, 4>(S, i, mode, smem); break;
   }
 }
 
@@ -455,22 +469,47 @@ __device__ __forceinline__ void rows_item(const BSub& S, int64_t i, bool split, 
 }
 
 // ------------------------------------------------------------ vector steps
+// Elements per thread whose loads are issued together in the row phases
+// (member pointers may alias, so the compiler cannot hoist a later
+// element's loads above an earlier element's stores by itself).
+constexpr int kEU = 4;
+
 __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, double* s_red) {
   const int r = S.r;
   const int64_t e0 = i * kRC * r, e1 = min(S.n, (i + 1) * kRC) * r;
   double loc = 0.0;
+  if (mode == M_INNER) {  // q = D_K (Y + lambda p) + rho p, every inner iteration
+    const int64_t stride = (int64_t)kEU * blockDim.x;
+    for (int64_t e = e0 + item_tid(); e < e1; e += stride) {
+      double y[kEU], pe[kEU], dk[kEU];
+#pragma unroll
+      for (int u = 0; u < kEU; ++u) {
+        const int64_t ee = e + (int64_t)u * blockDim.x;
+        const bool on = ee < e1;
+        const int64_t eo = on ? ee : e;
+        const int64_t s = eo / r;
+        y[u] = part_sum<float>(S.part, S.bf_ks, S.n, S.ldp, s, (int)(eo % r));
+        pe[u] = S.P[eo];
+        dk[u] = S.dKc[s];
+      }
+#pragma unroll
+      for (int u = 0; u < kEU; ++u) {
+        const int64_t ee = e + (int64_t)u * blockDim.x;
+        if (ee < e1) {
+          const double v = dk[u] * (y[u] + S.lam * pe[u]) + S.rho * pe[u];
+          S.Q[ee] = v;
+          loc += pe[u] * v;
+        }
+      }
+    }
+    const double t = block_sum(loc, s_red);
+    if (item_tid() == 0) S.red0[i] = t;
+    return;
+  }
   for (int64_t e = e0 + item_tid(); e < e1; e += blockDim.x) {
     const int64_t s = e / r;
     const int c = (int)(e % r);
     switch (mode) {
-      case M_INNER: {  // q = D_K (Y + lambda p) + rho p
-        const double y = part_sum<float>(S.part, S.bf_ks, S.n, S.ldp, s, c);
-        const double pe = S.P[e];
-        const double v = S.dKc[s] * (y + S.lam * pe) + S.rho * pe;
-        S.Q[e] = v;
-        loc += pe * v;
-        break;
-      }
       case M_RES: {  // rbar = bbar - (D_K (Y + lambda xbar) + rho xbar)
         const double y = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
         const double xa = S.XA[e];
@@ -519,7 +558,6 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
   }
   double* red = nullptr;
   switch (mode) {
-    case M_INNER: red = S.red0; break;
     case M_RES:
     case M_RES0:
     case M_CERT:
@@ -560,7 +598,7 @@ __device__ __forceinline__ bool inner_stop(const BSub& S, const BState* st, int 
 // rows' global loads are in flight together.  With UPD (inner iteration) the
 // rows are first updated, x += alpha p and r -= alpha q, and r^T r is summed
 // as well: the update and the preconditioner share one pass over the rows.
-constexpr int kPR = 4;
+constexpr int kPR = 8;
 static_assert((kBatchRank * kBatchRank + 4 * kPR * kWave) * 8 <= kSmemBytes, "precond LDS");
 
 template <bool UPD>
@@ -656,12 +694,27 @@ __device__ __forceinline__ void p_rows(const BSub& S, int64_t i, double beta, ch
   const int rows = (int)min((int64_t)kRC, S.n - s0);
   __bf16* th = (__bf16*)smem;
   __bf16* tl = th + kBatchRank * kRC;
-  for (int e = item_tid(); e < rows * r; e += blockDim.x) {
-    const int sr = e / r, c = e % r;
-    const int64_t s = s0 + sr, o = s * r + c;
-    const double pv = S.Z[o] + beta * S.P[o];
-    S.P[o] = pv;
-    split_pair(S.dKc[s] * pv, &th[c * kRC + sr], &tl[c * kRC + sr]);
+  const int ne = rows * r;
+  for (int e = item_tid(); e < ne; e += kEU * blockDim.x) {
+    double z[kEU], pp[kEU], dk[kEU];
+#pragma unroll
+    for (int u = 0; u < kEU; ++u) {
+      const int ee = min(e + u * (int)blockDim.x, ne - 1);
+      const int64_t s = s0 + ee / r, o = s0 * r + ee;
+      z[u] = S.Z[o];
+      pp[u] = S.P[o];
+      dk[u] = S.dKc[s];
+    }
+#pragma unroll
+    for (int u = 0; u < kEU; ++u) {
+      const int ee = e + u * (int)blockDim.x;
+      if (ee < ne) {
+        const int sr = ee / r, c = ee % r;
+        const double pv = z[u] + beta * pp[u];
+        S.P[s0 * r + ee] = pv;
+        split_pair(dk[u] * pv, &th[c * kRC + sr], &tl[c * kRC + sr]);
+      }
+    }
   }
   store_split(S, s0, rows, th, tl);
 }
@@ -804,7 +857,7 @@ __device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, in
         case M_FINAL: gemm_item(S, G_UKT, S.XA, i, smem); break;
       }
       break;
-    case S_OBS: obs_item(S, i, mode); break;
+    case S_OBS: obs_item(S, i, mode, smem); break;
     case S_ROWS: rows_item(S, i, mode == M_INNER, smem); break;
     case S_B:
       switch (mode) {
@@ -1184,6 +1237,11 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     if (d.n > kMaxN) {
       set_error("member %d: n = %lld exceeds the batched limit %lld", b, (long long)d.n,
                 (long long)kMaxN);
+      return CPHIFI_UNSUPPORTED;
+    }
+    if ((int64_t)d.J * d.r * (int64_t)sizeof(double) > kSmemBytes) {
+      set_error("member %d: J r = %lld exceeds the batched gather's LDS copy of B (%d)", b,
+                (long long)d.J * d.r, kSmemBytes / (int)sizeof(double));
       return CPHIFI_UNSUPPORTED;
     }
   }

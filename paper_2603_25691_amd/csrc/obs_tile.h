@@ -76,8 +76,9 @@ __device__ __forceinline__ double group_sum(double v) {
 constexpr int kGroups = 4;  // observations per row unrolled per step
 
 // Per-lane state of one row of the wave for one segment, and the step that
-// consumes kGroups of its observations.
-template <int L, int CPL, int FORM, int MODE>
+// consumes kGroups of its observations.  BL: the factor rows B(j,:) are read
+// from a copy in LDS (`Bsrc`, same row-major layout) instead of from HBM/L2.
+template <int L, int CPL, int FORM, int MODE, bool BL = false>
 struct ObsRow {
   uint32_t cidx[CPL];  // in-bounds column index used for loads
   bool con[CPL];       // real column
@@ -90,7 +91,7 @@ struct ObsRow {
   double acc[CPL];
   int32_t ii[kGroups], jj[kGroups];  // indices of the current step
 
-  __device__ __forceinline__ void init(const ObsDev& d, int cl) {
+  __device__ __forceinline__ void init(const ObsDev& d, int cl, const double* Bsrc) {
     const int r = d.a.r;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
@@ -106,7 +107,7 @@ struct ObsRow {
     Jmax = (uint32_t)(d.J - 1);
     ur = (uint32_t)r;
     Abytes = (const char*)d.a.A;
-    Bbytes = (const char*)d.a.B;
+    Bbytes = (const char*)(BL ? Bsrc : d.a.B);
 #pragma unroll
     for (int u = 0; u < kGroups; ++u) ii[u] = jj[u] = 0;
   }
@@ -194,10 +195,10 @@ struct ObsRow {
   }
 };
 
-// One wave per task (see the file comment).
-template <int L, int CPL, int FORM, int MODE, typename PT>
+// One wave per task (see the file comment).  BL / Bsrc: see ObsRow.
+template <int L, int CPL, int FORM, int MODE, typename PT, bool BL = false>
 __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int64_t task,
-                                         int lane) {
+                                         int lane, const double* Bsrc = nullptr) {
   constexpr int ROWS = 64 / L;  // observations per group
   constexpr int STEP = ROWS * kGroups;
   const ObsArgs& a = d.a;
@@ -206,8 +207,8 @@ __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int
   const int64_t beg = t.beg[task], end = t.end[task];
   const int32_t slot = t.slot[task];
 
-  ObsRow<L, CPL, FORM, MODE> R;
-  R.init(d, cl);
+  ObsRow<L, CPL, FORM, MODE, BL> R;
+  R.init(d, cl, Bsrc);
   auto obs_of = [&](int64_t base, int64_t (&o)[kGroups], bool (&on)[kGroups]) {
 #pragma unroll
     for (int u = 0; u < kGroups; ++u) {
@@ -260,9 +261,9 @@ __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int
 // [s0, s0 + nseg), nseg <= 64/L, read from the CSR obs_ptr; for segments that
 // are not split over several tasks (the caller checks) this gives the same
 // rows as obs_task.
-template <int L, int CPL, int FORM, int MODE, typename PT>
+template <int L, int CPL, int FORM, int MODE, typename PT, bool BL = false>
 __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr, int64_t s0,
-                                         int nseg, int lane) {
+                                         int nseg, int lane, const double* Bsrc = nullptr) {
   const ObsArgs& a = d.a;
   const int g = lane / L, cl = lane % L;
   const bool row_on = g < nseg;
@@ -271,8 +272,8 @@ __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr
   const int64_t end = row_on ? (int64_t)obs_ptr[s + 1] : beg;
   const int64_t last = end > beg ? end - 1 : -1;  // clamp target of masked loads
 
-  ObsRow<L, CPL, FORM, MODE> R;
-  R.init(d, cl);
+  ObsRow<L, CPL, FORM, MODE, BL> R;
+  R.init(d, cl, Bsrc);
   // wave-uniform step count: the longest segment of the wave
   int maxlen = (int)(end - beg);
 #pragma unroll

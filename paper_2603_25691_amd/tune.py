@@ -45,10 +45,15 @@ TAG = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 ESIZE = {"fp64": 8, "fp32": 4, "bf16": 2}
 
 
-def _operand(elt: str, n: int, gen: torch.Generator) -> torch.Tensor:
+def _operand(elt: str, n: int, gen: torch.Generator, ld_align: int = 1) -> torch.Tensor:
     U = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=gen)
     if elt == "fp64":
-        return U
+        ld = (n + ld_align - 1) // ld_align * ld_align
+        if ld == n:
+            return U
+        Up = torch.zeros(n, ld, dtype=torch.float64, device="cuda")
+        Up[:, :n] = U
+        return Up[:, :n]  # row stride ld
     if elt == "fp32":
         return U.float()
     ld = (n + 255) // 256 * 256
@@ -112,7 +117,8 @@ def sweep(ns, rs, elts, out_path: str, reps: int = 5) -> None:
     print(f"wrote {out_path}", file=sys.stderr)
 
 
-def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False) -> None:
+def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False,
+            ld_align: int = 1) -> None:
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
     if calib_mb > 0:
@@ -122,7 +128,7 @@ def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": calib_mb * 2 ** 20}), flush=True)
     for elt in elts:
-        U = _operand(elt, n, gen)
+        U = _operand(elt, n, gen, ld_align)
         X = torch.rand(n, r, dtype=torch.float64, device="cuda", generator=gen)
         Y = torch.empty_like(X)
         ws = torch.empty(C.cphifi_product_workspace_bytes(n, r, C.ELT_BF16) + 256,
@@ -130,6 +136,7 @@ def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False)
         ms = _time(lambda: product(U, X, elt, trans and elt != "bf16", (0, 0), 0, out=Y,
                                    workspace=ws), reps)
         print(json.dumps({"elt": elt, "n": n, "r": r, "ms": ms, "reps": reps,
+                          "ld": U.stride(0),
                           "algorithmic_bytes": ESIZE[elt] * n * n + 16 * n * r}), flush=True)
         del U
         torch.cuda.empty_cache()
@@ -215,6 +222,8 @@ def main(argv=None):
     m.add_argument("--elt", nargs="+", default=["bf16", "fp64"])
     m.add_argument("--reps", type=int, default=4)
     m.add_argument("--calib-mb", type=int, default=1024)
+    m.add_argument("--ld-align", type=int, default=1,
+                   help="FP64 operand row stride rounded up to a multiple of this")
     b = sub.add_parser("batch")
     b.add_argument("--count", type=int, default=64)
     b.add_argument("--seed", type=int, default=0)
@@ -226,7 +235,7 @@ def main(argv=None):
     elif a.cmd == "batch":
         batch(a.count, a.seed, a.out, a.reps)
     else:
-        measure(a.n, a.r, a.elt, a.reps, a.calib_mb)
+        measure(a.n, a.r, a.elt, a.reps, a.calib_mb, ld_align=a.ld_align)
 
 
 if __name__ == "__main__":

@@ -100,6 +100,7 @@ def test_batch_workspace_is_members_plus_scalars():
 @pytest.mark.parametrize("case,status", [
     ("rank49", c.UNSUPPORTED), ("fp64", c.UNSUPPORTED), ("fp32", c.UNSUPPORTED),
     ("explicit", c.UNSUPPORTED), ("n_too_large", c.UNSUPPORTED),
+    ("J_r_too_large", c.UNSUPPORTED),
 ])
 def test_batch_create_rejects_unsupported_members_without_gpu(case, status):
     d = _bf16_desc()
@@ -116,6 +117,8 @@ def test_batch_create_rejects_unsupported_members_without_gpu(case, status):
         d.gamma = 1.0
     elif case == "n_too_large":
         d.n, d.q = 70000, 70000
+    elif case == "J_r_too_large":  # B must fit the gather's LDS copy: J r <= 8192
+        d.r, d.J = 48, 171
     descs = [_bf16_desc(), d]
     inputs = [good, inp]
     nbytes = c.cphifi_batch_workspace_bytes(descs)

@@ -114,6 +114,22 @@ def test_apply_matches_oracle(name, uploaded):
     assert np.max(np.abs(y - want)) <= 1e-12 * np.max(np.abs(want)) * 10
 
 
+def test_gather_with_factor_rows_beyond_lds_copy():
+    """J r = 12000 doubles (96 KB): the gather reads B rows through L2 instead
+    of from its LDS copy (used up to 16 KB); right-hand side and operator
+    against the oracle."""
+    p = make_small(35, n=200, I=5, J=300, r=40, q=6000, kernel_param=0.1)
+    assert p.J * p.r * 8 > 65536
+    dp = upload(p)
+    s = UISolver(dp, p.lam, p.rho, p.tol)
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    b = host(s.rhs())
+    assert rel(b, O.rhs_matrix(p.K, O.mttkrp_observed(p.y, Zhat, p.obs_t, p.n))) <= 1e-12
+    X = np.random.default_rng(7).standard_normal((p.n, p.r))
+    y = host(s.apply(dev(X)))
+    assert rel(y, O.matvec_twostep(p.K, Zhat, p.obs_t, p.lam, p.rho, X)) <= 1e-12
+
+
 @pytest.mark.parametrize("name", ["c1", "ragged-r17", "r40"])
 def test_explicit_zhat_apply_matches_implicit(name, uploaded):
     p, dp = uploaded(name)
