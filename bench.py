@@ -34,19 +34,20 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 
-# HBM bytes per launch of the dominant kernel at the default workload, from
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled by a calibration copy
-# (profiles/products_n30658_r40_hbm_counters.md).  Keyed by kernel and shape;
-# clear an entry whenever that kernel changes.
 # K and U_K are stored with row strides rounded up to 16 doubles: every row
 # then starts on a 128-byte line, so a product's 16-element chunk of a row is
-# one line (with the odd stride n = 30658 each chunk straddles two lines and
-# the FP64 product fetched 1.24x its algorithmic bytes instead of 1.01x).
+# one line (with the stride n = 30658, 245264 bytes, each chunk straddles two
+# lines and the FP64 product fetched 1.24x its algorithmic bytes, not 1.01x).
 KROW_ALIGN = 16
 # Tiles of the batched solver written by `python -m paper_2603_25691_amd.tune batch`
 # on MI355X (the defaults apply when the file is absent).
 BATCH_TILES = os.path.join(ROOT, "paper_2603_25691_amd", "tiles_batch_mi355x.txt")
-MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2>", 30658, 40): 1.9963e9}
+# HBM bytes per launch of the product kernels at the default workload (rows
+# stored as above), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled
+# by a calibration copy (profiles/products_n30658_r40_hbm_counters.md).  Keyed
+# by kernel and shape; clear an entry whenever that kernel changes.
+MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2>", 30658, 40): 1.9939e9,
+                    ("gemm_k4_kernel<double, 3, 4, 4, false, 2>", 30658, 40): 7.6458e9}
 
 
 def log(msg: str) -> None:
@@ -299,8 +300,8 @@ def main():
     roof64 = {"bound": "hbm", "achieved": fp64_bytes / (fp64["gemm_avg_ms"] * 1e6),
               "peak": HBM_PEAK_GBPS, "unit": "GB/s"}
     roof64["frac"] = roof64["achieved"] / roof64["peak"]
-    roof64["traffic"] = None
     roof64["kernel"] = "gemm_k4_kernel<double, 3, 4, 4, false, 2> (K X and U_K^T R products)"
+    roof64["traffic"] = MEASURED_TRAFFIC.get((roof64["kernel"].split(" (")[0], n, r))
 
     # --------------------------------------------------- headline (mixed) form
     prec = a.precision
