@@ -25,6 +25,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   tiles::gemm_k4_tile<TA, NB, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
 }
 
+// FP64 products: 4x4x4 MFMA tile over NC4 groups of 4 columns.
+template <int NC4, int MW, int S, bool TRANS, int VW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_kernel(
+    GArgs g) {
+  if (g.done != nullptr && *g.done) return;
+  __shared__ double xs[tiles::k4x4_lds_elems<NC4, S>()];
+  tiles::gemm_f64x4_tile<NC4, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
+}
+
 template <int NB, int MW, int S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_kernel(
     GArgs g) {
@@ -91,6 +100,54 @@ int dispatch_cfg_k4(int mw, int s, int nb, const GArgs& g, int ksplit, hipStream
   return CPHIFI_INVALID_ARG;
 }
 
+// Column groups of 4 for r: rounded up to an even count (8 columns), which
+// bounds the instantiations and stays within the partials' 16 ceil(r/16).
+inline int f64_groups(int r) { return 2 * ((r + 7) / 8); }
+
+template <int NC4, int MW, int S, bool TRANS>
+int launch_f64(const GArgs& g, int ksplit, hipStream_t st) {
+  const int64_t rows = 4 * MW * 16;
+  dim3 grid((unsigned)((g.n + rows - 1) / rows), (unsigned)ksplit);
+  constexpr int VW = TRANS ? 1 : 2;
+  const bool vec_ok =
+      !TRANS && g.ldu % 2 == 0 && (reinterpret_cast<uintptr_t>(g.U) % 16) == 0;
+  if (vec_ok)
+    hipLaunchKernelGGL((gemm_f64_kernel<NC4, MW, S, TRANS, VW>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<NC4, MW, S, TRANS, 1>), grid, dim3(256), 0, st, g);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+template <int MW, int S, bool TRANS>
+int dispatch_nc4_f64(int nc4, const GArgs& g, int ksplit, hipStream_t st) {
+  switch (nc4) {
+    case 2: return launch_f64<2, MW, S, TRANS>(g, ksplit, st);
+    case 4: return launch_f64<4, MW, S, TRANS>(g, ksplit, st);
+    case 6: return launch_f64<6, MW, S, TRANS>(g, ksplit, st);
+    case 8: return launch_f64<8, MW, S, TRANS>(g, ksplit, st);
+    case 10: return launch_f64<10, MW, S, TRANS>(g, ksplit, st);
+    case 12: return launch_f64<12, MW, S, TRANS>(g, ksplit, st);
+    case 14: return launch_f64<14, MW, S, TRANS>(g, ksplit, st);
+    case 16: return launch_f64<16, MW, S, TRANS>(g, ksplit, st);
+  }
+  set_error("unsupported column group count %d", nc4);
+  return CPHIFI_INVALID_ARG;
+}
+
+template <bool TRANS>
+int dispatch_cfg_f64(int mw, int s, int nc4, const GArgs& g, int ksplit, hipStream_t st) {
+  if (mw == 1 && s == 4) return dispatch_nc4_f64<1, 4, TRANS>(nc4, g, ksplit, st);
+  if (mw == 1 && s == 8) return dispatch_nc4_f64<1, 8, TRANS>(nc4, g, ksplit, st);
+  if (mw == 2 && s == 4) return dispatch_nc4_f64<2, 4, TRANS>(nc4, g, ksplit, st);
+  if (mw == 2 && s == 8) return dispatch_nc4_f64<2, 8, TRANS>(nc4, g, ksplit, st);
+  if (mw == 4 && s == 2) return dispatch_nc4_f64<4, 2, TRANS>(nc4, g, ksplit, st);
+  // (4, 4): the 16x16x4 MFMA tile (columns in blocks of 16)
+  if (mw == 4 && s == 4) return dispatch_nb_k4<double, 4, 4, TRANS>((g.r + 15) / 16, g, ksplit, st);
+  set_error("unsupported FP64 product tile (mw=%d, s=%d)", mw, s);
+  return CPHIFI_INVALID_ARG;
+}
+
 template <int NB, int MW, int S>
 int launch_bf16(const GArgs& g, int ksplit, hipStream_t st) {
   const int64_t rows = 4 * MW * 16;
@@ -135,6 +192,35 @@ int occ_k4(int nb) {
   return e == hipSuccess && blocks > 0 ? blocks : 1;
 }
 
+template <int MW, int S, bool TRANS>
+int occ_f64(int nc4) {
+  constexpr int VW = TRANS ? 1 : 2;
+  int blocks = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (nc4) {
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f64_kernel<2, MW, S, TRANS, VW>, 256, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f64_kernel<4, MW, S, TRANS, VW>, 256, 0); break;
+    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f64_kernel<6, MW, S, TRANS, VW>, 256, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f64_kernel<8, MW, S, TRANS, VW>, 256, 0); break;
+    case 10: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f64_kernel<10, MW, S, TRANS, VW>, 256, 0); break;
+    case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f64_kernel<12, MW, S, TRANS, VW>, 256, 0); break;
+    case 14: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f64_kernel<14, MW, S, TRANS, VW>, 256, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_f64_kernel<16, MW, S, TRANS, VW>, 256, 0); break;
+  }
+  return e == hipSuccess && blocks > 0 ? blocks : 1;
+}
+
+template <bool TRANS>
+int occ_cfg_f64(int mw, int s, int nc4) {
+  if (mw == 1 && s == 4) return occ_f64<1, 4, TRANS>(nc4);
+  if (mw == 1 && s == 8) return occ_f64<1, 8, TRANS>(nc4);
+  if (mw == 2 && s == 4) return occ_f64<2, 4, TRANS>(nc4);
+  if (mw == 2 && s == 8) return occ_f64<2, 8, TRANS>(nc4);
+  if (mw == 4 && s == 2) return occ_f64<4, 2, TRANS>(nc4);
+  if (mw == 4 && s == 4) return occ_k4<double, 4, 4, TRANS>((2 * nc4 + 7) / 8);
+  return 1;
+}
+
 template <int MW, int S>
 int occ_bf16(int nb) {
   int blocks = 0;
@@ -171,7 +257,8 @@ int occ_cfg_bf16(int mw, int s, int nb) {
 int gemm_occupancy(Elt elt, bool trans, int mw, int s, int r) {
   const int nb = (r + 15) / 16;
   switch (elt) {
-    case Elt::F64: return trans ? occ_cfg_k4<double, true>(mw, s, nb) : occ_cfg_k4<double, false>(mw, s, nb);
+    case Elt::F64:
+      return trans ? occ_cfg_f64<true>(mw, s, f64_groups(r)) : occ_cfg_f64<false>(mw, s, f64_groups(r));
     case Elt::F32: return trans ? occ_cfg_k4<float, true>(mw, s, nb) : occ_cfg_k4<float, false>(mw, s, nb);
     case Elt::BF16: return occ_cfg_bf16(mw, s, nb);
   }
@@ -184,6 +271,9 @@ bool gemm_cfg_valid(Elt elt, int mw, int s) {
   if (elt == Elt::BF16)
     return (mw == 1 && s == 4) || (mw == 2 && s == 2) || (mw == 2 && s == 4) ||
            (mw == 4 && s == 2);
+  if (elt == Elt::F64)
+    return (mw == 1 && (s == 4 || s == 8)) || (mw == 2 && (s == 4 || s == 8)) ||
+           (mw == 4 && (s == 2 || s == 4));
   return (mw == 1 && (s == 4 || s == 8)) || (mw == 2 && (s == 4 || s == 8)) ||
          (mw == 4 && s == 4);
 }
@@ -285,13 +375,23 @@ GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu) {
   if (table_tile(elt, trans && elt != Elt::BF16, n, r, &mw, &s, &ks))
     return make_gemm_plan(elt, trans && elt != Elt::BF16, n, r, mw, s, ks, num_cu);
   // (tiles that fit two workgroups per CU without spilling at this r)
-  const bool nb4 = r > 48;
   switch (elt) {
     case Elt::BF16: return make_gemm_plan(elt, false, n, r, 4, 2, 0, num_cu);
     case Elt::F32: return trans ? make_gemm_plan(elt, true, n, r, 4, 4, 0, num_cu)
                                 : make_gemm_plan(elt, false, n, r, 2, 4, 0, num_cu);
-    case Elt::F64: return trans ? make_gemm_plan(elt, true, n, r, 2, 4, 0, num_cu)
-                                : make_gemm_plan(elt, false, n, r, nb4 ? 2 : 4, 4, 0, num_cu);
+    case Elt::F64: {
+      // Measured at n = 30658, r = 40 on one MI355X (128-byte rows): NN 16x16x4
+      // 4x4 tile 1.69 ms vs 4x4x4 4x2 1.72 ms (its 64-byte row chunks use half
+      // a line per chunk); transposed 4x4x4 4x2 1.57 ms (every load 4 full
+      // lines) vs 1.68 ms for the next best.  Non-spilling tiles for larger r.
+      const int g4 = f64_groups(r);
+      if (trans)
+        return g4 <= 10 ? make_gemm_plan(elt, true, n, r, 4, 2, 0, num_cu)
+               : g4 <= 14 ? make_gemm_plan(elt, true, n, r, 2, 4, 0, num_cu)
+                          : make_gemm_plan(elt, true, n, r, 1, 8, 0, num_cu);
+      return r <= 48 ? make_gemm_plan(elt, false, n, r, 4, 4, 0, num_cu)
+                     : make_gemm_plan(elt, false, n, r, 2, 4, 0, num_cu);
+    }
   }
   return make_gemm_plan(elt, trans, n, r, 2, 8, 0, num_cu);
 }
@@ -324,8 +424,8 @@ int launch_gemm(Elt elt, bool trans, const GemmPlan& gp, const void* U, int64_t 
   g.ldp = nb * 16;
   g.done = done;
   if (elt == Elt::F64)
-    return trans ? dispatch_cfg_k4<double, true>(gp.mw, gp.s, nb, g, gp.ksplit, st)
-                 : dispatch_cfg_k4<double, false>(gp.mw, gp.s, nb, g, gp.ksplit, st);
+    return trans ? dispatch_cfg_f64<true>(gp.mw, gp.s, f64_groups(r), g, gp.ksplit, st)
+                 : dispatch_cfg_f64<false>(gp.mw, gp.s, f64_groups(r), g, gp.ksplit, st);
   return trans ? dispatch_cfg_k4<float, true>(gp.mw, gp.s, nb, g, gp.ksplit, st)
                : dispatch_cfg_k4<float, false>(gp.mw, gp.s, nb, g, gp.ksplit, st);
 }

@@ -273,6 +273,206 @@ __device__ __forceinline__ void gemm_k4_tile(const GArgs& g, int64_t bx, int64_t
       }
 }
 
+// --------------------------------------------------- FP64 4x4x4 (4-block) tile
+// The FP64 16x16x4 MFMA needs N in multiples of 16 (r = 40 pads to 48, 17 %
+// wasted), and one wave can start one only every ~128 cycles, so the pipe
+// (64 cycles per instruction) is full only while both waves of a SIMD issue.
+// v_mfma_f64_4x4x4_4b runs four independent 4x4x4 products per instruction at
+// the same flop rate (16 cycles each) and a single wave can issue them back to
+// back.  Its lanes: block b = (lane / 4) % 4; A_b[i][k] in lane 16 k + 4 b + i,
+// B_b[k][j] in lane 16 k + 4 b + j, D_b[i][j] in lane 16 i + 4 b + j.  Here the
+// four blocks are four groups of 4 output rows sharing one 4-column group of X:
+// lane (li = lane % 16, kk = lane / 16) supplies A = U[row li][k kk] -- the same
+// operand as the 16x16x4 tile -- and B = X[k kk][4 c + lane % 4]; the result
+// of column group c sits at row 4 ((lane / 4) % 4) + lane / 16, column
+// 4 c + lane % 4.  NC4 column groups cover 4 NC4 >= r columns.
+__device__ __forceinline__ double mfma4x4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int NC4, int S>
+constexpr int k4x4_lds_elems() {
+  return 2 * (4 * S) * (4 * NC4 + 16 / S);
+}
+
+template <int NC4, int MW, int S, bool TRANS, int VW>
+__device__ __forceinline__ void gemm_f64x4_tile(const GArgs& g, int64_t bx, int64_t by,
+                                                double* xs, int tid) {
+  typedef double VecT __attribute__((ext_vector_type(VW)));
+  static_assert(S % VW == 0, "S must be a multiple of the vector width");
+  constexpr int BK = 4 * S;
+  constexpr int NC = 4 * NC4;
+  constexpr int LDX = NC + 16 / S;  // pad spreads the 4 k-groups over distinct banks
+  constexpr int XE = BK * NC;
+  constexpr int XB = BK * LDX;
+  constexpr int XPT = (XE + 255) / 256;
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, kk = lane >> 4;
+  const int jj = lane & 3;                                // column within a group
+  const int orow = 4 * ((lane >> 2) & 3) + (lane >> 4);  // output row within 16
+  const int64_t n = g.n;
+  const int64_t ldu = g.ldu;
+  const int64_t mbase = bx * (4 * MW * 16) + (int64_t)wave * (MW * 16);
+  const int64_t kbeg = by * g.kper;
+  const int64_t kend = min(n, kbeg + g.kper);
+  const double* __restrict__ U = (const double*)g.U;
+
+  const double* abase[MW];
+#pragma unroll
+  for (int mb = 0; mb < MW; ++mb) {
+    const int64_t rc = min(mbase + mb * 16 + li, n - 1);
+    abase[mb] = TRANS ? U + (int64_t)(kk * S) * ldu + rc : U + rc * ldu + kk * S;
+  }
+  const double* __restrict__ X = g.X;
+  int xoff[XPT], xlds[XPT], xkid[XPT];
+  bool xon[XPT];
+#pragma unroll
+  for (int j = 0; j < XPT; ++j) {
+    const int e = tid + j * 256;
+    const int kidx = e / NC, c = e % NC;
+    xkid[j] = kidx;
+    xoff[j] = kidx * (int)g.ldx + c;
+    xlds[j] = kidx * LDX + c;
+    xon[j] = e < XE && c < g.r;
+  }
+
+  double acc[MW][NC4];
+#pragma unroll
+  for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) acc[mb][c] = 0.0;
+
+  const int64_t span = kend - kbeg;
+  const int64_t nfull = span > 0 ? span / BK : 0;
+  const bool has_tail = span > 0 && (span % BK) != 0;
+  const int64_t nchunk = nfull + (has_tail ? 1 : 0);
+
+  auto loadA = [&](double (&dst)[MW][S], int64_t k0) {
+#pragma unroll
+    for (int mb = 0; mb < MW; ++mb) {
+      if (TRANS) {
+        const double* p = abase[mb] + k0 * ldu;
+#pragma unroll
+        for (int s = 0; s < S; ++s) dst[mb][s] = p[(int64_t)s * ldu];
+      } else {
+        const double* p = abase[mb] + k0;
+#pragma unroll
+        for (int v = 0; v < S / VW; ++v) {
+          const VecT t = *(const VecT*)(p + v * VW);
+#pragma unroll
+          for (int w = 0; w < VW; ++w) dst[mb][v * VW + w] = t[w];
+        }
+      }
+    }
+  };
+  auto loadA_tail = [&](double (&dst)[MW][S], int64_t k0) {
+#pragma unroll
+    for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int64_t k = k0 + kk * S + s;
+        const int64_t dk = min(k, n - 1) - kk * S;
+        const double v = TRANS ? abase[mb][dk * ldu] : abase[mb][dk];
+        dst[mb][s] = (k < kend) ? v : 0.0;
+      }
+  };
+  auto stageX = [&](double (&xr)[XPT], int64_t k0, bool tail) {
+    const double* xp = X + k0 * g.ldx;
+#pragma unroll
+    for (int j = 0; j < XPT; ++j) {
+      double v = 0.0;
+      const bool on = xon[j] && (!tail || k0 + xkid[j] < kend);
+      if (on) {
+        v = xp[xoff[j]];
+        if (g.xscale != nullptr) v *= g.xscale[k0 + xkid[j]];
+      }
+      xr[j] = v;
+    }
+  };
+  auto storeX = [&](int buf, const double (&xr)[XPT]) {
+#pragma unroll
+    for (int j = 0; j < XPT; ++j)
+      if (tid + j * 256 < XE) xs[buf * XB + xlds[j]] = xr[j];
+  };
+  auto compute = [&](const double (&a)[MW][S], int buf) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double b[NC4];
+#pragma unroll
+      for (int c = 0; c < NC4; ++c) b[c] = xs[buf * XB + (kk * S + s) * LDX + 4 * c + jj];
+#pragma unroll
+      for (int mb = 0; mb < MW; ++mb)
+#pragma unroll
+        for (int c = 0; c < NC4; ++c) acc[mb][c] = mfma4x4(a[mb][s], b[c], acc[mb][c]);
+    }
+  };
+  auto fetch = [&](double (&xr)[XPT], double (&dst)[MW][S], int64_t c) {
+    const int64_t k0 = kbeg + c * BK;
+    const bool tail = c == nfull;
+    stageX(xr, k0, tail);
+    if (tail)
+      loadA_tail(dst, k0);
+    else
+      loadA(dst, k0);
+  };
+  auto fetch_full = [&](double (&xr)[XPT], double (&dst)[MW][S], int64_t c) {
+    const int64_t k0 = kbeg + c * BK;
+    stageX(xr, k0, false);
+    loadA(dst, k0);
+  };
+  // Same chunk loop as gemm_k4_tile (ping-pong registers, branch-free steady
+  // state over full chunks, tail-aware epilogue).
+  if (nchunk > 0) {
+    double a0[MW][S], a1[MW][S];
+    double xr[XPT];
+    fetch(xr, a0, 0);
+    storeX(0, xr);
+    __syncthreads();
+    int64_t c = 0;
+    while (c + 2 < nfull) {
+      fetch_full(xr, a1, c + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a0, (int)(c & 1));
+      storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      ++c;
+      fetch_full(xr, a0, c + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, (int)(c & 1));
+      storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      ++c;
+    }
+    for (;;) {
+      bool more = c + 1 < nchunk;
+      if (more) fetch(xr, a1, c + 1);
+      compute(a0, (int)(c & 1));
+      if (more) storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      if (!more) break;
+      ++c;
+      more = c + 1 < nchunk;
+      if (more) fetch(xr, a0, c + 1);
+      compute(a1, (int)(c & 1));
+      if (more) storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      if (!more) break;
+      ++c;
+    }
+  }
+
+  double* part = (double*)g.part + by * n * g.ldp;
+#pragma unroll
+  for (int mb = 0; mb < MW; ++mb) {
+    const int64_t row = mbase + mb * 16 + orow;
+    if (row < n) {
+#pragma unroll
+      for (int c = 0; c < NC4; ++c) part[row * g.ldp + 4 * c + jj] = acc[mb][c];
+    }
+  }
+}
+
 // ------------------------------------------------------- BF16 (16x16x32) tile
 // U is a zero-padded bf16 copy (row stride ldu >= round_up(n, BK)); the n x r
 // operand arrives pre-split as hi + lo bf16 parts, transposed to c-major rows

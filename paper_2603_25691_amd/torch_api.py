@@ -295,7 +295,11 @@ def product(U: torch.Tensor, X: torch.Tensor, elt: str = "fp64", trans: bool = F
         if e == _c.ELT_BF16:
             mw, s = 4, 2
         elif e == _c.ELT_F64:
-            mw, s = (2, 4) if trans or r > 48 else (4, 4)
+            g4 = 2 * ((r + 7) // 8)
+            if trans:
+                mw, s = (4, 2) if g4 <= 10 else (2, 4) if g4 <= 14 else (1, 8)
+            else:
+                mw, s = (4, 4) if r <= 48 else (2, 4)
         else:
             mw, s = (4, 4) if trans else (2, 4)
     ws_bytes = _c.cphifi_product_workspace_bytes(n, r, e)

@@ -38,7 +38,7 @@ import torch
 from . import cphifi as C
 from .torch_api import product
 
-TILES = {"fp64": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
+TILES = {"fp64": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 2), (4, 4)],
          "fp32": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
          "bf16": [(1, 4), (2, 2), (2, 4), (4, 2)]}
 TAG = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
@@ -74,14 +74,14 @@ def _time(fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def sweep(ns, rs, elts, out_path: str, reps: int = 5) -> None:
+def sweep(ns, rs, elts, out_path: str, reps: int = 5, ld_align: int = 1) -> None:
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
     lines = []
     for elt in elts:
         transes = (False,) if elt == "bf16" else (False, True)
         for n in sorted(ns):
-            U = _operand(elt, n, gen)
+            U = _operand(elt, n, gen, ld_align)
             for r in sorted(rs):
                 X = torch.rand(n, r, dtype=torch.float64, device="cuda", generator=gen)
                 Y = torch.empty_like(X)
@@ -216,6 +216,8 @@ def main(argv=None):
     s.add_argument("--elt", nargs="+", default=["fp64", "bf16"])
     s.add_argument("--out", default="tiles.txt")
     s.add_argument("--reps", type=int, default=5)
+    s.add_argument("--ld-align", type=int, default=1,
+                   help="FP64 operand row stride rounded up to a multiple of this")
     m = sub.add_parser("measure")
     m.add_argument("--n", type=int, required=True)
     m.add_argument("--r", type=int, required=True)
@@ -231,7 +233,7 @@ def main(argv=None):
     b.add_argument("--out", default="tiles_batch.txt")
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
-        sweep(a.n, a.r, a.elt, a.out, a.reps)
+        sweep(a.n, a.r, a.elt, a.out, a.reps, ld_align=a.ld_align)
     elif a.cmd == "batch":
         batch(a.count, a.seed, a.out, a.reps)
     else:

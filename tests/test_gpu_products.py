@@ -18,7 +18,7 @@ if torch.cuda.is_available():
     from paper_2603_25691_amd import cphifi as C  # noqa: E402
     from paper_2603_25691_amd.torch_api import product  # noqa: E402
 
-TILES = {"fp64": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
+TILES = {"fp64": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 2), (4, 4)],
          "fp32": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
          "bf16": [(1, 4), (2, 2), (2, 4), (4, 2)]}
 
