@@ -18,14 +18,15 @@ __global__ __launch_bounds__(256) void obs_kernel(TaskView t, ObsDev d) {
   obs_task<L, CPL, FORM, MODE, PT>(t, d, task, threadIdx.x & 63);
 }
 
-// Short segments: wave w takes segments [w kSegPerWave, ...), 64/L at a time.
+// Lane-row form: wave w takes segments [w spw, (w + 1) spw), 64/L at a time
+// (spw a multiple of 64/L, at most kSegPerWave).
 template <int L, int CPL, int FORM, int MODE, typename PT>
 __global__ __launch_bounds__(256) void obs_rows_kernel(ObsDev d, const int32_t* obs_ptr,
-                                                       int64_t n) {
+                                                       int64_t n, int spw) {
   if (d.a.done != nullptr && *d.a.done) return;
   constexpr int ROWS = 64 / L;
-  const int64_t sb = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kSegPerWave;
-  for (int k = 0; k < kSegPerWave; k += ROWS) {
+  const int64_t sb = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * spw;
+  for (int k = 0; k < spw; k += ROWS) {
     const int64_t s0 = sb + k;
     if (s0 >= n) break;
     tiles::obs_rows<L, CPL, FORM, MODE, PT>(d, obs_ptr, s0, (int)min((int64_t)ROWS, n - s0),
@@ -59,15 +60,15 @@ __global__ __launch_bounds__(256) void obs_lds_kernel(TaskView t, ObsDev d) {
 
 template <int L, int CPL, int FORM, int MODE, typename PT>
 __global__ __launch_bounds__(256) void obs_rows_lds_kernel(ObsDev d, const int32_t* obs_ptr,
-                                                           int64_t n) {
+                                                           int64_t n, int spw) {
   if (d.a.done != nullptr && *d.a.done) return;
   extern __shared__ __attribute__((aligned(16))) double sB[];
   stage_rows(sB, d.a.B, d.J * d.a.r);
   constexpr int ROWS = 64 / L;
-  for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w * kSegPerWave < n;
+  for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w * spw < n;
        w += (int64_t)gridDim.x * 4) {
-    const int64_t sb = w * kSegPerWave;
-    for (int k = 0; k < kSegPerWave; k += ROWS) {
+    const int64_t sb = w * spw;
+    for (int k = 0; k < spw; k += ROWS) {
       const int64_t s0 = sb + k;
       if (s0 >= n) break;
       tiles::obs_rows<L, CPL, FORM, MODE, PT, true>(d, obs_ptr, s0,
@@ -91,20 +92,34 @@ __global__ void segment_reduce_kernel(const int32_t* __restrict__ mseg,
   out[(int64_t)mseg[m] * r + lane] = acc;
 }
 
+// Segments per wave of the lane-row form: enough waves for about 16 per CU
+// (latency-bound work), at least one segment per lane row.
+template <int L>
+int rows_per_wave(int64_t nseg) {
+  constexpr int ROWS = 64 / L;
+  constexpr int64_t kTargetWaves = 256 * 16;
+  int64_t spw = (nseg + kTargetWaves - 1) / kTargetWaves;
+  spw = (spw + ROWS - 1) / ROWS * ROWS;
+  return (int)std::max<int64_t>(ROWS, std::min<int64_t>(kSegPerWave, spw));
+}
+
 template <int L, int CPL, int FORM, int MODE>
 int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hipStream_t st) {
   const size_t lds = sizeof(double) * (size_t)d.J * d.a.r;
+  const int spw = rows_per_wave<L>(t.nseg);
   if (FORM != tiles::kExplicit && lds <= (size_t)kObsLdsBytes) {
     if (t.rows) {
-      const int64_t units = (t.nseg + kSegPerWave - 1) / kSegPerWave;
+      const int64_t units = (t.nseg + spw - 1) / spw;
       const int64_t blocks = std::min<int64_t>(kObsLdsGrid, (units + 3) / 4);
       if (blocks == 0) return CPHIFI_OK;
       if (pf)
         hipLaunchKernelGGL((obs_rows_lds_kernel<L, CPL, FORM, MODE, float>),
-                           dim3((unsigned)blocks), dim3(256), lds, st, d, t.obs_ptr, t.nseg);
+                           dim3((unsigned)blocks), dim3(256), lds, st, d, t.obs_ptr, t.nseg,
+                           spw);
       else
         hipLaunchKernelGGL((obs_rows_lds_kernel<L, CPL, FORM, MODE, double>),
-                           dim3((unsigned)blocks), dim3(256), lds, st, d, t.obs_ptr, t.nseg);
+                           dim3((unsigned)blocks), dim3(256), lds, st, d, t.obs_ptr, t.nseg,
+                           spw);
     } else {
       const int64_t blocks = std::min<int64_t>(kObsLdsGrid, (tv.ntask + 3) / 4);
       if (blocks == 0) return CPHIFI_OK;
@@ -119,14 +134,14 @@ int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hi
     return CPHIFI_OK;
   }
   if (t.rows) {
-    const int64_t blocks = (t.nseg + 4 * kSegPerWave - 1) / (4 * kSegPerWave);
+    const int64_t blocks = (t.nseg + 4 * (int64_t)spw - 1) / (4 * (int64_t)spw);
     if (blocks == 0) return CPHIFI_OK;
     if (pf)
       hipLaunchKernelGGL((obs_rows_kernel<L, CPL, FORM, MODE, float>), dim3((unsigned)blocks),
-                         dim3(256), 0, st, d, t.obs_ptr, t.nseg);
+                         dim3(256), 0, st, d, t.obs_ptr, t.nseg, spw);
     else
       hipLaunchKernelGGL((obs_rows_kernel<L, CPL, FORM, MODE, double>), dim3((unsigned)blocks),
-                         dim3(256), 0, st, d, t.obs_ptr, t.nseg);
+                         dim3(256), 0, st, d, t.obs_ptr, t.nseg, spw);
     CPHIFI_CHECK_LAUNCH();
     return CPHIFI_OK;
   }

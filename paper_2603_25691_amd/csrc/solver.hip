@@ -864,9 +864,14 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   p->tasks.first = (int32_t*)(ws + L.tfirst);
   p->tasks.mseg = (int32_t*)(ws + L.mseg);
   p->tasks.mptr = (int32_t*)(ws + L.mptr);
-  // Short segments (at most kShortSegment observations on average, none split):
-  // one lane row per segment instead of one wave per segment.
-  p->tasks.rows = mseg.empty() && q <= kShortSegment * n;
+  // One lane row per segment instead of one wave per segment when no segment
+  // is split and the segments are short (at most kShortSegment observations
+  // on average) or of nearly equal length (the longest at most 5/4 of the
+  // mean), so the rows of a wave finish together: each segment's setup (its
+  // indices, A row and Xhat row) then overlaps with 64/L - 1 others.
+  int64_t maxlen = 0;
+  for (int64_t s = 0; s < n; ++s) maxlen = std::max<int64_t>(maxlen, ptr[s + 1] - ptr[s]);
+  p->tasks.rows = mseg.empty() && (q <= kShortSegment * n || 4 * maxlen * n <= 5 * q);
   p->tasks.obs_ptr = in->obs_ptr;
   p->tasks.nseg = n;
   p->tasks.owner = owner;
