@@ -593,77 +593,98 @@ __device__ __forceinline__ bool inner_stop(const BSub& S, const BState* st, int 
 }
 
 // z = ((r U_V) had D) U_V^T for the chunk's rows (eq. fx in the eigenbasis of
-// K); partial r^T z.  Lane c of a wave owns column c; a wave takes kPR rows at
-// a time, so every U_V element read from LDS feeds kPR multiply-adds and the
-// rows' global loads are in flight together.  With UPD (inner iteration) the
-// rows are first updated, x += alpha p and r -= alpha q, and r^T r is summed
-// as well: the update and the preconditioner share one pass over the rows.
-constexpr int kPR = 8;
-static_assert((kBatchRank * kBatchRank + 4 * kPR * kWave) * 8 <= kSmemBytes, "precond LDS");
+// K); partial r^T z.  The two r x r products run on the FP64 4x4x4 MFMA
+// (v_mfma_f64_4x4x4_4b; block b = (lane / 4) % 4, A_b[i][k] in lane
+// 16 k + 4 b + i, B_b[k][j] in lane 16 k + 4 b + j, D_b[i][j] in lane
+// 16 i + 4 b + j): a wave takes 16 rows at a time, the four blocks being four
+// groups of 4 rows that share one group of 4 columns; r is padded to a
+// multiple of 4 with zeros (at most kBatchRank).  With UPD (inner iteration)
+// the rows are first updated, x += alpha p and r -= alpha q, while they are
+// staged, and r^T r is summed as well: update and preconditioner share one
+// pass over the rows.
+constexpr int kPC4 = kBatchRank / 4;      // column groups at most
+constexpr int kPLT = kBatchRank + 1;      // row stride of a wave's 16-row tile
+static_assert((kBatchRank * kBatchRank + 4 * 16 * kPLT) * 8 <= kSmemBytes, "precond LDS");
 
 template <bool UPD>
 __device__ __forceinline__ void prec_rows(const BSub& S, int64_t i, char* smem, double* s_red,
                                           double alpha = 0.0) {
   const int r = S.r;
-  double* uv = (double*)smem;
-  double* buf = uv + kBatchRank * kBatchRank;
-  for (int e = item_tid(); e < r * r; e += blockDim.x) uv[e] = S.UV[e];
+  const int nc4 = (r + 3) / 4, rp = 4 * nc4;
+  double* uv = (double*)smem;  // rp x rp
+  const int wave = item_tid() >> 6, lane = item_tid() & 63;
+  double* wt = uv + kBatchRank * kBatchRank + wave * (16 * kPLT);
+  for (int e = item_tid(); e < rp * rp; e += blockDim.x) {
+    const int j = e / rp, c = e % rp;
+    uv[e] = (j < r && c < r) ? S.UV[j * r + c] : 0.0;
+  }
   __syncthreads();
-  const int wave = item_tid() >> 6, c = item_tid() & 63;
-  double* wb = buf + wave * (kPR * kWave);
+  const int li = lane & 15, kk = lane >> 4, jj = lane & 3;
+  const int orow = 4 * ((lane >> 2) & 3) + kk;
   const int64_t s0 = i * kRC, s1 = min(S.n, s0 + kRC);
-  const bool col = c < r;
   double loc = 0.0, loc_rr = 0.0;
-  for (int64_t sb = s0 + wave * kPR; sb < s1; sb += 4 * kPR) {
-    double t[kPR], u[kPR], dd[kPR];
-#pragma unroll
-    for (int k = 0; k < kPR; ++k) {
-      const bool on = col && sb + k < s1;
-      const int64_t o = (sb + k) * r + c;
-      if (UPD) {
-        double rv = 0.0;
-        if (on) {
+  for (int64_t row0 = s0 + 16 * wave; row0 < s1; row0 += 64) {
+    for (int e = lane; e < 16 * rp; e += 64) {
+      const int ri = e / rp, c = e % rp;
+      const int64_t s = row0 + ri;
+      double v = 0.0;
+      if (s < s1 && c < r) {
+        const int64_t o = s * r + c;
+        if (UPD) {
           S.X[o] += alpha * S.P[o];
-          rv = S.R[o] - alpha * S.Q[o];
-          S.R[o] = rv;
+          v = S.R[o] - alpha * S.Q[o];
+          S.R[o] = v;
+          loc_rr += v * v;
+        } else {
+          v = S.R[o];
         }
-        t[k] = rv;
-        loc_rr += rv * rv;
-      } else {
-        t[k] = on ? S.R[o] : 0.0;
       }
-      dd[k] = on ? S.D[o] : 0.0;
-      wb[k * kWave + c] = t[k];
+      wt[ri * kPLT + c] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    double acc[kPC4];
+#pragma unroll
+    for (int c = 0; c < kPC4; ++c) acc[c] = 0.0;
+    for (int ks = 0; ks < nc4; ++ks) {  // (r U_V)
+      const double a = wt[li * kPLT + 4 * ks + kk];
+#pragma unroll
+      for (int c = 0; c < kPC4; ++c)
+        if (c < nc4)
+          acc[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, uv[(4 * ks + kk) * rp + 4 * c + jj],
+                                                      acc[c], 0, 0, 0);
+    }
+    const int64_t s = row0 + orow;
+    const bool ron = s < s1;
+    double tv[kPC4];  // r at this lane's output elements, for r^T z
+#pragma unroll
+    for (int c = 0; c < kPC4; ++c) {
+      const int col = 4 * c + jj;
+      tv[c] = c < nc4 ? wt[orow * kPLT + col] : 0.0;
+      if (c < nc4) acc[c] *= (ron && col < r) ? S.D[s * r + col] : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int k = 0; k < kPR; ++k) u[k] = 0.0;
-    if (col) {
-      for (int j = 0; j < r; ++j) {
-        const double w = uv[j * r + c];
+    for (int c = 0; c < kPC4; ++c)
+      if (c < nc4) wt[orow * kPLT + 4 * c + jj] = acc[c];
+    __builtin_amdgcn_wave_barrier();
+    double z[kPC4];
 #pragma unroll
-        for (int k = 0; k < kPR; ++k) u[k] += wb[k * kWave + j] * w;
-      }
+    for (int c = 0; c < kPC4; ++c) z[c] = 0.0;
+    for (int ks = 0; ks < nc4; ++ks) {  // (. U_V^T)
+      const double a = wt[li * kPLT + 4 * ks + kk];
+#pragma unroll
+      for (int c = 0; c < kPC4; ++c)
+        if (c < nc4)
+          z[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, uv[(4 * c + jj) * rp + 4 * ks + kk], z[c],
+                                                    0, 0, 0);
     }
-    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int k = 0; k < kPR; ++k) wb[k * kWave + c] = u[k] * dd[k];
-    __builtin_amdgcn_wave_barrier();
-    if (col) {
-      double o[kPR];
-#pragma unroll
-      for (int k = 0; k < kPR; ++k) o[k] = 0.0;
-      for (int j = 0; j < r; ++j) {
-        const double w = uv[c * r + j];
-#pragma unroll
-        for (int k = 0; k < kPR; ++k) o[k] += wb[k * kWave + j] * w;
+    for (int c = 0; c < kPC4; ++c) {
+      const int col = 4 * c + jj;
+      if (c < nc4 && ron && col < r) {
+        S.Z[s * r + col] = z[c];
+        loc += tv[c] * z[c];
       }
-#pragma unroll
-      for (int k = 0; k < kPR; ++k)
-        if (sb + k < s1) {
-          S.Z[(sb + k) * r + c] = o[k];
-          loc += t[k] * o[k];
-        }
     }
     __builtin_amdgcn_wave_barrier();
   }

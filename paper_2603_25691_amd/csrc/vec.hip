@@ -240,39 +240,88 @@ __global__ void mirror_kernel(const DevScalars* src, DevScalars* dst) {
   for (int i = threadIdx.x; i < kWords; i += blockDim.x) d[i] = s[i];
 }
 
-// out[s,:] = ((t U_V) * D[s,:]) U_V^T, t = in[s,:] or the sum of partials.
-// One wave per row; U_V sits in LDS, t and u are exchanged through LDS.
-template <typename PT>
-__global__ __launch_bounds__(256) void prec_mid_kernel(const PT* part, int ksplit, int ldp,
-                                                       const double* in, int64_t n, int r,
-                                                       const double* UV, const double* D,
-                                                       double* out, const double* dotwith,
-                                                       double* red, const int32_t* done) {
+// out[s,:] = ((t U_V) * D[s,:]) U_V^T (the middle step of eq. fx), t = in[s,:]
+// or the sum of split-K partials; red <- partials of dotwith . out.  The two
+// r x r products run on the FP64 4x4x4 MFMA
+// (v_mfma_f64_4x4x4_4b: four independent 4x4x4 products; block b =
+// (lane / 4) % 4, A_b[i][k] in lane 16 k + 4 b + i, B_b[k][j] in lane
+// 16 k + 4 b + j, D_b[i][j] in lane 16 i + 4 b + j).  A wave takes 16 rows at
+// a time: the four blocks are four groups of 4 rows sharing one group of 4
+// columns, so lane (li = lane % 16, kk = lane / 16) supplies A = T[row li][k]
+// and the result of column group c lands at row 4 ((lane / 4) % 4) + lane / 16,
+// column 4 c + lane % 4.  r is padded to rp = 4 NC4 with zeros.  The rows of T
+// (and of T U_V * D, for the second product) pass through a per-wave LDS tile,
+// U_V through a block-shared one.
+template <typename PT, int NC4>
+__global__ __launch_bounds__(256) void prec_mid_mfma_kernel(const PT* part, int ksplit, int ldp,
+                                                            const double* in, int64_t n, int r,
+                                                            const double* UV, const double* D,
+                                                            double* out, const double* dotwith,
+                                                            double* red, const int32_t* done) {
   if (is_done(done)) return;
-  __shared__ double uv[kMaxRank * kMaxRank];
-  __shared__ double buf[4][kMaxRank];
-  for (int e = threadIdx.x; e < r * r; e += blockDim.x) uv[e] = UV[e];
+  constexpr int RP = 4 * NC4;
+  constexpr int LT = RP + 1;  // row stride of the per-wave tile (bank spread)
+  extern __shared__ double lds[];
+  double* uv = lds;                                   // RP x RP
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* wt = lds + RP * RP + wave * (16 * LT);     // 16 x LT
+  for (int e = threadIdx.x; e < RP * RP; e += blockDim.x) {
+    const int j = e / RP, c = e % RP;
+    uv[e] = (j < r && c < r) ? UV[j * r + c] : 0.0;
+  }
   __syncthreads();
-  const int wave = threadIdx.x >> 6, c = threadIdx.x & 63;
+  const int li = lane & 15, kk = lane >> 4, jj = lane & 3;
+  const int orow = 4 * ((lane >> 2) & 3) + kk;
   double loc = 0.0;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < n; s += (int64_t)gridDim.x * 4) {
-    double t = 0.0;
-    if (c < r) t = part != nullptr ? part_sum(part, ksplit, n, ldp, s, c) : in[s * r + c];
-    buf[wave][c] = t;
-    __builtin_amdgcn_wave_barrier();
-    double u = 0.0;
-    if (c < r) {
-      for (int j = 0; j < r; ++j) u += buf[wave][j] * uv[j * r + c];
-      u *= D[s * r + c];
+  for (int64_t rb = (int64_t)blockIdx.x * 4 + wave; rb * 16 < n; rb += (int64_t)gridDim.x * 4) {
+    const int64_t row0 = rb * 16;
+    for (int e = lane; e < 16 * RP; e += 64) {
+      const int i = e / RP, c = e % RP;
+      const int64_t s = row0 + i;
+      double v = 0.0;
+      if (s < n && c < r) v = part != nullptr ? part_sum(part, ksplit, n, ldp, s, c) : in[s * r + c];
+      wt[i * LT + c] = v;
     }
     __builtin_amdgcn_wave_barrier();
-    buf[wave][c] = u;
+    double acc[NC4];
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < NC4; ++ks) {  // (T U_V): k in groups of 4
+      const double a = wt[li * LT + 4 * ks + kk];
+#pragma unroll
+      for (int c = 0; c < NC4; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, uv[(4 * ks + kk) * RP + 4 * c + jj],
+                                                    acc[c], 0, 0, 0);
+    }
+    const int64_t s = row0 + orow;
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) {
+      const int col = 4 * c + jj;
+      acc[c] *= (s < n && col < r) ? D[s * r + col] : 0.0;
+    }
     __builtin_amdgcn_wave_barrier();
-    if (c < r) {
-      double o = 0.0;
-      for (int j = 0; j < r; ++j) o += buf[wave][j] * uv[c * r + j];
-      out[s * r + c] = o;
-      if (dotwith != nullptr) loc += dotwith[s * r + c] * o;
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) wt[orow * LT + 4 * c + jj] = acc[c];
+    __builtin_amdgcn_wave_barrier();
+    double z[NC4];
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) z[c] = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < NC4; ++ks) {  // (. U_V^T)
+      const double a = wt[li * LT + 4 * ks + kk];
+#pragma unroll
+      for (int c = 0; c < NC4; ++c)
+        z[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, uv[(4 * c + jj) * RP + 4 * ks + kk], z[c],
+                                                  0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) {
+      const int col = 4 * c + jj;
+      if (s < n && col < r) {
+        out[s * r + col] = z[c];
+        if (dotwith != nullptr) loc += dotwith[s * r + col] * z[c];
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -280,6 +329,34 @@ __global__ __launch_bounds__(256) void prec_mid_kernel(const PT* part, int kspli
     const double b = block_sum(loc);
     if (threadIdx.x == 0) red[blockIdx.x] = b;
   }
+}
+
+template <typename PT>
+int launch_prec_mfma(int nc4, int blocks, const PT* part, int ksplit, int ldp, const double* in,
+                     int64_t n, int r, const double* UV, const double* D, double* out,
+                     const double* dotwith, double* red, const int32_t* done, hipStream_t st) {
+  const size_t lds = sizeof(double) * ((size_t)16 * nc4 * nc4 + 4 * 16 * (4 * nc4 + 1));
+  // (r > 60 needs more than the default 64 KB of dynamic LDS)
+#define CPHIFI_PREC_CASE(K)                                                                   \
+  case K:                                                                                     \
+    if (lds > 65536)                                                                          \
+      CPHIFI_HIP(hipFuncSetAttribute((const void*)prec_mid_mfma_kernel<PT, K>,                \
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
+    hipLaunchKernelGGL((prec_mid_mfma_kernel<PT, K>), dim3(blocks), dim3(256), lds, st, part, \
+                       ksplit, ldp, in, n, r, UV, D, out, dotwith, red, done);                \
+    break;
+  switch (nc4) {
+    CPHIFI_PREC_CASE(1) CPHIFI_PREC_CASE(2) CPHIFI_PREC_CASE(3) CPHIFI_PREC_CASE(4)
+    CPHIFI_PREC_CASE(5) CPHIFI_PREC_CASE(6) CPHIFI_PREC_CASE(7) CPHIFI_PREC_CASE(8)
+    CPHIFI_PREC_CASE(9) CPHIFI_PREC_CASE(10) CPHIFI_PREC_CASE(11) CPHIFI_PREC_CASE(12)
+    CPHIFI_PREC_CASE(13) CPHIFI_PREC_CASE(14) CPHIFI_PREC_CASE(15) CPHIFI_PREC_CASE(16)
+    default:
+      set_error("preconditioner: rank %d beyond %d", r, kMaxRank);
+      return CPHIFI_INVALID_ARG;
+  }
+#undef CPHIFI_PREC_CASE
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
 }
 
 __global__ void axpby_kernel(double* y, double a, const double* x, double b, int64_t len,
@@ -550,14 +627,15 @@ int launch_prec_mid(const void* part, bool is_float, int ksplit, int ldp, const 
                     int64_t n, int r, const double* UV, const double* D, double* out,
                     const double* dotwith, double* red, int* nblk_out, const int32_t* done,
                     hipStream_t st) {
-  const int nb = (int)std::min<int64_t>(kMaxVecBlocks, (n + 3) / 4);
-  if (is_float)
-    hipLaunchKernelGGL(prec_mid_kernel<float>, dim3(nb), dim3(256), 0, st, (const float*)part,
-                       ksplit, ldp, in, n, r, UV, D, out, dotwith, red, done);
-  else
-    hipLaunchKernelGGL(prec_mid_kernel<double>, dim3(nb), dim3(256), 0, st, (const double*)part,
-                       ksplit, ldp, in, n, r, UV, D, out, dotwith, red, done);
-  CPHIFI_CHECK_LAUNCH();
+  // 16 rows per wave and step, 4 waves per block
+  const int nb = (int)std::min<int64_t>(kMaxVecBlocks, (n + 63) / 64);
+  const int nc4 = (r + 3) / 4;
+  const int rc = is_float ? launch_prec_mfma<float>(nc4, nb, (const float*)part, ksplit, ldp, in,
+                                                    n, r, UV, D, out, dotwith, red, done, st)
+                          : launch_prec_mfma<double>(nc4, nb, (const double*)part, ksplit, ldp,
+                                                     in, n, r, UV, D, out, dotwith, red, done,
+                                                     st);
+  if (rc != CPHIFI_OK) return rc;
   if (nblk_out) *nblk_out = nb;
   return CPHIFI_OK;
 }
