@@ -47,7 +47,7 @@ BATCH_TILES = os.path.join(ROOT, "paper_2603_25691_amd", "tiles_batch_mi355x.txt
 # by a calibration copy (profiles/products_n30658_r40_hbm_counters.md).  Keyed
 # by kernel and shape; clear an entry whenever that kernel changes.
 MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2>", 30658, 40): 1.9939e9,
-                    ("gemm_k4_kernel<double, 3, 4, 4, false, 2>", 30658, 40): 7.6458e9}
+                    ("gemm_f64_kernel<10, 4, 2, true, 1>", 30658, 40): 7.6937e9}
 
 
 def log(msg: str) -> None:
@@ -300,7 +300,7 @@ def main():
     roof64 = {"bound": "hbm", "achieved": fp64_bytes / (fp64["gemm_avg_ms"] * 1e6),
               "peak": HBM_PEAK_GBPS, "unit": "GB/s"}
     roof64["frac"] = roof64["achieved"] / roof64["peak"]
-    roof64["kernel"] = "gemm_k4_kernel<double, 3, 4, 4, false, 2> (K X and U_K^T R products)"
+    roof64["kernel"] = "gemm_f64_kernel<10, 4, 2, true, 1> (K X and U_K X products)"
     roof64["traffic"] = MEASURED_TRAFFIC.get((roof64["kernel"].split(" (")[0], n, r))
 
     # --------------------------------------------------- headline (mixed) form

@@ -76,7 +76,10 @@ enum cphifi_precision {
 enum cphifi_flags {
   CPHIFI_FLAG_WARM_START = 1,   /* W holds x0 on entry to solve (else x0 = 0) */
   CPHIFI_FLAG_VALIDATE = 2,     /* plan_create checks obs_* ranges on the host */
-  CPHIFI_FLAG_TIME_KERNELS = 4, /* record HIP events around each n x n product */
+  CPHIFI_FLAG_TIME_KERNELS = 4, /* record HIP events around the n x n products of
+                                   one kernel: FP64 plans the transposed FP64
+                                   product (K X, U_K X), mixed plans the low-
+                                   precision one */
   CPHIFI_FLAG_NO_PRECOND = 8,   /* plain CG (identity preconditioner), FP64 only */
   CPHIFI_FLAG_EIGENBASIS = 16   /* FP64 PCG in the eigenbasis of K (2 n x n passes
                                    per iteration instead of 4); same solution */

@@ -136,7 +136,7 @@ def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False,
         ms = _time(lambda: product(U, X, elt, trans and elt != "bf16", (0, 0), 0, out=Y,
                                    workspace=ws), reps)
         print(json.dumps({"elt": elt, "n": n, "r": r, "ms": ms, "reps": reps,
-                          "ld": U.stride(0),
+                          "trans": bool(trans and elt != "bf16"), "ld": U.stride(0),
                           "algorithmic_bytes": ESIZE[elt] * n * n + 16 * n * r}), flush=True)
         del U
         torch.cuda.empty_cache()
@@ -226,6 +226,8 @@ def main(argv=None):
     m.add_argument("--calib-mb", type=int, default=1024)
     m.add_argument("--ld-align", type=int, default=1,
                    help="FP64 operand row stride rounded up to a multiple of this")
+    m.add_argument("--trans", action="store_true",
+                   help="the transposed product (FP64 / FP32 only)")
     b = sub.add_parser("batch")
     b.add_argument("--count", type=int, default=64)
     b.add_argument("--seed", type=int, default=0)
@@ -237,7 +239,7 @@ def main(argv=None):
     elif a.cmd == "batch":
         batch(a.count, a.seed, a.out, a.reps)
     else:
-        measure(a.n, a.r, a.elt, a.reps, a.calib_mb, ld_align=a.ld_align)
+        measure(a.n, a.r, a.elt, a.reps, a.calib_mb, trans=a.trans, ld_align=a.ld_align)
 
 
 if __name__ == "__main__":
