@@ -81,8 +81,13 @@ enum cphifi_flags {
                                    product (K X, U_K X), mixed plans the low-
                                    precision one */
   CPHIFI_FLAG_NO_PRECOND = 8,   /* plain CG (identity preconditioner), FP64 only */
-  CPHIFI_FLAG_EIGENBASIS = 16   /* FP64 PCG in the eigenbasis of K (2 n x n passes
+  CPHIFI_FLAG_EIGENBASIS = 16,  /* FP64 PCG in the eigenbasis of K (2 n x n passes
                                    per iteration instead of 4); same solution */
+  CPHIFI_FLAG_NO_UKT_COPY = 32  /* plans with n >= 4096 keep a transposed copy of
+                                   U_K in the workspace (n ldk doubles, made at
+                                   plan creation), so U_K^T X runs the faster
+                                   transposed FP64 kernel too; this flag drops
+                                   the copy (row-major kernel for U_K^T X) */
 };
 
 /* Problem description (host struct). */

@@ -36,6 +36,7 @@ FLAG_VALIDATE = 2
 FLAG_TIME_KERNELS = 4
 FLAG_NO_PRECOND = 8
 FLAG_EIGENBASIS = 16
+FLAG_NO_UKT_COPY = 32
 
 PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 

@@ -1084,6 +1084,14 @@ struct BatchLayout {
   size_t total;
 };
 
+// A member's plan: the batched kernel runs its own product tiles on U_K as
+// given, so the plan needs no transposed copy of U_K.
+cphifi_ui_desc member_desc(const cphifi_ui_desc& d) {
+  cphifi_ui_desc m = d;
+  m.flags |= CPHIFI_FLAG_NO_UKT_COPY;
+  return m;
+}
+
 int batch_layout(int count, const cphifi_ui_desc* descs, BatchLayout* L) {
   if (count < 1 || count > kMaxBatch) {
     set_error("batch count %d outside 1..%d", count, kMaxBatch);
@@ -1108,7 +1116,8 @@ int batch_layout(int count, const cphifi_ui_desc* descs, BatchLayout* L) {
   L->member_bytes.resize(count);
   for (int b = 0; b < count; ++b) {
     size_t bytes = 0;
-    const int rc = cphifi_ui_workspace_bytes(&descs[b], &bytes);
+    const cphifi_ui_desc d = member_desc(descs[b]);
+    const int rc = cphifi_ui_workspace_bytes(&d, &bytes);
     if (rc != CPHIFI_OK) return rc;
     L->member[b] = take(bytes);
     L->member_bytes[b] = bytes;
@@ -1298,7 +1307,7 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
   }
   int max_rounds = 0;
   for (int b = 0; b < count; ++b) {
-    const cphifi_ui_desc& d = descs[b];
+    const cphifi_ui_desc d = member_desc(descs[b]);
     const cphifi_ui_inputs& in = inputs[b];
     int rc = cphifi_ui_plan_create(&bt->plans[b], &d, &in, ws + L.member[b], L.member_bytes[b],
                                    stream);

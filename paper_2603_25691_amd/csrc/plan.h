@@ -27,7 +27,7 @@ struct Layout {
   size_t red[3];
   size_t sc, sc2, hist;
   size_t V, UV, dV, D, dKc;
-  size_t ulp, utlp, xthi, xtlo;
+  size_t ulp, utlp, xthi, xtlo, ukt;
   size_t total;
   int64_t ldl;
   int64_t ntask_max, nslot_max, nmulti_max;
@@ -35,6 +35,12 @@ struct Layout {
 };
 
 inline int64_t eff_ldk(const cphifi_ui_desc& d) { return d.ldk > 0 ? d.ldk : d.n; }
+// Plans of this size or larger keep a transposed copy of U_K (see
+// CPHIFI_FLAG_NO_UKT_COPY).
+constexpr int64_t kUktMinN = 4096;
+inline bool keeps_ukt(const cphifi_ui_desc& d) {
+  return d.n >= kUktMinN && !(d.flags & CPHIFI_FLAG_NO_UKT_COPY);
+}
 inline int eff_maxit(const cphifi_ui_desc& d) { return d.maxit > 0 ? d.maxit : 500; }
 
 // Workspace layout of one subproblem (offsets into the caller's buffer).
@@ -68,6 +74,7 @@ struct cphifi_plan {
   double* hist = nullptr;
   double *V = nullptr, *UV = nullptr, *dV = nullptr, *D = nullptr, *dKc = nullptr;
   Elt lp = Elt::F64;
+  double* ukt = nullptr; // U_K transposed (eigenvector k = column k), or NULL
   void* ulp = nullptr;   // U_K rounded, row-major U (BF16 form only)
   void* utlp = nullptr;  // U_K rounded, row-major U^T (eigenvector k = row k)
   __bf16 *xthi = nullptr, *xtlo = nullptr;

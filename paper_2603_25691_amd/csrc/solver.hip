@@ -75,6 +75,7 @@ Layout make_layout(const cphifi_ui_desc& d) {
   L.dV = take(sizeof(double) * r);
   L.D = take(sizeof(double) * nr);
   L.dKc = take(sizeof(double) * n);
+  if (keeps_ukt(d)) L.ukt = take(sizeof(double) * (size_t)n * eff_ldk(d));
   L.ldl = round_up(n, kLowpAlign);
   if (d.precision == CPHIFI_MIXED_BF16) {
     L.ulp = take(sizeof(__bf16) * (size_t)n * L.ldl);
@@ -180,18 +181,26 @@ int prod_U(cphifi_plan* p, Elt elt, const double* X, const double* xscale,
   return timed_end(p, e0);
 }
 
-// part <- U^T X at element type elt (row-major NN product on U^T).
+// part <- U^T X at element type elt (row-major NN product on U^T, or in FP64
+// the transposed product on the plan's copy of U when it keeps one).
 int prod_Ut(cphifi_plan* p, Elt elt, const double* X, const int32_t* done) {
   if (elt == Elt::BF16)
     TRY(launch_split_bf16(X, p->r, (int)p->r, nullptr, p->n, p->xthi, p->xtlo, p->L.ldl, done,
                           p->st));
+  const bool tcopy = elt == Elt::F64 && p->ukt != nullptr;
   hipEvent_t e0;
-  TRY(timed_begin(p, elt, false, &e0));
+  TRY(timed_begin(p, elt, tcopy, &e0));
   switch (elt) {
     case Elt::F64:
-      TRY(launch_gemm(Elt::F64, false, p->gp64n, p->in.UK, p->ldk, p->n, X, p->r, (int)p->r,
-                      nullptr, p->part, done, p->st));
-      p->last_ksplit = p->gp64n.ksplit;
+      if (tcopy) {
+        TRY(launch_gemm(Elt::F64, true, p->gp64t, p->ukt, p->ldk, p->n, X, p->r, (int)p->r,
+                        nullptr, p->part, done, p->st));
+        p->last_ksplit = p->gp64t.ksplit;
+      } else {
+        TRY(launch_gemm(Elt::F64, false, p->gp64n, p->in.UK, p->ldk, p->n, X, p->r, (int)p->r,
+                        nullptr, p->part, done, p->st));
+        p->last_ksplit = p->gp64n.ksplit;
+      }
       break;
     case Elt::F32:
       TRY(launch_gemm(Elt::F32, false, p->gplpn, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
@@ -929,6 +938,11 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
                            choose_gemm(Elt::F64, false, n, rr, p->num_cu), p->num_cu);
   p->gp64t = plan_from_env("CPHIFI_TILE_F64T", Elt::F64, true, n, rr,
                            choose_gemm(Elt::F64, true, n, rr, p->num_cu), p->num_cu);
+  if (keeps_ukt(*d)) {
+    p->ukt = (double*)(ws + L.ukt);
+    if ((rc = launch_convert_lowp(Elt::F64, true, in->UK, p->ldk, n, p->ukt, p->ldk, st)))
+      return fail(rc);
+  }
   // timed kernel (CPHIFI_FLAG_TIME_KERNELS): FP64 plans time the transposed FP64
   // products (K X and U_K X, three of the four per iteration), mixed plans the
   // low-precision ones

@@ -30,6 +30,18 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(c.cphifi_solve_info) == 48
 
 
+def test_workspace_holds_transposed_eigenvectors_from_4096():
+    n, r = 5000, 10
+    base = c.cphifi_ui_workspace_bytes(c.make_desc(n, r, 100000, 100, 20))
+    lean = c.cphifi_ui_workspace_bytes(c.make_desc(n, r, 100000, 100, 20,
+                                                   flags=c.FLAG_NO_UKT_COPY))
+    assert base - lean >= 8 * n * n
+    assert base - lean <= 8 * n * n + 512
+    small = c.make_desc(4095, r, 100000, 100, 20)
+    assert c.cphifi_ui_workspace_bytes(small) == c.cphifi_ui_workspace_bytes(
+        c.make_desc(4095, r, 100000, 100, 20, flags=c.FLAG_NO_UKT_COPY))
+
+
 def test_workspace_grows_with_problem_and_precision():
     small = c.cphifi_ui_workspace_bytes(c.make_desc(200, 5, 2000, 20, 10))
     big = c.cphifi_ui_workspace_bytes(c.make_desc(3000, 40, 600000, 100, 200))

@@ -114,6 +114,33 @@ def test_apply_matches_oracle(name, uploaded):
     assert np.max(np.abs(y - want)) <= 1e-12 * np.max(np.abs(want)) * 10
 
 
+def test_transposed_eigenvector_copy():
+    """n >= 4096: the plan keeps a transposed copy of U_K, so U_K^T X runs the
+    transposed FP64 kernel.  Preconditioner against the oracle's eq. fx, and
+    FP64 and mixed solves against a plan without the copy."""
+    p = make_small(36, n=4500, I=150, J=4, r=6, q=27000, kernel_param=0.05)
+    dp = upload(p)
+    s1 = UISolver(dp, p.lam, p.rho, 1e-10)
+    s2 = UISolver(dp, p.lam, p.rho, 1e-10, flags=C.FLAG_NO_UKT_COPY)
+    s1.setup()
+    s2.setup()
+    X = np.random.default_rng(10).standard_normal((p.n, p.r))
+    z1, z2 = host(s1.precond(dev(X))), host(s2.precond(dev(X)))
+    dK, UK = O.kernel_eig(p.K)
+    dV, UV = np.linalg.eigh(O.gram_V(p.A, p.B))
+    assert rel(z1, O.precond_apply(UK, dK, UV, dV, p.gamma, p.lam, p.rho, X)) <= 1e-8
+    assert rel(z1, z2) <= 1e-12
+    W1, i1 = s1.solve_subproblem()
+    W1 = W1.clone()
+    W2, i2 = s2.solve_subproblem()
+    assert i1.status == C.OK and i2.status == C.OK
+    assert O.e_kw(p.K, host(W1), host(W2)) <= 1e-9
+    m1 = UISolver(dp, p.lam, p.rho, 1e-8, precision="mixed_bf16")
+    Wm, im = m1.solve_subproblem()
+    assert im.status == C.OK and im.relres_true <= 1e-8
+    assert O.e_kw(p.K, host(Wm), host(W1)) <= 1e-6
+
+
 def test_gather_with_factor_rows_beyond_lds_copy():
     """J r = 12000 doubles (96 KB): the gather reads B rows through L2 instead
     of from its LDS copy (used up to 16 KB); right-hand side and operator
