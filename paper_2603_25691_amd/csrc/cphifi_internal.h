@@ -194,6 +194,14 @@ int launch_apply_finish(const void* part, bool is_float, int ksplit, int ldp, in
                         const int32_t* done, hipStream_t st);
 int launch_dot(const double* a, const double* b, int64_t len, double* red, int* nblk_out,
                const int32_t* done, hipStream_t st);
+// One PCG iteration's x/r update fused with the eigenbasis preconditioner
+// z = ((r U_V) had D) U_V^T: alpha from the p^T q partials, x += alpha p,
+// r -= alpha q; partials of r^T r -> red_rr and of r^T z -> red_rz (one per
+// block, *nblk_out blocks); breakdown handling as launch_update_xr.
+int launch_update_prec(double* x, double* r, const double* p, const double* q, int64_t n,
+                       int rank, const double* UV, const double* D, double* z,
+                       const double* red_pq, int nblk_pq, double* red_rr, double* red_rz,
+                       int* nblk_out, DevScalars* sc, int it, hipStream_t st);
 int launch_update_xr(double* x, double* r, const double* p, const double* q, int64_t len,
                      const double* red_pq, int nblk_pq, double* red_rr, int* nblk_out,
                      DevScalars* sc, int it, hipStream_t st);

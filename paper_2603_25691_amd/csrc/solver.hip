@@ -183,8 +183,9 @@ int prod_U(cphifi_plan* p, Elt elt, const double* X, const double* xscale,
 
 // part <- U^T X at element type elt (row-major NN product on U^T, or in FP64
 // the transposed product on the plan's copy of U when it keeps one).
-int prod_Ut(cphifi_plan* p, Elt elt, const double* X, const int32_t* done) {
-  if (elt == Elt::BF16)
+int prod_Ut(cphifi_plan* p, Elt elt, const double* X, const int32_t* done,
+            bool presplit = false) {
+  if (elt == Elt::BF16 && !presplit)
     TRY(launch_split_bf16(X, p->r, (int)p->r, nullptr, p->n, p->xthi, p->xtlo, p->L.ldl, done,
                           p->st));
   const bool tcopy = elt == Elt::F64 && p->ukt != nullptr;
@@ -221,7 +222,10 @@ int ksplit_of(const cphifi_plan* p, Elt /*elt*/) { return p->last_ksplit; }
 
 // Gather-dot-scatter over the observations: out <- G applied to the product
 // held in part (gather mode), optionally storing Xhat.
-int obs_gather(cphifi_plan* p, Elt elt, double* xhat, double* out, const int32_t* done) {
+// With split (lane-row form only), the rows go out as the hi/lo BF16 operand
+// of the next product instead of to out.
+int obs_gather(cphifi_plan* p, Elt elt, double* xhat, double* out, const int32_t* done,
+               bool split = false) {
   ObsArgs a{};
   a.n = p->n;
   a.r = (int)p->r;
@@ -238,6 +242,11 @@ int obs_gather(cphifi_plan* p, Elt elt, double* xhat, double* out, const int32_t
   a.out = out;
   a.tpart = p->tpart;
   a.done = done;
+  if (split) {
+    a.xt_hi = p->xthi;
+    a.xt_lo = p->xtlo;
+    a.ldxt = p->L.ldl;
+  }
   return launch_obs(ObsMode::Gather, elt != Elt::F64, p->tasks, a, p->I, p->J, p->st);
 }
 
@@ -271,9 +280,13 @@ int op_precond_paper(cphifi_plan* p, const double* x, double* z, double* red, in
 // ybar = D_K U^T G(U D_K xbar) + lambda D_K xbar + rho xbar at element type elt.
 int op_apply_eig(cphifi_plan* p, Elt elt, const double* xb, double* yb, double* red, int* nblk,
                  const int32_t* done) {
+  // BF16 with the lane-row gather: the gather writes the split operand of
+  // U^T Yhat1 itself (the split of U (D_K xbar) before it has zeroed the
+  // padding rows and columns of that operand).
+  const bool fuse = elt == Elt::BF16 && p->tasks.rows;
   TRY(prod_U(p, elt, xb, p->dKc, done));
-  TRY(obs_gather(p, elt, nullptr, p->vec[V_Y1], done));
-  TRY(prod_Ut(p, elt, p->vec[V_Y1], done));
+  TRY(obs_gather(p, elt, nullptr, p->vec[V_Y1], done, fuse));
+  TRY(prod_Ut(p, elt, p->vec[V_Y1], done, fuse));
   return launch_apply_finish(p->part, elt != Elt::F64, ksplit_of(p, elt), p->ldp, p->n,
                              (int)p->r, nullptr, xb, p->dKc, p->d.lambda, p->d.rho, yb, red, nblk,
                              done, p->st);
@@ -333,9 +346,11 @@ int check_every(const cphifi_plan* p) {
 // reads the convergence flag that iteration's check wrote to host memory.
 // The stream keeps `every` iterations of work queued meanwhile; those left
 // over after convergence return at once.
+// fused_eig: the preconditioner is the eigenbasis one (op_precond_eig); the
+// iteration then runs the x/r update and the preconditioner as one kernel.
 int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double* b, double* x,
             bool have_x0, double tol, int maxit, const PcgVecs& v, DevScalars* sc,
-            double* hist, int hist_len, PcgOut* out) {
+            double* hist, int hist_len, PcgOut* out, bool fused_eig = false) {
   const int64_t len = p->n * p->r;
   hipStream_t st = p->st;
   int nb_bb = 0, nb_rr = 0, nb_rz = 0, nb_pq = 0;
@@ -361,7 +376,13 @@ int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double
   for (int it = 0; it < maxit; ++it) {
     p->cur_tag = 2 * it;
     TRY(apply(v.P, v.Q, red0, &nb_pq, &sc->done));
-    TRY(launch_update_xr(x, v.R, v.P, v.Q, len, red0, nb_pq, red1, &nb_rr, sc, it, st));
+    if (fused_eig) {
+      TRY(launch_update_prec(x, v.R, v.P, v.Q, p->n, (int)p->r, p->UV, p->D, v.Z, red0, nb_pq,
+                             red1, red2, &nb_rr, sc, it, st));
+      nb_rz = nb_rr;
+    } else {
+      TRY(launch_update_xr(x, v.R, v.P, v.Q, len, red0, nb_pq, red1, &nb_rr, sc, it, st));
+    }
     TRY(launch_check_conv(red1, nb_rr, sc, it, hist, hist_len, p->d_flag, st));
     CPHIFI_HIP(hipEventRecord(p->pev[it % kPollRing], st));
     if (it >= every) {
@@ -370,7 +391,7 @@ int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double
     }
     if (it + 1 == maxit) break;
     p->cur_tag = 2 * it + 1;
-    TRY(precond(v.R, v.Z, red2, &nb_rz, &sc->done));
+    if (!fused_eig) TRY(precond(v.R, v.Z, red2, &nb_rz, &sc->done));
     TRY(launch_update_p(v.P, v.Z, len, red2, nb_rz, sc, it, st));
   }
   p->cur_tag = -1;
@@ -444,7 +465,7 @@ int solve_fp64(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* in
     };
     TRY(run_pcg(p, A, M, p->vec[V_RB], p->vec[V_XB], warm, p->d.tol, maxit,
                 PcgVecs{p->vec[V_R2], p->vec[V_Z2], p->vec[V_P2], p->vec[V_Q2]}, p->sc, p->hist,
-                p->L.hist_len, &o));
+                p->L.hist_len, &o, true));
     TRY(rotate_out(p, Elt::F64, p->vec[V_XB], W));
   } else {
     OpFn A = [p](const double* x, double* y, double* red, int* nb, const int32_t* done) {
@@ -557,7 +578,7 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
       PcgOut o;
       TRY(run_pcg(p, A, M, rbar, p->vec[V_XB], false, inner_tol, maxit,
                   PcgVecs{p->vec[V_R2], p->vec[V_Z2], p->vec[V_P2], p->vec[V_Q2]}, p->sc,
-                  nullptr, 0, &o));
+                  nullptr, 0, &o, true));
       total_inner += o.iters;
       if (o.status == CPHIFI_NUMERIC) {
         status = CPHIFI_NUMERIC;

@@ -252,13 +252,47 @@ __global__ void mirror_kernel(const DevScalars* src, DevScalars* dst) {
 // column 4 c + lane % 4.  r is padded to rp = 4 NC4 with zeros.  The rows of T
 // (and of T U_V * D, for the second product) pass through a per-wave LDS tile,
 // U_V through a block-shared one.
-template <typename PT, int NC4>
+// With UPD (a PCG iteration in the eigenbasis), the rows are first updated as
+// they are staged -- alpha = r^T z / p^T q from the partials of p^T q, x +=
+// alpha p, r -= alpha q, partials of r^T r into u.red_rr -- and the map is
+// applied to the new r (`in` is r then, and `dotwith` too): the update and the
+// preconditioner share one pass over the rows.
+struct UpdArgs {
+  double* x;
+  double* r;
+  const double* p;
+  const double* q;
+  const double* red_pq;
+  int nblk_pq;
+  double* red_rr;
+  DevScalars* sc;
+  int it;
+};
+
+template <typename PT, int NC4, bool UPD>
 __global__ __launch_bounds__(256) void prec_mid_mfma_kernel(const PT* part, int ksplit, int ldp,
                                                             const double* in, int64_t n, int r,
                                                             const double* UV, const double* D,
                                                             double* out, const double* dotwith,
-                                                            double* red, const int32_t* done) {
-  if (is_done(done)) return;
+                                                            double* red, const int32_t* done,
+                                                            UpdArgs u) {
+  if (UPD ? u.sc->done != 0 : is_done(done)) return;
+  double alpha = 0.0;
+  if (UPD) {  // as update_xr_kernel
+    const double pq = sum_partials(u.red_pq, u.nblk_pq);
+    const double rz = u.sc->rz[u.it & 1];
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        u.sc->pq = pq;
+        u.sc->status = (isfinite(pq) && isfinite(rz)) ? CPHIFI_BREAKDOWN : CPHIFI_NUMERIC;
+        u.sc->iters = u.it;
+        u.sc->done = 1;
+      }
+      return;
+    }
+    alpha = rz / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) u.sc->pq = pq;
+  }
   constexpr int RP = 4 * NC4;
   constexpr int LT = RP + 1;  // row stride of the per-wave tile (bank spread)
   extern __shared__ double lds[];
@@ -272,14 +306,24 @@ __global__ __launch_bounds__(256) void prec_mid_mfma_kernel(const PT* part, int 
   __syncthreads();
   const int li = lane & 15, kk = lane >> 4, jj = lane & 3;
   const int orow = 4 * ((lane >> 2) & 3) + kk;
-  double loc = 0.0;
+  double loc = 0.0, loc_rr = 0.0;
   for (int64_t rb = (int64_t)blockIdx.x * 4 + wave; rb * 16 < n; rb += (int64_t)gridDim.x * 4) {
     const int64_t row0 = rb * 16;
     for (int e = lane; e < 16 * RP; e += 64) {
       const int i = e / RP, c = e % RP;
       const int64_t s = row0 + i;
       double v = 0.0;
-      if (s < n && c < r) v = part != nullptr ? part_sum(part, ksplit, n, ldp, s, c) : in[s * r + c];
+      if (s < n && c < r) {
+        const int64_t o = s * r + c;
+        if (UPD) {
+          u.x[o] += alpha * u.p[o];
+          v = u.r[o] - alpha * u.q[o];
+          u.r[o] = v;
+          loc_rr += v * v;
+        } else {
+          v = part != nullptr ? part_sum(part, ksplit, n, ldp, s, c) : in[o];
+        }
+      }
       wt[i * LT + c] = v;
     }
     __builtin_amdgcn_wave_barrier();
@@ -295,9 +339,11 @@ __global__ __launch_bounds__(256) void prec_mid_mfma_kernel(const PT* part, int 
                                                     acc[c], 0, 0, 0);
     }
     const int64_t s = row0 + orow;
+    double tv[UPD ? NC4 : 1];  // UPD: the updated r at this lane's outputs, for r^T z
 #pragma unroll
     for (int c = 0; c < NC4; ++c) {
       const int col = 4 * c + jj;
+      if (UPD) tv[c] = wt[orow * LT + col];
       acc[c] *= (s < n && col < r) ? D[s * r + col] : 0.0;
     }
     __builtin_amdgcn_wave_barrier();
@@ -320,10 +366,17 @@ __global__ __launch_bounds__(256) void prec_mid_mfma_kernel(const PT* part, int 
       const int col = 4 * c + jj;
       if (s < n && col < r) {
         out[s * r + col] = z[c];
-        if (dotwith != nullptr) loc += dotwith[s * r + col] * z[c];
+        if (UPD)
+          loc += tv[c] * z[c];
+        else if (dotwith != nullptr)
+          loc += dotwith[s * r + col] * z[c];
       }
     }
     __builtin_amdgcn_wave_barrier();
+  }
+  if (UPD) {
+    const double b = block_sum(loc_rr);
+    if (threadIdx.x == 0) u.red_rr[blockIdx.x] = b;
   }
   if (red != nullptr) {
     const double b = block_sum(loc);
@@ -331,19 +384,20 @@ __global__ __launch_bounds__(256) void prec_mid_mfma_kernel(const PT* part, int 
   }
 }
 
-template <typename PT>
+template <typename PT, bool UPD = false>
 int launch_prec_mfma(int nc4, int blocks, const PT* part, int ksplit, int ldp, const double* in,
                      int64_t n, int r, const double* UV, const double* D, double* out,
-                     const double* dotwith, double* red, const int32_t* done, hipStream_t st) {
+                     const double* dotwith, double* red, const int32_t* done, hipStream_t st,
+                     const UpdArgs& u = UpdArgs{}) {
   const size_t lds = sizeof(double) * ((size_t)16 * nc4 * nc4 + 4 * 16 * (4 * nc4 + 1));
   // (r > 60 needs more than the default 64 KB of dynamic LDS)
 #define CPHIFI_PREC_CASE(K)                                                                   \
   case K:                                                                                     \
     if (lds > 65536)                                                                          \
-      CPHIFI_HIP(hipFuncSetAttribute((const void*)prec_mid_mfma_kernel<PT, K>,                \
+      CPHIFI_HIP(hipFuncSetAttribute((const void*)prec_mid_mfma_kernel<PT, K, UPD>,           \
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
-    hipLaunchKernelGGL((prec_mid_mfma_kernel<PT, K>), dim3(blocks), dim3(256), lds, st, part, \
-                       ksplit, ldp, in, n, r, UV, D, out, dotwith, red, done);                \
+    hipLaunchKernelGGL((prec_mid_mfma_kernel<PT, K, UPD>), dim3(blocks), dim3(256), lds, st,  \
+                       part, ksplit, ldp, in, n, r, UV, D, out, dotwith, red, done, u);       \
     break;
   switch (nc4) {
     CPHIFI_PREC_CASE(1) CPHIFI_PREC_CASE(2) CPHIFI_PREC_CASE(3) CPHIFI_PREC_CASE(4)
@@ -600,6 +654,19 @@ int launch_dot(const double* a, const double* b, int64_t len, double* red, int* 
   const int nb = vec_blocks(len);
   hipLaunchKernelGGL(dot_kernel, dim3(nb), dim3(256), 0, st, a, b, len, red, done);
   CPHIFI_CHECK_LAUNCH();
+  if (nblk_out) *nblk_out = nb;
+  return CPHIFI_OK;
+}
+
+int launch_update_prec(double* x, double* r, const double* p, const double* q, int64_t n,
+                       int rank, const double* UV, const double* D, double* z,
+                       const double* red_pq, int nblk_pq, double* red_rr, double* red_rz,
+                       int* nblk_out, DevScalars* sc, int it, hipStream_t st) {
+  const int nb = (int)std::min<int64_t>(kMaxVecBlocks, (n + 63) / 64);
+  UpdArgs u{x, r, p, q, red_pq, nblk_pq, red_rr, sc, it};
+  const int rc = launch_prec_mfma<double, true>((rank + 3) / 4, nb, nullptr, 1, 0, r, n, rank,
+                                                UV, D, z, nullptr, red_rz, nullptr, st, u);
+  if (rc != CPHIFI_OK) return rc;
   if (nblk_out) *nblk_out = nb;
   return CPHIFI_OK;
 }
