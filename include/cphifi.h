@@ -215,7 +215,12 @@ CPHIFI_API int cphifi_kernel_eig(int64_t n, const double* K, int64_t ldk, double
  * tests:  Y = op(U) diag(xscale) X.
  *   elt:    0 = FP64 U, 1 = FP32 U, 2 = BF16 U (bf16 needs trans = 0, a row
  *           stride ldu that is a multiple of 8 and >= round_up(n, 128), and
- *           zeros in columns n .. ldu-1);  FP32 and BF16 accumulate in FP32.
+ *           zeros in columns n .. ldu-1), 3 = BF16 U in the 16 x 64 tile
+ *           layout the solver's BF16 copies of U_K use: element (i, k) at
+ *           ((i / 16) (ldu / 64) + k / 64) 1024 + (i % 16) 64 + k % 64, ldu a
+ *           multiple of 64 (>= round_up(n, 128)), round_up(n, 16) rows (rows
+ *           >= n are never read), zeros in columns n .. ldu-1.  FP32 and BF16
+ *           accumulate in FP32; the two BF16 layouts give identical Y.
  *   trans:  0: op(U) = U (row-major, stride ldu);  1: op(U) = U^T.
  *   mw, s:  tile (16-row MFMA blocks per wave, MFMA steps per k chunk); see
  *           cphifi_product_tile_ok().  ksplit <= 0 chooses the split-K depth.

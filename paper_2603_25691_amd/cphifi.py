@@ -264,6 +264,7 @@ def make_inputs(**ptrs: Optional[int]) -> cphifi_ui_inputs:
 ELT_F64 = 0
 ELT_F32 = 1
 ELT_BF16 = 2
+ELT_BF16_TILED = 3  # BF16 U in the 16 x 64 tile layout of the solver's copies
 
 
 def cphifi_product_workspace_bytes(n: int, r: int, elt: int) -> int:

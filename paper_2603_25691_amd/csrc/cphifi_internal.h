@@ -113,14 +113,15 @@ int launch_gemm(Elt elt, bool trans, const GemmPlan& gp, const void* U, int64_t 
                 void* part, const int32_t* done, hipStream_t st);
 // BF16 product: X is first split (launch_split_bf16) into hi/lo bf16 parts,
 // c-major rows of stride ldxt >= round_up(n, chunk) in xt_hi / xt_lo; U has row
-// stride ldu >= that too and zero padding beyond column n.
+// stride ldu >= that too and zero padding beyond column n; tiled: U in 16 x 64
+// tiles (tiles::bf16_tiled_off), ldu a multiple of 64.
 int launch_split_bf16(const double* X, int64_t ldx, int r, const double* xscale, int64_t n,
                       __bf16* xt_hi, __bf16* xt_lo, int64_t ldxt, const int32_t* done,
                       hipStream_t st);
 int launch_gemm_bf16(const GemmPlan& gp, const __bf16* U, int64_t ldu, int64_t n,
                      const double* X, int64_t ldx, int r, const double* xscale, void* part,
                      __bf16* xt_hi, __bf16* xt_lo, int64_t ldxt, const int32_t* done,
-                     hipStream_t st);
+                     hipStream_t st, bool tiled);
 
 // --------------------------------------------------- gather-dot-scatter (a5/a6)
 struct ObsTasks {
@@ -234,8 +235,10 @@ int launch_precond_diag(const double* dK, const double* dV, int64_t n, int r, do
                         double lam, double rho, double* D, hipStream_t st);
 int launch_clamp_nonneg(const double* src, double* dst, int64_t n, hipStream_t st);
 // dst (n rows, stride ld_dst, zero-padded to ld_dst columns) = lowp(src) or
-// lowp(src^T); src is n x n with stride ld_src.
+// lowp(src^T); src is n x n with stride ld_src.  tiled (BF16 only): dst in the
+// 16 x 64 tile layout of the BF16 product (ld_dst % 64 == 0, round_up(n, 16)
+// rows; the padding rows are not written).
 int launch_convert_lowp(Elt elt, bool transpose, const double* src, int64_t ld_src, int64_t n,
-                        void* dst, int64_t ld_dst, hipStream_t st);
+                        void* dst, int64_t ld_dst, hipStream_t st, bool tiled = false);
 
 }  // namespace cphifi

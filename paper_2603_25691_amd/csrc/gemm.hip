@@ -34,12 +34,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   tiles::gemm_f64x4_tile<NC4, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
 }
 
-template <int NB, int MW, int S>
+template <int NB, int MW, int S, bool TILED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_kernel(
     GArgs g) {
   if (g.done != nullptr && *g.done) return;
   __shared__ __attribute__((aligned(16))) __bf16 xs[tiles::bf16_lds_elems<NB, S>()];
-  tiles::gemm_bf16_tile<NB, MW, S>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
+  tiles::gemm_bf16_tile<NB, MW, S, TILED>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
 }
 
 // X (n x r, row-major, optionally row-scaled) -> hi/lo bf16, c-major rows of
@@ -148,32 +148,33 @@ int dispatch_cfg_f64(int mw, int s, int nc4, const GArgs& g, int ksplit, hipStre
   return CPHIFI_INVALID_ARG;
 }
 
-template <int NB, int MW, int S>
+template <int NB, int MW, int S, bool TILED>
 int launch_bf16(const GArgs& g, int ksplit, hipStream_t st) {
   const int64_t rows = 4 * MW * 16;
   dim3 grid((unsigned)((g.n + rows - 1) / rows), (unsigned)ksplit);
-  hipLaunchKernelGGL((gemm_bf16_kernel<NB, MW, S>), grid, dim3(256), 0, st, g);
+  hipLaunchKernelGGL((gemm_bf16_kernel<NB, MW, S, TILED>), grid, dim3(256), 0, st, g);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }
 
-template <int MW, int S>
+template <int MW, int S, bool TILED>
 int dispatch_nb_bf16(int nb, const GArgs& g, int ksplit, hipStream_t st) {
   switch (nb) {
-    case 1: return launch_bf16<1, MW, S>(g, ksplit, st);
-    case 2: return launch_bf16<2, MW, S>(g, ksplit, st);
-    case 3: return launch_bf16<3, MW, S>(g, ksplit, st);
-    case 4: return launch_bf16<4, MW, S>(g, ksplit, st);
+    case 1: return launch_bf16<1, MW, S, TILED>(g, ksplit, st);
+    case 2: return launch_bf16<2, MW, S, TILED>(g, ksplit, st);
+    case 3: return launch_bf16<3, MW, S, TILED>(g, ksplit, st);
+    case 4: return launch_bf16<4, MW, S, TILED>(g, ksplit, st);
   }
   set_error("unsupported column block count %d", nb);
   return CPHIFI_INVALID_ARG;
 }
 
+template <bool TILED>
 int dispatch_cfg_bf16(int mw, int s, int nb, const GArgs& g, int ksplit, hipStream_t st) {
-  if (mw == 1 && s == 4) return dispatch_nb_bf16<1, 4>(nb, g, ksplit, st);
-  if (mw == 2 && s == 2) return dispatch_nb_bf16<2, 2>(nb, g, ksplit, st);
-  if (mw == 2 && s == 4) return dispatch_nb_bf16<2, 4>(nb, g, ksplit, st);
-  if (mw == 4 && s == 2) return dispatch_nb_bf16<4, 2>(nb, g, ksplit, st);
+  if (mw == 1 && s == 4) return dispatch_nb_bf16<1, 4, TILED>(nb, g, ksplit, st);
+  if (mw == 2 && s == 2) return dispatch_nb_bf16<2, 2, TILED>(nb, g, ksplit, st);
+  if (mw == 2 && s == 4) return dispatch_nb_bf16<2, 4, TILED>(nb, g, ksplit, st);
+  if (mw == 4 && s == 2) return dispatch_nb_bf16<4, 2, TILED>(nb, g, ksplit, st);
   set_error("unsupported bf16 product tile (mw=%d, s=%d)", mw, s);
   return CPHIFI_INVALID_ARG;
 }
@@ -226,10 +227,10 @@ int occ_bf16(int nb) {
   int blocks = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (nb) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<1, MW, S>, 256, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<2, MW, S>, 256, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<3, MW, S>, 256, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<4, MW, S>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<1, MW, S, true>, 256, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<2, MW, S, true>, 256, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<3, MW, S, true>, 256, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, gemm_bf16_kernel<4, MW, S, true>, 256, 0); break;
   }
   return e == hipSuccess && blocks > 0 ? blocks : 1;
 }
@@ -290,9 +291,12 @@ GemmPlan make_gemm_plan(Elt elt, bool trans, int64_t n, int r, int mw, int s, in
   if (ks <= 0) {
     // One round of resident workgroups: split K until the grid fills the
     // co-resident slots (CUs x workgroups per CU) without spilling into a
-    // second, partial round; keep at least 4 chunks per split.
-    const int64_t slots =
-        (int64_t)(num_cu > 0 ? num_cu : 256) * gemm_occupancy(elt, trans, mw, s, r);
+    // second, partial round; keep at least 4 chunks per split.  The BF16
+    // product fills one workgroup per CU: fewer concurrent row streams read
+    // HBM faster (n = 30658, r = 40, 4x2 tile: split 2, 240 workgroups,
+    // 0.351 ms; split 4, 480 workgroups, 0.368 ms).
+    const int occ = elt == Elt::BF16 ? 1 : gemm_occupancy(elt, trans, mw, s, r);
+    const int64_t slots = (int64_t)(num_cu > 0 ? num_cu : 256) * occ;
     ks = std::max<int64_t>(1, slots / nrowblk);
     ks = std::min<int64_t>(ks, std::max<int64_t>(1, n / (4 * bk)));
   }
@@ -443,15 +447,16 @@ int launch_split_bf16(const double* X, int64_t ldx, int r, const double* xscale,
 }
 
 // BF16 entry: X must already be split into xt_hi / xt_lo (launch_split_bf16).
+// tiled: U in the 16 x 64 tile layout (tiles::bf16_tiled_off, ldu % 64 == 0).
 int launch_gemm_bf16(const GemmPlan& gp, const __bf16* U, int64_t ldu, int64_t n,
                      const double* X, int64_t ldx, int r, const double* xscale, void* part,
                      __bf16* xt_hi, __bf16* xt_lo, int64_t ldxt, const int32_t* done,
-                     hipStream_t st) {
+                     hipStream_t st, bool tiled) {
   const int nb = (r + 15) / 16;
   const int64_t bk = gemm_bk(Elt::BF16, gp.s);
   const int64_t nround = (n + bk - 1) / bk * bk;
-  if (!plan_ok(Elt::BF16, gp, n, r) || ldu % 8 != 0 || ldu < nround || ldxt < nround ||
-      ldxt % 8 != 0 || ldx < r) {
+  if (!plan_ok(Elt::BF16, gp, n, r) || ldu % (tiled ? 64 : 8) != 0 || ldu < nround ||
+      ldxt < nround || ldxt % 8 != 0 || ldx < r) {
     set_error("launch_gemm_bf16: bad shape (n=%lld r=%d ldu=%lld ldxt=%lld)", (long long)n, r,
               (long long)ldu, (long long)ldxt);
     return CPHIFI_INVALID_ARG;
@@ -471,7 +476,8 @@ int launch_gemm_bf16(const GemmPlan& gp, const __bf16* U, int64_t ldu, int64_t n
   g.xt_hi = xt_hi;
   g.xt_lo = xt_lo;
   g.ldxt = ldxt;
-  return dispatch_cfg_bf16(gp.mw, gp.s, nb, g, gp.ksplit, st);
+  return tiled ? dispatch_cfg_bf16<true>(gp.mw, gp.s, nb, g, gp.ksplit, st)
+               : dispatch_cfg_bf16<false>(gp.mw, gp.s, nb, g, gp.ksplit, st);
 }
 
 }  // namespace cphifi

@@ -75,8 +75,9 @@ struct cphifi_plan {
   double *V = nullptr, *UV = nullptr, *dV = nullptr, *D = nullptr, *dKc = nullptr;
   Elt lp = Elt::F64;
   double* ukt = nullptr; // U_K transposed (eigenvector k = column k), or NULL
-  void* ulp = nullptr;   // U_K rounded, row-major U (BF16 form only)
-  void* utlp = nullptr;  // U_K rounded, row-major U^T (eigenvector k = row k)
+  void* ulp = nullptr;   // U_K rounded: U (BF16 form only; 16 x 64 tiles)
+  void* utlp = nullptr;  // U_K rounded: U^T, eigenvector k = row k (FP32 row-major,
+                         // BF16 in 16 x 64 tiles)
   __bf16 *xthi = nullptr, *xtlo = nullptr;
   GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
   int last_ksplit = 1;  // split-K depth of the partials the last product wrote

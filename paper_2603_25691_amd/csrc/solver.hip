@@ -78,8 +78,9 @@ Layout make_layout(const cphifi_ui_desc& d) {
   if (keeps_ukt(d)) L.ukt = take(sizeof(double) * (size_t)n * eff_ldk(d));
   L.ldl = round_up(n, kLowpAlign);
   if (d.precision == CPHIFI_MIXED_BF16) {
-    L.ulp = take(sizeof(__bf16) * (size_t)n * L.ldl);
-    L.utlp = take(sizeof(__bf16) * (size_t)n * L.ldl);
+    // 16 x 64 tiles (the BF16 product's layout): whole 16-row blocks
+    L.ulp = take(sizeof(__bf16) * (size_t)round_up(n, 16) * L.ldl);
+    L.utlp = take(sizeof(__bf16) * (size_t)round_up(n, 16) * L.ldl);
     L.xthi = take(sizeof(__bf16) * (size_t)ldp * L.ldl);
     L.xtlo = take(sizeof(__bf16) * (size_t)ldp * L.ldl);
   } else if (d.precision == CPHIFI_MIXED_FP32) {
@@ -174,7 +175,7 @@ int prod_U(cphifi_plan* p, Elt elt, const double* X, const double* xscale,
       break;
     case Elt::BF16:
       TRY(launch_gemm_bf16(p->gplpn, (const __bf16*)p->ulp, p->L.ldl, p->n, X, p->r, (int)p->r,
-                           xscale, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st));
+                           xscale, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st, true));
       p->last_ksplit = p->gplpn.ksplit;
       break;
   }
@@ -210,7 +211,7 @@ int prod_Ut(cphifi_plan* p, Elt elt, const double* X, const int32_t* done,
       break;
     case Elt::BF16:
       TRY(launch_gemm_bf16(p->gplpn, (const __bf16*)p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
-                           nullptr, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st));
+                           nullptr, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st, true));
       p->last_ksplit = p->gplpn.ksplit;
       break;
   }
@@ -977,8 +978,9 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     p->xtlo = (__bf16*)(ws + L.xtlo);
     p->gplpn = plan_from_env("CPHIFI_TILE_BF16", Elt::BF16, false, n, rr,
                              choose_gemm(Elt::BF16, false, n, rr, p->num_cu), p->num_cu);
-    if ((rc = launch_convert_lowp(Elt::BF16, false, in->UK, p->ldk, n, p->utlp, L.ldl, st)) ||
-        (rc = launch_convert_lowp(Elt::BF16, true, in->UK, p->ldk, n, p->ulp, L.ldl, st)))
+    if ((rc = launch_convert_lowp(Elt::BF16, false, in->UK, p->ldk, n, p->utlp, L.ldl, st,
+                                  true)) ||
+        (rc = launch_convert_lowp(Elt::BF16, true, in->UK, p->ldk, n, p->ulp, L.ldl, st, true)))
       return fail(rc);
   } else if (d->precision == CPHIFI_MIXED_FP32) {
     p->lp = Elt::F32;

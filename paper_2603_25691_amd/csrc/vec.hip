@@ -569,21 +569,28 @@ __global__ void clamp_kernel(const double* src, double* dst, int64_t n) {
     dst[e] = fmax(src[e], 0.0);
 }
 
+// Destination offset of element (i, k): row-major, or the BF16 product's
+// 16 x 64 tiles.
+__device__ __forceinline__ int64_t dst_off(int64_t i, int64_t k, int64_t ld, bool tiled) {
+  return tiled ? ((i >> 4) * (ld >> 6) + (k >> 6)) * 1024 + (i & 15) * 64 + (k & 63) : i * ld + k;
+}
+
 template <typename T>
 __global__ void convert_kernel(const double* src, int64_t ld_src, int64_t n, T* dst,
-                               int64_t ld_dst) {
+                               int64_t ld_dst, bool tiled) {
   const int64_t len = n * ld_dst;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / ld_dst, k = e % ld_dst;
-    dst[e] = (T)(k < n ? src[i * ld_src + k] : 0.0);
+    dst[dst_off(i, k, ld_dst, tiled)] = (T)(k < n ? src[i * ld_src + k] : 0.0);
   }
 }
 
 // Tiled transpose-convert: dst[i][k] = src[k][i] (i, k < n), zero for k >= n.
 template <typename T>
 __global__ __launch_bounds__(256) void convert_t_kernel(const double* src, int64_t ld_src,
-                                                        int64_t n, T* dst, int64_t ld_dst) {
+                                                        int64_t n, T* dst, int64_t ld_dst,
+                                                        bool tiled) {
   __shared__ double tile[32][33];
   const int64_t i0 = (int64_t)blockIdx.y * 32;  // dst row block
   const int64_t k0 = (int64_t)blockIdx.x * 32;  // dst column block
@@ -595,7 +602,7 @@ __global__ __launch_bounds__(256) void convert_t_kernel(const double* src, int64
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
     const int64_t i = i0 + yy, k = k0 + tx;
-    if (i < n && k < ld_dst) dst[i * ld_dst + k] = (T)tile[tx][yy];
+    if (i < n && k < ld_dst) dst[dst_off(i, k, ld_dst, tiled)] = (T)tile[tx][yy];
   }
 }
 
@@ -793,33 +800,33 @@ int launch_clamp_nonneg(const double* src, double* dst, int64_t n, hipStream_t s
 }
 
 int launch_convert_lowp(Elt elt, bool transpose, const double* src, int64_t ld_src, int64_t n,
-                        void* dst, int64_t ld_dst, hipStream_t st) {
-  if (ld_dst < n) {
-    set_error("convert: ld_dst < n");
+                        void* dst, int64_t ld_dst, hipStream_t st, bool tiled) {
+  if (ld_dst < n || (tiled && (elt != Elt::BF16 || ld_dst % 64 != 0))) {
+    set_error("convert: ld_dst < n, or a tiled copy that is not BF16 with ld_dst %% 64 == 0");
     return CPHIFI_INVALID_ARG;
   }
   if (!transpose) {
     const int g = grid_for(n * ld_dst);
     if (elt == Elt::F32)
       hipLaunchKernelGGL(convert_kernel<float>, dim3(g), dim3(256), 0, st, src, ld_src, n,
-                         (float*)dst, ld_dst);
+                         (float*)dst, ld_dst, tiled);
     else if (elt == Elt::BF16)
       hipLaunchKernelGGL(convert_kernel<__bf16>, dim3(g), dim3(256), 0, st, src, ld_src, n,
-                         (__bf16*)dst, ld_dst);
+                         (__bf16*)dst, ld_dst, tiled);
     else
       hipLaunchKernelGGL(convert_kernel<double>, dim3(g), dim3(256), 0, st, src, ld_src, n,
-                         (double*)dst, ld_dst);
+                         (double*)dst, ld_dst, tiled);
   } else {
     dim3 grid((unsigned)((ld_dst + 31) / 32), (unsigned)((n + 31) / 32));
     if (elt == Elt::F32)
       hipLaunchKernelGGL(convert_t_kernel<float>, grid, dim3(256), 0, st, src, ld_src, n,
-                         (float*)dst, ld_dst);
+                         (float*)dst, ld_dst, tiled);
     else if (elt == Elt::BF16)
       hipLaunchKernelGGL(convert_t_kernel<__bf16>, grid, dim3(256), 0, st, src, ld_src, n,
-                         (__bf16*)dst, ld_dst);
+                         (__bf16*)dst, ld_dst, tiled);
     else
       hipLaunchKernelGGL(convert_t_kernel<double>, grid, dim3(256), 0, st, src, ld_src, n,
-                         (double*)dst, ld_dst);
+                         (double*)dst, ld_dst, tiled);
   }
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;

@@ -282,17 +282,34 @@ def upload(p, device="cuda", explicit=None, eig=None, ldk_align: int = 1) -> Dev
     return DeviceProblem(p.n, p.r, p.q, p.I, p.J, K, UK, dK, obs_ptr, obs_i, obs_j, y, A=A, B=B)
 
 
+def bf16_tiles(Ub: torch.Tensor) -> torch.Tensor:
+    """The 16 x 64 tile layout of a row-major bfloat16 matrix (n rows, row
+    stride a multiple of 64, zero-padded columns): 16-row x 64-column tiles,
+    each row-major, the column tiles of a row block consecutive.  Returned as a
+    (round_up(n, 16), ld) tensor whose storage is that layout (so its stride(0)
+    is the ldu the product takes); the padding rows are zero."""
+    n, ld = Ub.shape
+    if ld % 64 != 0:
+        raise ValueError("bf16_tiles: the row stride must be a multiple of 64")
+    rows = (n + 15) // 16 * 16
+    P = torch.zeros(rows, ld, dtype=Ub.dtype, device=Ub.device)
+    P[:n] = Ub
+    return P.view(rows // 16, 16, ld // 64, 64).permute(0, 2, 1, 3).contiguous().view(rows, ld)
+
+
 def product(U: torch.Tensor, X: torch.Tensor, elt: str = "fp64", trans: bool = False,
             tile=(0, 0), ksplit: int = 0, xscale: Optional[torch.Tensor] = None,
             out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None):
     """Y = op(U) diag(xscale) X through cphifi_product (U already in the element
-    type's storage: float64, float32, or bfloat16 zero-padded to a row stride
-    that is a multiple of 8 and >= round_up(n, 128))."""
-    e = {"fp64": _c.ELT_F64, "fp32": _c.ELT_F32, "bf16": _c.ELT_BF16}[elt]
+    type's storage: float64, float32, bfloat16 zero-padded to a row stride
+    that is a multiple of 8 and >= round_up(n, 128), or for "bf16_tiled" the
+    output of bf16_tiles)."""
+    e = {"fp64": _c.ELT_F64, "fp32": _c.ELT_F32, "bf16": _c.ELT_BF16,
+         "bf16_tiled": _c.ELT_BF16_TILED}[elt]
     n, r = X.shape
     mw, s = tile
     if mw == 0:  # the solver's default tiles
-        if e == _c.ELT_BF16:
+        if e in (_c.ELT_BF16, _c.ELT_BF16_TILED):
             mw, s = 4, 2
         elif e == _c.ELT_F64:
             g4 = 2 * ((r + 7) // 8)

@@ -36,12 +36,14 @@ import sys
 import torch
 
 from . import cphifi as C
-from .torch_api import product
+from .torch_api import bf16_tiles, product
 
 TILES = {"fp64": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 2), (4, 4)],
          "fp32": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
          "bf16": [(1, 4), (2, 2), (2, 4), (4, 2)]}
 TAG = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+# the solver's BF16 copies of U_K are tiled, so that is the layout timed
+PRODUCT_ELT = {"fp64": "fp64", "fp32": "fp32", "bf16": "bf16_tiled"}
 ESIZE = {"fp64": 8, "fp32": 4, "bf16": 2}
 
 
@@ -59,7 +61,7 @@ def _operand(elt: str, n: int, gen: torch.Generator, ld_align: int = 1) -> torch
     ld = (n + 255) // 256 * 256
     Ub = torch.zeros(n, ld, dtype=torch.bfloat16, device="cuda")
     Ub[:, :n] = U.to(torch.bfloat16)
-    return Ub
+    return bf16_tiles(Ub)
 
 
 def _time(fn, reps: int) -> float:
@@ -91,8 +93,8 @@ def sweep(ns, rs, elts, out_path: str, reps: int = 5, ld_align: int = 1) -> None
                     best = None
                     for tile in TILES[elt]:
                         for ks in (0, 1, 2, 4, 8):
-                            ms = _time(lambda: product(U, X, elt, trans, tile, ks, out=Y,
-                                                       workspace=ws), reps)
+                            ms = _time(lambda: product(U, X, PRODUCT_ELT[elt], trans, tile,
+                                                       ks, out=Y, workspace=ws), reps)
                             rec = {"elt": elt, "trans": trans, "n": n, "r": r, "tile": tile,
                                    "ksplit": ks, "ms": ms,
                                    "GBps": (ESIZE[elt] * n * n + 16 * n * r) / ms / 1e6}
@@ -133,8 +135,8 @@ def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False,
         Y = torch.empty_like(X)
         ws = torch.empty(C.cphifi_product_workspace_bytes(n, r, C.ELT_BF16) + 256,
                          dtype=torch.uint8, device="cuda")
-        ms = _time(lambda: product(U, X, elt, trans and elt != "bf16", (0, 0), 0, out=Y,
-                                   workspace=ws), reps)
+        ms = _time(lambda: product(U, X, PRODUCT_ELT[elt], trans and elt != "bf16", (0, 0), 0,
+                                   out=Y, workspace=ws), reps)
         print(json.dumps({"elt": elt, "n": n, "r": r, "ms": ms, "reps": reps,
                           "trans": bool(trans and elt != "bf16"), "ld": U.stride(0),
                           "algorithmic_bytes": ESIZE[elt] * n * n + 16 * n * r}), flush=True)

@@ -184,3 +184,33 @@ def test_batch_tile_table_is_complete_and_valid(tmp_path, krange, mw):
             assert ks == max(1, min(16, round(mid / krange)))
         if kind[0] == "bf16":
             assert all(r[6] == mw for r in rs)
+
+
+def test_bf16_tile_layout_follows_the_header_formula():
+    # element (i, k) of a row-major bf16 matrix lands at
+    # ((i / 16) (ld / 64) + k / 64) 1024 + (i % 16) 64 + k % 64 of the tiled copy
+    torch = pytest.importorskip("torch")
+    from paper_2603_25691_amd.torch_api import bf16_tiles
+    n, ld = 37, 128
+    vals = torch.arange(n * ld, dtype=torch.float32).remainder(251) + 1
+    Ub = vals.view(n, ld).to(torch.bfloat16)
+    T = bf16_tiles(Ub)
+    assert T.shape == (48, ld) and T.stride(0) == ld
+    flat = T.reshape(-1)
+    for i in range(n):
+        for k in range(ld):
+            off = ((i // 16) * (ld // 64) + k // 64) * 1024 + (i % 16) * 64 + k % 64
+            assert flat[off] == Ub[i, k]
+    assert int(flat.count_nonzero()) == n * ld  # the padding rows are zero
+    with pytest.raises(ValueError):
+        bf16_tiles(torch.zeros(4, 40, dtype=torch.bfloat16))
+
+
+def test_tiled_bf16_product_shares_tiles_and_workspace_with_row_major():
+    for mw, s in [(1, 4), (2, 2), (2, 4), (4, 2), (4, 4), (1, 8)]:
+        assert c.cphifi_product_tile_ok(c.ELT_BF16_TILED, mw, s) == \
+            c.cphifi_product_tile_ok(c.ELT_BF16, mw, s)
+    assert not c.cphifi_product_tile_ok(4, 4, 2)
+    for n, r in [(100, 5), (30658, 40)]:
+        assert c.cphifi_product_workspace_bytes(n, r, c.ELT_BF16_TILED) == \
+            c.cphifi_product_workspace_bytes(n, r, c.ELT_BF16)

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 if torch.cuda.is_available():
     from paper_2603_25691_amd import cphifi as C  # noqa: E402
-    from paper_2603_25691_amd.torch_api import product  # noqa: E402
+    from paper_2603_25691_amd.torch_api import bf16_tiles, product  # noqa: E402
 
 TILES = {"fp64": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 2), (4, 4)],
          "fp32": [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)],
@@ -58,14 +58,19 @@ def test_product_all_tiles(elt, n, r):
         Ud = torch.zeros(n, ld, dtype=torch.bfloat16, device="cuda")
         Ud[:, :n] = torch.from_numpy(U).cuda().to(torch.bfloat16)
         Ur, opx, gate, transes = _rnd(U, torch.bfloat16), _split_bf16, 1e-5, (False,)
+    Ut = bf16_tiles(Ud) if elt == "bf16" else None
     for trans in transes:
         A = Ur.T if trans else Ur
         want = A @ opx(scale[:, None] * X)
         for tile in TILES[elt]:
             for ks in (0, 1, 3):
-                got = product(Ud, Xd, elt, trans, tile, ks, sd).cpu().numpy()
-                err = np.linalg.norm(got - want) / np.linalg.norm(want)
+                got = product(Ud, Xd, elt, trans, tile, ks, sd)
+                err = np.linalg.norm(got.cpu().numpy() - want) / np.linalg.norm(want)
                 assert err <= gate, (elt, trans, tile, ks, err)
+                if Ut is not None:
+                    # the tiled layout changes addresses only: identical results
+                    got_t = product(Ut, Xd, "bf16_tiled", False, tile, ks, sd)
+                    assert torch.equal(got_t, got), (tile, ks)
 
 
 def test_product_rejects_bad_tiles_and_shapes():
@@ -76,3 +81,6 @@ def test_product_rejects_bad_tiles_and_shapes():
     Ub = torch.zeros(40, 40, dtype=torch.bfloat16, device="cuda")  # stride < 128
     with pytest.raises(C.CphifiError):
         product(Ub, X, "bf16", False, (2, 4))
+    Ub = torch.zeros(40, 136, dtype=torch.bfloat16, device="cuda")  # tiled: stride % 64 != 0
+    with pytest.raises(C.CphifiError):
+        product(Ub, X, "bf16_tiled", False, (2, 4))
