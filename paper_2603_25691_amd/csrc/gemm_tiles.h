@@ -490,9 +490,10 @@ __host__ __device__ __forceinline__ int64_t bf16_tiled_off(int64_t i, int64_t k,
 // pre-split as hi + lo bf16 parts, transposed to c-major rows of stride ldxt,
 // so the product carries ~16 significant bits of X while U stays at bf16.
 // Accumulation is FP32.  xs: LDS of bf16_lds_elems<NB, S>().
-template <int NB, int MW, int S, bool TILED = false>
+template <int NB, int MW, int S, bool TILED = false, int DEPTH = 2>
 __device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64_t by,
                                                __bf16* xs, int tid) {
+  static_assert(DEPTH == 2 || DEPTH == 3, "U chunks in flight: 2 or 3");
   constexpr int BK = 32 * S;
   constexpr int NC = NB * 16;
   constexpr int LDK = BK + 8;           // bf16 elements per LDS row (bank spread)
@@ -589,7 +590,48 @@ __device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64
     stageX(xr, kbeg + c * BK);
     loadA(dst, kbeg + c * BK);
   };
-  if (nchunk > 0) {
+  if (DEPTH == 3 && nchunk > 0) {
+    // Three U buffers: chunk c + 2 is loading while chunk c is multiplied (X
+    // stays one chunk ahead through LDS).  Steady state in groups of three
+    // steps, rotating the buffers; then at most four peeled steps.
+    u32x4 a0[MW][S], a1[MW][S], a2[MW][S];
+    u32x4 xr[2][XPT];
+    fetch(xr, a0, 0);
+    storeX(0, xr);
+    if (nchunk > 1) loadA(a1, kbeg + BK);
+    __syncthreads();
+    int64_t c = 0;
+    auto step = [&](const u32x4 (&cur)[MW][S], u32x4 (&ahead)[MW][S]) {
+      stageX(xr, kbeg + (c + 1) * BK);  // X of c + 1, then U of c + 2
+      loadA(ahead, kbeg + (c + 2) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(cur, (int)(c & 1));
+      storeX((int)((c + 1) & 1), xr);
+      __syncthreads();
+      ++c;
+    };
+    while (c + 5 <= nchunk) {
+      step(a0, a2);
+      step(a1, a0);
+      step(a2, a1);
+    }
+    auto tail = [&](const u32x4 (&cur)[MW][S], u32x4 (&ahead)[MW][S]) {
+      if (c >= nchunk) return;
+      const bool more = c + 1 < nchunk;
+      if (more) stageX(xr, kbeg + (c + 1) * BK);
+      if (c + 2 < nchunk) loadA(ahead, kbeg + (c + 2) * BK);
+      compute(cur, (int)(c & 1));
+      if (more) {
+        storeX((int)((c + 1) & 1), xr);
+        __syncthreads();
+      }
+      ++c;
+    };
+    tail(a0, a2);
+    tail(a1, a0);
+    tail(a2, a1);
+    tail(a0, a2);
+  } else if (nchunk > 0) {
     u32x4 a0[MW][S], a1[MW][S];
     u32x4 xr[2][XPT];
     fetch(xr, a0, 0);
