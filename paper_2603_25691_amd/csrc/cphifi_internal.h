@@ -154,6 +154,10 @@ struct ObsArgs {
   const int32_t* obs_j;
   const double* A;
   const double* B;
+  // FP32 copies of A and B: the gather over split partials in FP32 (the
+  // low-precision inner operator) computes in FP32 and reads these.
+  const float* A32;
+  const float* B32;
   const double* Zhat;
   const double* y;          // MTTKRP mode: observed values
   const void* part;         // gather mode: split partials of Xhat (double or float)
@@ -226,6 +230,8 @@ int launch_store_sum(const double* red, int nblk, DevScalars* sc, int slot, hipS
 int launch_axpby(double* y, double a, const double* x, double b, int64_t len,
                  const int32_t* done, hipStream_t st);
 int launch_copy(double* dst, const double* src, int64_t len, hipStream_t st);
+// dst = (float)src, len elements
+int launch_to_f32(float* dst, const double* src, int64_t len, hipStream_t st);
 int launch_fill(double* dst, double v, int64_t len, hipStream_t st);
 int launch_fill_i32(int32_t* dst, int32_t v, int64_t len, hipStream_t st);
 int launch_gram(const double* A, int64_t I, const double* B, int64_t J, int r, double* V,

@@ -15,11 +15,13 @@ __global__ __launch_bounds__(256) void obs_kernel(TaskView t, ObsDev d) {
   if (d.a.done != nullptr && *d.a.done) return;
   const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= t.ntask) return;
-  obs_task<L, CPL, FORM, MODE, PT>(t, d, task, threadIdx.x & 63);
+  obs_task<L, CPL, FORM, MODE, PT, false, PT>(t, d, task, threadIdx.x & 63);
 }
 
 // Lane-row form: wave w takes segments [w spw, (w + 1) spw), 64/L at a time
-// (spw a multiple of 64/L, at most kSegPerWave).
+// (spw a multiple of 64/L, at most kSegPerWave).  In every form the arithmetic
+// type is that of the partials: FP64 after an FP64 product, FP32 (with the
+// plan's FP32 copies of A and B) after a low-precision one.
 template <int L, int CPL, int FORM, int MODE, typename PT>
 __global__ __launch_bounds__(256) void obs_rows_kernel(ObsDev d, const int32_t* obs_ptr,
                                                        int64_t n, int spw) {
@@ -29,41 +31,47 @@ __global__ __launch_bounds__(256) void obs_rows_kernel(ObsDev d, const int32_t* 
   for (int k = 0; k < spw; k += ROWS) {
     const int64_t s0 = sb + k;
     if (s0 >= n) break;
-    tiles::obs_rows<L, CPL, FORM, MODE, PT>(d, obs_ptr, s0, (int)min((int64_t)ROWS, n - s0),
-                                            threadIdx.x & 63);
+    tiles::obs_rows<L, CPL, FORM, MODE, PT, false, PT>(
+        d, obs_ptr, s0, (int)min((int64_t)ROWS, n - s0), threadIdx.x & 63);
   }
 }
 
-// B (J x r, FP64) staged in LDS once per workgroup, then read from there by
-// every observation; the workgroups stride over the tasks (or short-segment
-// wave units) so the staging is amortised.  Used in the implicit and owner
-// forms when J r doubles fit kObsLdsBytes: a larger copy limits the
+// B (J x r, FP64 or the FP32 copy) staged in LDS once per workgroup, then read
+// from there by every observation; the workgroups stride over the tasks (or
+// short-segment wave units) so the staging is amortised.  Used in the implicit
+// and owner forms when the J r elements fit kObsLdsBytes: a larger copy limits the
 // workgroups per CU, and the gather is latency-bound (at J r = 8000 the LDS
 // form measured 190-210 us against 177-187 us reading B through L2).
 constexpr int kObsLdsBytes = 16384;
 constexpr int kObsLdsGrid = 1024;  // workgroups of the staged form (grid-stride)
 
-__device__ __forceinline__ void stage_rows(double* dst, const double* src, int64_t len) {
+template <typename T>
+__device__ __forceinline__ void stage_rows(T* dst, const T* src, int64_t len) {
   for (int64_t e = threadIdx.x; e < len; e += blockDim.x) dst[e] = src[e];
   __syncthreads();
 }
 
+__device__ __forceinline__ const double* factor_b(const ObsDev& d, double) { return d.a.B; }
+__device__ __forceinline__ const float* factor_b(const ObsDev& d, float) { return d.a.B32; }
+
 template <int L, int CPL, int FORM, int MODE, typename PT>
 __global__ __launch_bounds__(256) void obs_lds_kernel(TaskView t, ObsDev d) {
   if (d.a.done != nullptr && *d.a.done) return;
-  extern __shared__ __attribute__((aligned(16))) double sB[];
-  stage_rows(sB, d.a.B, d.J * d.a.r);
+  extern __shared__ __attribute__((aligned(16))) double lds_raw[];
+  PT* sB = reinterpret_cast<PT*>(lds_raw);
+  stage_rows(sB, factor_b(d, PT(0)), d.J * d.a.r);
   for (int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); task < t.ntask;
        task += (int64_t)gridDim.x * 4)
-    obs_task<L, CPL, FORM, MODE, PT, true>(t, d, task, threadIdx.x & 63, sB);
+    obs_task<L, CPL, FORM, MODE, PT, true, PT>(t, d, task, threadIdx.x & 63, sB);
 }
 
 template <int L, int CPL, int FORM, int MODE, typename PT>
 __global__ __launch_bounds__(256) void obs_rows_lds_kernel(ObsDev d, const int32_t* obs_ptr,
                                                            int64_t n, int spw) {
   if (d.a.done != nullptr && *d.a.done) return;
-  extern __shared__ __attribute__((aligned(16))) double sB[];
-  stage_rows(sB, d.a.B, d.J * d.a.r);
+  extern __shared__ __attribute__((aligned(16))) double lds_raw[];
+  PT* sB = reinterpret_cast<PT*>(lds_raw);
+  stage_rows(sB, factor_b(d, PT(0)), d.J * d.a.r);
   constexpr int ROWS = 64 / L;
   for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w * spw < n;
        w += (int64_t)gridDim.x * 4) {
@@ -71,9 +79,9 @@ __global__ __launch_bounds__(256) void obs_rows_lds_kernel(ObsDev d, const int32
     for (int k = 0; k < spw; k += ROWS) {
       const int64_t s0 = sb + k;
       if (s0 >= n) break;
-      tiles::obs_rows<L, CPL, FORM, MODE, PT, true>(d, obs_ptr, s0,
-                                                    (int)min((int64_t)ROWS, n - s0),
-                                                    threadIdx.x & 63, sB);
+      tiles::obs_rows<L, CPL, FORM, MODE, PT, true, PT>(d, obs_ptr, s0,
+                                                        (int)min((int64_t)ROWS, n - s0),
+                                                        threadIdx.x & 63, sB);
     }
   }
 }
@@ -105,7 +113,7 @@ int rows_per_wave(int64_t nseg) {
 
 template <int L, int CPL, int FORM, int MODE>
 int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hipStream_t st) {
-  const size_t lds = sizeof(double) * (size_t)d.J * d.a.r;
+  const size_t lds = (pf ? sizeof(float) : sizeof(double)) * (size_t)d.J * d.a.r;
   const int spw = rows_per_wave<L>(t.nseg);
   if (FORM != tiles::kExplicit && lds <= (size_t)kObsLdsBytes) {
     if (t.rows) {
@@ -190,6 +198,11 @@ int launch_obs(ObsMode mode, bool part_is_float, const ObsTasks& t, const ObsArg
   if (!expl && (I * a.r * 8 > (int64_t)UINT32_MAX || J * a.r * 8 > (int64_t)UINT32_MAX)) {
     set_error("launch_obs: factor matrices beyond 4 GiB need the explicit Zhat form");
     return CPHIFI_UNSUPPORTED;
+  }
+  if (!expl && part_is_float && mode == ObsMode::Gather &&
+      (a.A32 == nullptr || a.B32 == nullptr)) {
+    set_error("launch_obs: the FP32 gather needs FP32 copies of A and B");
+    return CPHIFI_INVALID_ARG;
   }
   TaskView tv{t.seg, t.beg, t.end, t.slot, t.first, t.ntask};
   ObsDev d{a, I, J};

@@ -60,12 +60,17 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_d(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
 
 // Sum over aligned groups of L lanes (L = 4, 8, 16), result in every lane of the
 // group: xor 1 and xor 2 (quad permutations), then the half-row mirror (pairs
 // the two quads of an 8-lane half) and the row mirror (pairs the two halves).
-template <int L>
-__device__ __forceinline__ double group_sum(double v) {
+template <int L, typename VT>
+__device__ __forceinline__ VT group_sum(VT v) {
   v += dpp_d<0xB1>(v);                      // quad_perm [1,0,3,2]
   v += dpp_d<0x4E>(v);                      // quad_perm [2,3,0,1]
   if (L >= 8) v += dpp_d<0x141>(v);         // row_half_mirror
@@ -75,10 +80,22 @@ __device__ __forceinline__ double group_sum(double v) {
 
 constexpr int kGroups = 4;  // observations per row unrolled per step
 
+// The factor rows in the element type VT of the arithmetic: FP64, or the
+// FP32 copies.
+__device__ __forceinline__ const char* factor_bytes(const double* f64, const float* f32, double) {
+  return (const char*)f64;
+}
+__device__ __forceinline__ const char* factor_bytes(const double* f64, const float* f32, float) {
+  return (const char*)f32;
+}
+
 // Per-lane state of one row of the wave for one segment, and the step that
 // consumes kGroups of its observations.  BL: the factor rows B(j,:) are read
 // from a copy in LDS (`Bsrc`, same row-major layout) instead of from HBM/L2.
-template <int L, int CPL, int FORM, int MODE, bool BL = false>
+// VT: element type of the factor rows and of the arithmetic (double, or float
+// for the low-precision inner operator: half the bytes per factor row, one
+// DPP step per lane-row reduction step instead of two).
+template <int L, int CPL, int FORM, int MODE, bool BL = false, typename VT = double>
 struct ObsRow {
   uint32_t cidx[CPL];  // in-bounds column index used for loads
   bool con[CPL];       // real column
@@ -86,28 +103,28 @@ struct ObsRow {
   uint32_t Imax, Jmax, ur;
   const char* Abytes;
   const char* Bbytes;
-  double arow[CPL];  // kOwner: A(i, :) of the segment's sample
-  double xv[CPL];    // Xhat(s,:), times A(i,:) for kOwner (zero in padding)
-  double acc[CPL];
+  VT arow[CPL];  // kOwner: A(i, :) of the segment's sample
+  VT xv[CPL];    // Xhat(s,:), times A(i,:) for kOwner (zero in padding)
+  VT acc[CPL];
   int32_t ii[kGroups], jj[kGroups];  // indices of the current step
 
-  __device__ __forceinline__ void init(const ObsDev& d, int cl, const double* Bsrc) {
+  __device__ __forceinline__ void init(const ObsDev& d, int cl, const VT* Bsrc) {
     const int r = d.a.r;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
       const int c = cl + L * j;
       con[j] = c < r;
       cidx[j] = (uint32_t)min(c, r - 1);
-      cbyte[j] = cidx[j] * 8u;
-      arow[j] = 1.0;
-      xv[j] = 0.0;
-      acc[j] = 0.0;
+      cbyte[j] = cidx[j] * (uint32_t)sizeof(VT);
+      arow[j] = VT(1);
+      xv[j] = VT(0);
+      acc[j] = VT(0);
     }
     Imax = (uint32_t)(d.I - 1);
     Jmax = (uint32_t)(d.J - 1);
     ur = (uint32_t)r;
-    Abytes = (const char*)d.a.A;
-    Bbytes = (const char*)(BL ? Bsrc : d.a.B);
+    Abytes = factor_bytes(d.a.A, d.a.A32, VT(0));
+    Bbytes = BL ? (const char*)Bsrc : factor_bytes(d.a.B, d.a.B32, VT(0));
 #pragma unroll
     for (int u = 0; u < kGroups; ++u) ii[u] = jj[u] = 0;
   }
@@ -117,9 +134,9 @@ struct ObsRow {
   __device__ __forceinline__ void owner(const ObsDev& d, int64_t o) {
     if (FORM != kOwner) return;
     const int32_t i = o >= 0 ? d.a.obs_i[o] : 0;
-    const uint32_t ib = min((uint32_t)max(i, 0), Imax) * ur * 8u;
+    const uint32_t ib = min((uint32_t)max(i, 0), Imax) * ur * (uint32_t)sizeof(VT);
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) arow[j] = *(const double*)(Abytes + (ib + cbyte[j]));
+    for (int j = 0; j < CPL; ++j) arow[j] = *(const VT*)(Abytes + (ib + cbyte[j]));
   }
 
   // Xhat(s,:) summed over the split-K slabs of the product that made it.
@@ -133,7 +150,7 @@ struct ObsRow {
       for (int sp = 0; sp < a.ksplit; ++sp)
         v += (double)part[((int64_t)sp * a.n + s) * a.ldp + cidx[j]];
       if (store && a.Xhat != nullptr && con[j]) a.Xhat[s * a.r + cidx[j]] = v;
-      xv[j] = con[j] ? v * arow[j] : 0.0;
+      xv[j] = con[j] ? (VT)(v * (double)arow[j]) : VT(0);
     }
   }
 
@@ -155,37 +172,38 @@ struct ObsRow {
   __device__ __forceinline__ void step(const ObsDev& d, const int64_t (&o)[kGroups],
                                        const bool (&on)[kGroups]) {
     const ObsArgs& a = d.a;
-    double z[kGroups][CPL];
-    double w[kGroups];
+    VT z[kGroups][CPL];
+    VT w[kGroups];
 #pragma unroll
     for (int u = 0; u < kGroups; ++u) {
       if (FORM == kExplicit) {
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) z[u][j] = o[u] >= 0 ? a.Zhat[o[u] * a.r + cidx[j]] : 0.0;
+        for (int j = 0; j < CPL; ++j)
+          z[u][j] = o[u] >= 0 ? (VT)a.Zhat[o[u] * a.r + cidx[j]] : VT(0);
       } else {
         // byte offsets in 32 bits (I r and J r doubles fit, checked on the host)
-        const uint32_t jb = min((uint32_t)max(jj[u], 0), Jmax) * ur * 8u;
+        const uint32_t jb = min((uint32_t)max(jj[u], 0), Jmax) * ur * (uint32_t)sizeof(VT);
         if (FORM == kOwner) {
 #pragma unroll
-          for (int j = 0; j < CPL; ++j) z[u][j] = *(const double*)(Bbytes + (jb + cbyte[j]));
+          for (int j = 0; j < CPL; ++j) z[u][j] = *(const VT*)(Bbytes + (jb + cbyte[j]));
         } else {
-          const uint32_t ib = min((uint32_t)max(ii[u], 0), Imax) * ur * 8u;
+          const uint32_t ib = min((uint32_t)max(ii[u], 0), Imax) * ur * (uint32_t)sizeof(VT);
 #pragma unroll
           for (int j = 0; j < CPL; ++j)
-            z[u][j] = *(const double*)(Abytes + (ib + cbyte[j])) *
-                      *(const double*)(Bbytes + (jb + cbyte[j]));
+            z[u][j] = *(const VT*)(Abytes + (ib + cbyte[j])) *
+                      *(const VT*)(Bbytes + (jb + cbyte[j]));
         }
       }
-      if (MODE == 1) w[u] = on[u] ? a.y[o[u]] : 0.0;
+      if (MODE == 1) w[u] = on[u] ? (VT)a.y[o[u]] : VT(0);
     }
     if (MODE == 0) {
 #pragma unroll
       for (int u = 0; u < kGroups; ++u) {
-        double part = 0.0;
+        VT part = VT(0);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) part += z[u][j] * xv[j];
-        const double xb = group_sum<L>(part);  // xbar_l, eq. vl
-        w[u] = on[u] ? xb : 0.0;
+        const VT xb = group_sum<L>(part);  // xbar_l, eq. vl
+        w[u] = on[u] ? xb : VT(0);
       }
     }
 #pragma unroll
@@ -195,10 +213,10 @@ struct ObsRow {
   }
 };
 
-// One wave per task (see the file comment).  BL / Bsrc: see ObsRow.
-template <int L, int CPL, int FORM, int MODE, typename PT, bool BL = false>
+// One wave per task (see the file comment).  BL / Bsrc / VT: see ObsRow.
+template <int L, int CPL, int FORM, int MODE, typename PT, bool BL = false, typename VT = double>
 __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int64_t task,
-                                         int lane, const double* Bsrc = nullptr) {
+                                         int lane, const VT* Bsrc = nullptr) {
   constexpr int ROWS = 64 / L;  // observations per group
   constexpr int STEP = ROWS * kGroups;
   const ObsArgs& a = d.a;
@@ -207,7 +225,7 @@ __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int
   const int64_t beg = t.beg[task], end = t.end[task];
   const int32_t slot = t.slot[task];
 
-  ObsRow<L, CPL, FORM, MODE, BL> R;
+  ObsRow<L, CPL, FORM, MODE, BL, VT> R;
   R.init(d, cl, Bsrc);
   auto obs_of = [&](int64_t base, int64_t (&o)[kGroups], bool (&on)[kGroups]) {
 #pragma unroll
@@ -253,7 +271,7 @@ __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int
     double* dst = slot < 0 ? a.out + s * a.r : a.tpart + (int64_t)slot * a.r;
 #pragma unroll
     for (int j = 0; j < CPL; ++j)
-      if (R.con[j]) dst[R.cidx[j]] = R.acc[j] * R.arow[j];
+      if (R.con[j]) dst[R.cidx[j]] = (double)(R.acc[j] * R.arow[j]);
   }
 }
 
@@ -261,9 +279,9 @@ __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int
 // [s0, s0 + nseg), nseg <= 64/L, read from the CSR obs_ptr; for segments that
 // are not split over several tasks (the caller checks) this gives the same
 // rows as obs_task.
-template <int L, int CPL, int FORM, int MODE, typename PT, bool BL = false>
+template <int L, int CPL, int FORM, int MODE, typename PT, bool BL = false, typename VT = double>
 __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr, int64_t s0,
-                                         int nseg, int lane, const double* Bsrc = nullptr) {
+                                         int nseg, int lane, const VT* Bsrc = nullptr) {
   const ObsArgs& a = d.a;
   const int g = lane / L, cl = lane % L;
   const bool row_on = g < nseg;
@@ -272,7 +290,7 @@ __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr
   const int64_t end = row_on ? (int64_t)obs_ptr[s + 1] : beg;
   const int64_t last = end > beg ? end - 1 : -1;  // clamp target of masked loads
 
-  ObsRow<L, CPL, FORM, MODE, BL> R;
+  ObsRow<L, CPL, FORM, MODE, BL, VT> R;
   R.init(d, cl, Bsrc);
   // wave-uniform step count: the longest segment of the wave
   int maxlen = (int)(end - beg);
@@ -318,7 +336,7 @@ __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr
 #pragma unroll
     for (int j = 0; j < CPL; ++j)
       if (R.con[j]) {
-        const double v = R.acc[j] * R.arow[j];
+        const double v = (double)(R.acc[j] * R.arow[j]);
         if (a.xt_hi != nullptr) {
           const int64_t o = (int64_t)R.cidx[j] * a.ldxt + s;
           split_pair(v, &a.xt_hi[o], &a.xt_lo[o]);

@@ -27,7 +27,7 @@ struct Layout {
   size_t red[3];
   size_t sc, sc2, hist;
   size_t V, UV, dV, D, dKc;
-  size_t ulp, utlp, xthi, xtlo, ukt;
+  size_t ulp, utlp, xthi, xtlo, ukt, a32, b32;
   size_t total;
   int64_t ldl;
   int64_t ntask_max, nslot_max, nmulti_max;
@@ -75,6 +75,8 @@ struct cphifi_plan {
   double *V = nullptr, *UV = nullptr, *dV = nullptr, *D = nullptr, *dKc = nullptr;
   Elt lp = Elt::F64;
   double* ukt = nullptr; // U_K transposed (eigenvector k = column k), or NULL
+  float* a32 = nullptr;  // mixed forms, implicit factors: FP32 copies of A and B
+  float* b32 = nullptr;  //   (the low-precision gather computes in FP32)
   void* ulp = nullptr;   // U_K rounded: U (BF16 form only; 16 x 64 tiles)
   void* utlp = nullptr;  // U_K rounded: U^T, eigenvector k = row k (FP32 row-major,
                          // BF16 in 16 x 64 tiles)

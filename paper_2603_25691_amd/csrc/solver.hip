@@ -77,6 +77,10 @@ Layout make_layout(const cphifi_ui_desc& d) {
   L.dKc = take(sizeof(double) * n);
   if (keeps_ukt(d)) L.ukt = take(sizeof(double) * (size_t)n * eff_ldk(d));
   L.ldl = round_up(n, kLowpAlign);
+  if (d.precision != CPHIFI_FP64 && d.I > 0 && d.J > 0) {
+    L.a32 = take(sizeof(float) * (size_t)d.I * r);
+    L.b32 = take(sizeof(float) * (size_t)d.J * r);
+  }
   if (d.precision == CPHIFI_MIXED_BF16) {
     // 16 x 64 tiles (the BF16 product's layout): whole 16-row blocks
     L.ulp = take(sizeof(__bf16) * (size_t)round_up(n, 16) * L.ldl);
@@ -234,6 +238,8 @@ int obs_gather(cphifi_plan* p, Elt elt, double* xhat, double* out, const int32_t
   a.obs_j = p->in.obs_j;
   a.A = p->in.A;
   a.B = p->in.B;
+  a.A32 = p->a32;
+  a.B32 = p->b32;
   a.Zhat = p->in.Zhat;
   a.y = nullptr;
   a.part = p->part;
@@ -969,6 +975,13 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   // products (K X and U_K X, three of the four per iteration), mixed plans the
   // low-precision ones
   p->timed_trans = d->precision == CPHIFI_FP64;
+  if (d->precision != CPHIFI_FP64 && in->A != nullptr && L.a32 != 0) {
+    p->a32 = (float*)(ws + L.a32);
+    p->b32 = (float*)(ws + L.b32);
+    if ((rc = launch_to_f32(p->a32, in->A, d->I * d->r, st)) ||
+        (rc = launch_to_f32(p->b32, in->B, d->J * d->r, st)))
+      return fail(rc);
+  }
   if (d->precision == CPHIFI_MIXED_BF16) {
     p->lp = Elt::BF16;
     p->timed_elt = Elt::BF16;

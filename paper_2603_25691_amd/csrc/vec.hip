@@ -575,6 +575,13 @@ __device__ __forceinline__ int64_t dst_off(int64_t i, int64_t k, int64_t ld, boo
   return tiled ? ((i >> 4) * (ld >> 6) + (k >> 6)) * 1024 + (i & 15) * 64 + (k & 63) : i * ld + k;
 }
 
+__global__ void to_f32_kernel(float* __restrict__ dst, const double* __restrict__ src,
+                              int64_t len) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
 template <typename T>
 __global__ void convert_kernel(const double* src, int64_t ld_src, int64_t n, T* dst,
                                int64_t ld_dst, bool tiled) {
@@ -795,6 +802,13 @@ int launch_precond_diag(const double* dK, const double* dV, int64_t n, int r, do
 
 int launch_clamp_nonneg(const double* src, double* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(clamp_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_to_f32(float* dst, const double* src, int64_t len, hipStream_t st) {
+  if (len <= 0) return CPHIFI_OK;
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(len)), dim3(256), 0, st, dst, src, len);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }
