@@ -104,6 +104,7 @@ struct BSub {
   const int32_t* obs_j;
   const double* A;
   const double* B;
+  const float *A32, *B32;  // FP32 copies (the inner gather computes in FP32)
   const int32_t *tseg, *tbeg, *tend, *tslot, *tfirst, *mptr, *rowm, *obs_ptr;
   void* part;
   double* tpart;
@@ -145,6 +146,8 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
   s.obs_j = global_word<decltype(s.obs_j)>(w[offsetof(BSub, obs_j) / 8]);
   s.A = global_word<decltype(s.A)>(w[offsetof(BSub, A) / 8]);
   s.B = global_word<decltype(s.B)>(w[offsetof(BSub, B) / 8]);
+  s.A32 = global_word<decltype(s.A32)>(w[offsetof(BSub, A32) / 8]);
+  s.B32 = global_word<decltype(s.B32)>(w[offsetof(BSub, B32) / 8]);
   s.tseg = global_word<decltype(s.tseg)>(w[offsetof(BSub, tseg) / 8]);
   s.tbeg = global_word<decltype(s.tbeg)>(w[offsetof(BSub, tbeg) / 8]);
   s.tend = global_word<decltype(s.tend)>(w[offsetof(BSub, tend) / 8]);
@@ -358,8 +361,9 @@ __device__ __forceinline__ void gemm_item(const BSub& S, int kind, const double*
 // ------------------------------------------------------ gather-dot-scatter
 // Work item i: wave w takes tasks [(4 i + w) kTPW, ...) of the member's list,
 // or, for short segments, segments [(4 i + w) kSegPerWave, ...) by lane rows.
+// The arithmetic type is that of the partials (FP32 after the BF16 products).
 template <int L, int CPL, int FORM, typename PT, bool BL>
-__device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, const double* Bl) {
+__device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, const PT* Bl) {
   const int64_t wv = 4 * i + (item_tid() >> 6);
   const int64_t t0 = wv * kTPW;
   const int64_t t1 = min((int64_t)S.ntask, t0 + kTPW);
@@ -371,6 +375,8 @@ __device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, c
   d.a.obs_j = S.obs_j;
   d.a.A = S.A;
   d.a.B = S.B;
+  d.a.A32 = S.A32;
+  d.a.B32 = S.B32;
   d.a.Zhat = nullptr;
   d.a.y = nullptr;
   d.a.part = S.part;
@@ -393,24 +399,28 @@ __device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, c
     for (int k = 0; k < kSegPerWave; k += ROWS) {
       const int64_t s0 = wv * kSegPerWave + k;
       if (s0 >= S.n) break;
-      tiles::obs_rows<L, CPL, FORM, 0, PT, BL>(d, S.obs_ptr, s0,
-                                               (int)min((int64_t)ROWS, S.n - s0),
-                                               item_tid() & 63, Bl);
+      tiles::obs_rows<L, CPL, FORM, 0, PT, BL, PT>(d, S.obs_ptr, s0,
+                                                   (int)min((int64_t)ROWS, S.n - s0),
+                                                   item_tid() & 63, Bl);
     }
     return;
   }
   for (int64_t task = t0; task < t1; ++task)
-    tiles::obs_task<L, CPL, FORM, 0, PT, BL>(tv, d, task, item_tid() & 63, Bl);
+    tiles::obs_task<L, CPL, FORM, 0, PT, BL, PT>(tv, d, task, item_tid() & 63, Bl);
 }
 
-// B (J x r, at most kSmemBytes; checked at batch creation) goes to LDS first,
-// so every observation reads its factor row from LDS instead of L2.
+// B (J x r, at most kSmemBytes as FP64; checked at batch creation) goes to LDS
+// first, so every observation reads its factor row from LDS instead of L2.
+__device__ __forceinline__ const double* factor_b(const BSub& S, double) { return S.B; }
+__device__ __forceinline__ const float* factor_b(const BSub& S, float) { return S.B32; }
+
 template <int L, int CPL, int FORM, typename PT>
 __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, int mode, char* smem) {
   const int64_t len = (int64_t)S.J * S.r;
   if (len * (int64_t)sizeof(double) <= kSmemBytes) {
-    double* Bl = (double*)smem;
-    for (int64_t e = item_tid(); e < len; e += blockDim.x) Bl[e] = S.B[e];
+    PT* Bl = (PT*)smem;
+    const PT* src = factor_b(S, PT(0));
+    for (int64_t e = item_tid(); e < len; e += blockDim.x) Bl[e] = src[e];
     __syncthreads();
     obs_item_b<L, CPL, FORM, PT, true>(S, i, mode, Bl);
   }
@@ -1320,6 +1330,10 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
       return rc;
     }
     cphifi_plan* p = bt->plans[b];
+    if (p->a32 == nullptr || p->b32 == nullptr) {  // made by every MIXED_BF16 (A, B) plan
+      set_error("member %d: no FP32 copies of A and B", b);
+      return fail(CPHIFI_UNSUPPORTED);
+    }
     // zero padding rows / columns of the BF16 split operand once
     const size_t xt_bytes = sizeof(__bf16) * (size_t)p->ldp * p->L.ldl;
     if (hipMemsetAsync(p->xthi, 0, xt_bytes, st) != hipSuccess ||
@@ -1351,6 +1365,8 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.obs_j = in.obs_j;
     S.A = in.A;
     S.B = in.B;
+    S.A32 = p->a32;
+    S.B32 = p->b32;
     S.tseg = p->tasks.seg;
     S.tbeg = p->tasks.beg;
     S.tend = p->tasks.end;
