@@ -1409,7 +1409,7 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.lam = d.lambda;
     S.rho = d.rho;
     S.tol = d.tol;
-    const double itol = d.inner_tol > 0.0 ? d.inner_tol : 1e-3;
+    const double itol = d.inner_tol > 0.0 ? d.inner_tol : kInnerTol;
     S.inner_tol2 = itol * itol;
     S.maxit = eff_maxit(d);
     S.max_refine = d.max_refine > 0 ? d.max_refine : 30;

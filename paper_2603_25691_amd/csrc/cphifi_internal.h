@@ -45,6 +45,14 @@ constexpr int kMaxVecBlocks = 1024;  // upper bound on their grid (reduction par
 constexpr int kMaxSplit = 16;        // upper bound on split-K of the n x n products
 constexpr int kObsChunk = 1024;      // max observations per gather-scatter task
 constexpr int kLowpAlign = 256;      // row stride alignment (elements) of the low-precision copies
+// Default inner PCG relative tolerance of the mixed forms.  Each refinement
+// step contracts the FP64 residual by about this much, so the last step
+// over-solves: the certified residual ends well below tol, which keeps the
+// error of K W within 1e-6 when tol = 1e-7.  Looser values were faster
+// (3e-3: 15 against 17 inner iterations at n = 30658, r = 40) but left a test
+// case (n = 650, r = 40, lambda = 1e-2) with relres just under 1e-7 and e_KW
+// 1.7e-6.
+constexpr double kInnerTol = 1e-3;
 
 // Thread index behind an opaque register move.  The tiles also run as work
 // items inside the loop of a persistent kernel; there the compiler would hoist

@@ -529,7 +529,7 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
   const int64_t len = p->n * p->r;
   const int maxit = eff_maxit(p->d);
   const int max_refine = p->d.max_refine > 0 ? p->d.max_refine : 30;
-  const double inner_tol = p->d.inner_tol > 0.0 ? p->d.inner_tol : 1e-3;
+  const double inner_tol = p->d.inner_tol > 0.0 ? p->d.inner_tol : kInnerTol;
   const Elt elt = p->lp;
   double* bbar = p->vec[V_T2];
   double* xbar = p->vec[V_TMP];
