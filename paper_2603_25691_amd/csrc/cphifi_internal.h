@@ -53,6 +53,10 @@ constexpr int kLowpAlign = 256;      // row stride alignment (elements) of the l
 // case (n = 650, r = 40, lambda = 1e-2) with relres just under 1e-7 and e_KW
 // 1.7e-6.
 constexpr double kInnerTol = 1e-3;
+// Mixed forms: a refinement step whose predicted residual (the last step's
+// contraction applied once more) is below kCertifyFirst * tol goes straight to
+// the certificate.
+constexpr double kCertifyFirst = 0.1;
 
 // Thread index behind an opaque register move.  The tiles also run as work
 // items inside the loop of a persistent kernel; there the compiler would hoist

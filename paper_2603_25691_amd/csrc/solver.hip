@@ -517,7 +517,11 @@ int solve_fp64(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* in
 // Abar_lp dbar = rbar at low precision and adds dbar to xbar.  W = U xbar is
 // formed once at the end and certified by the FP64 residual of the original
 // system (two passes over K); should that certificate miss the target while
-// the rotated one met it, refinement continues.
+// the rotated one met it, refinement continues.  When the last step's
+// contraction predicts that the next residual meets tol with a margin
+// (kCertifyFirst), the rotated residual is skipped and W is certified at once
+// (three passes instead of five); on a miss the certificate's residual,
+// rotated into the eigenbasis (one pass), continues the refinement.
 //
 // The right-hand side comes either as b = K Bm or, from the whole-subproblem
 // entry, as Bm itself (the observed MTTKRP, eq. for B in Section 4.4): then
@@ -559,65 +563,84 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
     return op_precond_eig(p, x, z, red, nbk, done);
   };
   int total_inner = 0, k = 0, status = CPHIFI_NOT_CONVERGED;
-  double rel = INFINITY, cert = INFINITY, bb_bar = 0.0;
-  bool force = false;  // one more correction although the rotated residual met tol
+  double rel = INFINITY, rel_prev = INFINITY, cert = INFINITY, bb_bar = 0.0;
   bool fresh = !warm;  // xbar = 0: its residual is bbar
-  for (;;) {
-    for (;; ++k) {
-      if (fresh) {
-        TRY(launch_copy(rbar, bbar, len, p->st));
-      } else {
-        TRY(op_apply_eig(p, Elt::F64, xbar, p->vec[V_Q], nullptr, nullptr, nullptr));
-        TRY(launch_copy(rbar, bbar, len, p->st));
-        TRY(launch_axpby(rbar, -1.0, p->vec[V_Q], 1.0, len, nullptr, p->st));
-      }
-      TRY(launch_dot(rbar, rbar, len, p->red[0], &nb, nullptr, p->st));
-      TRY(launch_store_sum(p->red[0], nb, p->sc2, 0, p->st));
-      TRY(poll(p, p->sc2));
-      const double rr = p->h_sc->scratch[0], bb = p->h_sc->scratch[1];
-      bb_bar = bb;
-      rel = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
-      if (!std::isfinite(rel)) {
-        status = CPHIFI_NUMERIC;
-        break;
-      }
-      if ((rel <= p->d.tol && !force) || k >= max_refine) break;
-      PcgOut o;
-      TRY(run_pcg(p, A, M, rbar, p->vec[V_XB], false, inner_tol, maxit,
-                  PcgVecs{p->vec[V_R2], p->vec[V_Z2], p->vec[V_P2], p->vec[V_Q2]}, p->sc,
-                  nullptr, 0, &o, true));
-      total_inner += o.iters;
-      if (o.status == CPHIFI_NUMERIC) {
-        status = CPHIFI_NUMERIC;
-        break;
-      }
-      TRY(launch_axpby(xbar, 1.0, p->vec[V_XB], 1.0, len, nullptr, p->st));
-      force = false;
-      fresh = false;
-    }
-    if (status == CPHIFI_NUMERIC) break;
+  // W = U xbar and its certificate (not part of the kernel timing).  It
+  // leaves b - A W in vec[V_RF].  ||b|| = ||U^T b|| (U_K orthogonal) when b is
+  // not formed.
+  auto certify = [&](double* c) -> int {
     TRY(rotate_out(p, Elt::F64, xbar, W));
-    // The certificate is not part of the kernel timing.
     const bool t = p->timing;
     p->timing = false;
-    // ||b|| = ||U^T b|| (U_K orthogonal) when b is not formed
-    const int rs = Bm != nullptr ? true_relres_from_B(p, Bm, W, bb_bar, &cert)
-                                 : true_relres(p, b, W, &cert);
+    const int rs = Bm != nullptr ? true_relres_from_B(p, Bm, W, bb_bar, c)
+                                 : true_relres(p, b, W, c);
     p->timing = t;
-    TRY(rs);
-    if (!std::isfinite(cert)) {
+    return rs;
+  };
+  for (;;) {
+    // The residual of xbar in the eigenbasis.
+    bool certified = false;
+    if (fresh) {
+      TRY(launch_copy(rbar, bbar, len, p->st));
+    } else if (std::isfinite(rel_prev) && rel_prev > 0.0 &&
+               rel * (rel / rel_prev) <= kCertifyFirst * p->d.tol) {
+      // The contraction of the last step predicts convergence: certify
+      // W = U xbar at once (one pass over U_K, two over K) rather than first
+      // forming the rotated residual (two passes over U_K).  Should the
+      // certificate miss, its residual b - A W rotated by U^T (one pass) is
+      // the next step's right-hand side.
+      TRY(certify(&cert));
+      certified = true;
+      if (!std::isfinite(cert)) {
+        status = CPHIFI_NUMERIC;
+        break;
+      }
+      if (cert <= p->d.tol || k >= max_refine) {
+        status = cert <= p->d.tol ? CPHIFI_OK : CPHIFI_NOT_CONVERGED;
+        rel = cert;  // = ||U^T (b - A W)|| / ||b|| up to rounding
+        break;
+      }
+      TRY(rotate_in(p, Elt::F64, p->vec[V_RF], rbar));
+    } else {
+      TRY(op_apply_eig(p, Elt::F64, xbar, p->vec[V_Q], nullptr, nullptr, nullptr));
+      TRY(launch_copy(rbar, bbar, len, p->st));
+      TRY(launch_axpby(rbar, -1.0, p->vec[V_Q], 1.0, len, nullptr, p->st));
+    }
+    TRY(launch_dot(rbar, rbar, len, p->red[0], &nb, nullptr, p->st));
+    TRY(launch_store_sum(p->red[0], nb, p->sc2, 0, p->st));
+    TRY(poll(p, p->sc2));
+    const double rr = p->h_sc->scratch[0], bb = p->h_sc->scratch[1];
+    bb_bar = bb;
+    rel_prev = rel;
+    rel = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+    if (!std::isfinite(rel)) {
       status = CPHIFI_NUMERIC;
       break;
     }
-    if (cert <= p->d.tol) {
-      status = CPHIFI_OK;
+    if (!certified && (rel <= p->d.tol || k >= max_refine)) {
+      TRY(certify(&cert));
+      if (!std::isfinite(cert)) {
+        status = CPHIFI_NUMERIC;
+        break;
+      }
+      if (cert <= p->d.tol || k >= max_refine) {
+        status = cert <= p->d.tol ? CPHIFI_OK : CPHIFI_NOT_CONVERGED;
+        break;
+      }
+      // the rotated residual met tol, the certificate did not: refine on
+    }
+    PcgOut o;
+    TRY(run_pcg(p, A, M, rbar, p->vec[V_XB], false, inner_tol, maxit,
+                PcgVecs{p->vec[V_R2], p->vec[V_Z2], p->vec[V_P2], p->vec[V_Q2]}, p->sc, nullptr,
+                0, &o, true));
+    total_inner += o.iters;
+    if (o.status == CPHIFI_NUMERIC) {
+      status = CPHIFI_NUMERIC;
       break;
     }
-    if (k >= max_refine) {
-      status = CPHIFI_NOT_CONVERGED;
-      break;
-    }
-    force = true;
+    TRY(launch_axpby(xbar, 1.0, p->vec[V_XB], 1.0, len, nullptr, p->st));
+    ++k;
+    fresh = false;
   }
   info->iters = total_inner;
   info->refine_steps = k;
