@@ -85,7 +85,8 @@ enum : int32_t {
   M_INNER = 5,  // one inner PCG iteration
   M_FINAL = 6,  // W = U xbar
   M_CERT = 7,   // FP64 residual of W
-  M_DONE = 8
+  M_DONE = 8,
+  M_RESC = 9    // rbar = U^T rf (a certificate missed: its residual continues)
 };
 enum : int { S_A = 0, S_OBS = 1, S_ROWS = 2, S_B = 3, S_FIN = 4, S_UPD = 5, S_PREC = 6, S_CTRL = 7 };
 
@@ -185,6 +186,7 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
 struct BState {
   int32_t mode, k, it, total_inner, status, force;  // force: refine although rel <= tol
   double bb, bbar, rel, cert, tol2, rz[2];           // ||b||^2, ||bbar||^2, relres, ...
+  double rel_prev;  // the rotated residual before rel (0: none yet)
 };
 
 // Batch-wide control words.
@@ -272,6 +274,8 @@ __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
       return slot == S_A ? ft : slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
     case M_RES0:
       return (slot == S_FIN || slot == S_PREC || slot == S_CTRL) ? S.nrc : 0;
+    case M_RESC:
+      return slot == S_A ? fn : (slot == S_FIN || slot == S_PREC || slot == S_CTRL) ? S.nrc : 0;
     case M_RES:
       switch (slot) {
         case S_A: return ft;
@@ -538,6 +542,13 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
         loc += v * v;
         break;
       }
+      case M_RESC: {  // rbar = U^T rf
+        const double v = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
+        S.R[e] = v;
+        S.X[e] = 0.0;
+        loc += v * v;
+        break;
+      }
       case M_CERT: {  // rf = b - (Y + lambda Xhat + rho W)
         const double y = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
         const double q = y + S.lam * S.XH[e] + S.rho * S.W[e];
@@ -571,6 +582,7 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
   switch (mode) {
     case M_RES:
     case M_RES0:
+    case M_RESC:
     case M_CERT:
     case M_ROT_B: red = S.red1; break;
     case M_INIT: red = S.red2; break;
@@ -784,10 +796,15 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
           st->total_inner += it + 1;
           st->k += 1;
           st->force = 0;
-          if (finite)
-            finish_member(st, M_RES, 0);
-          else
+          // As in the single solve: when the last step's contraction predicts
+          // convergence, W = U xbar is certified at once (M_FINAL, M_CERT)
+          // instead of forming the rotated residual first (M_RES).
+          const bool predict = st->rel_prev > 0.0 &&
+                               st->rel * (st->rel / st->rel_prev) <= kCertifyFirst * S.tol;
+          if (!finite)
             finish_member(st, M_DONE, CPHIFI_NUMERIC);
+          else
+            finish_member(st, predict ? M_FINAL : M_RES, 0);
         }
         return;
       }
@@ -799,7 +816,8 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
       return;
     }
     case M_RES:
-    case M_RES0: {
+    case M_RES0:
+    case M_RESC: {
       double rel = 0.0;
       const bool on = refine_on(S, st, s_red, &rel);
       double rz0 = 0.0;
@@ -808,6 +826,7 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
         if (rz0 > 0.0 && isfinite(rz0)) p_rows(S, i, 0.0, smem);
       }
       if (lead) {
+        st->rel_prev = st->rel;
         st->rel = rel;
         if (!isfinite(rel) || (on && !isfinite(rz0))) {
           finish_member(st, M_DONE, CPHIFI_NUMERIC);
@@ -834,12 +853,14 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
         if (!isfinite(cert)) {
           finish_member(st, M_DONE, CPHIFI_NUMERIC);
         } else if (cert <= S.tol) {
+          if (!(st->rel <= S.tol)) st->rel = cert;  // certified without a rotated residual
           finish_member(st, M_DONE, CPHIFI_OK);
         } else if (st->k >= S.max_refine) {
           finish_member(st, M_DONE, CPHIFI_NOT_CONVERGED);
         } else {
-          st->force = 1;  // the rotated residual met tol, the certificate did not
-          finish_member(st, M_RES, 0);
+          // the certificate missed: its residual, rotated, is the next right-hand side
+          st->force = 1;
+          finish_member(st, M_RESC, 0);
         }
       }
       return;
@@ -887,6 +908,7 @@ __device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, in
         case M_ROT_B: gemm_item(S, G_UKN, S.b, i, smem); break;
         case M_ROT_W: gemm_item(S, G_UKN, S.W, i, smem); break;
         case M_FINAL: gemm_item(S, G_UKT, S.XA, i, smem); break;
+        case M_RESC: gemm_item(S, G_UKN, S.RF, i, smem); break;
       }
       break;
     case S_OBS: obs_item(S, i, mode, smem); break;
@@ -900,7 +922,7 @@ __device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, in
       break;
     case S_FIN: fin_item(S, mode, i, s_red); break;
     case S_UPD: upd_item(S, st, it, i, smem, s_red); break;
-    case S_PREC: {  // M_RES, M_RES0 (the inner iteration's is fused into S_UPD)
+    case S_PREC: {  // M_RES, M_RES0, M_RESC (the inner iteration's is fused into S_UPD)
       double rel = 0.0;
       if (refine_on(S, st, s_red, &rel)) prec_rows<false>(S, i, smem, s_red);
       break;
