@@ -185,6 +185,7 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
 // Mutable scalars of one member.
 struct BState {
   int32_t mode, k, it, total_inner, status, force;  // force: refine although rel <= tol
+  int32_t true_res;  // a certificate missed: every later step certifies first
   double bb, bbar, rel, cert, tol2, rz[2];           // ||b||^2, ||bbar||^2, relres, ...
   double rel_prev;  // the rotated residual before rel (0: none yet)
 };
@@ -799,8 +800,8 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
           // As in the single solve: when the last step's contraction predicts
           // convergence, W = U xbar is certified at once (M_FINAL, M_CERT)
           // instead of forming the rotated residual first (M_RES).
-          const bool predict = st->rel_prev > 0.0 &&
-                               st->rel * (st->rel / st->rel_prev) <= kCertifyFirst * S.tol;
+          const bool predict = st->true_res || (st->rel_prev > 0.0 &&
+                               st->rel * (st->rel / st->rel_prev) <= kCertifyFirst * S.tol);
           if (!finite)
             finish_member(st, M_DONE, CPHIFI_NUMERIC);
           else
@@ -858,8 +859,11 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
         } else if (st->k >= S.max_refine) {
           finish_member(st, M_DONE, CPHIFI_NOT_CONVERGED);
         } else {
-          // the certificate missed: its residual, rotated, is the next right-hand side
+          // the certificate missed: its residual, rotated, is the next right-hand
+          // side, and so for every later step (the rotated residual disagrees
+          // with the original system's)
           st->force = 1;
+          st->true_res = 1;
           finish_member(st, M_RESC, 0);
         }
       }

@@ -577,13 +577,28 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
     p->timing = t;
     return rs;
   };
+  // ||rbar|| / ||bbar|| (||bbar||^2 sits in scratch[1] of sc2).
+  auto rbar_rel = [&](double* out) -> int {
+    TRY(launch_dot(rbar, rbar, len, p->red[0], &nb, nullptr, p->st));
+    TRY(launch_store_sum(p->red[0], nb, p->sc2, 0, p->st));
+    TRY(poll(p, p->sc2));
+    const double rr = p->h_sc->scratch[0], bb = p->h_sc->scratch[1];
+    bb_bar = bb;
+    *out = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+    return CPHIFI_OK;
+  };
+  // Set once a certificate has missed: the eigenbasis residual then disagrees
+  // with the residual of the original system (e.g. eigenpairs that are not
+  // those of K to working accuracy), and every later step starts from the
+  // certificate's own residual b - A W, rotated by U^T.
+  bool true_res = false;
   for (;;) {
     // The residual of xbar in the eigenbasis.
     bool certified = false;
     if (fresh) {
       TRY(launch_copy(rbar, bbar, len, p->st));
-    } else if (std::isfinite(rel_prev) && rel_prev > 0.0 &&
-               rel * (rel / rel_prev) <= kCertifyFirst * p->d.tol) {
+    } else if (true_res || (std::isfinite(rel_prev) && rel_prev > 0.0 &&
+                            rel * (rel / rel_prev) <= kCertifyFirst * p->d.tol)) {
       // The contraction of the last step predicts convergence: certify
       // W = U xbar at once (one pass over U_K, two over K) rather than first
       // forming the rotated residual (two passes over U_K).  Should the
@@ -600,19 +615,15 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
         rel = cert;  // = ||U^T (b - A W)|| / ||b|| up to rounding
         break;
       }
+      true_res = true;
       TRY(rotate_in(p, Elt::F64, p->vec[V_RF], rbar));
     } else {
       TRY(op_apply_eig(p, Elt::F64, xbar, p->vec[V_Q], nullptr, nullptr, nullptr));
       TRY(launch_copy(rbar, bbar, len, p->st));
       TRY(launch_axpby(rbar, -1.0, p->vec[V_Q], 1.0, len, nullptr, p->st));
     }
-    TRY(launch_dot(rbar, rbar, len, p->red[0], &nb, nullptr, p->st));
-    TRY(launch_store_sum(p->red[0], nb, p->sc2, 0, p->st));
-    TRY(poll(p, p->sc2));
-    const double rr = p->h_sc->scratch[0], bb = p->h_sc->scratch[1];
-    bb_bar = bb;
     rel_prev = rel;
-    rel = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+    TRY(rbar_rel(&rel));
     if (!std::isfinite(rel)) {
       status = CPHIFI_NUMERIC;
       break;
@@ -628,6 +639,14 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
         break;
       }
       // the rotated residual met tol, the certificate did not: refine on
+      // from the certificate's residual
+      true_res = true;
+      TRY(rotate_in(p, Elt::F64, p->vec[V_RF], rbar));
+      TRY(rbar_rel(&rel));
+      if (!std::isfinite(rel)) {
+        status = CPHIFI_NUMERIC;
+        break;
+      }
     }
     PcgOut o;
     TRY(run_pcg(p, A, M, rbar, p->vec[V_XB], false, inner_tol, maxit,

@@ -246,3 +246,32 @@ def test_batch_with_tuner_table(batch, tmp_path):
             assert O.e_kw(probs[k].K, host(W), batch["W"][k]) <= 1e-6, MEMBERS[k][0]
     finally:
         bs.close()
+
+
+def test_batch_member_with_inexact_eigenpairs_converges():
+    """A member whose eigenpairs are those of K + E (||E|| = 1e-7 ||K||): its
+    certificate misses after the eigenbasis refinement converges, and the
+    member must go on from the certificate's residual (and certify every later
+    step) until the original system meets tol; the other member is unaffected."""
+    p = config_c1()
+    q = make_small(31, n=77, I=5, J=7, r=3, q=400, kernel_param=0.2)
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal(p.K.shape)
+    E = (E + E.T) / 2
+    E *= 1e-7 * np.linalg.norm(p.K, 2) / np.linalg.norm(E, 2)
+    dK, U = np.linalg.eigh(p.K + E)
+    dps = [upload(p, eig=(np.ascontiguousarray(U.T), dK)), upload(q)]
+    bs = BatchSolver(dps, [p.lam, q.lam], [p.rho, q.rho], TOL, **CAPS)
+    rhs = bs.rhs()
+    Ws = [torch.empty_like(b) for b in rhs]
+    status, infos = bs.solve(rhs, Ws)
+    assert status == C.OK, [i.as_dict() for i in infos]
+    assert infos[0].refine_steps > 3  # the eigenbasis alone stops at ~8e-7
+    for pr, W, info in zip((p, q), Ws, infos):
+        assert info.status == C.OK, info.as_dict()
+        Zhat = _zhat(pr)
+        cert = O.relres(pr.K, Zhat, pr.obs_t, pr.y, pr.lam, pr.rho, host(W))
+        assert cert <= 2 * TOL, cert
+        Wo = O.solve_dense(pr.K, Zhat, pr.obs_t, pr.y, pr.lam, pr.rho)
+        assert O.e_kw(pr.K, host(W), Wo) <= 1e-6
+    bs.close()

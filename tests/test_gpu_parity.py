@@ -466,3 +466,41 @@ def test_c3_recipe_at_reduced_size():
     Wb, infob = sb.solve_subproblem()
     assert infob.status == C.OK, infob.as_dict()
     assert O.e_kw(p.K, host(Wb), tight.X) <= 1e-6
+
+
+def _perturbed_eig(p, delta, seed):
+    """Eigenpairs of K + E, E symmetric with ||E||_2 = delta ||K||_2: a
+    caller's eigendecomposition that is off by delta."""
+    rng = np.random.default_rng(seed)
+    E = rng.standard_normal(p.K.shape)
+    E = (E + E.T) / 2
+    E *= delta * np.linalg.norm(p.K, 2) / np.linalg.norm(E, 2)
+    dK, U = np.linalg.eigh(p.K + E)
+    return np.ascontiguousarray(U.T), dK
+
+
+@pytest.mark.parametrize("entry", ["subproblem", "rhs"])
+def test_mixed_refinement_recovers_from_inexact_eigenpairs(entry, uploaded):
+    """Eigenpairs of K + E with ||E|| = 1e-7 ||K||: the refinement in the
+    eigenbasis alone converges to the perturbed system's solution, whose true
+    residual is ~8e-7 for c1 (exact refinement emulated on the CPU), so the
+    FP64 certificate (formed with K) misses tol = 1e-8.  The refinement must
+    then continue from the certificate's own residual b - A W, rotated into
+    the eigenbasis, and reach tol for the original system."""
+    p, _ = uploaded("c1")
+    dp = upload(p, eig=_perturbed_eig(p, 1e-7, 5))
+    tol = 1e-8
+    s = UISolver(dp, p.lam, p.rho, tol, precision="mixed_bf16")
+    if entry == "subproblem":
+        W, info = s.solve_subproblem()
+    else:
+        s.setup()
+        W, info = s.solve(s.rhs())
+    assert info.status == C.OK, info.as_dict()
+    assert info.relres_true <= tol
+    # the eigenbasis alone stops at ~8e-7: more steps than the usual three
+    assert info.refine_steps > 3
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    cert = O.relres(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, host(W))
+    assert cert <= 2 * tol
+    assert O.e_kw(p.K, host(W), _dense(p)) <= 1e-6
