@@ -183,7 +183,11 @@ CPHIFI_API int cphifi_ui_apply_lowp(cphifi_plan* p, const double* xbar, double* 
 /* Solve A w = b (b: n x r device, e.g. from cphifi_ui_rhs) by the plan's
  * method; W (n x r device) receives the solution (and holds x0 on entry when
  * FLAG_WARM_START is set).  info (host) is filled; its status is also the
- * return value unless an argument or HIP error occurred first.  sync. */
+ * return value unless an argument or HIP error occurred first.  The mixed
+ * forms return OK only when the FP64 residual of the original system (with
+ * K, not its eigenpairs) meets tol: relres_true; when a certificate misses,
+ * refinement goes on from that residual (so eigenpairs that are not those of
+ * K to working accuracy cost steps, not accuracy).  sync. */
 CPHIFI_API int cphifi_ui_solve(cphifi_plan* p, const double* b, double* W,
                     cphifi_solve_info* info);
 
