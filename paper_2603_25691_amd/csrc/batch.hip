@@ -312,7 +312,7 @@ __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
 // ---------------------------------------------------------------- products
 // Products: BF16 U (D_K p) / U^T Y (inner), FP64 K X, FP64 U^T X (NN on the
 // stored U^T), FP64 U X and U (D_K X) (transposed form).
-enum : int { G_BF_U = 0, G_BF_UT = 1, G_K = 2, G_UKN = 3, G_UKT = 4, G_UKT_D = 5 };
+enum : int { G_BF_U = 0, G_BF_UT = 1, G_K = 2, G_UKN = 3, G_UKT = 4 };
 
 template <int NB>
 __device__ __forceinline__ void gemm_item_nb(const BSub& S, int kind, const double* X, int64_t i, char* smem) {
@@ -336,11 +336,10 @@ __device__ __forceinline__ void gemm_item_nb(const BSub& S, int kind, const doub
       tiles::gemm_bf16_tile<NB, 4, 2, true>(g, bx, by, (__bf16*)smem, item_tid());
     else
       tiles::gemm_bf16_tile<NB, 2, 2, true>(g, bx, by, (__bf16*)smem, item_tid());
-  } else if (kind == G_UKT || kind == G_UKT_D) {
+  } else if (kind == G_UKT) {
     g.U = S.UK;
     g.ldu = S.ldk;
     g.kper = S.ft_kper;
-    g.xscale = kind == G_UKT_D ? S.dKc : nullptr;
     const int64_t bx = i % S.ft_nrb, by = i / S.ft_nrb;
     tiles::gemm_k4_tile<double, NB, 2, 4, true, 1>(g, bx, by, (double*)smem, item_tid());
   } else {
@@ -565,9 +564,12 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
         loc += v * v;
         break;
       }
-      case M_ROT_W:  // xbar = U^T W
-        S.XA[e] = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
+      case M_ROT_W: {  // xbar = U^T W (and D_K xbar, as in accumulate_rows)
+        const double v = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
+        S.XA[e] = v;
+        S.XH[e] = S.dKc[s] * v;
         break;
+      }
       case M_FINAL:  // W = U xbar
         S.W[e] = part_sum<double>(S.part, S.ft_ks, S.n, S.ldp, s, c);
         break;
@@ -769,11 +771,18 @@ __device__ __forceinline__ void finish_member(BState* st, int32_t mode, int32_t 
   if (mode == M_DONE) st->status = status;
 }
 
-// xbar += dbar for the chunk's rows (the inner solve's correction).
+// xbar += dbar for the chunk's rows (the inner solve's correction), and
+// D_K xbar into XH for the rotated residual's product U (D_K xbar) (scaled
+// here rather than while the product stages X, where waiting for the scale
+// loads would hold back its prefetch of U).
 __device__ __forceinline__ void accumulate_rows(const BSub& S, int64_t i) {
   const int r = S.r;
   const int64_t e0 = i * kRC * r, e1 = min(S.n, (i + 1) * kRC) * r;
-  for (int64_t e = e0 + item_tid(); e < e1; e += blockDim.x) S.XA[e] += S.X[e];
+  for (int64_t e = e0 + item_tid(); e < e1; e += blockDim.x) {
+    const double v = S.XA[e] + S.X[e];
+    S.XA[e] = v;
+    S.XH[e] = S.dKc[e / r] * v;
+  }
 }
 
 __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, int it, int64_t i,
@@ -907,7 +916,7 @@ __device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, in
     case S_A:
       switch (mode) {
         case M_INNER: gemm_item(S, G_BF_U, nullptr, i, smem); break;
-        case M_RES: gemm_item(S, G_UKT_D, S.XA, i, smem); break;
+        case M_RES: gemm_item(S, G_UKT, S.XH, i, smem); break;  // U (D_K xbar)
         case M_CERT: gemm_item(S, G_K, S.W, i, smem); break;
         case M_ROT_B: gemm_item(S, G_UKN, S.b, i, smem); break;
         case M_ROT_W: gemm_item(S, G_UKN, S.W, i, smem); break;

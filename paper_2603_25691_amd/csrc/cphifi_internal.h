@@ -242,6 +242,9 @@ int launch_store_sum(const double* red, int nblk, DevScalars* sc, int slot, hipS
 int launch_axpby(double* y, double a, const double* x, double b, int64_t len,
                  const int32_t* done, hipStream_t st);
 int launch_copy(double* dst, const double* src, int64_t len, hipStream_t st);
+// out = diag(s) x for x n x r row-major (out may not alias x)
+int launch_scale_rows(double* out, const double* x, const double* s, int64_t n, int r,
+                      const int32_t* done, hipStream_t st);
 // dst = (float)src, len elements
 int launch_to_f32(float* dst, const double* src, int64_t len, hipStream_t st);
 int launch_fill(double* dst, double v, int64_t len, hipStream_t st);

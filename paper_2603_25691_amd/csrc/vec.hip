@@ -575,6 +575,16 @@ __device__ __forceinline__ int64_t dst_off(int64_t i, int64_t k, int64_t ld, boo
   return tiled ? ((i >> 4) * (ld >> 6) + (k >> 6)) * 1024 + (i & 15) * 64 + (k & 63) : i * ld + k;
 }
 
+__global__ void scale_rows_kernel(double* __restrict__ out, const double* __restrict__ x,
+                                  const double* __restrict__ s, int64_t n, int r,
+                                  const int32_t* done) {
+  if (done != nullptr && *done) return;
+  const int64_t len = n * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = s[e / r] * x[e];
+}
+
 __global__ void to_f32_kernel(float* __restrict__ dst, const double* __restrict__ src,
                               int64_t len) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
@@ -802,6 +812,14 @@ int launch_precond_diag(const double* dK, const double* dV, int64_t n, int r, do
 
 int launch_clamp_nonneg(const double* src, double* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(clamp_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+int launch_scale_rows(double* out, const double* x, const double* s, int64_t n, int r,
+                      const int32_t* done, hipStream_t st) {
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(vec_blocks(n * r)), dim3(kVecThreads), 0, st, out,
+                     x, s, n, r, done);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }
