@@ -34,21 +34,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   tiles::gemm_f64x4_tile<NC4, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
 }
 
-// U chunks in flight of the BF16 tile: three for the tiled layout where the
-// registers allow (accumulators plus three U buffers within 144 VGPRs; the
-// 4-block x 4-row-block tile spills with three), else two.  At n = 30658,
-// r = 40 (4x2 tile) the third buffer took the product from 0.327 to 0.320 ms.
-constexpr int bf16_depth(bool tiled, int nb, int mw, int s) {
-  return tiled && mw * nb * 4 + 3 * mw * s * 4 <= 144 ? 3 : 2;
-}
+// U chunks in flight of the BF16 tile: three for the tiled layout (compiled
+// for one wave per SIMD, so the buffers fit every tile shape), else two.  At
+// n = 30658, r = 40 (4x2 tile) the third buffer took the product from 0.327
+// to 0.320 ms.
+constexpr int bf16_depth(bool tiled) { return tiled ? 3 : 2; }
 
 template <int NB, int MW, int S, bool TILED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TILED ? 1 : 2, TILED ? 1 : 2))) void gemm_bf16_kernel(
     GArgs g) {
   if (g.done != nullptr && *g.done) return;
   __shared__ __attribute__((aligned(16))) __bf16 xs[tiles::bf16_lds_elems<NB, S>()];
-  tiles::gemm_bf16_tile<NB, MW, S, TILED, bf16_depth(TILED, NB, MW, S)>(g, blockIdx.x, blockIdx.y,
-                                                                         xs, threadIdx.x);
+  tiles::gemm_bf16_tile<NB, MW, S, TILED, bf16_depth(TILED)>(g, blockIdx.x, blockIdx.y, xs,
+                                                              threadIdx.x);
 }
 
 // X (n x r, row-major, optionally row-scaled) -> hi/lo bf16, c-major rows of
