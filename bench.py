@@ -46,7 +46,7 @@ BATCH_TILES = os.path.join(ROOT, "paper_2603_25691_amd", "tiles_batch_mi355x.txt
 # stored as above), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled
 # by a calibration copy (profiles/products_n30658_r40_hbm_counters.md).  Keyed
 # by kernel and shape; clear an entry whenever that kernel changes.
-MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2, true>", 30658, 40): 1.9485e9,
+MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2, true>", 30658, 40): 1.9480e9,
                     ("gemm_f64_kernel<10, 4, 2, true, 1>", 30658, 40): 7.6937e9}
 
 
