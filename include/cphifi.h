@@ -8,7 +8,7 @@
  * matrix K (n x n) of the RKHS mode, the observed entries Omega of the data
  * tensor (q of them, each with a time index t_l in [0,n), indices i_l, j_l
  * into the two other modes and a value y_l), the other modes' factor rows and
- * the regularisers lambda > 0 and rho >= 0, find W (n x r) solving
+ * the regularisers lambda > 0 and rho > 0, find W (n x r) solving
  *
  *     (F^T F + lambda (I_r kron K) + rho I) vec(W) = vec(K B),
  *
@@ -75,7 +75,8 @@ enum cphifi_precision {
 /* ------------------------------------------------------------------ flags */
 enum cphifi_flags {
   CPHIFI_FLAG_WARM_START = 1,   /* W holds x0 on entry to solve (else x0 = 0) */
-  CPHIFI_FLAG_VALIDATE = 2,     /* plan_create checks obs_* ranges on the host */
+  CPHIFI_FLAG_VALIDATE = 2,     /* accepted for compatibility: plan_create always
+                                   range-checks obs_i / obs_j on the host */
   CPHIFI_FLAG_TIME_KERNELS = 4, /* record HIP events around the n x n products of
                                    one kernel: FP64 plans the transposed FP64
                                    product (K X, U_K X), mixed plans the low-
@@ -83,11 +84,15 @@ enum cphifi_flags {
   CPHIFI_FLAG_NO_PRECOND = 8,   /* plain CG (identity preconditioner), FP64 only */
   CPHIFI_FLAG_EIGENBASIS = 16,  /* FP64 PCG in the eigenbasis of K (2 n x n passes
                                    per iteration instead of 4); same solution */
-  CPHIFI_FLAG_NO_UKT_COPY = 32  /* plans with n >= 4096 keep a transposed copy of
+  CPHIFI_FLAG_NO_UKT_COPY = 32, /* plans with n >= 4096 keep a transposed copy of
                                    U_K in the workspace (n ldk doubles, made at
                                    plan creation), so U_K^T X runs the faster
                                    transposed FP64 kernel too; this flag drops
                                    the copy (row-major kernel for U_K^T X) */
+  CPHIFI_FLAG_TIME_FP64 = 64    /* with FLAG_TIME_KERNELS: mixed plans time the
+                                   transposed FP64 product (the rotations, the
+                                   FP64 residuals and the certificate) instead
+                                   of the low-precision one */
 };
 
 /* Problem description (host struct). */
@@ -98,7 +103,7 @@ typedef struct cphifi_ui_desc {
   int64_t I, J;       /* rows of A and B (implicit factor form); ignored with Zhat */
   int64_t ldk;        /* row stride of K and UK in elements, >= n; 0 means n */
   double lambda;      /* RKHS regulariser, > 0 */
-  double rho;         /* shift of Section 4.1, >= 0 */
+  double rho;         /* shift of Section 4.1, > 0 */
   double gamma;       /* density of the preconditioner; <= 0 means q / (n I J) */
   double tol;         /* relative residual target ||b - A w|| / ||b|| */
   double inner_tol;   /* mixed forms: inner PCG relative tolerance (<= 0: 1e-3) */
@@ -148,10 +153,10 @@ CPHIFI_API int cphifi_ui_workspace_bytes(const cphifi_ui_desc* d, size_t* bytes)
 /* Validate `d` and `in`, carve `workspace` (device, >= workspace_bytes bytes,
  * 256-byte aligned) and prepare per-K state: observation work lists and, for
  * the mixed forms, the low-precision copies of U_K.  sync.
- * Errors: INVALID_ARG (n, r, q, I, J out of range; r > 64; lambda <= 0; rho < 0;
+ * Errors: INVALID_ARG (n, r, q, I, J out of range; r > 64; lambda <= 0; rho <= 0;
  * tol <= 0; missing pointers; both or neither of Zhat / (A,B); Zhat without V;
- * workspace too small or misaligned; with FLAG_VALIDATE an obs index out of
- * range), HIP_ERROR. */
+ * workspace too small or misaligned; an obs_i / obs_j index out of range),
+ * HIP_ERROR. */
 CPHIFI_API int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d,
                           const cphifi_ui_inputs* in, void* workspace,
                           size_t workspace_bytes, void* stream);
@@ -166,6 +171,12 @@ CPHIFI_API int cphifi_ui_setup(cphifi_plan* p);
  * MTTKRP B(s,:) = sum_{l: t_l = s} y_l Zhat(l,:).  y: q doubles (device);
  * b: n x r row-major (device).  async. */
 CPHIFI_API int cphifi_ui_rhs(cphifi_plan* p, const double* y, double* b);
+
+/* The observed MTTKRP alone: Bm(s,:) = sum_{l: t_l = s} y_l Zhat(l,:)
+ * (Section 4; for a fully observed tensor this is T Z, the right-hand side
+ * of the aligned subproblem, eq. aligned-solve).  y: q doubles, Bm: n x r
+ * row-major (device).  async. */
+CPHIFI_API int cphifi_ui_mttkrp(cphifi_plan* p, const double* y, double* Bm);
 
 /* y = (F^T F + lambda I kron K + rho I) x by the two-step product of Section
  * 4.4.1, in FP64.  x, y: n x r row-major device buffers (distinct).  async. */
@@ -212,6 +223,57 @@ CPHIFI_API int cphifi_ui_plan_destroy(cphifi_plan* p);
  * to converge). */
 CPHIFI_API int cphifi_kernel_eig(int64_t n, const double* K, int64_t ldk, double* UK,
                       double* dK, void* stream);
+
+/* ------------------------------------------------------ aligned subproblem
+ * Section 3: every entry of the data tensor observed (one shared time grid).
+ * The RKHS factor then solves eq. aligned-solve,
+ *     (V kron K + lambda I) vec(W) = vec(Bm),  V = Z^T Z,  Bm = T Z (MTTKRP),
+ * by one of two methods on K = U_K D_K U_K^T (eq. eigK):
+ *   CPHIFI_ALIGNED_DECOUPLED: the decoupled direct solve of Section 3.2,
+ *     W = U_K ((U_K^T Bm U_V) had D) U_V^T, D = 1 / (dV_c dK_s + lambda)
+ *     (eq. W-decoupled; V = U_V D_V U_V^T, eq. eigV, by one-workgroup Jacobi);
+ *   CPHIFI_ALIGNED_PCG: PCG on the transformed system of Section 3.3,
+ *     (V kron D_K + lambda I) vec(Wbar) = vec(U_K^T Bm), product D_K X V +
+ *     lambda X (eq. pcg-matvec-ai), diagonal preconditioner diag(V)_c dK_s +
+ *     lambda (eq. precond-ai), x0 = 0, stop at ||r|| <= tol ||U_K^T Bm||;
+ *     the iteration loop runs in one single-workgroup kernel; W = U_K Wbar.
+ * Eigenvalues dK < 0 (rounding) are taken as 0.  info: iters (PCG),
+ * relres_true = ||Bbar - D_K Wbar V - lambda Wbar|| / ||Bbar|| in FP64 (the
+ * residual of eq. aligned-solve for an orthogonal U_K), status.
+ * Workspace: device, >= cphifi_aligned_workspace_bytes(), 256-byte aligned.
+ * sync.  Errors: INVALID_ARG (sizes, lambda <= 0, tol <= 0 for PCG, missing
+ * pointers, workspace), HIP_ERROR; PCG also BREAKDOWN, NUMERIC, NOT_CONVERGED
+ * (soft: W and info written). */
+enum cphifi_aligned_method {
+  CPHIFI_ALIGNED_DECOUPLED = 0,
+  CPHIFI_ALIGNED_PCG = 1
+};
+
+typedef struct cphifi_aligned_desc {
+  int64_t n;          /* grid points (rows of K), >= 1 */
+  int64_t r;          /* CP rank, 1..64 */
+  int64_t ldk;        /* row stride of UK in elements, >= n; 0 means n */
+  double lambda;      /* RKHS regulariser, > 0 */
+  double tol;         /* PCG: relative residual target of the transformed system */
+  int32_t method;     /* enum cphifi_aligned_method */
+  int32_t maxit;      /* PCG iteration cap; <= 0: 500 */
+} cphifi_aligned_desc;
+
+typedef struct cphifi_aligned_inputs {
+  const double* UK;   /* n x n (stride ldk), eigenvectors of K, column-major
+                         (eigenvector k in UK[k*ldk .. k*ldk + n-1]) */
+  const double* dK;   /* n eigenvalues of K */
+  const double* Bm;   /* n x r row-major MTTKRP T Z (e.g. cphifi_ui_mttkrp) */
+  const double* V;    /* r x r Gram Z^T Z, or NULL to form (A^T A) had (B^T B) */
+  const double* A;    /* I x r, B: J x r row-major factors (used when V is NULL) */
+  const double* B;
+  int64_t I, J;
+} cphifi_aligned_inputs;
+
+CPHIFI_API int cphifi_aligned_workspace_bytes(const cphifi_aligned_desc* d, size_t* bytes);
+CPHIFI_API int cphifi_aligned_solve(const cphifi_aligned_desc* d, const cphifi_aligned_inputs* in,
+                                    double* W, void* workspace, size_t workspace_bytes,
+                                    void* stream, cphifi_solve_info* info);
 
 /* ------------------------------------------------ products (tuning, tests)
  * The n x n by n x r products behind every step above (K X in Section 4.4.1,

@@ -41,11 +41,12 @@ import scipy.linalg as sla
 
 __all__ = [
     "vec", "unvec", "khatri_rao_rows", "khatri_rao", "forward_matrix",
-    "mttkrp_observed", "rhs_matrix", "system_matrix", "objective", "solve_dense",
+    "mttkrp_observed", "mttkrp_full", "rhs_matrix", "system_matrix", "objective", "solve_dense",
     "solve_dense_with_error",
     "solve_lstsq", "gram_V", "matvec_twostep", "precond_matrix", "precond_diag",
     "precond_apply", "kernel_eig", "pcg", "PcgResult", "solve_pcg",
     "solve_aligned_full", "solve_decoupled", "solve_aligned_rho_kron",
+    "solve_aligned_rho_kron_with_error", "solve_aligned_rho_decoupled",
     "aligned_matvec", "aligned_diag_precond", "solve_aligned_pcg",
     "e_kw", "e_fit", "e_w", "relres", "problem_arrays",
 ]
@@ -110,6 +111,17 @@ def mttkrp_observed(y: np.ndarray, Zhat: np.ndarray, obs_t: np.ndarray,
                     n: int) -> np.ndarray:
     """B = T Z with T zero outside Omega (Section 4): B(s,:) = sum_{l: t_l=s} y_l Zhat(l,:)."""
     return _segment_sum(obs_t, y[:, None] * Zhat, n)
+
+
+def mttkrp_full(Y: np.ndarray, A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """MTTKRP of a fully observed tensor (the aligned case of Section 3):
+    B(s,:) = sum_{i,j} Y[s,i,j] A(i,:) * B(j,:), i.e. the mode-1 unfolding of
+    Y times the Khatri-Rao product of the other two factors.  Y has shape
+    (n, I, J); the contraction over j is one matrix product, the sum over i a
+    weighted sum of rows."""
+    n, I, J = Y.shape
+    T = (Y.reshape(n * I, J) @ B).reshape(n, I, -1)   # T[s,i,:] = sum_j Y[s,i,j] B(j,:)
+    return np.sum(T * A[None, :, :], axis=1)
 
 
 def rhs_matrix(K: np.ndarray, Bm: np.ndarray) -> np.ndarray:
@@ -366,6 +378,36 @@ def solve_aligned_rho_kron(K: np.ndarray, V: np.ndarray, KB: np.ndarray, lam: fl
     H = np.kron(V, K @ K) + lam * np.kron(np.eye(r), K) + rho * np.eye(n * r)
     c = sla.cho_factor(H, lower=True)
     return unvec(sla.cho_solve(c, vec(KB)), n, r)
+
+
+def solve_aligned_rho_kron_with_error(K: np.ndarray, V: np.ndarray, KB: np.ndarray,
+                                      lam: float, rho: float):
+    """O-kron plus an estimate of its own forward error in K W: (W, delta) with
+    delta = ||K D|| / ||K W|| for the FP64 iterative-refinement correction
+    D = unvec(H^{-1}(vec(K B) - H w)), H = V kron K^2 + lam I kron K + rho I."""
+    n = K.shape[0]
+    r = V.shape[0]
+    H = np.kron(V, K @ K) + lam * np.kron(np.eye(r), K) + rho * np.eye(n * r)
+    c = sla.cho_factor(H, lower=True)
+    rhs = vec(KB)
+    w = sla.cho_solve(c, rhs)
+    dw = sla.cho_solve(c, rhs - H @ w)
+    W = unvec(w, n, r)
+    delta = float(np.linalg.norm(K @ unvec(dw, n, r)) / np.linalg.norm(K @ W))
+    return W, delta
+
+
+def solve_aligned_rho_decoupled(UK: np.ndarray, dK: np.ndarray, UV: np.ndarray,
+                                dV: np.ndarray, KB: np.ndarray, lam: float,
+                                rho: float) -> np.ndarray:
+    """O-dec for the rho-system of a fully observed tensor: with
+    F^T F = V kron K^2 the system matrix is diagonalised by U_V kron U_K (the
+    step of Section 3.2 that gives eq. W-decoupled, applied to the system of
+    eq. unaligned-infinite-1), so
+    W = U_K ((U_K^T (K B) U_V) / (dK^2 dV^T + lam dK 1^T + rho)) U_V^T
+    entrywise in the eigenbasis."""
+    D = dK[:, None] ** 2 * dV[None, :] + lam * dK[:, None] + rho
+    return UK @ (((UK.T @ KB) @ UV) / D) @ UV.T
 
 
 def aligned_matvec(dK: np.ndarray, V: np.ndarray, lam: float, X: np.ndarray) -> np.ndarray:

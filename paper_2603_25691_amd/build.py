@@ -18,7 +18,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcphifi.so")
-SOURCES = ["gemm.hip", "obs.hip", "vec.hip", "solver.hip", "eig.hip", "product.hip", "batch.hip"]
+SOURCES = ["gemm.hip", "obs.hip", "vec.hip", "solver.hip", "eig.hip", "product.hip", "batch.hip",
+           "aligned.hip"]
 ARCH = os.environ.get("CPHIFI_OFFLOAD_ARCH", "gfx950")
 
 

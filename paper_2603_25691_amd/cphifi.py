@@ -37,6 +37,7 @@ FLAG_TIME_KERNELS = 4
 FLAG_NO_PRECOND = 8
 FLAG_EIGENBASIS = 16
 FLAG_NO_UKT_COPY = 32
+FLAG_TIME_FP64 = 64
 
 PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 
@@ -74,6 +75,22 @@ class cphifi_solve_info(C.Structure):
         }
 
 
+ALIGNED_DECOUPLED = 0
+ALIGNED_PCG = 1
+ALIGNED_METHODS = {"decoupled": ALIGNED_DECOUPLED, "pcg": ALIGNED_PCG}
+
+
+class cphifi_aligned_desc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("r", C.c_int64), ("ldk", C.c_int64),
+                ("lambda_", C.c_double), ("tol", C.c_double),
+                ("method", C.c_int32), ("maxit", C.c_int32)]
+
+
+class cphifi_aligned_inputs(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in ("UK", "dK", "Bm", "V", "A", "B")] + \
+               [("I", C.c_int64), ("J", C.c_int64)]
+
+
 class CphifiError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: {status_string(status)}: {detail}")
@@ -106,6 +123,7 @@ def _load() -> C.CDLL:
                                             C.POINTER(cphifi_ui_inputs), P, C.c_size_t, P]),
         "cphifi_ui_setup": (C.c_int, [P]),
         "cphifi_ui_rhs": (C.c_int, [P, P, P]),
+        "cphifi_ui_mttkrp": (C.c_int, [P, P, P]),
         "cphifi_ui_apply": (C.c_int, [P, P, P]),
         "cphifi_ui_precond": (C.c_int, [P, P, P]),
         "cphifi_ui_apply_lowp": (C.c_int, [P, P, P]),
@@ -113,6 +131,11 @@ def _load() -> C.CDLL:
         "cphifi_ui_solve_subproblem": (C.c_int, [P, P, P, C.POINTER(cphifi_solve_info)]),
         "cphifi_ui_plan_destroy": (C.c_int, [P]),
         "cphifi_kernel_eig": (C.c_int, [C.c_int64, P, C.c_int64, P, P, P]),
+        "cphifi_aligned_workspace_bytes": (C.c_int, [C.POINTER(cphifi_aligned_desc),
+                                                     C.POINTER(C.c_size_t)]),
+        "cphifi_aligned_solve": (C.c_int, [C.POINTER(cphifi_aligned_desc),
+                                           C.POINTER(cphifi_aligned_inputs), P, P, C.c_size_t,
+                                           P, C.POINTER(cphifi_solve_info)]),
         "cphifi_product_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int,
                                                      C.POINTER(C.c_size_t)]),
         "cphifi_product_tile_ok": (C.c_int, [C.c_int, C.c_int, C.c_int]),
@@ -199,6 +222,11 @@ def cphifi_ui_rhs(plan: int, y: int, b: int) -> None:
     _check(_lib.cphifi_ui_rhs(C.c_void_p(plan), C.c_void_p(y), C.c_void_p(b)), "cphifi_ui_rhs")
 
 
+def cphifi_ui_mttkrp(plan: int, y: int, Bm: int) -> None:
+    _check(_lib.cphifi_ui_mttkrp(C.c_void_p(plan), C.c_void_p(y), C.c_void_p(Bm)),
+           "cphifi_ui_mttkrp")
+
+
 def cphifi_ui_apply(plan: int, x: int, y: int) -> None:
     _check(_lib.cphifi_ui_apply(C.c_void_p(plan), C.c_void_p(x), C.c_void_p(y)),
            "cphifi_ui_apply")
@@ -261,6 +289,30 @@ def make_inputs(**ptrs: Optional[int]) -> cphifi_ui_inputs:
     return inp
 
 
+def make_aligned_desc(n: int, r: int, lam: float, method: int, tol: float = 0.0,
+                      maxit: int = 0, ldk: int = 0) -> cphifi_aligned_desc:
+    d = cphifi_aligned_desc()
+    d.n, d.r, d.ldk, d.lambda_, d.tol, d.method, d.maxit = n, r, ldk, lam, tol, method, maxit
+    return d
+
+
+def cphifi_aligned_workspace_bytes(desc: cphifi_aligned_desc) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.cphifi_aligned_workspace_bytes(C.byref(desc), C.byref(out)),
+           "cphifi_aligned_workspace_bytes")
+    return int(out.value)
+
+
+def cphifi_aligned_solve(desc: cphifi_aligned_desc, inputs: cphifi_aligned_inputs, W: int,
+                         workspace: int, workspace_bytes: int, stream: int) -> cphifi_solve_info:
+    info = cphifi_solve_info()
+    st = _lib.cphifi_aligned_solve(C.byref(desc), C.byref(inputs), C.c_void_p(W),
+                                   C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+                                   C.c_void_p(stream), C.byref(info))
+    _check(st, "cphifi_aligned_solve", soft_ok=True)
+    return info
+
+
 ELT_F64 = 0
 ELT_F32 = 1
 ELT_BF16 = 2
@@ -285,7 +337,6 @@ def cphifi_product(elt: int, trans: int, mw: int, s: int, ksplit: int, n: int, U
                                r, C.c_void_p(xscale) if xscale else None, C.c_void_p(Y),
                                C.c_void_p(workspace), C.c_size_t(workspace_bytes),
                                C.c_void_p(stream)), "cphifi_product")
-
 
 
 # ------------------------------------------------------------- batched solver

@@ -693,9 +693,12 @@ int validate_desc(const cphifi_ui_desc* d) {
     set_error("ldk=%lld < n=%lld", (long long)d->ldk, (long long)d->n);
     return CPHIFI_INVALID_ARG;
   }
-  if (!(d->lambda > 0.0) || !(d->rho >= 0.0) || !std::isfinite(d->lambda) ||
+  // Section 4.1 adds the shift rho > 0 so that the system matrix is
+  // definite for any observation set (K may be singular); the preconditioner's
+  // diagonal 1 / (gamma dV dK^2 + lambda dK + rho) needs it too.
+  if (!(d->lambda > 0.0) || !(d->rho > 0.0) || !std::isfinite(d->lambda) ||
       !std::isfinite(d->rho)) {
-    set_error("need lambda > 0 and rho >= 0 (lambda=%g rho=%g)", d->lambda, d->rho);
+    set_error("need lambda > 0 and rho > 0 (lambda=%g rho=%g)", d->lambda, d->rho);
     return CPHIFI_INVALID_ARG;
   }
   if (!(d->tol > 0.0)) {
@@ -844,22 +847,21 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     }
   bool owner = false;
   if (!expl && q > 0) {
-    std::vector<int32_t> oi(q);
+    // Both index arrays are always range-checked here (the gather clamps an
+    // index to stay in bounds, which would otherwise turn a bad index into a
+    // wrong answer with status OK).
+    std::vector<int32_t> oi(q), oj(q);
     CPHIFI_HIP(hipMemcpyAsync(oi.data(), in->obs_i, sizeof(int32_t) * q, hipMemcpyDeviceToHost,
                               st));
+    CPHIFI_HIP(hipMemcpyAsync(oj.data(), in->obs_j, sizeof(int32_t) * q, hipMemcpyDeviceToHost,
+                              st));
     CPHIFI_HIP(hipStreamSynchronize(st));
-    if (d->flags & CPHIFI_FLAG_VALIDATE) {
-      std::vector<int32_t> oj(q);
-      CPHIFI_HIP(hipMemcpyAsync(oj.data(), in->obs_j, sizeof(int32_t) * q,
-                                hipMemcpyDeviceToHost, st));
-      CPHIFI_HIP(hipStreamSynchronize(st));
-      for (int64_t l = 0; l < q; ++l)
-        if (oi[l] < 0 || oi[l] >= d->I || oj[l] < 0 || oj[l] >= d->J) {
-          set_error("observation %lld has index (%d, %d) outside I=%lld, J=%lld", (long long)l,
-                    oi[l], oj[l], (long long)d->I, (long long)d->J);
-          return CPHIFI_INVALID_ARG;
-        }
-    }
+    for (int64_t l = 0; l < q; ++l)
+      if (oi[l] < 0 || oi[l] >= d->I || oj[l] < 0 || oj[l] >= d->J) {
+        set_error("observation %lld has index (%d, %d) outside I=%lld, J=%lld", (long long)l,
+                  oi[l], oj[l], (long long)d->I, (long long)d->J);
+        return CPHIFI_INVALID_ARG;
+      }
     // one sample per time point (the unaligned setting)?
     owner = true;
     for (int64_t s = 0; s < n && owner; ++s)
@@ -1056,6 +1058,10 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     if ((rc = launch_convert_lowp(Elt::F32, false, in->UK, p->ldk, n, p->utlp, L.ldl, st)))
       return fail(rc);
   }
+  if (d->flags & CPHIFI_FLAG_TIME_FP64) {
+    p->timed_elt = Elt::F64;
+    p->timed_trans = true;
+  }
   // scalars start in a defined state
   if ((rc = launch_fill((double*)p->sc, 0.0, sizeof(DevScalars) / sizeof(double), st)) ||
       (rc = launch_fill((double*)p->sc2, 0.0, sizeof(DevScalars) / sizeof(double), st)))
@@ -1102,6 +1108,15 @@ int cphifi_ui_rhs(cphifi_plan* p, const double* y, double* b) {
   TRY(rc);
   return launch_reduce_partials(p->part, false, p->last_ksplit, p->ldp, p->n, (int)p->r, b,
                                 nullptr, nullptr, nullptr, nullptr, p->st);
+}
+
+int cphifi_ui_mttkrp(cphifi_plan* p, const double* y, double* Bm) {
+  clear_error();
+  if (p == nullptr || Bm == nullptr || (y == nullptr && p->q > 0)) {
+    set_error("mttkrp: NULL argument");
+    return CPHIFI_INVALID_ARG;
+  }
+  return mttkrp(p, y, Bm);
 }
 
 int cphifi_ui_apply(cphifi_plan* p, const double* x, double* y) {

@@ -121,6 +121,12 @@ class UISolver:
         _c.cphifi_ui_rhs(self.plan, y.data_ptr(), out.data_ptr())
         return out
 
+    def mttkrp(self, y: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
+        y = self.prob.y if y is None else y
+        out = self._vec() if out is None else out
+        _c.cphifi_ui_mttkrp(self.plan, y.data_ptr(), out.data_ptr())
+        return out
+
     def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None):
         out = self._vec() if out is None else out
         _c.cphifi_ui_apply(self.plan, x.data_ptr(), out.data_ptr())
@@ -158,6 +164,53 @@ class UISolver:
             self.close()
         except Exception:
             pass
+
+
+class AlignedSolver:
+    """The aligned subproblem of Section 3 (cphifi_aligned_solve): the
+    decoupled direct solve or PCG on the transformed system, from U_K, d_K of
+    prob and a right-hand side Bm = T Z (n x r).  V = Z^T Z is formed on the
+    device from prob's factors when with_factors, else passed from the
+    host-side Gram given as V (a device tensor) or computed by the caller."""
+
+    def __init__(self, prob: DeviceProblem, lam: float, method: str = "decoupled",
+                 tol: float = 0.0, maxit: int = 0, V: Optional[torch.Tensor] = None,
+                 with_factors: bool = True):
+        self.prob = prob
+        n, r = prob.n, prob.r
+        _need(prob.UK, torch.float64, (n, _ldk(prob)), "UK")
+        _need(prob.dK, torch.float64, (n,), "dK")
+        if V is not None:
+            _need(V, torch.float64, (r, r), "V")
+            with_factors = False
+        self.V = V
+        self.desc = _c.make_aligned_desc(n, r, lam, _c.ALIGNED_METHODS[method], tol, maxit,
+                                         ldk=_ldk(prob))
+        self.inputs = _c.cphifi_aligned_inputs()
+        self.inputs.UK, self.inputs.dK = prob.UK.data_ptr(), prob.dK.data_ptr()
+        if V is not None:
+            self.inputs.V = V.data_ptr()
+        else:
+            _need(prob.A, torch.float64, (prob.I, r), "A")
+            _need(prob.B, torch.float64, (prob.J, r), "B")
+            self.inputs.A, self.inputs.B = prob.A.data_ptr(), prob.B.data_ptr()
+            self.inputs.I, self.inputs.J = prob.I, prob.J
+        self.ws_bytes = _c.cphifi_aligned_workspace_bytes(self.desc)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8,
+                                     device=prob.UK.device)
+        self._ws = (self.workspace.data_ptr() + 255) // 256 * 256
+
+    def solve(self, Bm: torch.Tensor, W: Optional[torch.Tensor] = None):
+        n, r = self.prob.n, self.prob.r
+        _need(Bm, torch.float64, (n, r), "Bm")
+        W = torch.empty(n, r, dtype=torch.float64, device=Bm.device) if W is None else W
+        self.inputs.Bm = Bm.data_ptr()
+        info = _c.cphifi_aligned_solve(self.desc, self.inputs, W.data_ptr(), self._ws,
+                                       self.ws_bytes, _stream())
+        return W, info
+
+    def close(self):
+        self.workspace = None
 
 
 class BatchSolver:

@@ -23,4 +23,6 @@ from .generator import (  # noqa: F401
     config_c3,
     config_c5,
     drop_observations,
+    sample_rows,
+    probe_matrices,
 )

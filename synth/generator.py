@@ -416,3 +416,23 @@ def make_paper_standin(shape=(199, 449, 151), sigmas=(4.0, 4.0, 3.0), q: int = 5
         Wstar=W3, lam=lam, rho=rho, gamma=q / (n1 * n2 * n3), tol=tol, maxit=75,
         kernel="rbf", kernel_param=sigmas[2], meta={"seed": seed, "shape": shape},
     )
+
+
+# --------------------------------------------------------------------------
+# Seeded sampling helpers for checks at full size (random numbers only)
+# --------------------------------------------------------------------------
+
+def sample_rows(seed, n: int, count: int) -> np.ndarray:
+    """Sorted distinct row indices in [0, n): the first and last row plus
+    count - 2 drawn without replacement (fewer when n is small)."""
+    rng = np.random.default_rng(seed)
+    inner = np.arange(1, n - 1)
+    k = max(0, min(count - 2, inner.shape[0]))
+    pick = rng.choice(inner, size=k, replace=False) if k > 0 else np.zeros(0, dtype=np.int64)
+    rows = np.concatenate([[0], pick, [n - 1]]) if n > 1 else np.array([0])
+    return np.unique(rows.astype(np.int64))
+
+
+def probe_matrices(seed, n: int, r: int, count: int) -> np.ndarray:
+    """count independent N(0, 1) matrices of shape (n, r), stacked."""
+    return np.random.default_rng(seed).standard_normal((count, n, r))

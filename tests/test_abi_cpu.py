@@ -58,7 +58,7 @@ def test_workspace_grows_with_problem_and_precision():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("n", 0), ("r", 0), ("r", 65), ("q", -1), ("lambda_", 0.0), ("rho", -1.0),
+    ("n", 0), ("r", 0), ("r", 65), ("q", -1), ("lambda_", 0.0), ("rho", -1.0), ("rho", 0.0),
     ("tol", 0.0), ("precision", 7), ("ldk", 5),
 ])
 def test_invalid_descriptions_are_rejected(field, value):

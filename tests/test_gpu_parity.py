@@ -13,9 +13,9 @@ Tolerances
 * FP64 solves at tol = 1e-12: e_KW <= max(1e-10, 3 delta), where delta is the
   dense reference's own forward error in K W estimated by one step of FP64
   iterative refinement (it exceeds 1e-10 only for the largest n r instance);
-  at a looser tol the GPU must agree with the oracle's PCG run to the same
-  tol (same algorithm) to within a tenth of that run's own distance from the
-  tight solution, since e_KW / tol depends on the problem;
+* the reduced large case (no dense solve fits): gates from the oracle's own
+  spread between two runs that differ only by rounding, measured by
+  tests/test_oracle_spread.py;
 * mixed-precision solves refined to relres 1e-7: e_KW <= 1e-6.
 """
 
@@ -46,6 +46,12 @@ def host(t):
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def row_err(a, b):
+    """Largest row error relative to the largest row of the reference: a wrong
+    tail or padding row shows here even when the Frobenius error is small."""
+    return float(np.max(np.linalg.norm(a - b, axis=1)) / np.max(np.linalg.norm(b, axis=1)))
 
 
 def small_cases():
@@ -100,6 +106,7 @@ def test_rhs_matches_oracle(name, uploaded):
     Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
     want = O.rhs_matrix(p.K, O.mttkrp_observed(p.y, Zhat, p.obs_t, p.n))
     assert rel(b, want) <= 1e-12
+    assert row_err(b, want) <= 1e-12
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -112,6 +119,7 @@ def test_apply_matches_oracle(name, uploaded):
     want = O.matvec_twostep(p.K, Zhat, p.obs_t, p.lam, p.rho, X)
     assert rel(y, want) <= 1e-12
     assert np.max(np.abs(y - want)) <= 1e-12 * np.max(np.abs(want)) * 10
+    assert row_err(y, want) <= 1e-12
 
 
 def test_transposed_eigenvector_copy():
@@ -192,6 +200,7 @@ def test_precond_matches_oracle(name, uploaded):
     dV, UV = np.linalg.eigh(O.gram_V(p.A, p.B))
     want = O.precond_apply(UK, dK, UV, dV, p.gamma, p.lam, p.rho, X)
     assert rel(z, want) <= 1e-8
+    assert row_err(z, want) <= 1e-8
 
 
 @pytest.mark.parametrize("name", ["ragged-r3", "c1"])
@@ -446,22 +455,26 @@ def test_c3_recipe_at_reduced_size():
     assert abs(info.iters - same.iters) <= 2
     # At this tol the GPU run must be as accurate as the oracle's own PCG run
     # (both measured against the tight solution), and the two runs of the same
-    # recurrence must agree to within half of that method error (their
-    # trajectories differ only by rounding).
+    # recurrence must agree to within half of that method error.  The gates
+    # are set from the oracle's own spread on this recipe
+    # (tests/test_oracle_spread.py): two oracle runs that differ only by
+    # rounding (another LAPACK eigensolver for the preconditioner, operator
+    # results perturbed by 4e-15) agree to 0.2 method errors, and the
+    # perturbed run is 1.1 method errors from the tight solution.
     method_err = O.e_kw(p.K, same.X, tight.X)
     assert O.e_kw(p.K, host(W), tight.X) <= 1.5 * method_err + 1e-10
     assert O.e_kw(p.K, host(W), same.X) <= 0.5 * method_err
     # Tight runs: each is certified by the oracle's own residual (<= 1e-11).
-    # At certified residuals ~2e-12 two solutions of this Matern system still
-    # differ by up to ~1e-9 in K W (the residual-to-K W amplification grows to
-    # ~1e2 in the poorly determined directions), so agreement is gated at 1e-9.
+    # Two certified oracle solutions of this Matern system (residuals ~3e-12)
+    # differ by 3.6e-9 in K W (measured in tests/test_oracle_spread.py), so
+    # agreement is gated at 1.5e-8, about 4x that floor.
     st = UISolver(dp, p.lam, p.rho, 1e-12)
     Wt, infot = st.solve_subproblem()
     assert infot.status == C.OK, infot.as_dict()
     cert_gpu = O.relres(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, host(Wt))
     cert_ref = O.relres(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, tight.X)
     assert cert_gpu <= 1e-11 and cert_ref <= 1e-11, (cert_gpu, cert_ref)
-    assert O.e_kw(p.K, host(Wt), tight.X) <= 1e-9
+    assert O.e_kw(p.K, host(Wt), tight.X) <= 1.5e-8
     sb = UISolver(dp, p.lam, p.rho, 1e-7, precision="mixed_bf16")
     Wb, infob = sb.solve_subproblem()
     assert infob.status == C.OK, infob.as_dict()

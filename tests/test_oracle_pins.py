@@ -263,6 +263,47 @@ def test_aligned_rho_kron_equals_dense():
     assert O.e_kw(p.K, Wk, Wd) < 1e-11
 
 
+def test_full_tensor_mttkrp_equals_observed_mttkrp():
+    """The MTTKRP of a fully observed tensor computed by unfolding (one matrix
+    product) equals the per-observation segment sums of Section 4 and a
+    triple loop over the entries."""
+    p = _aligned_tiny(n=5, I=4, J=3, r=3)
+    Y = p.y.reshape(p.n, p.I, p.J)
+    full = O.mttkrp_full(Y, p.A, p.B)
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    obs = O.mttkrp_observed(p.y, Zhat, p.obs_t, p.n)
+    loops = np.zeros((p.n, p.r))
+    for s in range(p.n):
+        for i in range(p.I):
+            for j in range(p.J):
+                for c in range(p.r):
+                    loops[s, c] += Y[s, i, j] * p.A[i, c] * p.B[j, c]
+    assert np.allclose(full, loops, rtol=1e-13, atol=1e-13)
+    assert np.allclose(obs, loops, rtol=1e-13, atol=1e-13)
+
+
+def test_aligned_rho_decoupled_equals_kron_and_dense():
+    """For a full observation set the rho-system diagonalises in the
+    eigenbases of K and V: the decoupled rho-solve equals O-kron and O-dense
+    (a different algorithm for the same system), and the error estimate of
+    O-kron is consistent with the distance to it."""
+    p = _aligned_tiny(n=9, I=4, J=3, r=3)
+    V = O.gram_V(p.A, p.B)
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    KB = p.K @ O.mttkrp_observed(p.y, Zhat, p.obs_t, p.n)
+    dK, UK = np.linalg.eigh(p.K)
+    dV, UV = np.linalg.eigh(V)
+    Wdec = O.solve_aligned_rho_decoupled(UK, dK, UV, dV, KB, p.lam, p.rho)
+    Wk, delta = O.solve_aligned_rho_kron_with_error(p.K, V, KB, p.lam, p.rho)
+    Wd = O.solve_dense(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho)
+    assert O.e_kw(p.K, Wdec, Wd) < 1e-11
+    assert O.e_kw(p.K, Wk, Wd) < 1e-11
+    assert delta < 1e-11
+    # a wrong shift is caught
+    Wbad = O.solve_aligned_rho_decoupled(UK, dK, UV, dV, KB, p.lam, 10 * p.rho)
+    assert O.e_kw(p.K, Wbad, Wd) > 1e-8
+
+
 # ------------------------------------------------------- special cases / PCG ----
 
 def test_single_mode_case_is_kernel_ridge_regression():
