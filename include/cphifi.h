@@ -302,6 +302,25 @@ CPHIFI_API int cphifi_product(int elt, int trans, int mw, int s, int ksplit, int
                               const double* xscale, double* Y, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* The product of cphifi_product for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results, with the split-K partials
+ * and the BF16 split of X in a static device array of the library
+ * (cphifi_product_static_max_bytes() = 64 MiB per GPU, held by every GPU the
+ * library runs on until the process ends) instead of a caller workspace.
+ * Calls no allocating routine.  ksplit <= 0 takes the split cphifi_product
+ * would, reduced until its partials fit; an explicit ksplit must fit.  Every
+ * call on a GPU shares that GPU's array, so calls that overlap on one GPU
+ * (different streams, or several threads) race: serialise them.  Arguments
+ * and layouts as cphifi_product.  async.  Errors: INVALID_ARG (as
+ * cphifi_product, and a product whose scratch exceeds the array: n (16
+ * ceil(r/16)) 8 bytes per split slab, plus 4 (16 ceil(r/16)) round_up(n, 256)
+ * bytes for BF16), UNSUPPORTED (device index >= 64), HIP_ERROR. */
+CPHIFI_API size_t cphifi_product_static_max_bytes(void);
+CPHIFI_API int cphifi_product_static(int elt, int trans, int mw, int s, int ksplit, int64_t n,
+                                     const void* U, int64_t ldu, const double* X, int64_t r,
+                                     const double* xscale, double* Y, void* stream);
+
 /* ------------------------------------------------------- batched solver
  * Many independent UI subproblems (Section 4.4) of uneven n and r solved by
  * the mixed-precision method of cphifi_ui_solve (precision MIXED_BF16: FP64

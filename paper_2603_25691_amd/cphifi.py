@@ -139,6 +139,9 @@ def _load() -> C.CDLL:
         "cphifi_product_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int,
                                                      C.POINTER(C.c_size_t)]),
         "cphifi_product_tile_ok": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+        "cphifi_product_static_max_bytes": (C.c_size_t, []),
+        "cphifi_product_static": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                            C.c_int64, P, C.c_int64, P, C.c_int64, P, P, P]),
         "cphifi_product": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, P,
                                      C.c_int64, P, C.c_int64, P, P, P, C.c_size_t, P]),
         "cphifi_batch_workspace_bytes": (C.c_int, [C.c_int, C.POINTER(cphifi_ui_desc),
@@ -337,6 +340,19 @@ def cphifi_product(elt: int, trans: int, mw: int, s: int, ksplit: int, n: int, U
                                r, C.c_void_p(xscale) if xscale else None, C.c_void_p(Y),
                                C.c_void_p(workspace), C.c_size_t(workspace_bytes),
                                C.c_void_p(stream)), "cphifi_product")
+
+
+def cphifi_product_static_max_bytes() -> int:
+    return int(_lib.cphifi_product_static_max_bytes())
+
+
+def cphifi_product_static(elt: int, trans: int, mw: int, s: int, ksplit: int, n: int, U: int,
+                          ldu: int, X: int, r: int, xscale: Optional[int], Y: int,
+                          stream: int) -> None:
+    _check(_lib.cphifi_product_static(elt, trans, mw, s, ksplit, n, C.c_void_p(U), ldu,
+                                      C.c_void_p(X), r,
+                                      C.c_void_p(xscale) if xscale else None, C.c_void_p(Y),
+                                      C.c_void_p(stream)), "cphifi_product_static")
 
 
 # ------------------------------------------------------------- batched solver

@@ -1,5 +1,8 @@
-// Stand-alone n x n by n x r product (tile tuning and per-variant tests).
+// Stand-alone n x n by n x r product (tile tuning and per-variant tests), and
+// its variant that takes no workspace (scratch in a static device array).
 #include "cphifi_internal.h"
+
+#include <mutex>
 
 using namespace cphifi;
 
@@ -15,13 +18,15 @@ struct ProductLayout {
   int64_t ldxt;
 };
 
-ProductLayout product_layout(int64_t n, int64_t r, int elt) {
+// Workspace of a product with `slabs` split-K partial slabs (FP64 for every
+// element type: the FP32 / BF16 products write float partials, which fit).
+ProductLayout product_layout(int64_t n, int64_t r, int elt, int slabs = kMaxSplit) {
   ProductLayout L{};
   const int64_t ldp = (r + 15) / 16 * 16;
   L.ldxt = (n + kLowpAlign - 1) / kLowpAlign * kLowpAlign;
   size_t off = 0;
   L.part = off;
-  off = align_up(off + sizeof(double) * (size_t)kMaxSplit * n * ldp, kAlign);
+  off = align_up(off + sizeof(double) * (size_t)slabs * n * ldp, kAlign);
   if (elt == (int)Elt::BF16 || elt == kEltBf16Tiled) {
     L.xthi = off;
     off = align_up(off + sizeof(__bf16) * (size_t)ldp * L.ldxt, kAlign);
@@ -30,6 +35,88 @@ ProductLayout product_layout(int64_t n, int64_t r, int elt) {
   }
   L.total = off;
   return L;
+}
+
+// Scratch of cphifi_product_static: one array per GPU (each device holds its
+// own copy of this module's globals), never allocated or freed by the library.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current).  In host code the array's name is only a
+// stand-in for the symbol, never a device address.
+int scratch_on_current_device(void** out) {
+  int dev = 0;
+  CPHIFI_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("cphifi_product_static: device %d beyond the supported %d", dev, kMaxDevices);
+    return CPHIFI_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    CPHIFI_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (ptr == nullptr || reinterpret_cast<uintptr_t>(ptr) % kAlign != 0) {
+      set_error("cphifi_product_static: scratch symbol has no aligned device address");
+      return CPHIFI_HIP_ERROR;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CPHIFI_OK;
+}
+
+int num_cus() {
+  int num_cu = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  return num_cu > 0 ? num_cu : 256;
+}
+
+// Y = op(U) diag(xscale) X with the split-K partials (and the BF16 split of X)
+// in `ws` laid out by L for gp.ksplit slabs.
+int run_product(Elt e, bool tiled, int trans, const GemmPlan& gp, int64_t n, const void* U,
+                int64_t ldu, const double* X, int64_t r, const double* xscale, double* Y,
+                char* ws, const ProductLayout& L, hipStream_t st) {
+  const int ldp = (int)((r + 15) / 16 * 16);
+  int rc;
+  if (e == Elt::BF16) {
+    __bf16* hi = (__bf16*)(ws + L.xthi);
+    __bf16* lo = (__bf16*)(ws + L.xtlo);
+    if ((rc = launch_split_bf16(X, r, (int)r, xscale, n, hi, lo, L.ldxt, nullptr, st))) return rc;
+    if ((rc = launch_gemm_bf16(gp, (const __bf16*)U, ldu, n, X, r, (int)r, xscale, ws + L.part,
+                               hi, lo, L.ldxt, nullptr, st, tiled)))
+      return rc;
+  } else {
+    if ((rc = launch_gemm(e, trans != 0, gp, U, ldu, n, X, r, (int)r, xscale, ws + L.part,
+                          nullptr, st)))
+      return rc;
+  }
+  return launch_reduce_partials(ws + L.part, e != Elt::F64, gp.ksplit, ldp, n, (int)r, Y,
+                                nullptr, nullptr, nullptr, nullptr, st);
+}
+
+int check_product_args(int elt, int trans, int mw, int s, int64_t n, const void* U, int64_t ldu,
+                       const double* X, int64_t r, double* Y, const char* where) {
+  if (elt < 0 || elt > kEltBf16Tiled || n < 1 || n > INT32_MAX || r < 1 || r > kMaxRank ||
+      U == nullptr || X == nullptr || Y == nullptr || ldu < n) {
+    set_error("%s: bad arguments", where);
+    return CPHIFI_INVALID_ARG;
+  }
+  const Elt e = elt == kEltBf16Tiled ? Elt::BF16 : (Elt)elt;
+  if (!gemm_cfg_valid(e, mw, s)) {
+    set_error("%s: unsupported tile (mw=%d, s=%d) for element type %d", where, mw, s, elt);
+    return CPHIFI_INVALID_ARG;
+  }
+  if (e == Elt::BF16 && trans) {
+    set_error("%s: the BF16 product has no transposed form", where);
+    return CPHIFI_INVALID_ARG;
+  }
+  return CPHIFI_OK;
 }
 
 }  // namespace
@@ -55,48 +142,51 @@ int cphifi_product(int elt, int trans, int mw, int s, int ksplit, int64_t n, con
                    int64_t ldu, const double* X, int64_t r, const double* xscale, double* Y,
                    void* workspace, size_t workspace_bytes, void* stream) {
   clear_error();
-  if (elt < 0 || elt > kEltBf16Tiled || n < 1 || n > INT32_MAX || r < 1 || r > kMaxRank ||
-      U == nullptr || X == nullptr || Y == nullptr || ldu < n || workspace == nullptr) {
-    set_error("cphifi_product: bad arguments");
+  int rc = check_product_args(elt, trans, mw, s, n, U, ldu, X, r, Y, "cphifi_product");
+  if (rc != CPHIFI_OK) return rc;
+  if (workspace == nullptr) {
+    set_error("cphifi_product: workspace is NULL");
     return CPHIFI_INVALID_ARG;
   }
   const bool tiled = elt == kEltBf16Tiled;
   const Elt e = tiled ? Elt::BF16 : (Elt)elt;
-  if (!gemm_cfg_valid(e, mw, s)) {
-    set_error("cphifi_product: unsupported tile (mw=%d, s=%d) for element type %d", mw, s, elt);
-    return CPHIFI_INVALID_ARG;
-  }
-  if (e == Elt::BF16 && trans) {
-    set_error("cphifi_product: the BF16 product has no transposed form");
-    return CPHIFI_INVALID_ARG;
-  }
   const ProductLayout L = product_layout(n, r, elt);
   if (workspace_bytes < L.total || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) {
     set_error("cphifi_product: workspace must be >= %zu bytes, 256-byte aligned", L.total);
     return CPHIFI_INVALID_ARG;
   }
-  hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  int num_cu = 256, dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess)
-    (void)hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  const GemmPlan gp = make_gemm_plan(e, trans != 0, n, (int)r, mw, s, ksplit, num_cu);
-  const int ldp = (int)((r + 15) / 16 * 16);
-  int rc;
-  if (e == Elt::BF16) {
-    __bf16* hi = (__bf16*)(ws + L.xthi);
-    __bf16* lo = (__bf16*)(ws + L.xtlo);
-    if ((rc = launch_split_bf16(X, r, (int)r, xscale, n, hi, lo, L.ldxt, nullptr, st))) return rc;
-    if ((rc = launch_gemm_bf16(gp, (const __bf16*)U, ldu, n, X, r, (int)r, xscale, ws + L.part,
-                               hi, lo, L.ldxt, nullptr, st, tiled)))
-      return rc;
-  } else {
-    if ((rc = launch_gemm(e, trans != 0, gp, U, ldu, n, X, r, (int)r, xscale, ws + L.part,
-                          nullptr, st)))
-      return rc;
+  const GemmPlan gp = make_gemm_plan(e, trans != 0, n, (int)r, mw, s, ksplit, num_cus());
+  return run_product(e, tiled, trans, gp, n, U, ldu, X, r, xscale, Y, (char*)workspace, L,
+                     (hipStream_t)stream);
+}
+
+size_t cphifi_product_static_max_bytes(void) { return kStaticScratchBytes; }
+
+int cphifi_product_static(int elt, int trans, int mw, int s, int ksplit, int64_t n,
+                          const void* U, int64_t ldu, const double* X, int64_t r,
+                          const double* xscale, double* Y, void* stream) {
+  clear_error();
+  int rc = check_product_args(elt, trans, mw, s, n, U, ldu, X, r, Y, "cphifi_product_static");
+  if (rc != CPHIFI_OK) return rc;
+  const bool tiled = elt == kEltBf16Tiled;
+  const Elt e = tiled ? Elt::BF16 : (Elt)elt;
+  const int num_cu = num_cus();
+  GemmPlan gp = make_gemm_plan(e, trans != 0, n, (int)r, mw, s, ksplit, num_cu);
+  // An automatic split takes as many slabs as fit the static scratch (the
+  // same split as cphifi_product whenever that fits); an explicit one must fit.
+  while (ksplit <= 0 && gp.ksplit > 1 && product_layout(n, r, elt, gp.ksplit).total > kStaticScratchBytes)
+    gp = make_gemm_plan(e, trans != 0, n, (int)r, mw, s, gp.ksplit - 1, num_cu);
+  const ProductLayout L = product_layout(n, r, elt, gp.ksplit);
+  if (L.total > kStaticScratchBytes) {
+    set_error("cphifi_product_static: n=%lld r=%lld with split %d needs %zu bytes of scratch; "
+              "the static scratch holds %zu (use cphifi_product with a workspace)",
+              (long long)n, (long long)r, gp.ksplit, L.total, kStaticScratchBytes);
+    return CPHIFI_INVALID_ARG;
   }
-  return launch_reduce_partials(ws + L.part, e != Elt::F64, gp.ksplit, ldp, n, (int)r, Y,
-                                nullptr, nullptr, nullptr, nullptr, st);
+  void* ptr = nullptr;
+  if ((rc = scratch_on_current_device(&ptr)) != CPHIFI_OK) return rc;
+  return run_product(e, tiled, trans, gp, n, U, ldu, X, r, xscale, Y, (char*)ptr, L,
+                     (hipStream_t)stream);
 }
 
 }  // extern "C"
