@@ -16,8 +16,10 @@ residual target (and at the workload's own 1e-8).
 Further fields: `matvec` (the FP64 two-step product of Section 4.4.1),
 `small` (I = 20, J = 10, r = 5: latency per solve, with the oracle's dense
 and least-squares solves timed on the host), `aligned` (n = 200 grid, I = 500,
-J = 100, q = 1e7, r = 10/20/40: FP64 and both mixed precisions, the oracle's
-Kronecker Cholesky and decoupled solves timed on the host) and `batched`
+J = 100, q = 1e7, r = 10/20/40: FP64 and both mixed precisions, the aligned
+solvers of Section 3, the oracle's Kronecker Cholesky and decoupled solves
+timed on the host), `paper_shapes` (the shapes of the paper's unaligned
+experiments, its PCG setting, against the oracle's PCG) and `batched`
 (64 subproblems of uneven size in one persistent, graph-captured launch,
 against the FP64 PCG over the same members).  One JSON line goes to stdout.
 """
@@ -86,6 +88,8 @@ def parse():
                     help="measure only the batched workload (prints its JSON object)")
     ap.add_argument("--no-small", action="store_true", help="skip the small workload")
     ap.add_argument("--no-aligned", action="store_true", help="skip the aligned workload")
+    ap.add_argument("--no-paper-shapes", action="store_true",
+                    help="skip the paper-shaped stand-ins")
     ap.add_argument("--eig-dir", default="",
                     help="read the batch members' eigenpairs from this directory "
                          "(written by --save-eig) instead of computing them")
@@ -201,7 +205,7 @@ def bench_aligned(torch, C, steps: int):
     precisions (K products in BF16 / FP32), e_KW against the oracle's decoupled
     rho-solve; the oracle's Kronecker Cholesky and decoupled solve on the host."""
     import oracle as O
-    from paper_2603_25691_amd.torch_api import UISolver, upload
+    from paper_2603_25691_amd.torch_api import AlignedSolver, UISolver, upload
     from synth import config_c2
 
     res = {"workload": "aligned RKHS subproblem: n=200 grid, I=500 J=100 q=1e7 RBF(0.05) "
@@ -236,17 +240,91 @@ def bench_aligned(torch, C, steps: int):
                          "status": C.status_string(info.status),
                          "e_KW_vs_oracle_decoupled": O.e_kw(p.K, W.cpu().numpy(), Wdec)}
             s.close()
+        # Section 3's own solvers on the GPU (rho = 0 system, right-hand side B):
+        # the MTTKRP from the observed values, then the decoupled direct solve or
+        # PCG on the transformed system; e_KW against the oracle's decoupled solve
+        dK0, UK0 = O.kernel_eig(p.K)
+        dV0, UV0 = np.linalg.eigh(V)
+        W0 = O.solve_decoupled(UK0, dK0, UV0, dV0, Bm, p.lam)
+        s = UISolver(dp, p.lam, p.rho, 1e-10)
+        Bd = s.mttkrp()
+        for meth, tol in (("decoupled", 0.0), ("pcg", 1e-10)):
+            al = AlignedSolver(dp, p.lam, method=meth, tol=tol)
+            Wa, ia = al.solve(s.mttkrp(out=Bd))
+
+            def step_al():
+                s.mttkrp(out=Bd)
+                return al.solve(Bd, W=Wa)
+
+            med, _, (Wa, ia) = timer.run(step_al, steps)
+            row[f"aligned_{meth}"] = {"ms_per_solve": med, "iters": ia.iters,
+                                      "relres_true": ia.relres_true,
+                                      "status": C.status_string(ia.status),
+                                      "e_KW_vs_oracle_decoupled_rho0":
+                                          O.e_kw(p.K, Wa.cpu().numpy(), W0)}
+            al.close()
+        s.close()
         row["gpu_fp64_vs_oracle_mttkrp_plus_decoupled"] = (
             (t_mttkrp + t_dec) * 1e3 / row["fp64"]["ms_per_solve"])
         res["ranks"][str(r)] = row
         log(f"aligned r={r}: fp64 {row['fp64']['ms_per_solve']:.2f} ms "
             f"(e_KW {row['fp64']['e_KW_vs_oracle_decoupled']:.1e}), bf16 "
             f"{row['mixed_bf16']['ms_per_solve']:.2f} ms, fp32 "
-            f"{row['mixed_fp32']['ms_per_solve']:.2f} ms; oracle mttkrp {1e3 * t_mttkrp:.0f} ms "
+            f"{row['mixed_fp32']['ms_per_solve']:.2f} ms; decoupled "
+            f"{row['aligned_decoupled']['ms_per_solve']:.2f} ms, aligned PCG "
+            f"{row['aligned_pcg']['ms_per_solve']:.2f} ms ({row['aligned_pcg']['iters']} its); "
+            f"oracle mttkrp {1e3 * t_mttkrp:.0f} ms "
             f"decoupled {1e3 * t_dec:.0f} ms kron {1e3 * t_kron:.0f} ms")
         del dp
         torch.cuda.empty_cache()
     return res
+
+
+# ------------------------------------------------------ paper shapes (C6)
+def bench_paper_shapes(torch, C, steps: int):
+    """Shape-only stand-ins of the paper's unaligned experiments (Section 5.2):
+    vortex 199 x 449 x 151 and Miranda 256 x 256 x 269 tensors, all modes RKHS
+    on integer grids (Gaussian bandwidths 4/4/3 and 1/1/2), q = 50,000 entries
+    uniformly without replacement, lambda = 0.1, rho = 1e-6; the last mode's
+    subproblem.  The paper's PCG setting (tol 1e-6, at most 75 iterations) in
+    FP64 on the GPU against the oracle's PCG (the same algorithm on the host),
+    per rank r."""
+    import oracle as O
+    from paper_2603_25691_amd.torch_api import UISolver, upload
+    from synth import make_paper_standin
+
+    model, cores = cpu_info()
+    out = {"workload": "paper-shaped stand-ins (vortex 199x449x151, Miranda 256x256x269): "
+                       "q=50000 uniform entries, Gaussian RKHS modes, lambda=0.1 rho=1e-6, "
+                       "PCG tol 1e-6 maxit 75 (the paper's setting)",
+           "host": f"{cores} threads ({model})", "cases": {}}
+    timer = StepTimer(torch)
+    for name, dims, sig in (("vortex", (199, 449, 151), (4.0, 4.0, 3.0)),
+                            ("miranda", (256, 256, 269), (1.0, 1.0, 2.0))):
+        for r in (5, 25, 50):
+            p = make_paper_standin(shape=dims, sigmas=sig, r=r)
+            dp = upload(p)
+            Zhat, V = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j), O.gram_V(p.A, p.B)
+            eig = O.kernel_eig(p.K)
+            t_pcg, ref = host_median(lambda: O.solve_pcg(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho,
+                                                         p.gamma, V, 1e-6, 75, eigK=eig))
+            row = {"n": p.n, "r": r, "oracle_pcg_ms": 1e3 * t_pcg, "oracle_iters": ref.iters}
+            for prec, tol in (("fp64", 1e-6), ("mixed_bf16", 1e-6)):
+                s = UISolver(dp, p.lam, p.rho, tol, precision=prec, maxit=75)
+                W, info = s.solve_subproblem()
+                med, _, (W, info) = timer.run(lambda: s.solve_subproblem(W=W), steps)
+                row[prec] = {"ms_per_solve": med, "iters": info.iters,
+                             "relres_true": info.relres_true,
+                             "status": C.status_string(info.status),
+                             "e_KW_vs_oracle_pcg": O.e_kw(p.K, W.cpu().numpy(), ref.X)}
+                s.close()
+            row["gpu_fp64_vs_oracle_pcg"] = row["oracle_pcg_ms"] / row["fp64"]["ms_per_solve"]
+            out["cases"][f"{name}-r{r}"] = row
+            log(f"paper shape {name} r={r}: fp64 {row['fp64']['ms_per_solve']:.2f} ms "
+                f"({row['fp64']['iters']} its), mixed {row['mixed_bf16']['ms_per_solve']:.2f} ms; "
+                f"oracle PCG {row['oracle_pcg_ms']:.0f} ms ({ref.iters} its)")
+            del dp
+    return out
 
 
 # ------------------------------------------------------------- batched (C5)
@@ -281,9 +359,11 @@ def bench_batch(a, torch, C):
     t0 = time.time()
     table = BATCH_TILES if os.path.exists(BATCH_TILES) else None
     bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], tol, tile_table=table)
+    # the right-hand sides b = K B of the FP64 baseline (the batched solve
+    # starts from the observed values and forms its own, inside the launch)
     rhs = bs.rhs()
     Ws = [torch.empty_like(b) for b in rhs]
-    bs.bind(rhs, Ws)
+    bs.bind(bs.ys(), Ws)
     status, infos = bs.solve()
     torch.cuda.synchronize()
     log(f"batch: created + first solve in {time.time() - t0:.1f} s, status {status}")
@@ -296,16 +376,15 @@ def bench_batch(a, torch, C):
     log(f"batch mixed: {ms_batch:.2f} ms per batch ({len(probs) * 1e3 / ms_batch:.1f} "
         f"subproblem solves/s), {rounds} rounds, grid {grid}, status {C.status_string(status)}")
 
-    # FP64 PCG (paper form), members one after another, to the same target
+    # FP64 PCG (paper form), members one after another, to the same target,
+    # each a whole subproblem from its observed values as in the batched launch
     solvers = [UISolver(dp, p.lam, p.rho, tol, precision="fp64") for p, dp in zip(probs, dps)]
-    for s_ in solvers:
-        s_.setup()
     W64 = [torch.empty_like(b) for b in rhs]
 
     def fp64_all():
         its = []
-        for s_, b, W in zip(solvers, rhs, W64):
-            _, info = s_.solve(b, W)
+        for s_, W in zip(solvers, W64):
+            _, info = s_.solve_subproblem(W=W)
             its.append(info.iters)
         return its
 
@@ -645,6 +724,8 @@ def main():
         out["small"] = bench_small(torch, C, max(a.steps, 10))
     if not a.no_aligned:
         out["aligned"] = bench_aligned(torch, C, max(3, min(a.steps, 10)))
+    if not a.no_paper_shapes:
+        out["paper_shapes"] = bench_paper_shapes(torch, C, max(3, min(a.steps, 10)))
     if a.batch_count > 0:
         out["batched"] = bench_batch(a, torch, C)
     print(json.dumps(out), flush=True)

@@ -323,11 +323,15 @@ CPHIFI_API int cphifi_product_static(int elt, int trans, int mw, int s, int kspl
 
 /* ------------------------------------------------------- batched solver
  * Many independent UI subproblems (Section 4.4) of uneven n and r solved by
- * the mixed-precision method of cphifi_ui_solve (precision MIXED_BF16: FP64
- * iterative refinement of the system of eq. unaligned-infinite-1 around inner
- * PCG solves in the eigenbasis of K with BF16 eigenvectors and the r x r step
- * of eq. fx), all members together in ONE persistent kernel launch that is
- * captured with its reset kernel in a HIP graph.  Members: implicit (A, B)
+ * the mixed-precision method of cphifi_ui_solve_subproblem (precision
+ * MIXED_BF16: FP64 iterative refinement of the system of eq.
+ * unaligned-infinite-1 around inner PCG solves in the eigenbasis of K with
+ * BF16 eigenvectors and the r x r step of eq. fx), all members together in
+ * ONE persistent kernel launch that is captured with its reset kernel in a
+ * HIP graph.  The launch starts from each member's observed values y: the
+ * per-solve setup of Section 4.4.2 (V = Z^T Z unless given, eig(V) by Jacobi,
+ * the inverse diagonal D), the observed MTTKRP B of the right-hand side
+ * b = K B, the refinement and the FP64 certificate all run inside it.  Members: implicit (A, B)
  * form, n <= 65536, r <= 48, J r <= 8192 (B is read from an LDS copy), up to
  * 256 per batch; each member's desc and
  * inputs follow cphifi_ui_plan_create (tol: FP64 relres target; inner_tol,
@@ -336,8 +340,9 @@ CPHIFI_API int cphifi_product_static(int elt, int trans, int mw, int s, int kspl
  * Workspace: device, >= cphifi_batch_workspace_bytes(), 256-byte aligned; it
  * holds every member's plan workspace plus the batch's scalars.  Product tiles
  * per member come from the autotuner's table at `tile_table` (NULL: the file
- * named by CPHIFI_TILE_TABLE, else built-in sizes).  create runs the per-member
- * setup (Section 4.4.2) and synchronizes `stream`.
+ * named by CPHIFI_TILE_TABLE, else built-in sizes).  create makes the member
+ * plans (cphifi_ui_plan_create and cphifi_ui_setup, so each plan also serves
+ * the cphifi_ui_* calls) and synchronizes `stream`.
  * Errors: INVALID_ARG, UNSUPPORTED (other precision, explicit Zhat, n too
  * large), HIP_ERROR, and any member's plan-creation error (member named in
  * cphifi_last_error). */
@@ -355,23 +360,25 @@ CPHIFI_API int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_u
  * solve, so do not run both at once. */
 CPHIFI_API int cphifi_batch_plan(cphifi_batch* bt, int member, cphifi_plan** out);
 
-/* Right-hand sides b_i = K_i B_i of all members (cphifi_ui_rhs per member).
- * y, b: host arrays of `count` device pointers.  async. */
+/* Right-hand sides b_i = K_i B_i of all members (cphifi_ui_rhs per member;
+ * the batched solve does not need them).  y, b: host arrays of `count` device
+ * pointers.  async. */
 CPHIFI_API int cphifi_batch_rhs(cphifi_batch* bt, const double* const* y, double* const* b);
 
-/* Bind the right-hand sides b_i (n_i x r_i, device) and solutions W_i (device;
- * x0 on entry for members with FLAG_WARM_START) that the graph reads and
- * writes.  b, W: host arrays of `count` device pointers.  stream-ordered. */
-CPHIFI_API int cphifi_batch_bind(cphifi_batch* bt, const double* const* b, double* const* W);
+/* Bind the observed values y_i (q_i doubles, device; may be NULL when
+ * q_i = 0) and solutions W_i (n_i x r_i, device; x0 on entry for members with
+ * FLAG_WARM_START) that the graph reads and writes.  y, W: host arrays of
+ * `count` device pointers.  stream-ordered. */
+CPHIFI_API int cphifi_batch_bind(cphifi_batch* bt, const double* const* y, double* const* W);
 
-/* Solve all members: binds b / W when given (else the last binding), launches
+/* Solve all members: binds y / W when given (else the last binding), launches
  * the graph on the batch's stream.  With infos (host array of `count`) it
  * waits and fills them (iters = total inner iterations, refine_steps,
- * relres_true = FP64 ||b - A w|| / ||b||, status); the return value is then
+ * relres_true = FP64 ||b - A w|| / ||b|| with b = K B, status); the return value is then
  * OK, NOT_CONVERGED, NUMERIC or HIP_ERROR (the worst member; HIP_ERROR also
  * when a bounded grid wait timed out).  With infos NULL it returns after the
  * launch (async); read the results with cphifi_batch_info. */
-CPHIFI_API int cphifi_batch_solve(cphifi_batch* bt, const double* const* b, double* const* W,
+CPHIFI_API int cphifi_batch_solve(cphifi_batch* bt, const double* const* y, double* const* W,
                                   cphifi_solve_info* infos);
 CPHIFI_API int cphifi_batch_info(cphifi_batch* bt, cphifi_solve_info* infos);
 
@@ -384,11 +391,12 @@ CPHIFI_API int cphifi_batch_graph(cphifi_batch* bt, void** graph_exec);
 CPHIFI_API int cphifi_batch_rounds(cphifi_batch* bt, int* rounds, int* grid);
 
 /* Where the last launch spent its time, from the device real-time clock as
- * seen by one workgroup: ms[0..7] the eight phases of a round (products A,
- * gather-scatter, segment rows + split, products B, finish, x/r update (with
- * the preconditioner in inner iterations), preconditioner (refinement steps),
- * control + p update), each including its closing grid barrier; ms[8] the
- * per-round setup.  ms: host array of 9.  sync. */
+ * seen by one workgroup: ms[0..7] the eight phases of a round (products A and
+ * the Gram V, gather-scatter and the MTTKRP, segment rows + split, products B
+ * and eig(V), finish and D, x/r update (with the preconditioner in inner
+ * iterations), preconditioner (refinement steps), control + p update), each
+ * including its closing grid barrier; ms[8] the per-round setup.  ms: host
+ * array of 9.  sync. */
 CPHIFI_API int cphifi_batch_phase_ms(cphifi_batch* bt, double* ms);
 
 /* Release the batch's host state and member plans (the workspace belongs to

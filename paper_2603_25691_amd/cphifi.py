@@ -394,16 +394,16 @@ def cphifi_batch_rhs(batch: int, y_ptrs, b_ptrs) -> None:
            "cphifi_batch_rhs")
 
 
-def cphifi_batch_bind(batch: int, b_ptrs, W_ptrs) -> None:
-    _check(_lib.cphifi_batch_bind(C.c_void_p(batch), _ptr_array(b_ptrs), _ptr_array(W_ptrs)),
+def cphifi_batch_bind(batch: int, y_ptrs, W_ptrs) -> None:
+    _check(_lib.cphifi_batch_bind(C.c_void_p(batch), _ptr_array(y_ptrs), _ptr_array(W_ptrs)),
            "cphifi_batch_bind")
 
 
-def cphifi_batch_solve(batch: int, count: int, b_ptrs=None, W_ptrs=None, wait: bool = True):
+def cphifi_batch_solve(batch: int, count: int, y_ptrs=None, W_ptrs=None, wait: bool = True):
     """Returns (status, [cphifi_solve_info]) when wait, else None (async launch)."""
     infos = (cphifi_solve_info * count)() if wait else None
     st = _lib.cphifi_batch_solve(C.c_void_p(batch),
-                                 _ptr_array(b_ptrs) if b_ptrs is not None else None,
+                                 _ptr_array(y_ptrs) if y_ptrs is not None else None,
                                  _ptr_array(W_ptrs) if W_ptrs is not None else None, infos)
     if not wait:
         _check(st, "cphifi_batch_solve")

@@ -11,25 +11,33 @@
 // step of eq. (fx) as preconditioner, xbar += dbar; at the end W = U xbar and
 // its FP64 residual in the original form certifies it.
 //
+// The launch starts from the observed values y: the per-solve setup of
+// Section 4.4.2 (V = Z^T Z, eig(V) by Jacobi, the inverse diagonal D) and the
+// observed MTTKRP B of the right-hand side b = K B (Section 4) run inside it,
+// b itself is never formed: bbar = U^T b = D_K U^T B, and the certificate is
+// b - A W = K (B - Yhat1 - lambda W) - rho W with ||b|| = ||bbar||.
+//
 // Execution model.  Each member runs a small state machine (mode):
-//   INIT -> ROT_B [-> ROT_W] -> RES0 -> INNER ... INNER -> RES -> INNER ...
-//        -> RES -> FINAL -> CERT -> DONE   (or back to RES if CERT misses tol)
+//   SETUP -> ROT_B [-> ROT_W] -> RES0 -> INNER ... INNER -> RES -> INNER ...
+//         -> RES -> FINAL -> CERT -> DONE   (or back to RES if CERT misses tol)
 // and the kernel advances every member by one step per *round*.  A round has
 // eight phases; in each phase every active member contributes work items
 // according to its mode:
 //
 //   phase  INNER (one PCG iteration)     RES (rotated FP64 residual)   CERT (FP64 residual of W)
 //   A      BF16 U (D_K p)                FP64 U (D_K xbar)             FP64 K W
-//   OBS    gather-dot-scatter (eqs. vl, yhat1)                         (with Xhat)
-//   ROWS   split segments + hi/lo BF16 split of Yhat1; elsewhere split segments only
-//   B      BF16 U^T Yhat1                FP64 U^T Yhat1                FP64 K Yhat1
-//   FIN    q = D_K(Y + lambda p) + rho p rbar = bbar - Abar xbar       rf = b - A W
+//   OBS    gather-dot-scatter (eqs. vl, yhat1)
+//   ROWS   split segments + hi/lo BF16 split of Yhat1; split segments; T = B - Yhat1 - lambda W
+//   B      BF16 U^T Yhat1                FP64 U^T Yhat1                FP64 K T
+//   FIN    q = D_K(Y + lambda p) + rho p rbar = bbar - Abar xbar       rf = K T - rho W
 //   UPD    alpha; dbar, r update         -                             -
 //   PREC   z = ((r U_V) had D) U_V^T     z (when refining on)          -
 //   CTRL   beta; p update + split;       relres test; p = z + split    certificate test
 //          at the stop xbar += dbar
-// ROT_B / ROT_W (U^T b, U^T W0 for a warm start) and FINAL (W = U xbar) use
-// phases A and FIN; INIT (||b||) and RES0 (rbar = bbar) have no products.
+// SETUP uses A (V, one item), OBS (the MTTKRP gather), ROWS (split segments),
+// B (eig(V), one item) and FIN (D and dK clamped, W = 0 unless warm);
+// ROT_B / ROT_W (D_K U^T B, U^T W0 for a warm start) and FINAL (W = U xbar)
+// use phases A and FIN; RES0 (rbar = bbar) has no products.
 //
 // Work items of a phase (product tiles, wave tasks of the gather, row chunks
 // of the vector steps) are handed out by an atomic counter; phases are
@@ -40,6 +48,7 @@
 // leaves, so the launch always drains.
 #include "cphifi_internal.h"
 #include "gemm_tiles.h"
+#include "jacobi.h"
 #include "obs_tile.h"
 #include "plan.h"
 
@@ -75,10 +84,11 @@ static_assert(tiles::k4_lds_elems<double, 3, 4>() * 8 <= kSmemBytes, "f64 NN til
 static_assert(tiles::k4_lds_elems<double, 3, 4>() * 8 <= kSmemBytes, "f64 T tile LDS");
 static_assert((kBatchRank * kBatchRank + 4 * kWave) * 8 <= kSmemBytes, "preconditioner LDS");
 static_assert(2 * kBatchRank * kRC * 2 <= kSmemBytes, "split transpose LDS");
+static_assert(sizeof(JacobiLds<kBatchRank>) <= kSmemBytes, "Jacobi LDS");
 
 enum : int32_t {
-  M_INIT = 0,   // ||b||^2; W = 0 unless warm
-  M_ROT_B = 1,  // bbar = U^T b
+  M_SETUP = 0,  // V, eig(V), D, the observed MTTKRP B; W = 0 unless warm
+  M_ROT_B = 1,  // bbar = U^T b = D_K U^T B; ||b||^2 = ||bbar||^2
   M_ROT_W = 2,  // xbar = U^T W (warm start)
   M_RES0 = 3,   // rbar = bbar (xbar = 0)
   M_RES = 4,    // rbar = bbar - Abar xbar (FP64)
@@ -99,7 +109,9 @@ struct BSub {
                                        // sample per time point (A read per segment)
   const double* K;
   const double* UK;
-  const double* b;
+  const double* dK;   // eigenvalues of K as given (clamped at 0 into dKc)
+  const double* y;    // observed values (bound per solve)
+  const double* Vin;  // caller's V = Z^T Z, or null: formed from A and B
   double* W;
   const int32_t* obs_i;
   const int32_t* obs_j;
@@ -109,15 +121,16 @@ struct BSub {
   const int32_t *tseg, *tbeg, *tend, *tslot, *tfirst, *mptr, *rowm, *obs_ptr;
   void* part;
   double* tpart;
-  const double *UV, *D, *dKc;
+  double *V, *UV, *dV, *D, *dKc;
   const __bf16 *ulp, *utlp;
   __bf16 *xthi, *xtlo;
   double *X, *R, *Z, *P, *Q, *XH, *Y1, *RF;
   double *BB, *XA;  // bbar = U^T b, accumulated xbar
+  double* BM;       // the observed MTTKRP B
   double *red0, *red1, *red2;
   int32_t bf_mw, bf_ks, bf_nrb, fn_ks, fn_nrb, fn_vw, ft_mw, ft_ks, ft_nrb, pad0;
   int64_t bf_kper, fn_kper, ft_kper;
-  double lam, rho, tol, inner_tol2;
+  double lam, rho, gamma, tol, inner_tol2;
   int32_t maxit, max_refine, warm, pad1;
 };
 
@@ -141,7 +154,9 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
   // pointer lets the compiler use global (not flat) loads and stores.
   s.K = global_word<decltype(s.K)>(w[offsetof(BSub, K) / 8]);
   s.UK = global_word<decltype(s.UK)>(w[offsetof(BSub, UK) / 8]);
-  s.b = global_word<decltype(s.b)>(w[offsetof(BSub, b) / 8]);
+  s.dK = global_word<decltype(s.dK)>(w[offsetof(BSub, dK) / 8]);
+  s.y = global_word<decltype(s.y)>(w[offsetof(BSub, y) / 8]);
+  s.Vin = global_word<decltype(s.Vin)>(w[offsetof(BSub, Vin) / 8]);
   s.W = global_word<decltype(s.W)>(w[offsetof(BSub, W) / 8]);
   s.obs_i = global_word<decltype(s.obs_i)>(w[offsetof(BSub, obs_i) / 8]);
   s.obs_j = global_word<decltype(s.obs_j)>(w[offsetof(BSub, obs_j) / 8]);
@@ -159,7 +174,9 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
   s.obs_ptr = global_word<decltype(s.obs_ptr)>(w[offsetof(BSub, obs_ptr) / 8]);
   s.part = global_word<decltype(s.part)>(w[offsetof(BSub, part) / 8]);
   s.tpart = global_word<decltype(s.tpart)>(w[offsetof(BSub, tpart) / 8]);
+  s.V = global_word<decltype(s.V)>(w[offsetof(BSub, V) / 8]);
   s.UV = global_word<decltype(s.UV)>(w[offsetof(BSub, UV) / 8]);
+  s.dV = global_word<decltype(s.dV)>(w[offsetof(BSub, dV) / 8]);
   s.D = global_word<decltype(s.D)>(w[offsetof(BSub, D) / 8]);
   s.dKc = global_word<decltype(s.dKc)>(w[offsetof(BSub, dKc) / 8]);
   s.ulp = global_word<decltype(s.ulp)>(w[offsetof(BSub, ulp) / 8]);
@@ -176,6 +193,7 @@ __device__ __forceinline__ BSub load_sub(const BSub* sub, int b) {
   s.RF = global_word<decltype(s.RF)>(w[offsetof(BSub, RF) / 8]);
   s.BB = global_word<decltype(s.BB)>(w[offsetof(BSub, BB) / 8]);
   s.XA = global_word<decltype(s.XA)>(w[offsetof(BSub, XA) / 8]);
+  s.BM = global_word<decltype(s.BM)>(w[offsetof(BSub, BM) / 8]);
   s.red0 = global_word<decltype(s.red0)>(w[offsetof(BSub, red0) / 8]);
   s.red1 = global_word<decltype(s.red1)>(w[offsetof(BSub, red1) / 8]);
   s.red2 = global_word<decltype(s.red2)>(w[offsetof(BSub, red2) / 8]);
@@ -266,8 +284,16 @@ __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
   const int fn = S.fn_nrb * S.fn_ks, ft = S.ft_nrb * S.ft_ks, bf = S.bf_nrb * S.bf_ks;
   const int rows = (S.nmulti > 0 && !S.orow) ? S.nrc : 0;  // split segments to add
   switch (mode) {
-    case M_INIT:
-      return slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
+    case M_SETUP:
+      switch (slot) {
+        case S_A:
+        case S_B:
+        case S_CTRL: return 1;
+        case S_OBS: return S.ntaskw;
+        case S_ROWS: return rows;
+        case S_FIN: return S.nrc;
+        default: return 0;
+      }
     case M_ROT_B:
     case M_ROT_W:
       return slot == S_A ? fn : slot == S_FIN ? S.nrc : slot == S_CTRL ? 1 : 0;
@@ -291,7 +317,7 @@ __device__ __forceinline__ int item_count(const BSub& S, int mode, int slot) {
         case S_A:
         case S_B: return fn;
         case S_OBS: return S.ntaskw;
-        case S_ROWS: return rows;
+        case S_ROWS: return S.nrc;  // T = B - Yhat1 - lambda W
         case S_FIN: return S.nrc;
         case S_CTRL: return 1;
         default: return 0;
@@ -366,7 +392,7 @@ __device__ __forceinline__ void gemm_item(const BSub& S, int kind, const double*
 // Work item i: wave w takes tasks [(4 i + w) kTPW, ...) of the member's list,
 // or, for short segments, segments [(4 i + w) kSegPerWave, ...) by lane rows.
 // The arithmetic type is that of the partials (FP32 after the BF16 products).
-template <int L, int CPL, int FORM, typename PT, bool BL>
+template <int L, int CPL, int FORM, int MODE, typename PT, bool BL>
 __device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, const PT* Bl) {
   const int64_t wv = 4 * i + (item_tid() >> 6);
   const int64_t t0 = wv * kTPW;
@@ -382,13 +408,13 @@ __device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, c
   d.a.A32 = S.A32;
   d.a.B32 = S.B32;
   d.a.Zhat = nullptr;
-  d.a.y = nullptr;
-  d.a.part = S.part;
+  d.a.y = MODE == 1 ? S.y : nullptr;
+  d.a.part = MODE == 1 ? nullptr : S.part;
   // split-K depth of the product A that made Xhat
   d.a.ksplit = mode == M_INNER ? S.bf_ks : mode == M_RES ? S.ft_ks : S.fn_ks;
   d.a.ldp = S.ldp;
-  d.a.Xhat = mode == M_CERT ? S.XH : nullptr;
-  d.a.out = S.Y1;
+  d.a.Xhat = nullptr;
+  d.a.out = MODE == 1 ? S.BM : S.Y1;
   d.a.tpart = S.tpart;
   d.a.done = nullptr;
   d.I = S.I;
@@ -403,14 +429,14 @@ __device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, c
     for (int k = 0; k < kSegPerWave; k += ROWS) {
       const int64_t s0 = wv * kSegPerWave + k;
       if (s0 >= S.n) break;
-      tiles::obs_rows<L, CPL, FORM, 0, PT, BL, PT>(d, S.obs_ptr, s0,
+      tiles::obs_rows<L, CPL, FORM, MODE, PT, BL, PT>(d, S.obs_ptr, s0,
                                                    (int)min((int64_t)ROWS, S.n - s0),
                                                    item_tid() & 63, Bl);
     }
     return;
   }
   for (int64_t task = t0; task < t1; ++task)
-    tiles::obs_task<L, CPL, FORM, 0, PT, BL, PT>(tv, d, task, item_tid() & 63, Bl);
+    tiles::obs_task<L, CPL, FORM, MODE, PT, BL, PT>(tv, d, task, item_tid() & 63, Bl);
 }
 
 // B (J x r, at most kSmemBytes as FP64; checked at batch creation) goes to LDS
@@ -418,7 +444,7 @@ __device__ __forceinline__ void obs_item_b(const BSub& S, int64_t i, int mode, c
 __device__ __forceinline__ const double* factor_b(const BSub& S, double) { return S.B; }
 __device__ __forceinline__ const float* factor_b(const BSub& S, float) { return S.B32; }
 
-template <int L, int CPL, int FORM, typename PT>
+template <int L, int CPL, int FORM, int MODE, typename PT>
 __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, int mode, char* smem) {
   const int64_t len = (int64_t)S.J * S.r;
   if (len * (int64_t)sizeof(double) <= kSmemBytes) {
@@ -426,23 +452,28 @@ __device__ __forceinline__ void obs_item_c(const BSub& S, int64_t i, int mode, c
     const PT* src = factor_b(S, PT(0));
     for (int64_t e = item_tid(); e < len; e += blockDim.x) Bl[e] = src[e];
     __syncthreads();
-    obs_item_b<L, CPL, FORM, PT, true>(S, i, mode, Bl);
+    obs_item_b<L, CPL, FORM, MODE, PT, true>(S, i, mode, Bl);
   }
 }
 
 template <int L, int CPL>
 __device__ __forceinline__ void obs_item_l(const BSub& S, int64_t i, int mode, char* smem) {
   const bool f = mode == M_INNER;  // BF16 products leave float partials
-  if (S.own) {
-    if (f)
-      obs_item_c<L, CPL, tiles::kOwner, float>(S, i, mode, smem);
+  if (mode == M_SETUP) {            // the observed MTTKRP B (FP64)
+    if (S.own)
+      obs_item_c<L, CPL, tiles::kOwner, 1, double>(S, i, mode, smem);
     else
-      obs_item_c<L, CPL, tiles::kOwner, double>(S, i, mode, smem);
+      obs_item_c<L, CPL, tiles::kImplicit, 1, double>(S, i, mode, smem);
+  } else if (S.own) {
+    if (f)
+      obs_item_c<L, CPL, tiles::kOwner, 0, float>(S, i, mode, smem);
+    else
+      obs_item_c<L, CPL, tiles::kOwner, 0, double>(S, i, mode, smem);
   } else {
     if (f)
-      obs_item_c<L, CPL, tiles::kImplicit, float>(S, i, mode, smem);
+      obs_item_c<L, CPL, tiles::kImplicit, 0, float>(S, i, mode, smem);
     else
-      obs_item_c<L, CPL, tiles::kImplicit, double>(S, i, mode, smem);
+      obs_item_c<L, CPL, tiles::kImplicit, 0, double>(S, i, mode, smem);
   }
 }
 
@@ -456,10 +487,14 @@ __device__ __forceinline__ void obs_item(const BSub& S, int64_t i, int mode, cha
   }
 }
 
-// Rows of segments split over several gather tasks: Yhat1 = sum of their
-// partial rows (fixed order).  With `split`, also the hi/lo BF16 operand of
-// the U^T Yhat1 product for the chunk's rows.
-__device__ __forceinline__ void rows_item(const BSub& S, int64_t i, bool split, char* smem) {
+// Rows of segments split over several gather tasks: the gather's output row
+// (Yhat1, or the MTTKRP B in SETUP) = sum of their partial rows (fixed order).
+// INNER also writes the hi/lo BF16 operand of the U^T Yhat1 product for the
+// chunk's rows; CERT forms T = B - Yhat1 - lambda W for the K T product.
+__device__ __forceinline__ void rows_item(const BSub& S, int64_t i, int mode, char* smem) {
+  const bool split = mode == M_INNER;
+  const bool cert = mode == M_CERT;
+  double* out = mode == M_SETUP ? S.BM : S.Y1;
   const int64_t s0 = i * kRC;
   const int rows = (int)min((int64_t)kRC, S.n - s0);
   const int r = S.r;
@@ -468,19 +503,39 @@ __device__ __forceinline__ void rows_item(const BSub& S, int64_t i, bool split, 
   for (int e = item_tid(); e < rows * r; e += blockDim.x) {
     const int sr = e / r, c = e % r;
     const int64_t s = s0 + sr;
-    const int32_t m = S.rowm[s];
+    const int32_t m = (S.nmulti > 0 && !S.orow) ? S.rowm[s] : -1;
     double v;
     if (m >= 0) {
       v = 0.0;
       for (int32_t k = S.mptr[m]; k < S.mptr[m + 1]; ++k) v += S.tpart[(int64_t)k * r + c];
-      if (!split) S.Y1[s * r + c] = v;
+      if (!split && !cert) out[s * r + c] = v;
     } else {
-      if (!split) continue;
+      if (!split && !cert) continue;
       v = S.Y1[s * r + c];
     }
-    split_pair(v, &th[c * kRC + sr], &tl[c * kRC + sr]);
+    if (cert) {
+      const int64_t o = s * r + c;
+      S.Q[o] = S.BM[o] - v - S.lam * S.W[o];
+    } else if (split) {
+      split_pair(v, &th[c * kRC + sr], &tl[c * kRC + sr]);
+    }
   }
   if (split) store_split(S, s0, rows, th, tl);
+}
+
+// V = (A^T A) had (B^T B) of one member (or the caller's V), one work item.
+__device__ __forceinline__ void gram_item(const BSub& S) {
+  const int r = S.r;
+  for (int e = item_tid(); e < r * r; e += blockDim.x) {
+    const int a = e / r, b = e % r;
+    if (S.Vin != nullptr) {
+      S.V[e] = S.Vin[e];
+    } else if (a <= b) {
+      const double v = gram_entry(S.A, S.I, S.B, S.J, r, a, b);
+      S.V[a * r + b] = v;
+      S.V[b * r + a] = v;
+    }
+  }
 }
 
 // ------------------------------------------------------------ vector steps
@@ -549,16 +604,14 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
         loc += v * v;
         break;
       }
-      case M_CERT: {  // rf = b - (Y + lambda Xhat + rho W)
-        const double y = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
-        const double q = y + S.lam * S.XH[e] + S.rho * S.W[e];
-        const double v = S.b[e] - q;
+      case M_CERT: {  // rf = b - A W = K (B - Yhat1 - lambda W) - rho W
+        const double v = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c) - S.rho * S.W[e];
         S.RF[e] = v;
         loc += v * v;
         break;
       }
-      case M_ROT_B: {  // bbar = U^T b
-        const double v = part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
+      case M_ROT_B: {  // bbar = U^T b = U^T K B = D_K U^T B
+        const double v = S.dKc[s] * part_sum<double>(S.part, S.fn_ks, S.n, S.ldp, s, c);
         S.BB[e] = v;
         if (!S.warm) S.XA[e] = 0.0;
         loc += v * v;
@@ -573,10 +626,11 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
       case M_FINAL:  // W = U xbar
         S.W[e] = part_sum<double>(S.part, S.ft_ks, S.n, S.ldp, s, c);
         break;
-      default: {  // M_INIT: ||b||^2
-        const double v = S.b[e];
+      default: {  // M_SETUP: dK clamped at 0, D (eq. fx), W = 0 unless warm
+        const double dk = S.dK[s];
+        if (c == 0) S.dKc[s] = fmax(dk, 0.0);
+        S.D[e] = precond_entry(dk, S.dV[c], S.gamma, S.lam, S.rho);
         if (!S.warm) S.W[e] = 0.0;
-        loc += v * v;
         break;
       }
     }
@@ -588,7 +642,6 @@ __device__ __forceinline__ void fin_item(const BSub& S, int mode, int64_t i, dou
     case M_RESC:
     case M_CERT:
     case M_ROT_B: red = S.red1; break;
-    case M_INIT: red = S.red2; break;
     default: break;
   }
   if (red != nullptr) {
@@ -878,11 +931,19 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
       }
       return;
     }
-    case M_ROT_B: {
+    case M_ROT_B: {  // ||b||^2 = ||bbar||^2 (U_K orthogonal)
       const double bb = sum_partials(S.red1, S.nrc, s_red);
       if (lead) {
         st->bbar = bb;
-        finish_member(st, S.warm ? M_ROT_W : M_RES0, 0);
+        st->bb = bb;
+        if (!isfinite(bb)) {
+          finish_member(st, M_DONE, CPHIFI_NUMERIC);
+        } else if (bb == 0.0 && !S.warm) {
+          st->rel = st->cert = 0.0;  // b = 0: w = 0 is exact
+          finish_member(st, M_DONE, CPHIFI_OK);
+        } else {
+          finish_member(st, S.warm ? M_ROT_W : M_RES0, 0);
+        }
       }
       return;
     }
@@ -892,21 +953,9 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
     case M_FINAL:
       if (lead) finish_member(st, M_CERT, 0);
       return;
-    default: {  // M_INIT
-      const double bb = sum_partials(S.red2, S.nrc, s_red);
-      if (lead) {
-        st->bb = bb;
-        if (!isfinite(bb)) {
-          finish_member(st, M_DONE, CPHIFI_NUMERIC);
-        } else if (bb == 0.0 && !S.warm) {
-          st->rel = st->cert = 0.0;  // b = 0: w = 0 is exact
-          finish_member(st, M_DONE, CPHIFI_OK);
-        } else {
-          finish_member(st, M_ROT_B, 0);
-        }
-      }
+    default:  // M_SETUP
+      if (lead) finish_member(st, M_ROT_B, 0);
       return;
-    }
   }
 }
 
@@ -918,19 +967,24 @@ __device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, in
         case M_INNER: gemm_item(S, G_BF_U, nullptr, i, smem); break;
         case M_RES: gemm_item(S, G_UKT, S.XH, i, smem); break;  // U (D_K xbar)
         case M_CERT: gemm_item(S, G_K, S.W, i, smem); break;
-        case M_ROT_B: gemm_item(S, G_UKN, S.b, i, smem); break;
+        case M_ROT_B: gemm_item(S, G_UKN, S.BM, i, smem); break;
+        case M_SETUP: gram_item(S); break;
         case M_ROT_W: gemm_item(S, G_UKN, S.W, i, smem); break;
         case M_FINAL: gemm_item(S, G_UKT, S.XA, i, smem); break;
         case M_RESC: gemm_item(S, G_UKN, S.RF, i, smem); break;
       }
       break;
     case S_OBS: obs_item(S, i, mode, smem); break;
-    case S_ROWS: rows_item(S, i, mode == M_INNER, smem); break;
+    case S_ROWS: rows_item(S, i, mode, smem); break;
     case S_B:
       switch (mode) {
         case M_INNER: gemm_item(S, G_BF_UT, nullptr, i, smem); break;
         case M_RES: gemm_item(S, G_UKN, S.Y1, i, smem); break;
-        default: gemm_item(S, G_K, S.Y1, i, smem); break;  // M_CERT
+        case M_SETUP:  // eq. eigV
+          jacobi_sym<kBatchRank>(S.V, S.r, S.UV, S.dV, *(JacobiLds<kBatchRank>*)smem,
+                                 item_tid());
+          break;
+        default: gemm_item(S, G_K, S.Q, i, smem); break;  // M_CERT: K T
       }
       break;
     case S_FIN: fin_item(S, mode, i, s_red); break;
@@ -1085,7 +1139,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   }
 }
 
-// Start state of a launch: control words cleared, every member at INIT.
+// Start state of a launch: control words cleared, every member at SETUP.
 __global__ void batch_reset_kernel(BArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.ctl->bar = 0;
@@ -1096,7 +1150,7 @@ __global__ void batch_reset_kernel(BArgs a) {
   }
   for (int b = threadIdx.x; b < a.count; b += blockDim.x) {
     BState s{};
-    s.mode = M_INIT;
+    s.mode = M_SETUP;
     s.status = CPHIFI_NOT_CONVERGED;
     a.st[b] = s;
   }
@@ -1396,6 +1450,8 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.nmulti = p->tasks.nmulti;
     S.K = in.K;
     S.UK = in.UK;
+    S.dK = in.dK;
+    S.Vin = in.V;
     S.obs_i = in.obs_i;
     S.obs_j = in.obs_j;
     S.A = in.A;
@@ -1411,7 +1467,9 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.rowm = p->rowm;
     S.part = p->part;
     S.tpart = p->tpart;
+    S.V = p->V;
     S.UV = p->UV;
+    S.dV = p->dV;
     S.D = p->D;
     S.dKc = p->dKc;
     S.ulp = (const __bf16*)p->ulp;
@@ -1428,6 +1486,7 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.RF = p->vec[V_RF];
     S.BB = p->vec[V_T2];
     S.XA = p->vec[V_TMP];
+    S.BM = p->vec[V_B];
     S.red0 = p->red[0];
     S.red1 = p->red[1];
     S.red2 = p->red[2];
@@ -1443,6 +1502,7 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.fn_vw = (p->ldk % 2 == 0 && aligned) ? 2 : 1;
     S.lam = d.lambda;
     S.rho = d.rho;
+    S.gamma = p->gamma;
     S.tol = d.tol;
     const double itol = d.inner_tol > 0.0 ? d.inner_tol : kInnerTol;
     S.inner_tol2 = itol * itol;
@@ -1501,20 +1561,20 @@ int cphifi_batch_rhs(cphifi_batch* bt, const double* const* y, double* const* b)
   return CPHIFI_OK;
 }
 
-int cphifi_batch_bind(cphifi_batch* bt, const double* const* b, double* const* W) {
+int cphifi_batch_bind(cphifi_batch* bt, const double* const* y, double* const* W) {
   clear_error();
-  if (bt == nullptr || b == nullptr || W == nullptr) {
-    set_error("bad batch, b or W");
+  if (bt == nullptr || y == nullptr || W == nullptr) {
+    set_error("bad batch, y or W");
     return CPHIFI_INVALID_ARG;
   }
   for (int i = 0; i < bt->count; ++i)
-    if (b[i] == nullptr || W[i] == nullptr) {
-      set_error("member %d: b / W is NULL", i);
+    if ((y[i] == nullptr && bt->plans[i]->q > 0) || W[i] == nullptr) {
+      set_error("member %d: y / W is NULL", i);
       return CPHIFI_INVALID_ARG;
     }
   CPHIFI_HIP(hipStreamSynchronize(bt->st));  // the mirror may still be in flight
   for (int i = 0; i < bt->count; ++i) {
-    bt->h_sub[i].b = b[i];
+    bt->h_sub[i].y = y[i];
     bt->h_sub[i].W = W[i];
   }
   CPHIFI_HIP(hipMemcpyAsync(bt->d_sub, bt->h_sub, sizeof(BSub) * bt->count,
@@ -1568,17 +1628,17 @@ int cphifi_batch_info(cphifi_batch* bt, cphifi_solve_info* infos) {
   return worst;
 }
 
-int cphifi_batch_solve(cphifi_batch* bt, const double* const* b, double* const* W,
+int cphifi_batch_solve(cphifi_batch* bt, const double* const* y, double* const* W,
                        cphifi_solve_info* infos) {
   clear_error();
   if (bt == nullptr) {
     set_error("batch is NULL");
     return CPHIFI_INVALID_ARG;
   }
-  if (b != nullptr || W != nullptr) TRY_RC(cphifi_batch_bind(bt, b, W));
+  if (y != nullptr || W != nullptr) TRY_RC(cphifi_batch_bind(bt, y, W));
   for (int i = 0; i < bt->count; ++i)
-    if (bt->h_sub[i].b == nullptr || bt->h_sub[i].W == nullptr) {
-      set_error("member %d has no bound b / W", i);
+    if ((bt->h_sub[i].y == nullptr && bt->plans[i]->q > 0) || bt->h_sub[i].W == nullptr) {
+      set_error("member %d has no bound y / W", i);
       return CPHIFI_INVALID_ARG;
     }
   TRY_RC(build_graph(bt));

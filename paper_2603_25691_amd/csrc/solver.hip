@@ -573,13 +573,14 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
   int total_inner = 0, k = 0, status = CPHIFI_NOT_CONVERGED;
   double rel = INFINITY, rel_prev = INFINITY, cert = INFINITY, bb_bar = 0.0;
   bool fresh = !warm;  // xbar = 0: its residual is bbar
-  // W = U xbar and its certificate (not part of the kernel timing).  It
-  // leaves b - A W in vec[V_RF].  ||b|| = ||U^T b|| (U_K orthogonal) when b is
-  // not formed.
+  // W = U xbar and its certificate.  It leaves b - A W in vec[V_RF].
+  // ||b|| = ||U^T b|| (U_K orthogonal) when b is not formed.  The
+  // certificate's products are timed only when the FP64 product is the timed
+  // kernel (CPHIFI_FLAG_TIME_FP64: every FP64 product of the solve).
   auto certify = [&](double* c) -> int {
     TRY(rotate_out(p, Elt::F64, xbar, W));
     const bool t = p->timing;
-    p->timing = false;
+    p->timing = t && (p->d.flags & CPHIFI_FLAG_TIME_FP64);
     const int rs = Bm != nullptr ? true_relres_from_B(p, Bm, W, bb_bar, c)
                                  : true_relres(p, b, W, c);
     p->timing = t;

@@ -8,6 +8,7 @@
 // that need a finished scalar (alpha, beta, the convergence test) recompute it
 // from the partials themselves, so no host round trip sits inside an iteration.
 #include "cphifi_internal.h"
+#include "jacobi.h"
 
 #include <cmath>
 
@@ -440,115 +441,26 @@ __global__ void fill_i32_kernel(int32_t* dst, int32_t v, int64_t len) {
 }
 
 // V = (A^T A) had (B^T B): the Gram of the Khatri-Rao product of the other
-// modes' factors (Section 3, reused in Section 4.4.2).  One block per entry of
-// the upper triangle, each a deterministic block reduction over I and J.
+// modes' factors (Section 3, reused in Section 4.4.2).  One thread per entry
+// of the upper triangle, each summed in a fixed order (gram_entry, shared with
+// the batched solver's setup phase).
 __global__ __launch_bounds__(256) void gram_kernel(const double* A, int64_t I, const double* B,
                                                    int64_t J, int r, double* V) {
-  // block -> (a, b) with a <= b, row-major over the upper triangle
-  int idx = blockIdx.x, a = 0;
-  while (idx >= r - a) {
-    idx -= r - a;
-    ++a;
-  }
-  const int b = a + idx;
-  double ga = 0.0, gb = 0.0;
-  for (int64_t i = threadIdx.x; i < I; i += blockDim.x) ga += A[i * r + a] * A[i * r + b];
-  for (int64_t j = threadIdx.x; j < J; j += blockDim.x) gb += B[j * r + a] * B[j * r + b];
-  ga = block_sum(ga);
-  gb = block_sum(gb);
-  if (threadIdx.x == 0) {
-    V[a * r + b] = ga * gb;
-    V[b * r + a] = ga * gb;
-  }
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * r) return;
+  const int a = e / r, b = e % r;
+  if (a > b) return;
+  const double v = gram_entry(A, I, B, J, r, a, b);
+  V[a * r + b] = v;
+  V[b * r + a] = v;
 }
 
-// Cyclic Jacobi eigensolver for the symmetric r x r Gram V (eq. eigV), one
-// block.  Disjoint rotation pairs of a round-robin schedule are applied in
-// parallel: rows first (J^T A), then columns (A J) and the eigenvector
-// accumulator (V J).  Stops when the off-diagonal mass is below (1e-15)^2 of
-// the Frobenius mass, or after 60 sweeps.
+// Eigendecomposition of the r x r Gram V (eq. eigV) by one workgroup
+// (jacobi_sym, shared with the batched solver's setup phase).
 __global__ __launch_bounds__(256) void jacobi_kernel(const double* Vin, int r, double* UV,
                                                      double* dV) {
-  constexpr int L = kMaxRank + 1;
-  __shared__ double a[kMaxRank * L];
-  __shared__ double v[kMaxRank * L];
-  __shared__ double cs[kMaxRank / 2][2];
-  __shared__ int pr[kMaxRank / 2][2];
-  const int tid = threadIdx.x;
-  const int m = r + (r & 1);  // even player count; index r is a dummy when r is odd
-  for (int e = tid; e < m * m; e += blockDim.x) {
-    const int i = e / m, j = e % m;
-    a[i * L + j] = (i < r && j < r) ? Vin[i * r + j] : 0.0;
-    v[i * L + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  double fro = 0.0;
-  for (int e = tid; e < r * r; e += blockDim.x) {
-    const double x = a[(e / r) * L + (e % r)];
-    fro += x * x;
-  }
-  fro = block_sum(fro);
-  for (int sweep = 0; sweep < 60 && m > 1; ++sweep) {
-    double off = 0.0;
-    for (int e = tid; e < r * r; e += blockDim.x) {
-      const int i = e / r, j = e % r;
-      if (i != j) off += a[i * L + j] * a[i * L + j];
-    }
-    off = block_sum(off);
-    if (!(off > 1e-30 * fro)) break;
-    for (int round = 0; round < m - 1; ++round) {
-      if (tid < m / 2) {
-        // circle method: player 0 fixed, others rotate
-        int p, q;
-        if (tid == 0) {
-          p = 0;
-          q = 1 + (round % (m - 1));
-        } else {
-          p = 1 + ((round + tid) % (m - 1));
-          q = 1 + ((round + (m - 1) - tid) % (m - 1));
-        }
-        if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < r) {
-          const double apq = a[p * L + q];
-          if (apq != 0.0) {
-            const double tau = (a[q * L + q] - a[p * L + p]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
-        }
-        pr[tid][0] = p;
-        pr[tid][1] = q;
-        cs[tid][0] = c;
-        cs[tid][1] = s;
-      }
-      __syncthreads();
-      for (int e = tid; e < (m / 2) * m; e += blockDim.x) {  // rows
-        const int k = e / m, j = e % m;
-        const int p = pr[k][0], q = pr[k][1];
-        const double c = cs[k][0], s = cs[k][1];
-        const double ap = a[p * L + j], aq = a[q * L + j];
-        a[p * L + j] = c * ap - s * aq;
-        a[q * L + j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      for (int e = tid; e < (m / 2) * m; e += blockDim.x) {  // columns and vectors
-        const int k = e / m, i = e % m;
-        const int p = pr[k][0], q = pr[k][1];
-        const double c = cs[k][0], s = cs[k][1];
-        const double ap = a[i * L + p], aq = a[i * L + q];
-        a[i * L + p] = c * ap - s * aq;
-        a[i * L + q] = s * ap + c * aq;
-        const double vp = v[i * L + p], vq = v[i * L + q];
-        v[i * L + p] = c * vp - s * vq;
-        v[i * L + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-    }
-  }
-  for (int e = tid; e < r * r; e += blockDim.x) UV[e] = v[(e / r) * L + (e % r)];
-  for (int i = tid; i < r; i += blockDim.x) dV[i] = a[i * L + i];
+  __shared__ JacobiLds<kMaxRank> w;
+  jacobi_sym<kMaxRank>(Vin, r, UV, dV, w, threadIdx.x);
 }
 
 __global__ void precond_diag_kernel(const double* dK, const double* dV, int64_t n, int r,
@@ -558,8 +470,7 @@ __global__ void precond_diag_kernel(const double* dK, const double* dV, int64_t 
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = e / r;
     const int c = (int)(e % r);
-    const double d = fmax(dK[s], 0.0);
-    D[e] = 1.0 / (gamma * dV[c] * d * d + lam * d + rho);
+    D[e] = precond_entry(dK[s], dV[c], gamma, lam, rho);
   }
 }
 
@@ -787,7 +698,7 @@ int launch_fill_i32(int32_t* dst, int32_t v, int64_t len, hipStream_t st) {
 
 int launch_gram(const double* A, int64_t I, const double* B, int64_t J, int r, double* V,
                 hipStream_t st) {
-  hipLaunchKernelGGL(gram_kernel, dim3(r * (r + 1) / 2), dim3(256), 0, st, A, I, B, J, r, V);
+  hipLaunchKernelGGL(gram_kernel, dim3((r * r + 255) / 256), dim3(256), 0, st, A, I, B, J, r, V);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }

@@ -261,13 +261,18 @@ class BatchSolver:
                             [b.data_ptr() for b in bs])
         return bs
 
-    def bind(self, bs, Ws):
-        _c.cphifi_batch_bind(self.batch, [b.data_ptr() for b in bs], [W.data_ptr() for W in Ws])
+    def ys(self):
+        """The members' observed values (the batched solve starts from them)."""
+        return [p.y for p in self.probs]
 
-    def solve(self, bs=None, Ws=None, wait: bool = True):
-        """Returns (status, infos) when wait, else None."""
+    def bind(self, ys, Ws):
+        _c.cphifi_batch_bind(self.batch, [y.data_ptr() for y in ys], [W.data_ptr() for W in Ws])
+
+    def solve(self, ys=None, Ws=None, wait: bool = True):
+        """Solve every member from its observed values ys (device q_i doubles)
+        into Ws (n_i x r_i).  Returns (status, infos) when wait, else None."""
         return _c.cphifi_batch_solve(self.batch, len(self.probs),
-                                     None if bs is None else [b.data_ptr() for b in bs],
+                                     None if ys is None else [y.data_ptr() for y in ys],
                                      None if Ws is None else [W.data_ptr() for W in Ws], wait)
 
     def info(self):

@@ -106,7 +106,7 @@ def test_decoupled_solve_matches_oracle(r, cases):
     # V formed from the factors on the device: the same solution
     a2 = AlignedSolver(c["dp"], p.lam, method="decoupled", with_factors=True)
     W2, info2 = a2.solve(Bm)
-    assert O.e_kw(p.K, host(W2), Wg) <= 1e-12
+    assert O.e_kw(p.K, host(W2), Wg) <= c["gate"]
     a.close()
     a2.close()
 

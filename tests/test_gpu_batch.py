@@ -6,7 +6,9 @@ certificate ||K B - A(W)|| / ||K B|| (two-step product in numpy) must meet the
 member's tolerance, and for members small enough for the dense normal-equation
 solve, e_KW = ||K (W - W_o)|| / ||K W_o|| <= 1e-6 (the mixed form's bar after
 refinement).  Batched and unbatched (the same member's plan solved alone by
-cphifi_ui_solve at MIXED_BF16) must agree to e_KW <= 1e-6; both are refined to
+cphifi_ui_solve_subproblem at MIXED_BF16, from the same observed values: the
+batched launch also runs the per-solve setup and the MTTKRP) must agree to
+e_KW <= 1e-6; both are refined to
 relres 1e-8, so their distance is bounded by the conditioning of the map from
 residual to K W, which for these members is far below 1e2.
 """
@@ -64,7 +66,7 @@ def batch():
     bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], TOL, **CAPS)
     rhs = bs.rhs()
     Ws = [torch.empty_like(b) for b in rhs]
-    status, infos = bs.solve(rhs, Ws)
+    status, infos = bs.solve(bs.ys(), Ws)
     return {"probs": probs, "dps": dps, "bs": bs, "rhs": rhs, "W": [host(W) for W in Ws],
             "status": status, "infos": infos}
 
@@ -94,7 +96,7 @@ def test_batch_status_and_rounds(batch):
     rounds, grid = batch["bs"].rounds()
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     assert grid >= n_cu
-    # every member needs at least INIT, ROT_IN, one inner iteration, ROT_OUT, RES
+    # every member needs at least SETUP, ROT_B, one inner iteration, FINAL, CERT
     assert rounds >= 5
     assert rounds >= max(i.iters for i in batch["infos"])
 
@@ -105,7 +107,8 @@ def test_batched_equals_unbatched(batch, k):
     bs = batch["bs"]
     b = batch["rhs"][k]
     Ws = torch.zeros_like(b)
-    info = C.cphifi_ui_solve(bs.plan(k), b.data_ptr(), Ws.data_ptr())
+    # the same whole-subproblem method from the observed values, one member alone
+    info = C.cphifi_ui_solve_subproblem(bs.plan(k), batch["dps"][k].y.data_ptr(), Ws.data_ptr())
     assert info.status == C.OK, info.as_dict()
     assert info.relres_true <= TOL
     assert O.e_kw(p.K, batch["W"][k], host(Ws)) <= 1e-6
@@ -116,7 +119,7 @@ def test_batched_equals_unbatched(batch, k):
 def test_batch_is_deterministic(batch):
     bs = batch["bs"]
     Ws = [torch.empty_like(b) for b in batch["rhs"]]
-    status, infos = bs.solve(batch["rhs"], Ws)
+    status, infos = bs.solve(bs.ys(), Ws)
     assert status == C.OK
     for k, W in enumerate(Ws):
         assert np.array_equal(host(W), batch["W"][k]), MEMBERS[k][0]
@@ -124,21 +127,21 @@ def test_batch_is_deterministic(batch):
         assert infos[k].relres_true == batch["infos"][k].relres_true
 
 
-def test_batch_rebind_scaled_rhs(batch):
+def test_batch_rebind_scaled_observations(batch):
     bs = batch["bs"]
-    rhs2 = [2.0 * b for b in batch["rhs"]]
-    Ws = [torch.empty_like(b) for b in rhs2]
-    status, infos = bs.solve(rhs2, Ws)
+    ys2 = [2.0 * y for y in bs.ys()]
+    Ws = [torch.empty_like(b) for b in batch["rhs"]]
+    status, infos = bs.solve(ys2, Ws)
     assert status == C.OK
     for k, W in enumerate(Ws):
         p = batch["probs"][k]
         assert O.e_kw(p.K, host(W), 2.0 * batch["W"][k]) <= 1e-6
 
 
-def test_batch_zero_rhs_and_async_info(batch):
+def test_batch_zero_observations_and_async_info(batch):
     bs = batch["bs"]
-    zeros = [torch.zeros_like(b) for b in batch["rhs"]]
-    Ws = [torch.full_like(b, 3.0) for b in zeros]
+    zeros = [torch.zeros_like(y) for y in bs.ys()]
+    Ws = [torch.full_like(b, 3.0) for b in batch["rhs"]]
     assert bs.solve(zeros, Ws, wait=False) is None
     status, infos = bs.info()
     assert status == C.OK
@@ -155,7 +158,7 @@ def test_batch_warm_start_from_solution(batch):
     try:
         rhs = bs.rhs()
         Ws = [torch.from_numpy(batch["W"][k]).cuda() for k in range(3)]
-        status, infos = bs.solve(rhs, Ws)
+        status, infos = bs.solve(bs.ys(), Ws)
         assert status == C.OK
         for k, info in enumerate(infos):
             assert info.status == C.OK
@@ -183,7 +186,7 @@ def test_batch_barrier_timeout_is_reported_and_drains(batch):
         rhs = bs.rhs()
         Ws = [torch.empty_like(b) for b in rhs]
         with pytest.raises(C.CphifiError) as ei:
-            bs.solve(rhs, Ws)
+            bs.solve(bs.ys(), Ws)
         assert ei.value.status == C.HIP_ERROR
         assert "timed out" in str(ei.value)
     finally:
@@ -192,7 +195,7 @@ def test_batch_barrier_timeout_is_reported_and_drains(batch):
     try:
         rhs = bs2.rhs()
         Ws = [torch.empty_like(b) for b in rhs]
-        status, infos = bs2.solve(rhs, Ws)
+        status, infos = bs2.solve(bs2.ys(), Ws)
         assert status == C.OK
         for k in range(2):
             assert np.array_equal(host(Ws[k]), batch["W"][k])
@@ -216,7 +219,7 @@ def test_batch_with_padded_kernel_stride(batch):
     try:
         rhs = bs.rhs()
         Ws = [torch.empty_like(b) for b in rhs]
-        status, infos = bs.solve(rhs, Ws)
+        status, infos = bs.solve(bs.ys(), Ws)
         assert status == C.OK
         for j, k in enumerate(idx):
             p = batch["probs"][k]
@@ -239,7 +242,7 @@ def test_batch_with_tuner_table(batch, tmp_path):
     try:
         rhs = bs.rhs()
         Ws = [torch.empty_like(b) for b in rhs]
-        status, infos = bs.solve(rhs, Ws)
+        status, infos = bs.solve(bs.ys(), Ws)
         assert status == C.OK
         for k, W in enumerate(Ws):
             assert infos[k].relres_true <= TOL, MEMBERS[k][0]
@@ -264,7 +267,7 @@ def test_batch_member_with_inexact_eigenpairs_converges():
     bs = BatchSolver(dps, [p.lam, q.lam], [p.rho, q.rho], TOL, **CAPS)
     rhs = bs.rhs()
     Ws = [torch.empty_like(b) for b in rhs]
-    status, infos = bs.solve(rhs, Ws)
+    status, infos = bs.solve(bs.ys(), Ws)
     assert status == C.OK, [i.as_dict() for i in infos]
     assert infos[0].refine_steps > 3  # the eigenbasis alone stops at ~8e-7
     for pr, W, info in zip((p, q), Ws, infos):

@@ -52,14 +52,13 @@ def solved():
     assert [p.n for p in probs] == list(refs["n"]) and [p.r for p in probs] == list(refs["r"])
     bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], TOL,
                      tile_table=TILES if os.path.exists(TILES) else None)
-    rhs = bs.rhs()
-    Ws = [torch.empty_like(b) for b in rhs]
-    status, infos = bs.solve(rhs, Ws)
+    Ws = [torch.empty(p.n, p.r, dtype=torch.float64, device="cuda") for p in probs]
+    status, infos = bs.solve(bs.ys(), Ws)
     torch.cuda.synchronize()
     out = {"probs": probs, "refs": refs, "status": status, "infos": infos,
            "W": [W.cpu().numpy() for W in Ws]}
     bs.close()
-    del dps, rhs, Ws
+    del dps, Ws
     torch.cuda.empty_cache()
     return out
 
