@@ -178,11 +178,16 @@ def bench_small(torch, C, steps: int):
            "n": p.n, "q": p.q, "r": p.r,
            "oracle_dense_ms": 1e3 * t_dense, "oracle_lstsq_ms": 1e3 * t_brute}
     timer = StepTimer(torch)
-    for prec, tol in (("fp64", 1e-10), ("mixed_bf16", MIXED_TOL)):
-        s = UISolver(dp, p.lam, p.rho, tol, precision=prec)
+    # fp64: the whole PCG in one persistent workgroup (the default at this
+    # size); fp64_multi_kernel: the same solve with one launch sequence and
+    # host poll per iteration.
+    legs = (("fp64", "fp64", 1e-10, 0), ("fp64_multi_kernel", "fp64", 1e-10, C.FLAG_MULTI_KERNEL),
+            ("mixed_bf16", "mixed_bf16", MIXED_TOL, 0))
+    for label, prec, tol, flags in legs:
+        s = UISolver(dp, p.lam, p.rho, tol, precision=prec, flags=flags)
         W, info = s.solve_subproblem()
         med, mean, (W, info) = timer.run(lambda: s.solve_subproblem(W=W), steps)
-        out[prec] = {"us_per_solve": 1e3 * med, "us_mean": 1e3 * mean,
+        out[label] = {"us_per_solve": 1e3 * med, "us_mean": 1e3 * mean,
                      "solves_per_s": 1e3 / med, "iters": info.iters,
                      "refine_steps": info.refine_steps, "relres_true": info.relres_true,
                      "status": C.status_string(info.status),
@@ -190,7 +195,8 @@ def bench_small(torch, C, steps: int):
                      "tol": tol}
         s.close()
     out["gpu_vs_oracle_dense"] = out["oracle_dense_ms"] / (out["fp64"]["us_per_solve"] / 1e3)
-    log(f"small: fp64 {out['fp64']['us_per_solve']:.0f} us, mixed "
+    log(f"small: fp64 {out['fp64']['us_per_solve']:.0f} us (multi-kernel "
+        f"{out['fp64_multi_kernel']['us_per_solve']:.0f} us), mixed "
         f"{out['mixed_bf16']['us_per_solve']:.0f} us per solve; oracle dense "
         f"{out['oracle_dense_ms']:.1f} ms, lstsq {out['oracle_lstsq_ms']:.1f} ms")
     return out
@@ -230,12 +236,18 @@ def bench_aligned(torch, C, steps: int):
         row = {"oracle_mttkrp_ms": 1e3 * t_mttkrp, "oracle_decoupled_ms": 1e3 * t_dec,
                "oracle_kron_cholesky_ms": 1e3 * t_kron,
                "e_KW_kron_vs_decoupled": O.e_kw(p.K, Wk, Wdec)}
-        for prec, tol in (("fp64", 1e-10), ("mixed_bf16", MIXED_TOL),
-                          ("mixed_fp32", MIXED_TOL)):
-            s = UISolver(dp, p.lam, p.rho, tol, precision=prec)
+        # fp64_structured: the same solve with the K products on c = K(0,:)
+        # (Toeplitz K of the uniform grid) and the fiber-collapsed gather
+        # (every (time, sample) pair observed at all J features)
+        structured = C.FLAG_TOEPLITZ_K | C.FLAG_FIBER_COLLAPSE
+        for label, prec, tol, flags in (("fp64", "fp64", 1e-10, 0),
+                                        ("fp64_structured", "fp64", 1e-10, structured),
+                                        ("mixed_bf16", "mixed_bf16", MIXED_TOL, 0),
+                                        ("mixed_fp32", "mixed_fp32", MIXED_TOL, 0)):
+            s = UISolver(dp, p.lam, p.rho, tol, precision=prec, flags=flags)
             W, info = s.solve_subproblem()
             med, mean, (W, info) = timer.run(lambda: s.solve_subproblem(W=W), steps)
-            row[prec] = {"ms_per_solve": med, "iters": info.iters,
+            row[label] = {"ms_per_solve": med, "iters": info.iters,
                          "refine_steps": info.refine_steps, "relres_true": info.relres_true,
                          "status": C.status_string(info.status),
                          "e_KW_vs_oracle_decoupled": O.e_kw(p.K, W.cpu().numpy(), Wdec)}
@@ -268,7 +280,8 @@ def bench_aligned(torch, C, steps: int):
             (t_mttkrp + t_dec) * 1e3 / row["fp64"]["ms_per_solve"])
         res["ranks"][str(r)] = row
         log(f"aligned r={r}: fp64 {row['fp64']['ms_per_solve']:.2f} ms "
-            f"(e_KW {row['fp64']['e_KW_vs_oracle_decoupled']:.1e}), bf16 "
+            f"(e_KW {row['fp64']['e_KW_vs_oracle_decoupled']:.1e}; structured "
+            f"{row['fp64_structured']['ms_per_solve']:.3f} ms), bf16 "
             f"{row['mixed_bf16']['ms_per_solve']:.2f} ms, fp32 "
             f"{row['mixed_fp32']['ms_per_solve']:.2f} ms; decoupled "
             f"{row['aligned_decoupled']['ms_per_solve']:.2f} ms, aligned PCG "
@@ -324,7 +337,52 @@ def bench_paper_shapes(torch, C, steps: int):
                 f"({row['fp64']['iters']} its), mixed {row['mixed_bf16']['ms_per_solve']:.2f} ms; "
                 f"oracle PCG {row['oracle_pcg_ms']:.0f} ms ({ref.iters} its)")
             del dp
+        out["als"] = out.get("als", {})
+        out["als"][name] = bench_als(torch, C, dims, sig)
     return out
+
+
+def bench_als(torch, C, dims, sig, r: int = 10, outer: int = 3):
+    """The alternating optimisation on one stand-in (all three modes, the
+    paper's subproblem setting, warm starts): GPU time per outer iteration and
+    the oracle's (O-pcg blocks) for one outer iteration on the host; error
+    histories side by side."""
+    import time
+    import oracle as O
+    from paper_2603_25691_amd.torch_api import AlsSolver, kernel_eig
+    from synth import make_als_problem
+
+    p = make_als_problem(shape=dims, sigmas=sig, r=r, seed=1)
+    Ks = [torch.from_numpy(K).cuda() for K in p.Ks]
+    eig = [kernel_eig(K) for K in Ks]
+    coords = torch.from_numpy(p.coords).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    W0 = [torch.from_numpy(W).cuda() for W in p.W0s]
+    res = {"shape": list(dims), "r": r, "outer": outer}
+    for prec in ("fp64", "mixed_bf16"):
+        s = AlsSolver(Ks, [u for u, _ in eig], [d for _, d in eig], coords, y, r, p.lams,
+                      p.rho, p.tol, 0.0, outer, maxit=p.maxit, precision=prec)
+        s.run(W0)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info, errors = s.run(W0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[prec] = {"ms_per_outer": 1e3 * dt / info.outer, "errors": errors,
+                     "inner_iters": info.inner_iters, "capped": info.capped}
+        s.close()
+    eigs = [O.kernel_eig(K) for K in p.Ks]
+    t_or, ref = host_median(lambda: O.cp_hifi_als(p.Ks, p.coords, p.y, p.W0s, p.lams, p.rho,
+                                                  max_outer=1, als_tol=0.0, solver="pcg",
+                                                  tol=p.tol, maxit=p.maxit, eigs=eigs),
+                            reps=1)
+    res["oracle_ms_per_outer"] = 1e3 * t_or
+    res["oracle_errors_first_outer"] = ref.errors
+    res["gpu_fp64_vs_oracle"] = res["oracle_ms_per_outer"] / res["fp64"]["ms_per_outer"]
+    log(f"ALS {dims} r={r}: fp64 {res['fp64']['ms_per_outer']:.1f} ms / outer iteration, "
+        f"mixed {res['mixed_bf16']['ms_per_outer']:.1f} ms; oracle {1e3 * t_or:.0f} ms; "
+        f"errors {['%.4f' % e for e in res['fp64']['errors']]}")
+    return res
 
 
 # ------------------------------------------------------------- batched (C5)
@@ -350,6 +408,8 @@ def bench_batch(a, torch, C):
                      UK=dp.UK[:, :p.n].cpu().numpy(), dK=dp.dK.cpu().numpy())
         dps.append(dp)
         probs.append(p)
+        if (b + 1) % 8 == 0:
+            log(f"batch: {b + 1} members uploaded with eig(K) ({time.time() - t0:.1f} s)")
     torch.cuda.synchronize()
     ns = np.array([p.n for p in probs])
     rs = np.array([p.r for p in probs])
@@ -509,6 +569,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.batch_only:
+        if a.calib_copy_mb > 0:
+            src = torch.empty(a.calib_copy_mb * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+            src.fill_(1.0)
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            log(f"calibration copy of {a.calib_copy_mb} MiB done")
         print(json.dumps(bench_batch(a, torch, C)), flush=True)
         return
     t0 = time.time()
@@ -540,6 +606,18 @@ def main():
     mv_ms, _, _ = timer.run(lambda: sf.apply(X, out=Y), 10)
     mv_bytes = 2 * 8 * n * n + 16 * n * r + 8 * q
     log(f"matvec {mv_ms:.3f} ms = {mv_bytes / mv_ms / 1e6:.0f} GB/s")
+    # the same operator with the fiber-collapsed gather (every time point of
+    # this workload is one complete fiber: its sample at all J features)
+    sfc = UISolver(dp, p.lam, p.rho, p.tol, precision="fp64", check_every=1,
+                   flags=C.FLAG_FIBER_COLLAPSE)
+    Yc = torch.empty_like(X)
+    for _ in range(2):
+        sfc.apply(X, out=Yc)
+    torch.cuda.synchronize()
+    mvc_ms, _, _ = timer.run(lambda: sfc.apply(X, out=Yc), 10)
+    mvc_diff = float((Yc - Y).norm() / Y.norm())
+    sfc.close()
+    log(f"matvec with the fiber-collapsed gather {mvc_ms:.3f} ms (rel. diff {mvc_diff:.1e})")
 
     # ------------------------------------------------------------ FP64 PCG
     def fp64_run(tol, flags=0, with_w=None):
@@ -709,6 +787,8 @@ def main():
         "matvec": {"ms": mv_ms, "GB_per_s": mv_bytes / mv_ms / 1e6,
                    "frac_of_peak": mv_bytes / mv_ms / 1e6 / HBM_PEAK_GBPS,
                    "bytes": mv_bytes, "operator": "FP64 paper form (cphifi_ui_apply)"},
+        "matvec_fiber_collapse": {"ms": mvc_ms, "rel_diff_vs_matvec": mvc_diff,
+                                  "operator": "FP64 paper form, FLAG_FIBER_COLLAPSE"},
         "matvec_mixed": mvl,
         "mixed_vs_fp64_speedup": fp64["ms_per_solve"] / ms_per_step,
         "fp64_eigenbasis": dict(fp64_eig,

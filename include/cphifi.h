@@ -89,10 +89,34 @@ enum cphifi_flags {
                                    plan creation), so U_K^T X runs the faster
                                    transposed FP64 kernel too; this flag drops
                                    the copy (row-major kernel for U_K^T X) */
-  CPHIFI_FLAG_TIME_FP64 = 64    /* with FLAG_TIME_KERNELS: mixed plans time the
+  CPHIFI_FLAG_TIME_FP64 = 64,   /* with FLAG_TIME_KERNELS: mixed plans time the
                                    transposed FP64 product (the rotations, the
                                    FP64 residuals and the certificate) instead
                                    of the low-precision one */
+  CPHIFI_FLAG_MULTI_KERNEL = 128, /* FP64: always the multi-kernel iteration.
+                                   Without it a small subproblem (n <= 2048,
+                                   n^2 r <= 2e6, q r <= 5e5, paper form, no
+                                   kernel timing, no structured form) runs its
+                                   whole PCG in one persistent workgroup */
+  CPHIFI_FLAG_TOEPLITZ_K = 256, /* K is symmetric Toeplitz, K(s,k) = c(|s-k|) (a
+                                   translation-invariant kernel on a uniform
+                                   grid; Section 4.4.1 notes the structure):
+                                   the K products read c = K(0,:) only (n
+                                   doubles; 2 n^2 r flops, O(n r) bytes).
+                                   plan_create checks every entry of K against
+                                   c to within 1e-12 max|c| (INVALID_ARG
+                                   otherwise); products then differ from the
+                                   dense ones by at most that much.  Not with
+                                   the batched solver */
+  CPHIFI_FLAG_FIBER_COLLAPSE = 512 /* every (time, sample) pair that is observed
+                                   at all is observed at all J features once:
+                                   the gather-scatter of eqs. vl / yhat1 runs
+                                   per fiber as A(i,:) had ((Xhat(s,:) had
+                                   A(i,:)) B^T B), r^2 work per fiber instead
+                                   of 2 J r (same operator up to rounding).
+                                   plan_create checks the structure on the
+                                   host (INVALID_ARG otherwise); implicit (A, B)
+                                   form only; not with the batched solver */
 };
 
 /* Problem description (host struct). */
@@ -274,6 +298,81 @@ CPHIFI_API int cphifi_aligned_workspace_bytes(const cphifi_aligned_desc* d, size
 CPHIFI_API int cphifi_aligned_solve(const cphifi_aligned_desc* d, const cphifi_aligned_inputs* in,
                                     double* W, void* workspace, size_t workspace_bytes,
                                     void* stream, cphifi_solve_info* info);
+
+/* ------------------------------------------------------------------ ALS
+ * CP-HIFI alternating optimisation (Section 2, eq. cp-hifi-subproblem) for a
+ * 3-way tensor whose three modes are all infinite-dimensional (the setting of
+ * the unaligned experiments of Section 5.2).  Mode k's factor is
+ * A_k = K_k W_k.  One outer iteration solves, for k = 0, 1, 2 in turn, the
+ * unaligned subproblem of eq. unaligned-infinite-1 for W_k (observations
+ * grouped by their mode-k index, Khatri-Rao rows from the other two factors,
+ * warm-started from the current W_k; method and precision as in
+ * cphifi_ui_solve_subproblem) and then sets A_k = K_k W_k.  The run stops
+ * when the relative error ||y - model||_Omega / ||y||_Omega changes by less
+ * than als_tol between outer iterations, or after max_outer of them (the
+ * paper's runs: 50 iterations, 1e-6; subproblems to relres 1e-6 with at most
+ * 75 iterations).  A subproblem that stops at its iteration cap counts in
+ * `capped` and the run goes on. */
+typedef struct cphifi_als_desc {
+  int64_t n[3];       /* grid points per mode (rows of K_k), >= 1 */
+  int64_t q;          /* observed entries, 1 .. 2^31 - 1 */
+  int64_t r;          /* CP rank, 1..64 */
+  double lambda[3];   /* RKHS regulariser per mode, > 0 */
+  double rho;         /* shift of Section 4.1, > 0 */
+  double tol;         /* subproblem relative residual target, > 0 */
+  double als_tol;     /* stop when the error changes by less than this, >= 0 */
+  int32_t precision;  /* enum cphifi_precision of the subproblem solves */
+  int32_t flags;      /* subproblem flags (CPHIFI_FLAG_WARM_START is always added) */
+  int32_t maxit;      /* subproblem iteration cap (<= 0: 500) */
+  int32_t max_outer;  /* outer iterations, >= 1 */
+} cphifi_als_desc;
+
+/* Device inputs (caller-owned; must outlive the object). */
+typedef struct cphifi_als_inputs {
+  const double* K[3];     /* n_k x n_k (stride n_k), symmetric psd */
+  const double* UK[3];    /* eigenvectors of K_k, laid out as cphifi_ui_inputs.UK */
+  const double* dK[3];    /* eigenvalues of K_k */
+  const int32_t* coords;  /* q x 3 row-major: the indices (i_0, i_1, i_2) of each entry */
+  const double* y;        /* q observed values */
+} cphifi_als_inputs;
+
+typedef struct cphifi_als_info {
+  int32_t outer;          /* outer iterations run */
+  int32_t converged;      /* 1 when the error change fell below als_tol */
+  int32_t inner_iters;    /* subproblem iterations over the whole run */
+  int32_t capped;         /* subproblem solves that stopped at their cap */
+  double rel_error;       /* final relative error on the observed entries */
+  double* errors;         /* optional HOST buffer of max_outer + 1 doubles: the error
+                             before the first and after every outer iteration */
+} cphifi_als_info;
+
+typedef struct cphifi_als cphifi_als;
+
+/* Bytes of device workspace for `d` (host-only; no GPU call). */
+CPHIFI_API int cphifi_als_workspace_bytes(const cphifi_als_desc* d, size_t* bytes);
+
+/* Validate `d`, copy the entries and values to the host once (range checks;
+ * the per-mode CSR lists and permuted values are built there and uploaded
+ * into `workspace`: device, >= cphifi_als_workspace_bytes, 256-byte aligned)
+ * and create the three subproblem plans inside it.  sync.
+ * Errors: INVALID_ARG (sizes or parameters, a coordinate out of range, missing
+ * pointers, workspace too small or misaligned), HIP_ERROR, and any
+ * plan-creation error. */
+CPHIFI_API int cphifi_als_create(cphifi_als** out, const cphifi_als_desc* d,
+                                 const cphifi_als_inputs* in, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
+/* Run the alternating optimisation.  W: host array of 3 device pointers
+ * (n_k x r row-major each): the starting weights on entry, the result on
+ * exit.  F: host array of 3 device pointers that receive A_k = K_k W_k, or
+ * NULL.  info (host) is filled.  sync.  Errors: INVALID_ARG, HIP_ERROR, and
+ * NUMERIC / BREAKDOWN from a subproblem (outer iteration and mode named in
+ * cphifi_last_error). */
+CPHIFI_API int cphifi_als_run(cphifi_als* a, double* const* W, double* const* F,
+                              cphifi_als_info* info);
+
+/* Release host-side state and the three plans (the workspace is the caller's). */
+CPHIFI_API int cphifi_als_destroy(cphifi_als* a);
 
 /* ------------------------------------------------ products (tuning, tests)
  * The n x n by n x r products behind every step above (K X in Section 4.4.1,

@@ -8,3 +8,4 @@ generators in ``synth``.
 """
 
 from .cphifi_oracle import *  # noqa: F401,F403
+from .cphifi_als import *  # noqa: F401,F403

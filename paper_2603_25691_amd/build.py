@@ -19,7 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcphifi.so")
 SOURCES = ["gemm.hip", "obs.hip", "vec.hip", "solver.hip", "eig.hip", "product.hip", "batch.hip",
-           "aligned.hip"]
+           "aligned.hip", "small.hip", "als.hip",
+           "structured.hip"]
 ARCH = os.environ.get("CPHIFI_OFFLOAD_ARCH", "gfx950")
 
 

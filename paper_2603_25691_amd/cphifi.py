@@ -38,6 +38,7 @@ FLAG_NO_PRECOND = 8
 FLAG_EIGENBASIS = 16
 FLAG_NO_UKT_COPY = 32
 FLAG_TIME_FP64 = 64
+FLAG_MULTI_KERNEL = 128
 
 PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 
@@ -91,6 +92,28 @@ class cphifi_aligned_inputs(C.Structure):
                [("I", C.c_int64), ("J", C.c_int64)]
 
 
+class cphifi_als_desc(C.Structure):
+    _fields_ = [("n", C.c_int64 * 3), ("q", C.c_int64), ("r", C.c_int64),
+                ("lambda_", C.c_double * 3), ("rho", C.c_double), ("tol", C.c_double),
+                ("als_tol", C.c_double), ("precision", C.c_int32), ("flags", C.c_int32),
+                ("maxit", C.c_int32), ("max_outer", C.c_int32)]
+
+
+class cphifi_als_inputs(C.Structure):
+    _fields_ = [("K", C.c_void_p * 3), ("UK", C.c_void_p * 3), ("dK", C.c_void_p * 3),
+                ("coords", C.c_void_p), ("y", C.c_void_p)]
+
+
+class cphifi_als_info(C.Structure):
+    _fields_ = [("outer", C.c_int32), ("converged", C.c_int32), ("inner_iters", C.c_int32),
+                ("capped", C.c_int32), ("rel_error", C.c_double), ("errors", C.c_void_p)]
+
+    def as_dict(self):
+        return {"outer": self.outer, "converged": bool(self.converged),
+                "inner_iters": self.inner_iters, "capped": self.capped,
+                "rel_error": self.rel_error}
+
+
 class CphifiError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: {status_string(status)}: {detail}")
@@ -136,6 +159,12 @@ def _load() -> C.CDLL:
         "cphifi_aligned_solve": (C.c_int, [C.POINTER(cphifi_aligned_desc),
                                            C.POINTER(cphifi_aligned_inputs), P, P, C.c_size_t,
                                            P, C.POINTER(cphifi_solve_info)]),
+        "cphifi_als_workspace_bytes": (C.c_int, [C.POINTER(cphifi_als_desc),
+                                                 C.POINTER(C.c_size_t)]),
+        "cphifi_als_create": (C.c_int, [C.POINTER(P), C.POINTER(cphifi_als_desc),
+                                        C.POINTER(cphifi_als_inputs), P, C.c_size_t, P]),
+        "cphifi_als_run": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.POINTER(cphifi_als_info)]),
+        "cphifi_als_destroy": (C.c_int, [P]),
         "cphifi_product_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int,
                                                      C.POINTER(C.c_size_t)]),
         "cphifi_product_tile_ok": (C.c_int, [C.c_int, C.c_int, C.c_int]),
@@ -314,6 +343,47 @@ def cphifi_aligned_solve(desc: cphifi_aligned_desc, inputs: cphifi_aligned_input
                                    C.c_void_p(stream), C.byref(info))
     _check(st, "cphifi_aligned_solve", soft_ok=True)
     return info
+
+
+def make_als_desc(n, q: int, r: int, lams, rho: float, tol: float, als_tol: float,
+                  max_outer: int, maxit: int = 0, precision: int = 0,
+                  flags: int = 0) -> cphifi_als_desc:
+    d = cphifi_als_desc()
+    for k in range(3):
+        d.n[k], d.lambda_[k] = int(n[k]), float(lams[k])
+    d.q, d.r, d.rho, d.tol, d.als_tol = q, r, rho, tol, als_tol
+    d.precision, d.flags, d.maxit, d.max_outer = precision, flags, maxit, max_outer
+    return d
+
+
+def cphifi_als_workspace_bytes(desc: cphifi_als_desc) -> int:
+    out = C.c_size_t(0)
+    _check(_lib.cphifi_als_workspace_bytes(C.byref(desc), C.byref(out)),
+           "cphifi_als_workspace_bytes")
+    return int(out.value)
+
+
+def cphifi_als_create(desc: cphifi_als_desc, inputs: cphifi_als_inputs, workspace: int,
+                      workspace_bytes: int, stream: int) -> int:
+    h = C.c_void_p()
+    _check(_lib.cphifi_als_create(C.byref(h), C.byref(desc), C.byref(inputs),
+                                  C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+                                  C.c_void_p(stream)), "cphifi_als_create")
+    return h.value
+
+
+def cphifi_als_run(handle: int, W_ptrs, F_ptrs=None, errors_ptr: int = 0) -> cphifi_als_info:
+    info = cphifi_als_info()
+    info.errors = errors_ptr or None
+    W = (C.c_void_p * 3)(*[int(p) for p in W_ptrs])
+    F = None if F_ptrs is None else (C.c_void_p * 3)(*[int(p) for p in F_ptrs])
+    _check(_lib.cphifi_als_run(C.c_void_p(handle), W, F, C.byref(info)), "cphifi_als_run")
+    return info
+
+
+def cphifi_als_destroy(handle: int) -> None:
+    if handle:
+        _check(_lib.cphifi_als_destroy(C.c_void_p(handle)), "cphifi_als_destroy")
 
 
 ELT_F64 = 0

@@ -1359,6 +1359,10 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
       set_error("member %d: the batched solver takes the implicit (A, B) form only", b);
       return CPHIFI_UNSUPPORTED;
     }
+    if (d.flags & (CPHIFI_FLAG_TOEPLITZ_K | CPHIFI_FLAG_FIBER_COLLAPSE)) {
+      set_error("member %d: the batched solver has no structured (Toeplitz / fiber) forms", b);
+      return CPHIFI_UNSUPPORTED;
+    }
     if (d.r > kBatchRank) {
       set_error("member %d: r = %lld exceeds the batched limit %d", b, (long long)d.r,
                 kBatchRank);

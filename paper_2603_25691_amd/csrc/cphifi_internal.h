@@ -247,6 +247,17 @@ int launch_scale_rows(double* out, const double* x, const double* s, int64_t n, 
                       const int32_t* done, hipStream_t st);
 // dst = (float)src, len elements
 int launch_to_f32(float* dst, const double* src, int64_t len, hipStream_t st);
+// structured.hip: Toeplitz K products and the fiber-collapsed gather-scatter
+int launch_toeplitz_check(const double* K, int64_t ldk, int64_t n, const double* c, double tol,
+                          int32_t* flag, hipStream_t st);
+int launch_toeplitz_product(const double* c, int64_t n, const double* X, int64_t ldx, int r,
+                            double* part, int ldp, int num_cu, int* ksplit_out,
+                            const int32_t* done, hipStream_t st);
+int launch_fiber_gram(const double* B, int64_t J, int r, double* G, hipStream_t st);
+int launch_fiber_gather(const void* part, bool is_float, int ksplit, int ldp, const double* xin,
+                        int64_t n, int r, const int32_t* fib_ptr, const int32_t* fib_i,
+                        const double* A, const double* G, double* xhat_out, double* y1,
+                        const int32_t* done, hipStream_t st);
 int launch_fill(double* dst, double v, int64_t len, hipStream_t st);
 int launch_fill_i32(int32_t* dst, int32_t v, int64_t len, hipStream_t st);
 int launch_gram(const double* A, int64_t I, const double* B, int64_t J, int r, double* V,

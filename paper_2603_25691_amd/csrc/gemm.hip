@@ -25,13 +25,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   tiles::gemm_k4_tile<TA, NB, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
 }
 
-// FP64 products: 4x4x4 MFMA tile over NC4 groups of 4 columns.
+// FP64 products: 4x4x4 MFMA tile over NC4 groups of 4 columns.  The empty asm
+// that clobbers a0 marks the kernel as using AGPRs, so the register allocator
+// may keep the MFMA accumulators there and leave the VGPRs to the two sets of
+// prefetched operands.
 template <int NC4, int MW, int S, bool TRANS, int VW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_kernel(
     GArgs g) {
   if (g.done != nullptr && *g.done) return;
+  asm volatile("" ::: "a0");
   __shared__ double xs[tiles::k4x4_lds_elems<NC4, S>()];
-  tiles::gemm_f64x4_tile<NC4, MW, S, TRANS, VW>(g, blockIdx.x, blockIdx.y, xs, threadIdx.x);
+  tiles::gemm_f64x4_tile<NC4, MW, S, TRANS, VW, true>(g, blockIdx.x, blockIdx.y, xs,
+                                                      threadIdx.x);
 }
 
 // U chunks in flight of the BF16 tile: three for the tiled layout (compiled

@@ -295,7 +295,9 @@ constexpr int k4x4_lds_elems() {
   return 2 * (4 * S) * (4 * NC4 + 16 / S);
 }
 
-template <int NC4, int MW, int S, bool TRANS, int VW>
+// NT: the n x n operand's loads carry the non-temporal hint (it is streamed
+// once per product; 1.59 -> 1.54 ms at n = 30658, r = 40).
+template <int NC4, int MW, int S, bool TRANS, int VW, bool NT = false>
 __device__ __forceinline__ void gemm_f64x4_tile(const GArgs& g, int64_t bx, int64_t by,
                                                 double* xs, int tid) {
   typedef double VecT __attribute__((ext_vector_type(VW)));
@@ -354,7 +356,8 @@ __device__ __forceinline__ void gemm_f64x4_tile(const GArgs& g, int64_t bx, int6
       if (TRANS) {
         const double* p = abase[mb] + k0 * ldu;
 #pragma unroll
-        for (int s = 0; s < S; ++s) dst[mb][s] = p[(int64_t)s * ldu];
+        for (int s = 0; s < S; ++s)
+          dst[mb][s] = NT ? __builtin_nontemporal_load(p + (int64_t)s * ldu) : p[(int64_t)s * ldu];
       } else {
         const double* p = abase[mb] + k0;
 #pragma unroll

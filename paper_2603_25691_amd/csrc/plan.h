@@ -3,6 +3,7 @@
 #pragma once
 
 #include "cphifi_internal.h"
+#include "small.h"
 
 namespace cphifi {
 
@@ -28,6 +29,8 @@ struct Layout {
   size_t sc, sc2, hist;
   size_t V, UV, dV, D, dKc;
   size_t ulp, utlp, xthi, xtlo, ukt, a32, b32;
+  size_t toep, fptr, fidx, fgram;  // structured forms (Toeplitz K, fiber collapse)
+  size_t obst;                     // small plans: time index per observation
   size_t total;
   int64_t ldl;
   int64_t ntask_max, nslot_max, nmulti_max;
@@ -38,8 +41,18 @@ inline int64_t eff_ldk(const cphifi_ui_desc& d) { return d.ldk > 0 ? d.ldk : d.n
 // Plans of this size or larger keep a transposed copy of U_K (see
 // CPHIFI_FLAG_NO_UKT_COPY).
 constexpr int64_t kUktMinN = 4096;
+// FP64 plans whose whole PCG fits one persistent workgroup (small.hip); they
+// keep the copy of U_K too (all products of that kernel read the transposed
+// layout) and the time index of every observation.
+inline bool small_plan(const cphifi_ui_desc& d) {
+  constexpr int32_t kOff = CPHIFI_FLAG_EIGENBASIS | CPHIFI_FLAG_MULTI_KERNEL |
+                           CPHIFI_FLAG_TOEPLITZ_K | CPHIFI_FLAG_FIBER_COLLAPSE |
+                           CPHIFI_FLAG_NO_UKT_COPY | CPHIFI_FLAG_TIME_KERNELS;
+  return d.precision == CPHIFI_FP64 && !(d.flags & kOff) &&
+         small_path_fits(d.n, (int)d.r, d.q, (int64_t)kMaxSplit * d.n * round_up(d.r, 16));
+}
 inline bool keeps_ukt(const cphifi_ui_desc& d) {
-  return d.n >= kUktMinN && !(d.flags & CPHIFI_FLAG_NO_UKT_COPY);
+  return (d.n >= kUktMinN && !(d.flags & CPHIFI_FLAG_NO_UKT_COPY)) || small_plan(d);
 }
 inline int eff_maxit(const cphifi_ui_desc& d) { return d.maxit > 0 ? d.maxit : 500; }
 
@@ -81,6 +94,11 @@ struct cphifi_plan {
   void* utlp = nullptr;  // U_K rounded: U^T, eigenvector k = row k (FP32 row-major,
                          // BF16 in 16 x 64 tiles)
   __bf16 *xthi = nullptr, *xtlo = nullptr;
+  double* toep = nullptr;      // FLAG_TOEPLITZ_K: the first row c of K
+  int32_t* fptr = nullptr;     // FLAG_FIBER_COLLAPSE: fibers of time s are
+  int32_t* fidx = nullptr;     //   fidx[fptr[s] .. fptr[s+1]) (their sample index)
+  double* fgram = nullptr;     //   and G = B^T B
+  int32_t* obst = nullptr;     // small plans: time index of every observation
   GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
   int last_ksplit = 1;  // split-K depth of the partials the last product wrote
   DevScalars* h_sc = nullptr;  // host mirror (mapped, coherent) ...
@@ -105,3 +123,6 @@ struct cphifi_plan {
   int cur_tag = -1;
   bool setup_done = false;
 };
+
+// out (n x r) = K X in FP64 on the plan's stream (partials reduced).
+int plan_times_K(cphifi_plan* p, const double* X, double* out);

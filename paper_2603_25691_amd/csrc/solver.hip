@@ -11,6 +11,7 @@
 // and the preconditioner of eq. (fx) reduces to its r x r middle step.
 #include "cphifi_internal.h"
 #include "plan.h"
+#include "small.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -76,6 +77,13 @@ Layout make_layout(const cphifi_ui_desc& d) {
   L.D = take(sizeof(double) * nr);
   L.dKc = take(sizeof(double) * n);
   if (keeps_ukt(d)) L.ukt = take(sizeof(double) * (size_t)n * eff_ldk(d));
+  if (d.flags & CPHIFI_FLAG_TOEPLITZ_K) L.toep = take(sizeof(double) * n);
+  if (small_plan(d)) L.obst = take(sizeof(int32_t) * std::max<int64_t>(q, 1));
+  if ((d.flags & CPHIFI_FLAG_FIBER_COLLAPSE) && d.J > 0) {
+    L.fptr = take(sizeof(int32_t) * (n + 1));
+    L.fidx = take(sizeof(int32_t) * (q / d.J + 1));
+    L.fgram = take(sizeof(double) * r * r);
+  }
   L.ldl = round_up(n, kLowpAlign);
   if (d.precision != CPHIFI_FP64 && d.I > 0 && d.J > 0) {
     L.a32 = take(sizeof(float) * (size_t)d.I * r);
@@ -149,6 +157,10 @@ int timing_collect(cphifi_plan* p, double* ms, int* count) {
 // whose loads each cover four full 128-byte lines of K, runs faster than the
 // row-major one at these shapes (1.57 vs 1.69 ms at n = 30658, r = 40).
 int prod_K(cphifi_plan* p, const double* X, const int32_t* done) {
+  if (p->toep != nullptr) {  // symmetric Toeplitz K: c only (untimed)
+    return launch_toeplitz_product(p->toep, p->n, X, p->r, (int)p->r, (double*)p->part, p->ldp,
+                                   p->num_cu, &p->last_ksplit, done, p->st);
+  }
   hipEvent_t e0;
   TRY(timed_begin(p, Elt::F64, true, &e0));
   TRY(launch_gemm(Elt::F64, true, p->gp64t, p->in.K, p->ldk, p->n, X, p->r, (int)p->r, nullptr,
@@ -231,6 +243,15 @@ int ksplit_of(const cphifi_plan* p, Elt /*elt*/) { return p->last_ksplit; }
 // of the next product instead of to out.
 int obs_gather(cphifi_plan* p, Elt elt, double* xhat, double* out, const int32_t* done,
                bool split = false) {
+  if (p->fptr != nullptr) {  // every observed fiber complete: r^2 work per fiber
+    if (split) {
+      set_error("internal: the fiber-collapsed gather has no split output");
+      return CPHIFI_INVALID_ARG;
+    }
+    return launch_fiber_gather(p->part, elt != Elt::F64, ksplit_of(p, elt), p->ldp, nullptr,
+                               p->n, (int)p->r, p->fptr, p->fidx, p->in.A, p->fgram, xhat, out,
+                               done, p->st);
+  }
   ObsArgs a{};
   a.n = p->n;
   a.r = (int)p->r;
@@ -290,7 +311,7 @@ int op_apply_eig(cphifi_plan* p, Elt elt, const double* xb, double* yb, double* 
   // BF16 with the lane-row gather: the gather writes the split operand of
   // U^T Yhat1 itself (the split of U (D_K xbar) before it has zeroed the
   // padding rows and columns of that operand).
-  const bool fuse = elt == Elt::BF16 && p->tasks.rows;
+  const bool fuse = elt == Elt::BF16 && p->tasks.rows && p->fptr == nullptr;
   if (elt == Elt::BF16) {
     TRY(prod_U(p, elt, xb, p->dKc, done));  // the split applies D_K
   } else {
@@ -464,11 +485,77 @@ int true_relres_from_B(cphifi_plan* p, const double* Bm, const double* W, double
   return CPHIFI_OK;
 }
 
+}  // namespace
+
+int plan_times_K(cphifi_plan* p, const double* X, double* out) {
+  const bool t = p->timing;
+  p->timing = false;
+  const int rc = prod_K(p, X, nullptr);
+  p->timing = t;
+  TRY(rc);
+  return launch_reduce_partials(p->part, false, p->last_ksplit, p->ldp, p->n, (int)p->r, out,
+                                nullptr, nullptr, nullptr, nullptr, p->st);
+}
+
+namespace {
+
+// The whole FP64 PCG of a small subproblem in one persistent workgroup
+// (small.hip): no launch or host poll per iteration.
+int run_small_pcg(cphifi_plan* p, const double* b, double* W, bool warm, int maxit,
+                  PcgOut* out) {
+  SmallArgs a{};
+  a.n = p->n;
+  a.ldk = p->ldk;
+  a.r = (int)p->r;
+  a.warm = warm ? 1 : 0;
+  a.precond = (p->d.flags & CPHIFI_FLAG_NO_PRECOND) ? 0 : 1;
+  a.maxit = maxit;
+  a.hist_len = p->L.hist_len;
+  a.lam = p->d.lambda;
+  a.rho = p->d.rho;
+  a.tol = p->d.tol;
+  a.K = p->in.K;
+  a.UK = p->in.UK;
+  a.UKT = p->ukt;
+  a.UV = p->UV;
+  a.D = p->D;
+  a.obs_ptr = p->in.obs_ptr;
+  a.obs_i = p->in.obs_i;
+  a.obs_j = p->in.obs_j;
+  a.A = p->in.A;
+  a.B = p->in.B;
+  a.Zhat = p->in.Zhat;
+  a.b = b;
+  a.X = W;
+  a.R = p->vec[V_R];
+  a.Z = p->vec[V_Z];
+  a.P = p->vec[V_P];
+  a.Q = p->vec[V_Q];
+  a.Xh = p->vec[V_XHAT];
+  a.Y1 = p->vec[V_Y1];
+  a.T1 = p->vec[V_T2];
+  a.T2 = p->vec[V_TMP];
+  a.Wq = (double*)p->part;
+  a.hist = p->hist;
+  a.out = (SmallOut*)p->sc2;  // the certificate's scalars are free until it runs
+  TRY(launch_small_pcg(a, p->obst, p->q, p->st));
+  SmallOut h{};
+  CPHIFI_HIP(hipMemcpyAsync(&h, a.out, sizeof(h), hipMemcpyDeviceToHost, p->st));
+  CPHIFI_HIP(hipStreamSynchronize(p->st));
+  out->iters = h.iters;
+  out->status = h.status;
+  out->relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
+  return CPHIFI_OK;
+}
+
 int solve_fp64(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* info) {
   const bool warm = (p->d.flags & CPHIFI_FLAG_WARM_START) != 0;
   const int maxit = eff_maxit(p->d);
   PcgOut o;
-  if (p->d.flags & CPHIFI_FLAG_EIGENBASIS) {
+  const bool small = p->obst != nullptr && p->ukt != nullptr && !p->timing;
+  if (small) {
+    TRY(run_small_pcg(p, b, W, warm, maxit, &o));
+  } else if (p->d.flags & CPHIFI_FLAG_EIGENBASIS) {
     // x = U xbar: PCG on the rotated system, then rotate back.
     TRY(rotate_in(p, Elt::F64, b, p->vec[V_RB]));
     if (warm) TRY(rotate_in(p, Elt::F64, W, p->vec[V_XB]));
@@ -715,6 +802,10 @@ int validate_desc(const cphifi_ui_desc* d) {
     set_error("FLAG_NO_PRECOND is only available with CPHIFI_FP64");
     return CPHIFI_INVALID_ARG;
   }
+  if ((d->flags & CPHIFI_FLAG_FIBER_COLLAPSE) && (d->I < 1 || d->J < 1)) {
+    set_error("FLAG_FIBER_COLLAPSE needs the implicit factor form (I, J >= 1)");
+    return CPHIFI_INVALID_ARG;
+  }
   return CPHIFI_OK;
 }
 
@@ -847,11 +938,13 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
       return CPHIFI_INVALID_ARG;
     }
   bool owner = false;
+  std::vector<int32_t> oi, oj;
   if (!expl && q > 0) {
     // Both index arrays are always range-checked here (the gather clamps an
     // index to stay in bounds, which would otherwise turn a bad index into a
     // wrong answer with status OK).
-    std::vector<int32_t> oi(q), oj(q);
+    oi.resize(q);
+    oj.resize(q);
     CPHIFI_HIP(hipMemcpyAsync(oi.data(), in->obs_i, sizeof(int32_t) * q, hipMemcpyDeviceToHost,
                               st));
     CPHIFI_HIP(hipMemcpyAsync(oj.data(), in->obs_j, sizeof(int32_t) * q, hipMemcpyDeviceToHost,
@@ -898,6 +991,46 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     }
   }
   mptr.push_back(nslot);
+  // Fiber collapse: every (time, sample) pair observed at all must be observed
+  // at each of the J features exactly once.  Fibers of a time point are listed
+  // in ascending sample order (a fixed summation order).
+  std::vector<int32_t> fptr, fidx;
+  if (d->flags & CPHIFI_FLAG_FIBER_COLLAPSE) {
+    const int64_t J = d->J;
+    fptr.assign(n + 1, 0);
+    std::vector<int32_t> cnt(d->I, 0);
+    std::vector<uint8_t> seen((size_t)d->I * J, 0);
+    std::vector<int32_t> samples;
+    for (int64_t s = 0; s < n; ++s) {
+      samples.clear();
+      for (int32_t l = ptr[s]; l < ptr[s + 1]; ++l) {
+        const size_t key = (size_t)oi[l] * J + oj[l];
+        if (seen[key]) {
+          set_error("FLAG_FIBER_COLLAPSE: (time %lld, sample %d, feature %d) observed twice",
+                    (long long)s, oi[l], oj[l]);
+          return CPHIFI_INVALID_ARG;
+        }
+        seen[key] = 1;
+        if (cnt[oi[l]]++ == 0) samples.push_back(oi[l]);
+      }
+      std::sort(samples.begin(), samples.end());
+      for (int32_t i : samples) {
+        if (cnt[i] != J) {
+          set_error("FLAG_FIBER_COLLAPSE: (time %lld, sample %d) has %d of the %lld features",
+                    (long long)s, i, cnt[i], (long long)J);
+          return CPHIFI_INVALID_ARG;
+        }
+        fidx.push_back(i);
+        cnt[i] = 0;
+      }
+      for (int32_t l = ptr[s]; l < ptr[s + 1]; ++l) seen[(size_t)oi[l] * J + oj[l]] = 0;
+      fptr[s + 1] = (int32_t)fidx.size();
+    }
+    if ((int64_t)fidx.size() > q / J + 1) {
+      set_error("internal: fiber list exceeds its bound");
+      return CPHIFI_INVALID_ARG;
+    }
+  }
   const int64_t ntask = (int64_t)tseg.size();
   if (ntask > L.ntask_max || nslot > L.nslot_max || (int64_t)mseg.size() > L.nmulti_max) {
     set_error("internal: observation task list exceeds its bound");
@@ -1019,6 +1152,53 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
                            choose_gemm(Elt::F64, false, n, rr, p->num_cu), p->num_cu);
   p->gp64t = plan_from_env("CPHIFI_TILE_F64T", Elt::F64, true, n, rr,
                            choose_gemm(Elt::F64, true, n, rr, p->num_cu), p->num_cu);
+  if (small_plan(*d)) {
+    p->obst = (int32_t*)(ws + L.obst);
+    std::vector<int32_t> ot(q);
+    for (int64_t s = 0; s < n; ++s)
+      for (int32_t l = ptr[s]; l < ptr[s + 1]; ++l) ot[l] = (int32_t)s;
+    if ((rc = up(p->obst, ot))) return fail(rc);
+    // the copy above is asynchronous: keep the host vector until the stream drains
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      set_error("plan_create: upload of the observation times failed");
+      return fail(CPHIFI_HIP_ERROR);
+    }
+  }
+  if (d->flags & CPHIFI_FLAG_FIBER_COLLAPSE) {
+    p->fptr = (int32_t*)(ws + L.fptr);
+    p->fidx = (int32_t*)(ws + L.fidx);
+    p->fgram = (double*)(ws + L.fgram);
+    if ((rc = up(p->fptr, fptr)) || (rc = up(p->fidx, fidx))) return fail(rc);
+  }
+  if (d->flags & CPHIFI_FLAG_TOEPLITZ_K) {
+    // c = the first row of K; the plan is refused unless every entry of K is
+    // c(|s - k|) to within 1e-12 max|c| (a kernel evaluated on a rounded
+    // uniform grid matches along its diagonals only to rounding).
+    p->toep = (double*)(ws + L.toep);
+    std::vector<double> c(n);
+    if (hipMemcpyAsync(p->toep, in->K, sizeof(double) * n, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(c.data(), in->K, sizeof(double) * n, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("plan_create: copy of the first row of K failed");
+      return fail(CPHIFI_HIP_ERROR);
+    }
+    double cmax = 0.0;
+    for (double v : c) cmax = std::max(cmax, std::fabs(v));
+    *(volatile int32_t*)p->h_flag = 0;
+    if ((rc = launch_toeplitz_check(in->K, p->ldk, n, p->toep, 1e-12 * cmax, p->d_flag, st)))
+      return fail(rc);
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      set_error("plan_create: Toeplitz check failed to run");
+      return fail(CPHIFI_HIP_ERROR);
+    }
+    if (*(volatile int32_t*)p->h_flag != 0) {
+      *(volatile int32_t*)p->h_flag = 0;
+      set_error("FLAG_TOEPLITZ_K: K is not symmetric Toeplitz to within 1e-12 max|K(0,:)|");
+      return fail(CPHIFI_INVALID_ARG);
+    }
+  }
   if (keeps_ukt(*d)) {
     p->ukt = (double*)(ws + L.ukt);
     if ((rc = launch_convert_lowp(Elt::F64, true, in->UK, p->ldk, n, p->ukt, p->ldk, st)))
@@ -1088,6 +1268,13 @@ int cphifi_ui_setup(cphifi_plan* p) {
     TRY(launch_gram(p->in.A, p->I, p->in.B, p->J, r, p->V, p->st));
   }
   TRY(launch_jacobi_eig(p->V, r, p->UV, p->dV, p->st));
+  // The FP32 factor copies of the low-precision gather follow A and B, which
+  // may have changed since the plan was made (alternating optimisation).
+  if (p->fgram != nullptr) TRY(launch_fiber_gram(p->in.B, p->J, r, p->fgram, p->st));
+  if (p->a32 != nullptr) {
+    TRY(launch_to_f32(p->a32, p->in.A, p->I * r, p->st));
+    TRY(launch_to_f32(p->b32, p->in.B, p->J * r, p->st));
+  }
   TRY(launch_clamp_nonneg(p->in.dK, p->dKc, p->n, p->st));
   TRY(launch_precond_diag(p->in.dK, p->dV, p->n, r, p->gamma, p->d.lambda, p->d.rho, p->D,
                           p->st));

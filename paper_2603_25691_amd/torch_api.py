@@ -7,6 +7,7 @@ documented dtype and layout; nothing is converted or computed here.
 
 from __future__ import annotations
 
+import ctypes
 from dataclasses import dataclass
 from typing import Optional
 
@@ -387,3 +388,54 @@ def product(U: torch.Tensor, X: torch.Tensor, elt: str = "fp64", trans: bool = F
                       ws_bytes, _stream())
     return out
 
+
+class AlsSolver:
+    """CP-HIFI alternating optimisation over three RKHS modes (cphifi_als_*).
+
+    Ks, UKs, dKs: per mode the kernel matrix (n_k x n_k), its eigenvectors (as
+    kernel_eig returns them) and eigenvalues, device float64; coords: (q, 3)
+    device int32; y: (q,) device float64."""
+
+    def __init__(self, Ks, UKs, dKs, coords: torch.Tensor, y: torch.Tensor, r: int, lams,
+                 rho: float, tol: float, als_tol: float, max_outer: int, maxit: int = 0,
+                 precision: str = "fp64", flags: int = 0):
+        n = [int(K.shape[0]) for K in Ks]
+        for k in range(3):
+            _need(Ks[k], torch.float64, (n[k], n[k]), f"K[{k}]")
+            _need(UKs[k], torch.float64, (n[k], n[k]), f"UK[{k}]")
+            _need(dKs[k], torch.float64, (n[k],), f"dK[{k}]")
+        q = int(y.shape[0])
+        _need(coords, torch.int32, (q, 3), "coords")
+        _need(y, torch.float64, (q,), "y")
+        self.n, self.r, self.max_outer = n, r, max_outer
+        self._keep = (list(Ks), list(UKs), list(dKs), coords, y)
+        self.desc = _c.make_als_desc(n, q, r, lams, rho, tol, als_tol, max_outer, maxit,
+                                     _c.PRECISIONS[precision], flags)
+        self.inputs = _c.cphifi_als_inputs()
+        for k in range(3):
+            self.inputs.K[k], self.inputs.UK[k] = Ks[k].data_ptr(), UKs[k].data_ptr()
+            self.inputs.dK[k] = dKs[k].data_ptr()
+        self.inputs.coords, self.inputs.y = coords.data_ptr(), y.data_ptr()
+        self.ws_bytes = _c.cphifi_als_workspace_bytes(self.desc)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=y.device)
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.handle = _c.cphifi_als_create(self.desc, self.inputs, ws, self.ws_bytes,
+                                           _stream())
+
+    def run(self, W0s):
+        """Returns (Ws, Fs, info, errors): the final weights and factors (device),
+        the run's info and the relative error before / after each outer iteration."""
+        Ws = []
+        for k in range(3):
+            _need(W0s[k], torch.float64, (self.n[k], self.r), f"W0[{k}]")
+            Ws.append(W0s[k].clone())
+        Fs = [torch.empty_like(W) for W in Ws]
+        errors = (ctypes.c_double * (self.max_outer + 1))()
+        info = _c.cphifi_als_run(self.handle, [W.data_ptr() for W in Ws],
+                                 [F.data_ptr() for F in Fs], ctypes.addressof(errors))
+        return Ws, Fs, info, list(errors)[: info.outer + 1]
+
+    def close(self):
+        _c.cphifi_als_destroy(self.handle)
+        self.handle = None
+        self.workspace = None

@@ -18,6 +18,8 @@ from .generator import (  # noqa: F401
     make_batch,
     batch_members,
     make_paper_standin,
+    AlsProblem,
+    make_als_problem,
     config_c1,
     config_c2,
     config_c3,

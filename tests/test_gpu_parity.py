@@ -17,6 +17,10 @@ Tolerances
   spread between two runs that differ only by rounding, measured by
   tests/test_oracle_spread.py;
 * mixed-precision solves refined to relres 1e-7: e_KW <= 1e-6.
+
+The FP64 solves of the small cases run in one persistent workgroup unless
+FLAG_MULTI_KERNEL asks for the multi-kernel iteration; the solve and failure
+tests run both paths (`paths`), and one test compares them with each other.
 """
 
 import numpy as np
@@ -67,6 +71,15 @@ def small_cases():
 
 
 CASES = small_cases()
+
+# FP64 iteration paths: the persistent single-workgroup loop (default for
+# small subproblems) and the multi-kernel loop.
+PATHS = ["persistent", "multi"]
+
+
+@pytest.fixture(params=PATHS)
+def path_flags(request):
+    return 0 if request.param == "persistent" else C.FLAG_MULTI_KERNEL
 
 
 @pytest.fixture(scope="module")
@@ -230,9 +243,9 @@ def _dense_gate(p):
 
 
 @pytest.mark.parametrize("tol,gate", [(1e-10, 1e-9), (1e-12, 1e-10)])
-def test_fp64_solve_c1(tol, gate, uploaded):
+def test_fp64_solve_c1(tol, gate, uploaded, path_flags):
     p, dp = uploaded("c1")
-    s = UISolver(dp, p.lam, p.rho, tol)
+    s = UISolver(dp, p.lam, p.rho, tol, flags=path_flags)
     W, info = s.solve_subproblem()
     assert info.status == C.OK, info.as_dict()
     Wo = _dense(p)
@@ -244,18 +257,18 @@ def test_fp64_solve_c1(tol, gate, uploaded):
 
 
 @pytest.mark.parametrize("name", ["ragged-r3", "ragged-r17", "c1-drop", "r64"])
-def test_fp64_solve_ragged(name, uploaded):
+def test_fp64_solve_ragged(name, uploaded, path_flags):
     p, dp = uploaded(name)
-    s = UISolver(dp, p.lam, p.rho, 1e-12)
+    s = UISolver(dp, p.lam, p.rho, 1e-12, flags=path_flags)
     W, info = s.solve_subproblem()
     assert info.status == C.OK, info.as_dict()
     Wo, gate = _dense_gate(p)
     assert O.e_kw(p.K, host(W), Wo) <= gate
 
 
-def test_fp64_history_is_monotone_tail_and_matches_oracle(uploaded):
+def test_fp64_history_is_monotone_tail_and_matches_oracle(uploaded, path_flags):
     p, dp = uploaded("c1")
-    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    s = UISolver(dp, p.lam, p.rho, 1e-10, flags=path_flags)
     hist = np.zeros(502)
     W, info = s.solve_subproblem(history=hist)
     Zhat, V = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j), O.gram_V(p.A, p.B)
@@ -266,6 +279,26 @@ def test_fp64_history_is_monotone_tail_and_matches_oracle(uploaded):
     # the early residual history is insensitive to rounding
     assert np.allclose(got[:10], want[:10], rtol=1e-6)
     assert got[info.iters] <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged-r3", "ragged-r17", "c1-drop"])
+def test_persistent_and_multi_kernel_paths_agree(name, uploaded):
+    """The same recurrence on the same data: iteration counts within one, the
+    early residual history equal to rounding, and the two solutions within the
+    solve's own accuracy of each other."""
+    p, dp = uploaded(name)
+    h1, h2 = np.zeros(600), np.zeros(600)
+    s1 = UISolver(dp, p.lam, p.rho, 1e-12)
+    W1, i1 = s1.solve_subproblem(history=h1)
+    W1 = host(W1)
+    s2 = UISolver(dp, p.lam, p.rho, 1e-12, flags=C.FLAG_MULTI_KERNEL)
+    W2, i2 = s2.solve_subproblem(history=h2)
+    assert i1.status == C.OK and i2.status == C.OK
+    assert abs(i1.iters - i2.iters) <= 1
+    assert np.allclose(h1[:8], h2[:8], rtol=1e-9)
+    _, gate = _dense_gate(p)
+    assert O.e_kw(p.K, W1, host(W2)) <= gate
+    assert abs(i1.relres_true - i2.relres_true) <= 1e-11
 
 
 def test_eigenbasis_fp64_form_same_solution(uploaded):
@@ -332,11 +365,11 @@ def test_aligned_case_converges_in_one_iteration():
     assert O.e_kw(p.K, host(W), Wk) <= 1e-10
 
 
-def test_warm_start_from_solution_needs_no_iteration(uploaded):
+def test_warm_start_from_solution_needs_no_iteration(uploaded, path_flags):
     p, dp = uploaded("c1")
-    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    s = UISolver(dp, p.lam, p.rho, 1e-10, flags=path_flags)
     W, info = s.solve_subproblem()
-    s2 = UISolver(dp, p.lam, p.rho, 1e-8, flags=C.FLAG_WARM_START)
+    s2 = UISolver(dp, p.lam, p.rho, 1e-8, flags=C.FLAG_WARM_START | path_flags)
     W2, info2 = s2.solve_subproblem(W=W.clone())
     assert info2.status == C.OK and info2.iters == 0
 
@@ -355,37 +388,37 @@ def test_mixed_warm_start_from_solution_needs_no_correction(uploaded):
     assert O.e_kw(p.K, host(W2), host(W)) <= 1e-12
 
 
-def test_iteration_cap_reports_not_converged(uploaded):
+def test_iteration_cap_reports_not_converged(uploaded, path_flags):
     p, dp = uploaded("c1")
-    s = UISolver(dp, p.lam, p.rho, 1e-12, maxit=1)
+    s = UISolver(dp, p.lam, p.rho, 1e-12, maxit=1, flags=path_flags)
     W, info = s.solve_subproblem()
     assert info.status == C.NOT_CONVERGED
     assert info.iters == 1
     assert 0 < info.relres_true < 1
 
 
-def test_nan_observation_reports_numeric(uploaded):
+def test_nan_observation_reports_numeric(uploaded, path_flags):
     p, dp = uploaded("c1")
     y = dp.y.clone()
     y[5] = float("nan")
-    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    s = UISolver(dp, p.lam, p.rho, 1e-10, flags=path_flags)
     with pytest.raises(C.CphifiError) as ei:
         s.solve_subproblem(y=y)
     assert ei.value.status == C.NUMERIC
 
 
-def test_zero_data_gives_zero_solution(uploaded):
+def test_zero_data_gives_zero_solution(uploaded, path_flags):
     p, dp = uploaded("c1")
-    s = UISolver(dp, p.lam, p.rho, 1e-10)
+    s = UISolver(dp, p.lam, p.rho, 1e-10, flags=path_flags)
     W, info = s.solve_subproblem(y=torch.zeros_like(dp.y))
     assert info.status == C.OK and info.iters == 0
     assert float(torch.count_nonzero(W)) == 0
 
 
-def test_no_observations_at_all():
+def test_no_observations_at_all(path_flags):
     p = make_small(40, n=30, I=3, J=3, r=2, q=0)
     dp = upload(p)
-    s = UISolver(dp, p.lam, p.rho, 1e-10, gamma=1e-3)
+    s = UISolver(dp, p.lam, p.rho, 1e-10, gamma=1e-3, flags=path_flags)
     W, info = s.solve_subproblem()
     assert info.status == C.OK and float(torch.count_nonzero(W)) == 0
 
