@@ -178,10 +178,10 @@ def bench_small(torch, C, steps: int):
            "n": p.n, "q": p.q, "r": p.r,
            "oracle_dense_ms": 1e3 * t_dense, "oracle_lstsq_ms": 1e3 * t_brute}
     timer = StepTimer(torch)
-    # fp64: the whole PCG in one persistent workgroup (the default at this
-    # size); fp64_multi_kernel: the same solve with one launch sequence and
-    # host poll per iteration.
-    legs = (("fp64", "fp64", 1e-10, 0), ("fp64_multi_kernel", "fp64", 1e-10, C.FLAG_MULTI_KERNEL),
+    # fp64: the launch loop (one launch sequence per iteration, host poll every
+    # few iterations); fp64_persistent: the same solve in one persistent
+    # workgroup (CPHIFI_FLAG_PERSISTENT)
+    legs = (("fp64", "fp64", 1e-10, 0), ("fp64_persistent", "fp64", 1e-10, C.FLAG_PERSISTENT),
             ("mixed_bf16", "mixed_bf16", MIXED_TOL, 0))
     for label, prec, tol, flags in legs:
         s = UISolver(dp, p.lam, p.rho, tol, precision=prec, flags=flags)
@@ -195,8 +195,8 @@ def bench_small(torch, C, steps: int):
                      "tol": tol}
         s.close()
     out["gpu_vs_oracle_dense"] = out["oracle_dense_ms"] / (out["fp64"]["us_per_solve"] / 1e3)
-    log(f"small: fp64 {out['fp64']['us_per_solve']:.0f} us (multi-kernel "
-        f"{out['fp64_multi_kernel']['us_per_solve']:.0f} us), mixed "
+    log(f"small: fp64 {out['fp64']['us_per_solve']:.0f} us (persistent workgroup "
+        f"{out['fp64_persistent']['us_per_solve']:.0f} us), mixed "
         f"{out['mixed_bf16']['us_per_solve']:.0f} us per solve; oracle dense "
         f"{out['oracle_dense_ms']:.1f} ms, lstsq {out['oracle_lstsq_ms']:.1f} ms")
     return out

@@ -93,11 +93,15 @@ enum cphifi_flags {
                                    transposed FP64 product (the rotations, the
                                    FP64 residuals and the certificate) instead
                                    of the low-precision one */
-  CPHIFI_FLAG_MULTI_KERNEL = 128, /* FP64: always the multi-kernel iteration.
-                                   Without it a small subproblem (n <= 2048,
-                                   n^2 r <= 2e6, q r <= 5e5, paper form, no
-                                   kernel timing, no structured form) runs its
-                                   whole PCG in one persistent workgroup */
+  CPHIFI_FLAG_PERSISTENT = 128, /* FP64, small subproblems (n <= 2048, n r <=
+                                   4096, n^2 r <= 2e6, q r <= 5e5; paper form,
+                                   no kernel timing, no structured form): the
+                                   whole PCG in one persistent workgroup, no
+                                   launch or host poll per iteration.  Opt-in:
+                                   at the small case (n = 208, r = 5) it ran
+                                   3.97 ms per solve against 2.32 ms for the
+                                   launch loop (one workgroup cannot keep
+                                   enough loads in flight) */
   CPHIFI_FLAG_TOEPLITZ_K = 256, /* K is symmetric Toeplitz, K(s,k) = c(|s-k|) (a
                                    translation-invariant kernel on a uniform
                                    grid; Section 4.4.1 notes the structure):
@@ -247,6 +251,21 @@ CPHIFI_API int cphifi_ui_plan_destroy(cphifi_plan* p);
  * to converge). */
 CPHIFI_API int cphifi_kernel_eig(int64_t n, const double* K, int64_t ldk, double* UK,
                       double* dK, void* stream);
+
+/* The same decomposition by the cyclic Jacobi method, parallel round-robin
+ * ordering (every step rotates m/2 disjoint index pairs, m = n rounded up to
+ * even; each rotation is the symmetric 2 x 2 Schur decomposition that
+ * annihilates one off-diagonal entry), written for the device: two launches
+ * per step, n steps per sweep, O(n^3) work and traffic per sweep.  Stops when
+ * the off-diagonal mass ||A - diag(A)||_F falls to tol ||K||_F (tol > 0, e.g.
+ * 1e-14) or after max_sweeps sweeps; sweeps_out (host, may be NULL) receives
+ * the count.  K is symmetrised ((K + K^T) / 2) on entry.  Output as
+ * cphifi_kernel_eig: UK row k = eigenvector k, dK ascending.  n <= 8192.
+ * Allocates and frees its own scratch (2 n^2 doubles; setup path only).  sync.
+ * Errors: INVALID_ARG, HIP_ERROR, NUMERIC (not converged within max_sweeps). */
+CPHIFI_API int cphifi_kernel_eig_jacobi(int64_t n, const double* K, int64_t ldk, double* UK,
+                                        double* dK, double tol, int max_sweeps, int* sweeps_out,
+                                        void* stream);
 
 /* ------------------------------------------------------ aligned subproblem
  * Section 3: every entry of the data tensor observed (one shared time grid).

@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcphifi.so")
 SOURCES = ["gemm.hip", "obs.hip", "vec.hip", "solver.hip", "eig.hip", "product.hip", "batch.hip",
            "aligned.hip", "small.hip", "als.hip",
-           "structured.hip"]
+           "structured.hip", "jacobi_eig.hip"]
 ARCH = os.environ.get("CPHIFI_OFFLOAD_ARCH", "gfx950")
 
 

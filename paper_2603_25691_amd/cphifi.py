@@ -38,7 +38,9 @@ FLAG_NO_PRECOND = 8
 FLAG_EIGENBASIS = 16
 FLAG_NO_UKT_COPY = 32
 FLAG_TIME_FP64 = 64
-FLAG_MULTI_KERNEL = 128
+FLAG_PERSISTENT = 128
+FLAG_TOEPLITZ_K = 256
+FLAG_FIBER_COLLAPSE = 512
 
 PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 
@@ -154,6 +156,8 @@ def _load() -> C.CDLL:
         "cphifi_ui_solve_subproblem": (C.c_int, [P, P, P, C.POINTER(cphifi_solve_info)]),
         "cphifi_ui_plan_destroy": (C.c_int, [P]),
         "cphifi_kernel_eig": (C.c_int, [C.c_int64, P, C.c_int64, P, P, P]),
+        "cphifi_kernel_eig_jacobi": (C.c_int, [C.c_int64, P, C.c_int64, P, P, C.c_double, C.c_int,
+                                               C.POINTER(C.c_int), P]),
         "cphifi_aligned_workspace_bytes": (C.c_int, [C.POINTER(cphifi_aligned_desc),
                                                      C.POINTER(C.c_size_t)]),
         "cphifi_aligned_solve": (C.c_int, [C.POINTER(cphifi_aligned_desc),
@@ -300,6 +304,15 @@ def cphifi_ui_plan_destroy(plan: int) -> None:
 def cphifi_kernel_eig(n: int, K: int, ldk: int, UK: int, dK: int, stream: int) -> None:
     _check(_lib.cphifi_kernel_eig(C.c_int64(n), C.c_void_p(K), C.c_int64(ldk), C.c_void_p(UK),
                                   C.c_void_p(dK), C.c_void_p(stream)), "cphifi_kernel_eig")
+
+
+def cphifi_kernel_eig_jacobi(n: int, K: int, ldk: int, UK: int, dK: int, tol: float,
+                             max_sweeps: int, stream: int) -> int:
+    sweeps = C.c_int(0)
+    _check(_lib.cphifi_kernel_eig_jacobi(n, C.c_void_p(K), ldk, C.c_void_p(UK), C.c_void_p(dK),
+                                         tol, max_sweeps, C.byref(sweeps), C.c_void_p(stream)),
+           "cphifi_kernel_eig_jacobi")
+    return int(sweeps.value)
 
 
 def make_desc(n: int, r: int, q: int, I: int = 0, J: int = 0, lam: float = 1e-3,

@@ -39,6 +39,7 @@ void clear_error();
   } while (0)
 
 constexpr int kMaxRank = 64;
+constexpr int64_t kJacobiMaxN = 8192;  // largest n of cphifi_kernel_eig_jacobi
 constexpr int kWave = 64;
 constexpr int kVecThreads = 256;     // threads of the elementwise / reduction kernels
 constexpr int kMaxVecBlocks = 1024;  // upper bound on their grid (reduction partials)
@@ -107,6 +108,8 @@ struct GemmPlan {
   int64_t kper = 0;
   int mw = 2;   // 16-row MFMA blocks per wave (4 waves per workgroup)
   int s = 8;    // MFMA steps per k chunk (chunk = 4*s rows of X; 32*s for BF16)
+  int sk = 0;   // FP64 transposed 4x4x4 tile: > 0 = stream-K over this many
+                // workgroups (ksplit then counts the slabs every row receives)
 };
 GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu);
 // Plan with an explicit tile; ksplit_req <= 0 picks the split from the CU count

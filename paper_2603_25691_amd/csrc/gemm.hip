@@ -35,8 +35,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   if (g.done != nullptr && *g.done) return;
   asm volatile("" ::: "a0");
   __shared__ double xs[tiles::k4x4_lds_elems<NC4, S>()];
-  tiles::gemm_f64x4_tile<NC4, MW, S, TRANS, VW, true>(g, blockIdx.x, blockIdx.y, xs,
-                                                      threadIdx.x);
+  const int64_t kbeg = (int64_t)blockIdx.y * g.kper;
+  tiles::gemm_f64x4_tile<NC4, MW, S, TRANS, VW, true>(g, blockIdx.x, kbeg, min(g.n, kbeg + g.kper),
+                                                      blockIdx.y, xs, threadIdx.x);
+}
+
+// Stream-K form of the transposed FP64 product: the (row block, k chunk)
+// iterations are dealt out evenly to exactly one round of resident
+// workgroups, so no slot idles at the end (the split-K grid of 120 row blocks
+// x 4 splits at n = 30658 fills 480 of 512 slots).  A workgroup runs the
+// tile once per row block its range touches and writes that part into slab
+// (its rank among the row block's contributors); the last contributor of a
+// row block zeroes the slabs past their count, so every row has sk.ksplit
+// slabs like a split-K product.
+struct SkArgs {
+  int64_t nrb, nch;  // row blocks, k chunks per row block
+  int64_t wgs;       // workgroups (grid size)
+  int ksplit;        // slabs every row ends up with
+};
+
+__device__ __forceinline__ int64_t sk_first(int64_t x, int64_t wgs, int64_t T) {
+  // the workgroup whose range [w T / wgs, (w + 1) T / wgs) holds iteration x
+  return ((x + 1) * wgs - 1) / T;
+}
+
+template <int NC4, int MW, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_sk_kernel(
+    GArgs g, SkArgs sk) {
+  if (g.done != nullptr && *g.done) return;
+  asm volatile("" ::: "a0");
+  __shared__ double xs[tiles::k4x4_lds_elems<NC4, S>()];
+  constexpr int BK = 4 * S;
+  constexpr int64_t ROWS = 4 * MW * 16;
+  const int64_t T = sk.nrb * sk.nch;
+  const int64_t w = blockIdx.x;
+  const int64_t c1 = (w + 1) * T / sk.wgs;
+  for (int64_t c = w * T / sk.wgs; c < c1;) {
+    const int64_t b = c / sk.nch;
+    const int64_t cend = min(c1, (b + 1) * sk.nch);
+    const int64_t wf = sk_first(b * sk.nch, sk.wgs, T);
+    const int64_t wl = sk_first((b + 1) * sk.nch - 1, sk.wgs, T);
+    // the zeroing goes first: it keeps the loop state out of the tile's live range
+    if (w == wl) {  // last contributor: zero the unused slabs of this row block
+      const int64_t r0 = b * ROWS, r1 = min(g.n, r0 + ROWS);
+      double* part = (double*)g.part;
+      for (int64_t sl = wl - wf + 1; sl < sk.ksplit; ++sl)
+        for (int64_t e = threadIdx.x; e < (r1 - r0) * g.ldp; e += 256)
+          part[(sl * g.n + r0) * g.ldp + e] = 0.0;
+    }
+    tiles::gemm_f64x4_tile<NC4, MW, S, true, 1, true>(
+        g, b, (c - b * sk.nch) * BK, min(g.n, (cend - b * sk.nch) * BK), w - wf, xs,
+        threadIdx.x);
+    c = cend;
+  }
 }
 
 // U chunks in flight of the BF16 tile: three for the tiled layout (compiled
@@ -144,6 +195,43 @@ int dispatch_nc4_f64(int nc4, const GArgs& g, int ksplit, hipStream_t st) {
     case 16: return launch_f64<16, MW, S, TRANS>(g, ksplit, st);
   }
   set_error("unsupported column group count %d", nc4);
+  return CPHIFI_INVALID_ARG;
+}
+
+template <int NC4, int MW, int S>
+int launch_f64_sk(const GemmPlan& gp, const GArgs& g, hipStream_t st) {
+  SkArgs sk;
+  sk.nrb = (g.n + 4 * MW * 16 - 1) / (4 * MW * 16);
+  sk.nch = (g.n + 4 * S - 1) / (4 * S);
+  sk.wgs = gp.sk;
+  sk.ksplit = gp.ksplit;
+  hipLaunchKernelGGL((gemm_f64_sk_kernel<NC4, MW, S>), dim3((unsigned)gp.sk), dim3(256), 0, st,
+                     g, sk);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
+template <int MW, int S>
+int dispatch_nc4_f64_sk(int nc4, const GemmPlan& gp, const GArgs& g, hipStream_t st) {
+  switch (nc4) {
+    case 2: return launch_f64_sk<2, MW, S>(gp, g, st);
+    case 4: return launch_f64_sk<4, MW, S>(gp, g, st);
+    case 6: return launch_f64_sk<6, MW, S>(gp, g, st);
+    case 8: return launch_f64_sk<8, MW, S>(gp, g, st);
+    case 10: return launch_f64_sk<10, MW, S>(gp, g, st);
+    case 12: return launch_f64_sk<12, MW, S>(gp, g, st);
+    case 14: return launch_f64_sk<14, MW, S>(gp, g, st);
+    case 16: return launch_f64_sk<16, MW, S>(gp, g, st);
+  }
+  set_error("unsupported column group count %d", nc4);
+  return CPHIFI_INVALID_ARG;
+}
+
+int dispatch_f64_sk(const GemmPlan& gp, int nc4, const GArgs& g, hipStream_t st) {
+  if (gp.mw == 4 && gp.s == 2) return dispatch_nc4_f64_sk<4, 2>(nc4, gp, g, st);
+  if (gp.mw == 2 && gp.s == 4) return dispatch_nc4_f64_sk<2, 4>(nc4, gp, g, st);
+  if (gp.mw == 1 && gp.s == 8) return dispatch_nc4_f64_sk<1, 8>(nc4, gp, g, st);
+  set_error("unsupported stream-K FP64 tile (mw=%d, s=%d)", gp.mw, gp.s);
   return CPHIFI_INVALID_ARG;
 }
 
@@ -291,6 +379,9 @@ bool gemm_cfg_valid(Elt elt, int mw, int s) {
          (mw == 4 && s == 4);
 }
 
+// Stream-K for the transposed FP64 product unless CPHIFI_F64_STREAMK says otherwise.
+constexpr bool kF64StreamKDefault = false;
+
 GemmPlan make_gemm_plan(Elt elt, bool trans, int64_t n, int r, int mw, int s, int ksplit_req,
                         int num_cu) {
   GemmPlan gp;
@@ -317,6 +408,33 @@ GemmPlan make_gemm_plan(Elt elt, bool trans, int64_t n, int r, int mw, int s, in
   kper = (kper + bk - 1) / bk * bk;
   gp.kper = kper;
   gp.ksplit = (int)((n + kper - 1) / kper);
+  // Stream-K for the transposed FP64 4x4x4 tile when the split-K grid leaves
+  // resident slots idle (CPHIFI_F64_STREAMK=0 / 1 forces it off / on).
+  const bool x4 = elt == Elt::F64 && trans && ((mw == 4 && s == 2) || (mw == 2 && s == 4) ||
+                                              (mw == 1 && s == 8));
+  if (x4 && ksplit_req <= 0) {
+    const char* env = std::getenv("CPHIFI_F64_STREAMK");
+    const int occ = gemm_occupancy(elt, trans, mw, s, r);
+    const int64_t slots = (int64_t)(num_cu > 0 ? num_cu : 256) * occ;
+    const int64_t grid = nrowblk * gp.ksplit;
+    const bool want = env != nullptr ? std::atoi(env) != 0 : kF64StreamKDefault;
+    const int64_t nch = (n + bk - 1) / bk;
+    const int64_t T = nrowblk * nch;
+    if (want && grid < slots && T >= slots) {
+      const int64_t W = slots;
+      int ksp = 1;
+      for (int64_t b = 0; b < nrowblk; ++b) {
+        const int64_t wf = ((b * nch + 1) * W - 1) / T;
+        const int64_t wl = (((b + 1) * nch) * W - 1) / T;
+        ksp = std::max<int>(ksp, (int)(wl - wf + 1));
+      }
+      if (ksp <= kMaxSplit) {
+        gp.sk = (int)W;
+        gp.ksplit = ksp;
+        gp.kper = nch * bk;
+      }
+    }
+  }
   return gp;
 }
 
@@ -413,6 +531,9 @@ GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu) {
 }
 
 static bool plan_ok(Elt elt, const GemmPlan& gp, int64_t n, int r) {
+  if (gp.sk > 0)
+    return elt == Elt::F64 && r >= 1 && r <= kMaxRank && n >= 1 && gp.ksplit >= 1 &&
+           gp.ksplit <= kMaxSplit && gemm_cfg_valid(elt, gp.mw, gp.s);
   return r >= 1 && r <= kMaxRank && n >= 1 && gp.ksplit >= 1 && gp.ksplit <= kMaxSplit &&
          gemm_cfg_valid(elt, gp.mw, gp.s) && gp.kper % gemm_bk(elt, gp.s) == 0 &&
          (int64_t)gp.ksplit * gp.kper >= n && (int64_t)(gp.ksplit - 1) * gp.kper < n;
@@ -439,6 +560,13 @@ int launch_gemm(Elt elt, bool trans, const GemmPlan& gp, const void* U, int64_t 
   g.kper = gp.kper;
   g.ldp = nb * 16;
   g.done = done;
+  if (elt == Elt::F64 && gp.sk > 0) {
+    if (!trans) {
+      set_error("launch_gemm: stream-K plan for the row-major product");
+      return CPHIFI_INVALID_ARG;
+    }
+    return dispatch_f64_sk(gp, f64_groups(r), g, st);
+  }
   if (elt == Elt::F64)
     return trans ? dispatch_cfg_f64<true>(gp.mw, gp.s, f64_groups(r), g, gp.ksplit, st)
                  : dispatch_cfg_f64<false>(gp.mw, gp.s, f64_groups(r), g, gp.ksplit, st);

@@ -295,11 +295,14 @@ constexpr int k4x4_lds_elems() {
   return 2 * (4 * S) * (4 * NC4 + 16 / S);
 }
 
-// NT: the n x n operand's loads carry the non-temporal hint (it is streamed
-// once per product; 1.59 -> 1.54 ms at n = 30658, r = 40).
+// Rows [bx*tile_rows(MW), ...) over k in [kbeg, kend) (kbeg a multiple of
+// 4 S) into partial slab `slab`.  NT: the n x n operand's loads carry the
+// non-temporal hint (it is streamed once per product; 1.59 -> 1.54 ms at
+// n = 30658, r = 40).
 template <int NC4, int MW, int S, bool TRANS, int VW, bool NT = false>
-__device__ __forceinline__ void gemm_f64x4_tile(const GArgs& g, int64_t bx, int64_t by,
-                                                double* xs, int tid) {
+__device__ __forceinline__ void gemm_f64x4_tile(const GArgs& g, int64_t bx, int64_t kbeg,
+                                                int64_t kend, int64_t slab, double* xs,
+                                                int tid) {
   typedef double VecT __attribute__((ext_vector_type(VW)));
   static_assert(S % VW == 0, "S must be a multiple of the vector width");
   constexpr int BK = 4 * S;
@@ -316,8 +319,6 @@ __device__ __forceinline__ void gemm_f64x4_tile(const GArgs& g, int64_t bx, int6
   const int64_t n = g.n;
   const int64_t ldu = g.ldu;
   const int64_t mbase = bx * (4 * MW * 16) + (int64_t)wave * (MW * 16);
-  const int64_t kbeg = by * g.kper;
-  const int64_t kend = min(n, kbeg + g.kper);
   const double* __restrict__ U = (const double*)g.U;
 
   const double* abase[MW];
@@ -465,7 +466,7 @@ __device__ __forceinline__ void gemm_f64x4_tile(const GArgs& g, int64_t bx, int6
     }
   }
 
-  double* part = (double*)g.part + by * n * g.ldp;
+  double* part = (double*)g.part + slab * n * g.ldp;
 #pragma unroll
   for (int mb = 0; mb < MW; ++mb) {
     const int64_t row = mbase + mb * 16 + orow;

@@ -41,14 +41,14 @@ inline int64_t eff_ldk(const cphifi_ui_desc& d) { return d.ldk > 0 ? d.ldk : d.n
 // Plans of this size or larger keep a transposed copy of U_K (see
 // CPHIFI_FLAG_NO_UKT_COPY).
 constexpr int64_t kUktMinN = 4096;
-// FP64 plans whose whole PCG fits one persistent workgroup (small.hip); they
+// FP64 plans that asked for the persistent PCG (small.hip) and fit it; they
 // keep the copy of U_K too (all products of that kernel read the transposed
 // layout) and the time index of every observation.
 inline bool small_plan(const cphifi_ui_desc& d) {
-  constexpr int32_t kOff = CPHIFI_FLAG_EIGENBASIS | CPHIFI_FLAG_MULTI_KERNEL |
-                           CPHIFI_FLAG_TOEPLITZ_K | CPHIFI_FLAG_FIBER_COLLAPSE |
-                           CPHIFI_FLAG_NO_UKT_COPY | CPHIFI_FLAG_TIME_KERNELS;
-  return d.precision == CPHIFI_FP64 && !(d.flags & kOff) &&
+  constexpr int32_t kOff = CPHIFI_FLAG_EIGENBASIS | CPHIFI_FLAG_TOEPLITZ_K |
+                           CPHIFI_FLAG_FIBER_COLLAPSE | CPHIFI_FLAG_NO_UKT_COPY |
+                           CPHIFI_FLAG_TIME_KERNELS;
+  return d.precision == CPHIFI_FP64 && (d.flags & CPHIFI_FLAG_PERSISTENT) && !(d.flags & kOff) &&
          small_path_fits(d.n, (int)d.r, d.q, (int64_t)kMaxSplit * d.n * round_up(d.r, 16));
 }
 inline bool keeps_ukt(const cphifi_ui_desc& d) {

@@ -1169,6 +1169,9 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     p->fidx = (int32_t*)(ws + L.fidx);
     p->fgram = (double*)(ws + L.fgram);
     if ((rc = up(p->fptr, fptr)) || (rc = up(p->fidx, fidx))) return fail(rc);
+    // G = B^T B now (the operator may be applied before any setup), and again
+    // at every setup (B may change between solves)
+    if ((rc = launch_fiber_gram(in->B, d->J, (int)d->r, p->fgram, st))) return fail(rc);
   }
   if (d->flags & CPHIFI_FLAG_TOEPLITZ_K) {
     // c = the first row of K; the plan is refused unless every entry of K is

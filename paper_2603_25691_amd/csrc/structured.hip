@@ -17,8 +17,7 @@
 //        sum_j <Xhat(s,:), A(i,:) had B(j,:)> (A(i,:) had B(j,:))
 //          = A(i,:) had ((Xhat(s,:) had A(i,:)) G),
 //    r^2 work per fiber instead of 2 J r per fiber, and no per-observation
-//    indices are read.  One workgroup per time point; its four waves take
-//    the fibers in turn and their sums are added in a fixed order.
+//    indices are read.  One wave per time point, its fibers in order.
 #include "cphifi_internal.h"
 
 #include <cmath>
@@ -118,7 +117,8 @@ __global__ void fiber_gram_kernel(const double* __restrict__ B, int64_t J, int r
 
 // Y1(s,:) = sum over the fibers f of time s of A(i_f,:) had ((Xhat(s,:) had A(i_f,:)) G),
 // Xhat(s,:) from the split-K partials of K P (PT) or from xin; written to
-// xhat_out when given.
+// xhat_out when given.  One wave per time point (lane c = column c), its
+// fibers in list order; G in LDS, the product (u G) by lane broadcasts.
 template <typename PT>
 __global__ __launch_bounds__(256) void fiber_gather_kernel(
     const PT* __restrict__ part, int ksplit, int ldp, const double* __restrict__ xin, int64_t n,
@@ -127,36 +127,30 @@ __global__ __launch_bounds__(256) void fiber_gather_kernel(
     double* __restrict__ y1, const int32_t* done) {
   if (structured_done(done)) return;
   __shared__ double Gs[kMaxRank * kMaxRank];
-  __shared__ double xsh[kMaxRank];
-  __shared__ double red[4][kMaxRank];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
   for (int e = tid; e < r * r; e += 256) Gs[e] = G[e];
-  for (int64_t s = blockIdx.x; s < n; s += gridDim.x) {
-    __syncthreads();  // Gs ready; xsh / red of the previous row consumed
-    if (tid < r) {
-      double x;
+  __syncthreads();
+  const bool on = lane < r;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + (tid >> 6); s < n; s += nwaves) {
+    double x = 0.0;
+    if (on) {
       if (part != nullptr) {
-        x = 0.0;
-        for (int k = 0; k < ksplit; ++k) x += (double)part[((int64_t)k * n + s) * ldp + tid];
+        for (int k = 0; k < ksplit; ++k) x += (double)part[((int64_t)k * n + s) * ldp + lane];
       } else {
-        x = xin[s * r + tid];
+        x = xin[s * r + lane];
       }
-      xsh[tid] = x;
-      if (xhat_out != nullptr) xhat_out[s * r + tid] = x;
+      if (xhat_out != nullptr) xhat_out[s * r + lane] = x;
     }
-    __syncthreads();
-    const double xl = lane < r ? xsh[lane] : 0.0;
     double acc = 0.0;
-    for (int32_t f = fib_ptr[s] + wave; f < fib_ptr[s + 1]; f += 4) {
-      const double a = lane < r ? A[(int64_t)fib_i[f] * r + lane] : 0.0;
-      const double u = xl * a;
+    for (int32_t f = fib_ptr[s]; f < fib_ptr[s + 1]; ++f) {
+      const double a = on ? A[(int64_t)fib_i[f] * r + lane] : 0.0;
+      const double u = x * a;
       double v = 0.0;
-      for (int cc = 0; cc < r; ++cc) v = fma(__shfl(u, cc, 64), lane < r ? Gs[cc * r + lane] : 0.0, v);
+      for (int cc = 0; cc < r; ++cc) v = fma(__shfl(u, cc, 64), on ? Gs[cc * r + lane] : 0.0, v);
       acc = fma(a, v, acc);
     }
-    if (lane < r) red[wave][lane] = acc;
-    __syncthreads();
-    if (tid < r) y1[s * r + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    if (on) y1[s * r + lane] = acc;
   }
 }
 
@@ -208,7 +202,7 @@ int launch_fiber_gather(const void* part, bool is_float, int ksplit, int ldp, co
     set_error("fiber gather: r = %d outside [1, %d]", r, kMaxRank);
     return CPHIFI_INVALID_ARG;
   }
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(n, 4096));
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, 2048));
   if (part != nullptr && is_float)
     hipLaunchKernelGGL(fiber_gather_kernel<float>, dim3(blocks), dim3(256), 0, st,
                        (const float*)part, ksplit, ldp, xin, n, r, fib_ptr, fib_i, A, G,

@@ -31,12 +31,15 @@ def _need(t: torch.Tensor, dtype, shape, name: str):
                          f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
 
-def kernel_eig(K: torch.Tensor):
+def kernel_eig(K: torch.Tensor, method: str = "divide_conquer", tol: float = 1e-14,
+               max_sweeps: int = 30):
     """One-time eigendecomposition of K on the device (library call).
 
     K: (n, ldk) storage with ldk >= n (row stride ldk).  Returns (UK, dK) with
     UK of the same storage shape holding eigenvector k in row k (the LAPACK
-    column-major order the ABI expects) and dK ascending.
+    column-major order the ABI expects) and dK ascending.  method:
+    "divide_conquer" (cphifi_kernel_eig) or "jacobi" (cphifi_kernel_eig_jacobi;
+    the sweep count is kept in kernel_eig.last_sweeps).
     """
     n, ldk = K.shape[0], K.shape[1]
     if ldk < n:
@@ -44,7 +47,13 @@ def kernel_eig(K: torch.Tensor):
     _need(K, torch.float64, (n, ldk), "K")
     UK = torch.empty_like(K)
     dK = torch.empty(n, dtype=torch.float64, device=K.device)
-    _c.cphifi_kernel_eig(n, K.data_ptr(), ldk, UK.data_ptr(), dK.data_ptr(), _stream())
+    if method == "jacobi":
+        kernel_eig.last_sweeps = _c.cphifi_kernel_eig_jacobi(
+            n, K.data_ptr(), ldk, UK.data_ptr(), dK.data_ptr(), tol, max_sweeps, _stream())
+    elif method == "divide_conquer":
+        _c.cphifi_kernel_eig(n, K.data_ptr(), ldk, UK.data_ptr(), dK.data_ptr(), _stream())
+    else:
+        raise ValueError(f"unknown eigensolver {method!r}")
     return UK, dK
 
 

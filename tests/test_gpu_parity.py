@@ -18,9 +18,9 @@ Tolerances
   tests/test_oracle_spread.py;
 * mixed-precision solves refined to relres 1e-7: e_KW <= 1e-6.
 
-The FP64 solves of the small cases run in one persistent workgroup unless
-FLAG_MULTI_KERNEL asks for the multi-kernel iteration; the solve and failure
-tests run both paths (`paths`), and one test compares them with each other.
+The FP64 solves run the launch loop unless FLAG_PERSISTENT asks for the
+single-workgroup iteration (small subproblems); the solve and failure tests run
+both paths (`paths`), and one test compares them with each other.
 """
 
 import numpy as np
@@ -72,14 +72,14 @@ def small_cases():
 
 CASES = small_cases()
 
-# FP64 iteration paths: the persistent single-workgroup loop (default for
-# small subproblems) and the multi-kernel loop.
+# FP64 iteration paths: the persistent single-workgroup loop (opt-in, small
+# subproblems) and the launch loop.
 PATHS = ["persistent", "multi"]
 
 
 @pytest.fixture(params=PATHS)
 def path_flags(request):
-    return 0 if request.param == "persistent" else C.FLAG_MULTI_KERNEL
+    return C.FLAG_PERSISTENT if request.param == "persistent" else 0
 
 
 @pytest.fixture(scope="module")
@@ -288,10 +288,10 @@ def test_persistent_and_multi_kernel_paths_agree(name, uploaded):
     solve's own accuracy of each other."""
     p, dp = uploaded(name)
     h1, h2 = np.zeros(600), np.zeros(600)
-    s1 = UISolver(dp, p.lam, p.rho, 1e-12)
+    s1 = UISolver(dp, p.lam, p.rho, 1e-12, flags=C.FLAG_PERSISTENT)
     W1, i1 = s1.solve_subproblem(history=h1)
     W1 = host(W1)
-    s2 = UISolver(dp, p.lam, p.rho, 1e-12, flags=C.FLAG_MULTI_KERNEL)
+    s2 = UISolver(dp, p.lam, p.rho, 1e-12)
     W2, i2 = s2.solve_subproblem(history=h2)
     assert i1.status == C.OK and i2.status == C.OK
     assert abs(i1.iters - i2.iters) <= 1

@@ -89,3 +89,20 @@ def test_product_rejects_bad_tiles_and_shapes():
     Ub = torch.zeros(40, 136, dtype=torch.bfloat16, device="cuda")  # tiled: stride % 64 != 0
     with pytest.raises(C.CphifiError):
         product(Ub, X, "bf16_tiled", False, (2, 4))
+
+
+@pytest.mark.parametrize("n,r", [(10300, 40), (12345, 5)])
+def test_fp64_stream_k_product(n, r, monkeypatch):
+    """The stream-K form of the transposed FP64 product (CPHIFI_F64_STREAMK=1;
+    used when the split-K grid leaves resident slots idle, which these sizes
+    do): every row against numpy, for each 4x4x4 tile shape."""
+    monkeypatch.setenv("CPHIFI_F64_STREAMK", "1")
+    U, X, scale = _case(n, r, n + r)
+    want = U.T @ (scale[:, None] * X)
+    Ud = torch.from_numpy(U).cuda()
+    Xd = torch.from_numpy(X).cuda()
+    sd = torch.from_numpy(scale).cuda()
+    for tile in [(4, 2), (2, 4), (1, 8)]:
+        gh = product(Ud, Xd, "fp64", True, tile, 0, sd).cpu().numpy()
+        rerr = np.max(np.linalg.norm(gh - want, axis=1) / np.linalg.norm(want, axis=1))
+        assert rerr <= 1e-12, (tile, rerr)
