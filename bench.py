@@ -54,7 +54,10 @@ BATCH_TILES = os.path.join(ROOT, "paper_2603_25691_amd", "tiles_batch_mi355x.txt
 # by a calibration copy (profiles/products_n30658_r40_hbm_counters.md).  Keyed
 # by kernel and shape; clear an entry whenever that kernel changes.
 MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2, true>", 30658, 40): 1.9480e9,
-                    ("gemm_f64_kernel<10, 4, 2, true, 1>", 30658, 40): 7.6937e9}
+                    ("gemm_f64_kernel<10, 4, 2, true, 1>", 30658, 40): 7.6591e9}
+# HBM bytes per launch of the batched kernel on the 64-member workload, from the
+# same two counters (profiles/c5_batch64_hbm_counters.md); clear on a change.
+BATCH_TRAFFIC = 2.339e11
 F64_KERNEL = "gemm_f64_kernel<10, 4, 2, true, 1>"
 BF16_KERNEL = "gemm_bf16_kernel<3, 4, 2, true>"
 # relative residual the mixed solves are refined to (e_KW within 1e-6), and
@@ -178,10 +181,11 @@ def bench_small(torch, C, steps: int):
            "n": p.n, "q": p.q, "r": p.r,
            "oracle_dense_ms": 1e3 * t_dense, "oracle_lstsq_ms": 1e3 * t_brute}
     timer = StepTimer(torch)
-    # fp64: the launch loop (one launch sequence per iteration, host poll every
-    # few iterations); fp64_persistent: the same solve in one persistent
-    # workgroup (CPHIFI_FLAG_PERSISTENT)
-    legs = (("fp64", "fp64", 1e-10, 0), ("fp64_persistent", "fp64", 1e-10, C.FLAG_PERSISTENT),
+    # fp64: replays of a captured graph of PCG iterations (the default at this
+    # size); fp64_launches: the launch-by-launch loop (CPHIFI_FLAG_NO_GRAPH);
+    # fp64_persistent: one persistent workgroup (CPHIFI_FLAG_PERSISTENT)
+    legs = (("fp64", "fp64", 1e-10, 0), ("fp64_launches", "fp64", 1e-10, C.FLAG_NO_GRAPH),
+            ("fp64_persistent", "fp64", 1e-10, C.FLAG_PERSISTENT),
             ("mixed_bf16", "mixed_bf16", MIXED_TOL, 0))
     for label, prec, tol, flags in legs:
         s = UISolver(dp, p.lam, p.rho, tol, precision=prec, flags=flags)
@@ -195,7 +199,8 @@ def bench_small(torch, C, steps: int):
                      "tol": tol}
         s.close()
     out["gpu_vs_oracle_dense"] = out["oracle_dense_ms"] / (out["fp64"]["us_per_solve"] / 1e3)
-    log(f"small: fp64 {out['fp64']['us_per_solve']:.0f} us (persistent workgroup "
+    log(f"small: fp64 {out['fp64']['us_per_solve']:.0f} us (launch loop "
+        f"{out['fp64_launches']['us_per_solve']:.0f} us, persistent workgroup "
         f"{out['fp64_persistent']['us_per_solve']:.0f} us), mixed "
         f"{out['mixed_bf16']['us_per_solve']:.0f} us per solve; oracle dense "
         f"{out['oracle_dense_ms']:.1f} ms, lstsq {out['oracle_lstsq_ms']:.1f} ms")
@@ -492,7 +497,8 @@ def bench_batch(a, torch, C):
         "mixed_vs_fp64_speedup": ms64 / ms_batch,
         "e_KW_vs_fp64_max": max(ekw),
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": gbps / HBM_PEAK_GBPS,
+                     "traffic": BATCH_TRAFFIC if len(probs) == 64 else None,
                      "kernel": "batch_kernel (whole batched solve, n x n passes only)",
                      "algorithmic_bytes": byts},
     }

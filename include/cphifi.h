@@ -112,6 +112,11 @@ enum cphifi_flags {
                                    otherwise); products then differ from the
                                    dense ones by at most that much.  Not with
                                    the batched solver */
+  CPHIFI_FLAG_NO_GRAPH = 1024,  /* FP64 paper form with n < 4096 normally replays
+                                   a HIP graph of 8 captured PCG iterations
+                                   (made on the plan's first solve; the host
+                                   checks convergence between replays); this
+                                   flag keeps the launch-by-launch loop */
   CPHIFI_FLAG_FIBER_COLLAPSE = 512 /* every (time, sample) pair that is observed
                                    at all is observed at all J features once:
                                    the gather-scatter of eqs. vl / yhat1 runs

@@ -41,6 +41,7 @@ FLAG_TIME_FP64 = 64
 FLAG_PERSISTENT = 128
 FLAG_TOEPLITZ_K = 256
 FLAG_FIBER_COLLAPSE = 512
+FLAG_NO_GRAPH = 1024
 
 PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 

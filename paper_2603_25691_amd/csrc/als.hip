@@ -356,7 +356,8 @@ int cphifi_als_run(cphifi_als* a, double* const* W, double* const* F, cphifi_als
       if (rc == CPHIFI_NOT_CONVERGED) {
         ++info->capped;  // the iteration cap of the paper's runs: keep going
       } else if (rc != CPHIFI_OK) {
-        set_error("als: outer iteration %d, mode %d: subproblem status %d", it, k, rc);
+        const std::string why = cphifi_last_error();
+        set_error("als: outer iteration %d, mode %d: %s", it, k, why.c_str());
         return rc;
       }
       info->inner_iters += si.iters;

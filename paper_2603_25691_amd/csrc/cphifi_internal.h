@@ -93,6 +93,9 @@ struct DevScalars {
   int32_t iters;  // iterations completed when done was set
   int32_t status; // CPHIFI_* decided on the device
   int32_t zero;   // always 0: "not done" flag for kernels run outside a PCG loop
+  int32_t it;     // iteration counter of a captured PCG loop (kernels given it < 0
+                  // read it; the convergence check advances it)
+  int32_t pad;
 };
 
 // Element type of the eigenvector / kernel matrix operand of a product.
@@ -260,7 +263,7 @@ int launch_fiber_gram(const double* B, int64_t J, int r, double* G, hipStream_t 
 int launch_fiber_gather(const void* part, bool is_float, int ksplit, int ldp, const double* xin,
                         int64_t n, int r, const int32_t* fib_ptr, const int32_t* fib_i,
                         const double* A, const double* G, double* xhat_out, double* y1,
-                        const int32_t* done, hipStream_t st);
+                        int max_fibers, const int32_t* done, hipStream_t st);
 int launch_fill(double* dst, double v, int64_t len, hipStream_t st);
 int launch_fill_i32(int32_t* dst, int32_t v, int64_t len, hipStream_t st);
 int launch_gram(const double* A, int64_t I, const double* B, int64_t J, int r, double* V,

@@ -64,6 +64,7 @@ Layout make_layout(const cphifi_ui_desc& d);
 using namespace cphifi;  // the plan is a global type behind the C ABI
 
 constexpr int kPollRing = 16;  // PCG iterations the host may enqueue ahead
+constexpr int64_t kGraphMaxN = 4096;  // FP64 plans below this n replay captured iterations
 constexpr int kNoWork = -2;    // timing tag of a launch issued after convergence
 
 struct cphifi_plan {
@@ -98,7 +99,9 @@ struct cphifi_plan {
   int32_t* fptr = nullptr;     // FLAG_FIBER_COLLAPSE: fibers of time s are
   int32_t* fidx = nullptr;     //   fidx[fptr[s] .. fptr[s+1]) (their sample index)
   double* fgram = nullptr;     //   and G = B^T B
+  int32_t fmax = 0;            //   most fibers at one time point
   int32_t* obst = nullptr;     // small plans: time index of every observation
+  hipGraphExec_t pcg_graph = nullptr;  // captured FP64 PCG iterations (paper form)
   GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
   int last_ksplit = 1;  // split-K depth of the partials the last product wrote
   DevScalars* h_sc = nullptr;  // host mirror (mapped, coherent) ...

@@ -250,7 +250,7 @@ int obs_gather(cphifi_plan* p, Elt elt, double* xhat, double* out, const int32_t
     }
     return launch_fiber_gather(p->part, elt != Elt::F64, ksplit_of(p, elt), p->ldp, nullptr,
                                p->n, (int)p->r, p->fptr, p->fidx, p->in.A, p->fgram, xhat, out,
-                               done, p->st);
+                               p->fmax, done, p->st);
   }
   ObsArgs a{};
   a.n = p->n;
@@ -384,11 +384,25 @@ int check_every(const cphifi_plan* p) {
 // over after convergence return at once.
 // fused_eig: the preconditioner is the eigenbasis one (op_precond_eig); the
 // iteration then runs the x/r update and the preconditioner as one kernel.
+// graph: the iterations run as replays of a HIP graph that holds
+// kGraphIters captured iterations (built on first use and kept in the plan);
+// the kernels then take the iteration index from the device counter, and x
+// lives in the plan's V_XB (the graph's pointers must not change between
+// solves), copied from / to the caller's x around the loop.
+constexpr int kGraphIters = 8;
+
 int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double* b, double* x,
             bool have_x0, double tol, int maxit, const PcgVecs& v, DevScalars* sc,
-            double* hist, int hist_len, PcgOut* out, bool fused_eig = false) {
+            double* hist, int hist_len, PcgOut* out, bool fused_eig = false,
+            bool graph = false) {
   const int64_t len = p->n * p->r;
   hipStream_t st = p->st;
+  const hipStream_t st_caller = st;
+  double* x_user = x;
+  if (graph) {
+    x = p->vec[V_XB];
+    if (have_x0) TRY(launch_copy(x, x_user, len, st));
+  }
   int nb_bb = 0, nb_rr = 0, nb_rz = 0, nb_pq = 0;
   double* red0 = p->red[0];
   double* red1 = p->red[1];
@@ -409,7 +423,68 @@ int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double
   const int every = check_every(p);
   *(volatile int32_t*)p->h_flag = 0;
   const size_t first_pair = p->ev_used / 2;
-  for (int it = 0; it < maxit; ++it) {
+  int it0 = 0;  // first iteration the loop below runs (after the graph replays)
+  if (graph) {
+    if (p->pcg_graph == nullptr) {
+      // Capture kGraphIters iterations with device-counted iteration indices,
+      // on a private stream (the caller's may be the null stream, which
+      // cannot be captured); replays go to the caller's stream.
+      hipGraph_t g = nullptr;
+      hipStream_t cap = nullptr;
+      CPHIFI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      if (hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        set_error("PCG graph: hipStreamBeginCapture failed");
+        return CPHIFI_HIP_ERROR;
+      }
+      p->st = cap;
+      st = cap;
+      int rc = CPHIFI_OK;
+      for (int k = 0; k < kGraphIters && rc == CPHIFI_OK; ++k) {
+        if ((rc = apply(v.P, v.Q, red0, &nb_pq, &sc->done)) != CPHIFI_OK ||
+            (rc = launch_update_xr(x, v.R, v.P, v.Q, len, red0, nb_pq, red1, &nb_rr, sc, -1,
+                                   st)) != CPHIFI_OK ||
+            (rc = launch_check_conv(red1, nb_rr, sc, -1, hist, hist_len, p->d_flag, st)) !=
+                CPHIFI_OK ||
+            (rc = precond(v.R, v.Z, red2, &nb_rz, &sc->done)) != CPHIFI_OK)
+          break;
+        rc = launch_update_p(v.P, v.Z, len, red2, nb_rz, sc, -1, st);
+      }
+      const hipError_t ec = hipStreamEndCapture(cap, &g);
+      p->st = st = st_caller;
+      (void)hipStreamDestroy(cap);
+      if (rc != CPHIFI_OK || ec != hipSuccess ||
+          hipGraphInstantiateWithFlags(&p->pcg_graph, g, 0) != hipSuccess) {
+        if (g != nullptr) (void)hipGraphDestroy(g);
+        p->pcg_graph = nullptr;
+        if (rc == CPHIFI_OK) set_error("PCG graph capture failed");
+        return rc != CPHIFI_OK ? rc : CPHIFI_HIP_ERROR;
+      }
+      (void)hipGraphDestroy(g);
+    }
+    // Replays, one ahead of the host's check of the convergence flag.
+    int launched = 0;
+    bool stop = false;
+    while (it0 + kGraphIters <= maxit) {
+      CPHIFI_HIP(hipGraphLaunch(p->pcg_graph, st));
+      CPHIFI_HIP(hipEventRecord(p->pev[launched % kPollRing], st));
+      ++launched;
+      it0 += kGraphIters;
+      if (launched >= 2) {
+        CPHIFI_HIP(hipEventSynchronize(p->pev[(launched - 2) % kPollRing]));
+        if (*(volatile int32_t*)p->h_flag) {
+          stop = true;
+          break;
+        }
+      }
+    }
+    if (!stop && launched > 0) {
+      CPHIFI_HIP(hipEventSynchronize(p->pev[(launched - 1) % kPollRing]));
+      stop = *(volatile int32_t*)p->h_flag != 0;
+    }
+    if (stop) it0 = maxit;  // done: the loop below runs nothing
+  }
+  for (int it = it0; it < maxit; ++it) {
     p->cur_tag = 2 * it;
     TRY(apply(v.P, v.Q, red0, &nb_pq, &sc->done));
     if (fused_eig) {
@@ -421,7 +496,7 @@ int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double
     }
     TRY(launch_check_conv(red1, nb_rr, sc, it, hist, hist_len, p->d_flag, st));
     CPHIFI_HIP(hipEventRecord(p->pev[it % kPollRing], st));
-    if (it >= every) {
+    if (it - it0 >= every) {
       CPHIFI_HIP(hipEventSynchronize(p->pev[(it - every) % kPollRing]));
       if (*(volatile int32_t*)p->h_flag) break;
     }
@@ -431,6 +506,7 @@ int run_pcg(cphifi_plan* p, const OpFn& apply, const OpFn& precond, const double
     TRY(launch_update_p(v.P, v.Z, len, red2, nb_rz, sc, it, st));
   }
   p->cur_tag = -1;
+  if (graph) TRY(launch_copy(x_user, x, len, st));
   TRY(poll(p, sc));
   const DevScalars& h = *p->h_sc;
   out->iters = h.done ? h.iters : maxit;
@@ -576,9 +652,12 @@ int solve_fp64(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* in
     OpFn M = [p](const double* x, double* z, double* red, int* nb, const int32_t* done) {
       return op_precond_paper(p, x, z, red, nb, done);
     };
+    // Small plans replay captured iterations: there the launches, not the
+    // kernels, set the iteration time.
+    const bool graph = p->n < kGraphMaxN && !p->timing && !(p->d.flags & CPHIFI_FLAG_NO_GRAPH);
     TRY(run_pcg(p, A, M, b, W, warm, p->d.tol, maxit,
                 PcgVecs{p->vec[V_R], p->vec[V_Z], p->vec[V_P], p->vec[V_Q]}, p->sc, p->hist,
-                p->L.hist_len, &o));
+                p->L.hist_len, &o, false, graph));
   }
   info->iters = o.iters;
   info->refine_steps = 0;
@@ -995,6 +1074,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   // at each of the J features exactly once.  Fibers of a time point are listed
   // in ascending sample order (a fixed summation order).
   std::vector<int32_t> fptr, fidx;
+  int32_t fmax = 0;
   if (d->flags & CPHIFI_FLAG_FIBER_COLLAPSE) {
     const int64_t J = d->J;
     fptr.assign(n + 1, 0);
@@ -1025,6 +1105,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
       }
       for (int32_t l = ptr[s]; l < ptr[s + 1]; ++l) seen[(size_t)oi[l] * J + oj[l]] = 0;
       fptr[s + 1] = (int32_t)fidx.size();
+      fmax = std::max<int32_t>(fmax, fptr[s + 1] - fptr[s]);
     }
     if ((int64_t)fidx.size() > q / J + 1) {
       set_error("internal: fiber list exceeds its bound");
@@ -1168,6 +1249,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     p->fptr = (int32_t*)(ws + L.fptr);
     p->fidx = (int32_t*)(ws + L.fidx);
     p->fgram = (double*)(ws + L.fgram);
+    p->fmax = fmax;
     if ((rc = up(p->fptr, fptr)) || (rc = up(p->fidx, fidx))) return fail(rc);
     // G = B^T B now (the operator may be applied before any setup), and again
     // at every setup (B may change between solves)
@@ -1388,6 +1470,7 @@ int cphifi_ui_solve_subproblem(cphifi_plan* p, const double* y, double* W,
 int cphifi_ui_plan_destroy(cphifi_plan* p) {
   clear_error();
   if (p == nullptr) return CPHIFI_OK;
+  if (p->pcg_graph != nullptr) (void)hipGraphExecDestroy(p->pcg_graph);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   release_host(p);
   delete p;

@@ -17,7 +17,8 @@
 //        sum_j <Xhat(s,:), A(i,:) had B(j,:)> (A(i,:) had B(j,:))
 //          = A(i,:) had ((Xhat(s,:) had A(i,:)) G),
 //    r^2 work per fiber instead of 2 J r per fiber, and no per-observation
-//    indices are read.  One wave per time point, its fibers in order.
+//    indices are read.  A wave per time point when time points have few
+//    fibers, a workgroup per time point when they have many.
 #include "cphifi_internal.h"
 
 #include <cmath>
@@ -27,6 +28,8 @@ namespace {
 
 constexpr int kTRows = 64;  // rows of K per Toeplitz workgroup
 constexpr int kTK = 64;     // k per staged chunk
+// Time points with at most this many fibers get one wave each; more, one workgroup.
+constexpr int kFibersPerWave = 8;
 
 __device__ __forceinline__ bool structured_done(const int32_t* done) {
   return done != nullptr && *(volatile const int32_t*)done != 0;
@@ -117,9 +120,13 @@ __global__ void fiber_gram_kernel(const double* __restrict__ B, int64_t J, int r
 
 // Y1(s,:) = sum over the fibers f of time s of A(i_f,:) had ((Xhat(s,:) had A(i_f,:)) G),
 // Xhat(s,:) from the split-K partials of K P (PT) or from xin; written to
-// xhat_out when given.  One wave per time point (lane c = column c), its
-// fibers in list order; G in LDS, the product (u G) by lane broadcasts.
-template <typename PT>
+// xhat_out when given.  Lane c holds column c; G in LDS; u G by lane
+// broadcasts.  Two forms: WAVE = one wave per time point (few fibers per time
+// point, e.g. one: the unaligned recipes), else one workgroup per time point
+// whose four waves take the fibers in turn, their sums added in a fixed order
+// (many fibers per time point: the aligned case's I = 500 per grid point, where
+// a wave per time point left the chip nearly idle).
+template <typename PT, bool WAVE>
 __global__ __launch_bounds__(256) void fiber_gather_kernel(
     const PT* __restrict__ part, int ksplit, int ldp, const double* __restrict__ xin, int64_t n,
     int r, const int32_t* __restrict__ fib_ptr, const int32_t* __restrict__ fib_i,
@@ -127,12 +134,14 @@ __global__ __launch_bounds__(256) void fiber_gather_kernel(
     double* __restrict__ y1, const int32_t* done) {
   if (structured_done(done)) return;
   __shared__ double Gs[kMaxRank * kMaxRank];
-  const int tid = threadIdx.x, lane = tid & 63;
+  __shared__ double red[4][kMaxRank];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < r * r; e += 256) Gs[e] = G[e];
   __syncthreads();
   const bool on = lane < r;
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t s = (int64_t)blockIdx.x * 4 + (tid >> 6); s < n; s += nwaves) {
+  const int64_t first = WAVE ? (int64_t)blockIdx.x * 4 + wave : blockIdx.x;
+  const int64_t step = WAVE ? (int64_t)gridDim.x * 4 : gridDim.x;
+  for (int64_t s = first; s < n; s += step) {
     double x = 0.0;
     if (on) {
       if (part != nullptr) {
@@ -140,17 +149,24 @@ __global__ __launch_bounds__(256) void fiber_gather_kernel(
       } else {
         x = xin[s * r + lane];
       }
-      if (xhat_out != nullptr) xhat_out[s * r + lane] = x;
+      if (xhat_out != nullptr && (WAVE || wave == 0)) xhat_out[s * r + lane] = x;
     }
     double acc = 0.0;
-    for (int32_t f = fib_ptr[s]; f < fib_ptr[s + 1]; ++f) {
+    for (int32_t f = fib_ptr[s] + (WAVE ? 0 : wave); f < fib_ptr[s + 1]; f += (WAVE ? 1 : 4)) {
       const double a = on ? A[(int64_t)fib_i[f] * r + lane] : 0.0;
       const double u = x * a;
       double v = 0.0;
       for (int cc = 0; cc < r; ++cc) v = fma(__shfl(u, cc, 64), on ? Gs[cc * r + lane] : 0.0, v);
       acc = fma(a, v, acc);
     }
-    if (on) y1[s * r + lane] = acc;
+    if (WAVE) {
+      if (on) y1[s * r + lane] = acc;
+    } else {
+      if (on) red[wave][lane] = acc;
+      __syncthreads();
+      if (tid < r) y1[s * r + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+      __syncthreads();
+    }
   }
 }
 
@@ -197,20 +213,30 @@ int launch_fiber_gram(const double* B, int64_t J, int r, double* G, hipStream_t 
 int launch_fiber_gather(const void* part, bool is_float, int ksplit, int ldp, const double* xin,
                         int64_t n, int r, const int32_t* fib_ptr, const int32_t* fib_i,
                         const double* A, const double* G, double* xhat_out, double* y1,
-                        const int32_t* done, hipStream_t st) {
+                        int max_fibers, const int32_t* done, hipStream_t st) {
   if (r < 1 || r > kMaxRank) {
     set_error("fiber gather: r = %d outside [1, %d]", r, kMaxRank);
     return CPHIFI_INVALID_ARG;
   }
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 3) / 4, 2048));
-  if (part != nullptr && is_float)
-    hipLaunchKernelGGL(fiber_gather_kernel<float>, dim3(blocks), dim3(256), 0, st,
-                       (const float*)part, ksplit, ldp, xin, n, r, fib_ptr, fib_i, A, G,
-                       xhat_out, y1, done);
-  else
-    hipLaunchKernelGGL(fiber_gather_kernel<double>, dim3(blocks), dim3(256), 0, st,
-                       (const double*)part, ksplit, ldp, xin, n, r, fib_ptr, fib_i, A, G,
-                       xhat_out, y1, done);
+  const bool wave = max_fibers <= kFibersPerWave;
+  const int64_t units = wave ? (n + 3) / 4 : n;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(units, 2048));
+#define CPHIFI_FIBER_LAUNCH(PT, W)                                                            \
+  hipLaunchKernelGGL((fiber_gather_kernel<PT, W>), dim3(blocks), dim3(256), 0, st,            \
+                     (const PT*)part, ksplit, ldp, xin, n, r, fib_ptr, fib_i, A, G, xhat_out, \
+                     y1, done)
+  if (part != nullptr && is_float) {
+    if (wave)
+      CPHIFI_FIBER_LAUNCH(float, true);
+    else
+      CPHIFI_FIBER_LAUNCH(float, false);
+  } else {
+    if (wave)
+      CPHIFI_FIBER_LAUNCH(double, true);
+    else
+      CPHIFI_FIBER_LAUNCH(double, false);
+  }
+#undef CPHIFI_FIBER_LAUNCH
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }

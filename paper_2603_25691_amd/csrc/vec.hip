@@ -122,6 +122,7 @@ __global__ __launch_bounds__(256) void update_xr_kernel(double* x, double* r, co
                                                         const double* red_pq, int nblk_pq,
                                                         double* red_rr, DevScalars* sc, int it) {
   if (sc->done) return;
+  if (it < 0) it = sc->it;  // captured loop: the device counter
   const double pq = sum_partials(red_pq, nblk_pq);
   const double rz = sc->rz[it & 1];
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
@@ -155,6 +156,8 @@ __global__ __launch_bounds__(256) void check_conv_kernel(const double* red_rr, i
     if (flag != nullptr && threadIdx.x == 0) *(volatile int32_t*)flag = 1;
     return;
   }
+  const bool counted = it < 0;  // captured loop: read and advance the device counter
+  if (counted) it = sc->it;
   const double rr = sum_partials(red_rr, nblk);
   if (threadIdx.x == 0) {
     sc->rr = rr;
@@ -170,6 +173,7 @@ __global__ __launch_bounds__(256) void check_conv_kernel(const double* red_rr, i
       sc->done = done = 1;
     }
     if (flag != nullptr) *(volatile int32_t*)flag = done;
+    if (counted) sc->it = it + 1;
   }
 }
 
@@ -178,6 +182,7 @@ __global__ __launch_bounds__(256) void update_p_kernel(double* p, const double* 
                                                        const double* red_rz, int nblk,
                                                        DevScalars* sc, int it) {
   if (sc->done) return;
+  if (it < 0) it = sc->it - 1;  // captured loop: the check of this iteration advanced it
   const double rz_new = sum_partials(red_rz, nblk);
   const double rz_old = sc->rz[it & 1];
   if (!(rz_new > 0.0) || !isfinite(rz_new)) {
@@ -214,6 +219,7 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(DevScalars* sc, const dou
     sc->status = CPHIFI_OK;
     sc->done = 0;
     sc->zero = 0;
+    sc->it = 0;
     if (hist != nullptr && hist_len > 0) hist[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz)) {
       sc->status = CPHIFI_NUMERIC;
@@ -280,6 +286,7 @@ __global__ __launch_bounds__(256) void prec_mid_mfma_kernel(const PT* part, int 
   if (UPD ? u.sc->done != 0 : is_done(done)) return;
   double alpha = 0.0;
   if (UPD) {  // as update_xr_kernel
+    if (u.it < 0) u.it = u.sc->it;  // captured loop: the device counter
     const double pq = sum_partials(u.red_pq, u.nblk_pq);
     const double rz = u.sc->rz[u.it & 1];
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
@@ -444,15 +451,39 @@ __global__ void fill_i32_kernel(int32_t* dst, int32_t v, int64_t len) {
 // modes' factors (Section 3, reused in Section 4.4.2).  One thread per entry
 // of the upper triangle, each summed in a fixed order (gram_entry, shared with
 // the batched solver's setup phase).
+// V = (A^T A) had (B^T B): one workgroup per entry (a <= b); thread t adds
+// rows t, t + 256, ... and the partial sums meet in a fixed order.  (One thread
+// per entry, summing all I + J rows in sequence, took 0.35 ms at I = 1000,
+// J = 200, r = 40: a chain of dependent loads per thread.)
 __global__ __launch_bounds__(256) void gram_kernel(const double* A, int64_t I, const double* B,
                                                    int64_t J, int r, double* V) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= r * r) return;
-  const int a = e / r, b = e % r;
-  if (a > b) return;
-  const double v = gram_entry(A, I, B, J, r, a, b);
-  V[a * r + b] = v;
-  V[b * r + a] = v;
+  __shared__ double red[2][4];
+  // blockIdx.x enumerates the upper triangle row by row
+  int a = 0, rem = blockIdx.x;
+  while (rem >= r - a) {
+    rem -= r - a;
+    ++a;
+  }
+  const int b = a + rem;
+  double ga = 0.0, gb = 0.0;
+  for (int64_t i = threadIdx.x; i < I; i += 256) ga += A[i * r + a] * A[i * r + b];
+  for (int64_t j = threadIdx.x; j < J; j += 256) gb += B[j * r + a] * B[j * r + b];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    ga += __shfl_xor(ga, off, 64);
+    gb += __shfl_xor(gb, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = ga;
+    red[1][threadIdx.x >> 6] = gb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double v = (((red[0][0] + red[0][1]) + red[0][2]) + red[0][3]) *
+                     (((red[1][0] + red[1][1]) + red[1][2]) + red[1][3]);
+    V[a * r + b] = v;
+    V[b * r + a] = v;
+  }
 }
 
 // Eigendecomposition of the r x r Gram V (eq. eigV) by one workgroup
@@ -698,7 +729,7 @@ int launch_fill_i32(int32_t* dst, int32_t v, int64_t len, hipStream_t st) {
 
 int launch_gram(const double* A, int64_t I, const double* B, int64_t J, int r, double* V,
                 hipStream_t st) {
-  hipLaunchKernelGGL(gram_kernel, dim3((r * r + 255) / 256), dim3(256), 0, st, A, I, B, J, r, V);
+  hipLaunchKernelGGL(gram_kernel, dim3(r * (r + 1) / 2), dim3(256), 0, st, A, I, B, J, r, V);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }

@@ -18,9 +18,10 @@ Tolerances
   tests/test_oracle_spread.py;
 * mixed-precision solves refined to relres 1e-7: e_KW <= 1e-6.
 
-The FP64 solves run the launch loop unless FLAG_PERSISTENT asks for the
-single-workgroup iteration (small subproblems); the solve and failure tests run
-both paths (`paths`), and one test compares them with each other.
+The FP64 solves of small plans replay a captured HIP graph of PCG iterations
+(FLAG_NO_GRAPH keeps the launch-by-launch loop; FLAG_PERSISTENT runs the
+single-workgroup iteration instead); the solve and failure tests run all three
+paths (`paths`), and two tests compare them with each other.
 """
 
 import numpy as np
@@ -72,14 +73,15 @@ def small_cases():
 
 CASES = small_cases()
 
-# FP64 iteration paths: the persistent single-workgroup loop (opt-in, small
-# subproblems) and the launch loop.
-PATHS = ["persistent", "multi"]
+# FP64 iteration paths: graph replays (the default for small plans), the
+# launch-by-launch loop, and the persistent single-workgroup loop.
+PATHS = ["graph", "launches", "persistent"]
 
 
 @pytest.fixture(params=PATHS)
 def path_flags(request):
-    return C.FLAG_PERSISTENT if request.param == "persistent" else 0
+    return {"graph": 0, "launches": C.FLAG_NO_GRAPH,
+            "persistent": C.FLAG_PERSISTENT}[request.param]
 
 
 @pytest.fixture(scope="module")
@@ -279,6 +281,26 @@ def test_fp64_history_is_monotone_tail_and_matches_oracle(uploaded, path_flags):
     # the early residual history is insensitive to rounding
     assert np.allclose(got[:10], want[:10], rtol=1e-6)
     assert got[info.iters] <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged-r3", "ragged-r17", "c1-drop"])
+def test_graph_and_launch_loop_are_bitwise_equal(name, uploaded):
+    """The graph replays the same kernels in the same order: identical W,
+    iteration count and history, on the plan's first solve (which captures the
+    graph) and on a second solve of the same plan (which replays it)."""
+    p, dp = uploaded(name)
+    outs = []
+    for flags in (0, C.FLAG_NO_GRAPH):
+        s = UISolver(dp, p.lam, p.rho, 1e-12, flags=flags)
+        for _ in range(2):
+            h = np.zeros(600)
+            W, info = s.solve_subproblem(history=h)
+            assert info.status == C.OK, info.as_dict()
+            outs.append((host(W), info.iters, h[: info.iters + 1].copy()))
+        s.close()
+    W0, i0, h0 = outs[0]
+    for Wk, ik, hk in outs[1:]:
+        assert ik == i0 and np.array_equal(Wk, W0) and np.array_equal(hk, h0)
 
 
 @pytest.mark.parametrize("name", ["c1", "ragged-r3", "ragged-r17", "c1-drop"])
