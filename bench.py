@@ -344,29 +344,34 @@ def bench_paper_shapes(torch, C, steps: int):
             del dp
         out["als"] = out.get("als", {})
         out["als"][name] = bench_als(torch, C, dims, sig)
+    # samples x features x time: two finite modes (CP-ALS rows) and one RKHS mode
+    out["als"]["finite-finite-rkhs"] = bench_als(torch, C, (200, 50, 300), (1.0, 1.0, 3.0),
+                                                 finite=(True, True, False), q=100000)
     return out
 
 
-def bench_als(torch, C, dims, sig, r: int = 10, outer: int = 3):
+def bench_als(torch, C, dims, sig, r: int = 10, outer: int = 3, finite=(False, False, False),
+              q: int = 50000):
     """The alternating optimisation on one stand-in (all three modes, the
     paper's subproblem setting, warm starts): GPU time per outer iteration and
-    the oracle's (O-pcg blocks) for one outer iteration on the host; error
-    histories side by side."""
+    the oracle's (O-pcg blocks; row solves for finite modes) for one outer
+    iteration on the host; error histories side by side."""
     import time
     import oracle as O
     from paper_2603_25691_amd.torch_api import AlsSolver, kernel_eig
     from synth import make_als_problem
 
-    p = make_als_problem(shape=dims, sigmas=sig, r=r, seed=1)
-    Ks = [torch.from_numpy(K).cuda() for K in p.Ks]
-    eig = [kernel_eig(K) for K in Ks]
+    p = make_als_problem(shape=dims, sigmas=sig, r=r, seed=1, q=q, finite=finite)
+    Ks = [None if K is None else torch.from_numpy(K).cuda() for K in p.Ks]
+    eig = [(None, None) if K is None else kernel_eig(K) for K in Ks]
     coords = torch.from_numpy(p.coords).cuda()
     y = torch.from_numpy(p.y).cuda()
     W0 = [torch.from_numpy(W).cuda() for W in p.W0s]
-    res = {"shape": list(dims), "r": r, "outer": outer}
+    res = {"shape": list(dims), "r": r, "outer": outer, "q": q,
+           "finite_modes": [k for k in range(3) if finite[k]]}
     for prec in ("fp64", "mixed_bf16"):
         s = AlsSolver(Ks, [u for u, _ in eig], [d for _, d in eig], coords, y, r, p.lams,
-                      p.rho, p.tol, 0.0, outer, maxit=p.maxit, precision=prec)
+                      p.rho, p.tol, 0.0, outer, maxit=p.maxit, precision=prec, n=list(dims))
         s.run(W0)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -376,7 +381,7 @@ def bench_als(torch, C, dims, sig, r: int = 10, outer: int = 3):
         res[prec] = {"ms_per_outer": 1e3 * dt / info.outer, "errors": errors,
                      "inner_iters": info.inner_iters, "capped": info.capped}
         s.close()
-    eigs = [O.kernel_eig(K) for K in p.Ks]
+    eigs = [None if K is None else O.kernel_eig(K) for K in p.Ks]
     t_or, ref = host_median(lambda: O.cp_hifi_als(p.Ks, p.coords, p.y, p.W0s, p.lams, p.rho,
                                                   max_outer=1, als_tol=0.0, solver="pcg",
                                                   tol=p.tol, maxit=p.maxit, eigs=eigs),

@@ -336,7 +336,8 @@ CPHIFI_API int cphifi_aligned_solve(const cphifi_aligned_desc* d, const cphifi_a
  * than als_tol between outer iterations, or after max_outer of them (the
  * paper's runs: 50 iterations, 1e-6; subproblems to relres 1e-6 with at most
  * 75 iterations).  A subproblem that stops at its iteration cap counts in
- * `capped` and the run goes on. */
+ * `capped` and the run goes on.  Modes flagged finite take the CP-ALS row
+ * update instead (see cphifi_als_desc.finite; W[k] then holds A_k). */
 typedef struct cphifi_als_desc {
   int64_t n[3];       /* grid points per mode (rows of K_k), >= 1 */
   int64_t q;          /* observed entries, 1 .. 2^31 - 1 */
@@ -349,11 +350,18 @@ typedef struct cphifi_als_desc {
   int32_t flags;      /* subproblem flags (CPHIFI_FLAG_WARM_START is always added) */
   int32_t maxit;      /* subproblem iteration cap (<= 0: 500) */
   int32_t max_outer;  /* outer iterations, >= 1 */
+  int32_t finite[3];  /* nonzero: mode k is finite-dimensional (Section 2: no
+                         regulariser, so a CP-ALS block with missing data): its
+                         factor A_k is the unknown itself, each row solving
+                         (sum_l z_l z_l^T + rho I) a_i = sum_l y_l z_l over its
+                         observations (rho keeps rows with few observations
+                         definite); K, UK, dK and lambda of the mode unused */
+  int32_t reserved;
 } cphifi_als_desc;
 
 /* Device inputs (caller-owned; must outlive the object). */
 typedef struct cphifi_als_inputs {
-  const double* K[3];     /* n_k x n_k (stride n_k), symmetric psd */
+  const double* K[3];     /* n_k x n_k (stride n_k), symmetric psd (NULL for finite modes) */
   const double* UK[3];    /* eigenvectors of K_k, laid out as cphifi_ui_inputs.UK */
   const double* dK[3];    /* eigenvalues of K_k */
   const int32_t* coords;  /* q x 3 row-major: the indices (i_0, i_1, i_2) of each entry */

@@ -4,12 +4,16 @@ cp-hifi-subproblem; the outer loop of the experiments of Section 5).
 TEST INFRASTRUCTURE ONLY, like the rest of this package: imported by tests,
 never by the library.
 
-The tensor is 3-way and every mode is infinite-dimensional, as in the paper's
-vortex and Miranda experiments: mode k has its own kernel matrix K_k and its
-factor is A_k = K_k W_k (Section 2).  With the other two factors fixed, W_k
+The tensor is 3-way.  An infinite-dimensional mode k (every mode of the
+paper's vortex and Miranda experiments) has its own kernel matrix K_k and its
+factor is A_k = K_k W_k (Section 2); with the other two factors fixed, W_k
 solves the unaligned subproblem of eq. unaligned-infinite-1: its observations
 are grouped by their mode-k index, and the Khatri-Rao row of an observation is
-the Hadamard product of the other two factors' rows at its indices.  One outer
+the Hadamard product of the other two factors' rows at its indices.  A
+finite-dimensional mode (K_k given as None) has no regulariser (Section 2), so
+its block is CP-ALS with missing data: each row a_i of A_k = W_k solves the
+least-squares problem over its observations, with the shift rho I added to
+the normal equations (a row with few observations stays definite).  One outer
 iteration updates modes 0, 1, 2 in turn; the loop ends when the relative error
 on the observed entries changes by less than ``als_tol`` between two outer
 iterations, or after ``max_outer`` of them (Section 5: 50 and 1e-6).
@@ -29,8 +33,8 @@ import numpy as np
 from .cphifi_oracle import (gram_V, kernel_eig, khatri_rao_rows, solve_dense,  # noqa: F401
                             solve_pcg)
 
-__all__ = ["cp_values", "als_rel_error", "als_objective", "mode_view", "AlsResult",
-           "cp_hifi_als"]
+__all__ = ["cp_values", "als_rel_error", "als_objective", "finite_mode_update", "mode_view",
+           "AlsResult", "cp_hifi_als"]
 
 
 def cp_values(factors: Sequence[np.ndarray], coords: np.ndarray) -> np.ndarray:
@@ -51,12 +55,29 @@ def als_objective(Ks: Sequence[np.ndarray], Ws: Sequence[np.ndarray], coords: np
                   y: np.ndarray, lams: Sequence[float], rho: float) -> float:
     """The function the block updates decrease: the misfit on the observed
     entries plus, per mode, lam_k tr(W_k^T K_k W_k) + rho ||W_k||_F^2 (the
-    regulariser of Section 2 and the shift of Section 4.1)."""
-    factors = [K @ W for K, W in zip(Ks, Ws)]
+    regulariser of Section 2 and the shift of Section 4.1); a finite mode
+    (K None) contributes rho ||W_k||_F^2 only."""
+    factors = [W if K is None else K @ W for K, W in zip(Ks, Ws)]
     misfit = float(np.sum((y - cp_values(factors, coords)) ** 2))
-    reg = sum(lam * float(np.trace(W.T @ K @ W)) + rho * float(np.sum(W * W))
-              for K, W, lam in zip(Ks, Ws, lams))
+    reg = sum((0.0 if K is None else lam * float(np.trace(W.T @ K @ W)))
+              + rho * float(np.sum(W * W)) for K, W, lam in zip(Ks, Ws, lams))
     return misfit + reg
+
+
+def finite_mode_update(coords: np.ndarray, y: np.ndarray, factors: Sequence[np.ndarray],
+                       k: int, n_k: int, rho: float) -> np.ndarray:
+    """CP-ALS block of a finite mode with missing data: for every row i,
+    (Z_i^T Z_i + rho I) a_i = Z_i^T y_i with Z_i the Khatri-Rao rows of the
+    observations whose mode-k index is i."""
+    t, i, j, a, b = mode_view(coords, k)
+    Z = khatri_rao_rows(factors[a], factors[b], i, j)
+    r = Z.shape[1]
+    W = np.zeros((n_k, r))
+    for row in range(n_k):
+        sel = t == row
+        Zi, yi = Z[sel], y[sel]
+        W[row] = np.linalg.solve(Zi.T @ Zi + rho * np.eye(r), Zi.T @ yi)
+    return W
 
 
 def mode_view(coords: np.ndarray, k: int):
@@ -96,10 +117,10 @@ def cp_hifi_als(Ks: Sequence[np.ndarray], coords: np.ndarray, y: np.ndarray,
     if d != 3 or coords.shape[1] != 3:
         raise ValueError("3-way tensors only")
     Ws = [np.array(W, dtype=np.float64, copy=True) for W in W0s]
-    factors = [K @ W for K, W in zip(Ks, Ws)]
+    factors = [W if K is None else K @ W for K, W in zip(Ks, Ws)]
     errors = [als_rel_error(factors, coords, y)]
     if eigs is None and solver == "pcg":
-        eigs = [kernel_eig(K) for K in Ks]
+        eigs = [None if K is None else kernel_eig(K) for K in Ks]
     q = coords.shape[0]
     inner: List[List[int]] = []
     objs: List[float] = []
@@ -109,11 +130,14 @@ def cp_hifi_als(Ks: Sequence[np.ndarray], coords: np.ndarray, y: np.ndarray,
         for k in range(d):
             t, i, j, a, b = mode_view(coords, k)
             Zhat = khatri_rao_rows(factors[a], factors[b], i, j)
-            if solver == "dense":
+            if Ks[k] is None:
+                Ws[k] = finite_mode_update(coords, y, factors, k, Ws[k].shape[0], rho)
+                its.append(0)
+            elif solver == "dense":
                 Ws[k] = solve_dense(Ks[k], Zhat, t, y, lams[k], rho)
                 its.append(0)
             elif solver == "pcg":
-                n_k, n_a, n_b = Ks[k].shape[0], Ks[a].shape[0], Ks[b].shape[0]
+                n_k, n_a, n_b = Ks[k].shape[0], Ws[a].shape[0], Ws[b].shape[0]
                 gamma = q / (n_k * n_a * n_b)
                 V = gram_V(factors[a], factors[b])
                 res = solve_pcg(Ks[k], Zhat, t, y, lams[k], rho, gamma, V, tol, maxit,
@@ -122,7 +146,7 @@ def cp_hifi_als(Ks: Sequence[np.ndarray], coords: np.ndarray, y: np.ndarray,
                 its.append(res.iters)
             else:
                 raise ValueError(f"unknown solver {solver!r}")
-            factors[k] = Ks[k] @ Ws[k]
+            factors[k] = Ws[k] if Ks[k] is None else Ks[k] @ Ws[k]
             if on_block is not None:
                 on_block(outer, k, Ws)
             if track_objective:

@@ -99,7 +99,8 @@ class cphifi_als_desc(C.Structure):
     _fields_ = [("n", C.c_int64 * 3), ("q", C.c_int64), ("r", C.c_int64),
                 ("lambda_", C.c_double * 3), ("rho", C.c_double), ("tol", C.c_double),
                 ("als_tol", C.c_double), ("precision", C.c_int32), ("flags", C.c_int32),
-                ("maxit", C.c_int32), ("max_outer", C.c_int32)]
+                ("maxit", C.c_int32), ("max_outer", C.c_int32), ("finite", C.c_int32 * 3),
+                ("reserved", C.c_int32)]
 
 
 class cphifi_als_inputs(C.Structure):
@@ -361,10 +362,10 @@ def cphifi_aligned_solve(desc: cphifi_aligned_desc, inputs: cphifi_aligned_input
 
 def make_als_desc(n, q: int, r: int, lams, rho: float, tol: float, als_tol: float,
                   max_outer: int, maxit: int = 0, precision: int = 0,
-                  flags: int = 0) -> cphifi_als_desc:
+                  flags: int = 0, finite=(False, False, False)) -> cphifi_als_desc:
     d = cphifi_als_desc()
     for k in range(3):
-        d.n[k], d.lambda_[k] = int(n[k]), float(lams[k])
+        d.n[k], d.lambda_[k], d.finite[k] = int(n[k]), float(lams[k]), int(bool(finite[k]))
     d.q, d.r, d.rho, d.tol, d.als_tol = q, r, rho, tol, als_tol
     d.precision, d.flags, d.maxit, d.max_outer = precision, flags, maxit, max_outer
     return d

@@ -68,8 +68,10 @@ int als_layout(const cphifi_als_desc& d, AlsLayout* L) {
   for (int k = 0; k < 3; ++k) {
     const cphifi_ui_desc u = mode_desc(d, k);
     size_t pb = 0;
-    const int rc = cphifi_ui_workspace_bytes(&u, &pb);
-    if (rc != CPHIFI_OK) return rc;
+    if (!d.finite[k]) {
+      const int rc = cphifi_ui_workspace_bytes(&u, &pb);
+      if (rc != CPHIFI_OK) return rc;
+    }
     L->ptr[k] = take(sizeof(int32_t) * (size_t)(d.n[k] + 1));
     L->oi[k] = take(sizeof(int32_t) * (size_t)d.q);
     L->oj[k] = take(sizeof(int32_t) * (size_t)d.q);
@@ -88,8 +90,8 @@ int check_desc(const cphifi_als_desc* d) {
     return CPHIFI_INVALID_ARG;
   }
   for (int k = 0; k < 3; ++k)
-    if (d->n[k] < 1 || d->n[k] > INT32_MAX || !(d->lambda[k] > 0.0)) {
-      set_error("als: mode %d needs n >= 1 and lambda > 0", k);
+    if (d->n[k] < 1 || d->n[k] > INT32_MAX || (!d->finite[k] && !(d->lambda[k] > 0.0))) {
+      set_error("als: mode %d needs n >= 1 and (an RKHS mode) lambda > 0", k);
       return CPHIFI_INVALID_ARG;
     }
   if (d->q < 1 || d->q > INT32_MAX || d->r < 1 || d->r > kMaxRank || !(d->rho > 0.0) ||
@@ -138,6 +140,88 @@ __global__ __launch_bounds__(kErrThreads) void als_error_kernel(
     }
     part[2 * blockIdx.x] = te;
     part[2 * blockIdx.x + 1] = ty;
+  }
+}
+
+// Finite-dimensional mode (Section 2: no regulariser, a CP-ALS block with
+// missing data): row i of A_k solves (sum_l z_l z_l^T + rho I) a_i = sum_l y_l z_l
+// over the observations l of row i, z_l = Fa(oi_l,:) had Fb(oj_l,:).  One
+// workgroup per row: the observations pass through LDS in chunks, each
+// thread accumulates its entries of the Gram matrix in a fixed order, then a
+// Cholesky factorisation and the two triangular solves in LDS.
+constexpr int kFinChunk = 32;
+constexpr int kFinPer = kMaxRank * kMaxRank / kErrThreads;  // Gram entries per thread
+
+__global__ __launch_bounds__(kErrThreads) void als_finite_kernel(
+    const int32_t* __restrict__ ptr, const int32_t* __restrict__ oi,
+    const int32_t* __restrict__ oj, const double* __restrict__ y,
+    const double* __restrict__ Fa, const double* __restrict__ Fb, int64_t n, int r, double rho,
+    double* __restrict__ Aout) {
+  __shared__ double G[kMaxRank * kMaxRank];
+  __shared__ double zs[kFinChunk * kMaxRank];
+  __shared__ double ys[kFinChunk];
+  __shared__ double rhs[kMaxRank];
+  const int tid = threadIdx.x;
+  for (int64_t row = blockIdx.x; row < n; row += gridDim.x) {
+    double acc[kFinPer];
+#pragma unroll
+    for (int m = 0; m < kFinPer; ++m) acc[m] = 0.0;
+    double racc = 0.0;
+    const int32_t l_end = ptr[row + 1];
+    for (int32_t l0 = ptr[row]; l0 < l_end; l0 += kFinChunk) {
+      const int cnt = min(kFinChunk, l_end - l0);
+      __syncthreads();  // zs / ys of the previous chunk consumed
+      for (int e = tid; e < cnt * r; e += kErrThreads) {
+        const int l = e / r, c = e % r;
+        zs[l * r + c] = Fa[(int64_t)oi[l0 + l] * r + c] * Fb[(int64_t)oj[l0 + l] * r + c];
+      }
+      for (int e = tid; e < cnt; e += kErrThreads) ys[e] = y[l0 + e];
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < kFinPer; ++m) {
+        const int e = tid + m * kErrThreads;
+        if (e < r * r) {
+          const int a = e / r, b = e % r;
+          for (int l = 0; l < cnt; ++l) acc[m] = fma(zs[l * r + a], zs[l * r + b], acc[m]);
+        }
+      }
+      if (tid < r)
+        for (int l = 0; l < cnt; ++l) racc = fma(ys[l], zs[l * r + tid], racc);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kFinPer; ++m) {
+      const int e = tid + m * kErrThreads;
+      if (e < r * r) G[e] = acc[m] + ((e / r == e % r) ? rho : 0.0);
+    }
+    if (tid < r) rhs[tid] = racc;
+    __syncthreads();
+    // Cholesky G = L L^T (lower triangle in place), column by column
+    for (int k = 0; k < r; ++k) {
+      if (tid == 0) G[k * r + k] = sqrt(G[k * r + k]);
+      __syncthreads();
+      for (int i = k + 1 + tid; i < r; i += kErrThreads) G[i * r + k] /= G[k * r + k];
+      __syncthreads();
+      for (int e = tid; e < r * r; e += kErrThreads) {
+        const int i = e / r, j = e % r;
+        if (j > k && i >= j) G[i * r + j] -= G[i * r + k] * G[j * r + k];
+      }
+      __syncthreads();
+    }
+    // L z = rhs, then L^T a = z (rhs overwritten)
+    for (int k = 0; k < r; ++k) {
+      if (tid == 0) rhs[k] /= G[k * r + k];
+      __syncthreads();
+      for (int i = k + 1 + tid; i < r; i += kErrThreads) rhs[i] -= G[i * r + k] * rhs[k];
+      __syncthreads();
+    }
+    for (int k = r - 1; k >= 0; --k) {
+      if (tid == 0) rhs[k] /= G[k * r + k];
+      __syncthreads();
+      for (int i = tid; i < k; i += kErrThreads) rhs[i] -= G[k * r + i] * rhs[k];
+      __syncthreads();
+    }
+    if (tid < r) Aout[row * r + tid] = rhs[tid];
   }
 }
 
@@ -230,8 +314,8 @@ int cphifi_als_create(cphifi_als** out, const cphifi_als_desc* d, const cphifi_a
   int rc = check_desc(d);
   if (rc != CPHIFI_OK) return rc;
   for (int k = 0; k < 3; ++k)
-    if (in->K[k] == nullptr || in->UK[k] == nullptr || in->dK[k] == nullptr) {
-      set_error("als: K, UK and dK of mode %d are required", k);
+    if (!d->finite[k] && (in->K[k] == nullptr || in->UK[k] == nullptr || in->dK[k] == nullptr)) {
+      set_error("als: K, UK and dK of RKHS mode %d are required", k);
       return CPHIFI_INVALID_ARG;
     }
   AlsLayout L{};
@@ -310,6 +394,7 @@ int cphifi_als_create(cphifi_als** out, const cphifi_als_desc* d, const cphifi_a
       delete a;
       return CPHIFI_HIP_ERROR;
     }
+    if (d->finite[k]) continue;  // a finite mode has no subproblem plan
     const cphifi_ui_desc u = mode_desc(*d, k);
     cphifi_ui_inputs ui{};
     ui.K = in->K[k];
@@ -344,13 +429,31 @@ int cphifi_als_run(cphifi_als* a, double* const* W, double* const* F, cphifi_als
   std::memset(info, 0, sizeof(*info));
   info->errors = errors;
   int rc = CPHIFI_OK;
-  for (int k = 0; k < 3; ++k)
-    if ((rc = plan_times_K(a->plan[k], W[k], a->F[k])) != CPHIFI_OK) return rc;
+  const int64_t r = a->d.r;
+  for (int k = 0; k < 3; ++k) {
+    if (a->d.finite[k]) {  // the factor is the unknown itself
+      CPHIFI_HIP(hipMemcpyAsync(a->F[k], W[k], sizeof(double) * a->d.n[k] * r,
+                                hipMemcpyDeviceToDevice, a->st));
+    } else if ((rc = plan_times_K(a->plan[k], W[k], a->F[k])) != CPHIFI_OK) {
+      return rc;
+    }
+  }
   double err = 0.0;
   if ((rc = rel_error(a, &err)) != CPHIFI_OK) return rc;
   if (errors != nullptr) errors[0] = err;
   for (int it = 0; it < a->d.max_outer; ++it) {
     for (int k = 0; k < 3; ++k) {
+      if (a->d.finite[k]) {
+        const int m0 = k == 0 ? 1 : 0, m1 = k == 2 ? 1 : 2;
+        const int blocks = (int)std::min<int64_t>(a->d.n[k], 4096);
+        hipLaunchKernelGGL(als_finite_kernel, dim3(blocks), dim3(kErrThreads), 0, a->st,
+                           (const int32_t*)(a->ws + a->L.ptr[k]),
+                           (const int32_t*)(a->ws + a->L.oi[k]),
+                           (const int32_t*)(a->ws + a->L.oj[k]), a->y[k], a->F[m0], a->F[m1],
+                           a->d.n[k], (int)r, a->d.rho, a->F[k]);
+        CPHIFI_CHECK_LAUNCH();
+        continue;
+      }
       cphifi_solve_info si{};
       rc = cphifi_ui_solve_subproblem(a->plan[k], a->y[k], W[k], &si);
       if (rc == CPHIFI_NOT_CONVERGED) {
@@ -373,6 +476,10 @@ int cphifi_als_run(cphifi_als* a, double* const* W, double* const* F, cphifi_als
     }
   }
   info->rel_error = err;
+  for (int k = 0; k < 3; ++k)
+    if (a->d.finite[k])
+      CPHIFI_HIP(hipMemcpyAsync(W[k], a->F[k], sizeof(double) * a->d.n[k] * r,
+                                hipMemcpyDeviceToDevice, a->st));
   if (F != nullptr)
     for (int k = 0; k < 3; ++k)
       if (F[k] != nullptr)

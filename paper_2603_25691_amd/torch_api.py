@@ -402,14 +402,18 @@ class AlsSolver:
     """CP-HIFI alternating optimisation over three RKHS modes (cphifi_als_*).
 
     Ks, UKs, dKs: per mode the kernel matrix (n_k x n_k), its eigenvectors (as
-    kernel_eig returns them) and eigenvalues, device float64; coords: (q, 3)
-    device int32; y: (q,) device float64."""
+    kernel_eig returns them) and eigenvalues, device float64, or None for a
+    finite-dimensional mode (then n[k] gives its size); coords: (q, 3) device
+    int32; y: (q,) device float64."""
 
     def __init__(self, Ks, UKs, dKs, coords: torch.Tensor, y: torch.Tensor, r: int, lams,
                  rho: float, tol: float, als_tol: float, max_outer: int, maxit: int = 0,
-                 precision: str = "fp64", flags: int = 0):
-        n = [int(K.shape[0]) for K in Ks]
+                 precision: str = "fp64", flags: int = 0, n=None):
+        finite = [K is None for K in Ks]
+        n = [int(Ks[k].shape[0]) if not finite[k] else int(n[k]) for k in range(3)]
         for k in range(3):
+            if finite[k]:
+                continue
             _need(Ks[k], torch.float64, (n[k], n[k]), f"K[{k}]")
             _need(UKs[k], torch.float64, (n[k], n[k]), f"UK[{k}]")
             _need(dKs[k], torch.float64, (n[k],), f"dK[{k}]")
@@ -419,11 +423,12 @@ class AlsSolver:
         self.n, self.r, self.max_outer = n, r, max_outer
         self._keep = (list(Ks), list(UKs), list(dKs), coords, y)
         self.desc = _c.make_als_desc(n, q, r, lams, rho, tol, als_tol, max_outer, maxit,
-                                     _c.PRECISIONS[precision], flags)
+                                     _c.PRECISIONS[precision], flags, finite)
         self.inputs = _c.cphifi_als_inputs()
         for k in range(3):
-            self.inputs.K[k], self.inputs.UK[k] = Ks[k].data_ptr(), UKs[k].data_ptr()
-            self.inputs.dK[k] = dKs[k].data_ptr()
+            if not finite[k]:
+                self.inputs.K[k], self.inputs.UK[k] = Ks[k].data_ptr(), UKs[k].data_ptr()
+                self.inputs.dK[k] = dKs[k].data_ptr()
         self.inputs.coords, self.inputs.y = coords.data_ptr(), y.data_ptr()
         self.ws_bytes = _c.cphifi_als_workspace_bytes(self.desc)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=y.device)

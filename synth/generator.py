@@ -464,23 +464,26 @@ class AlsProblem:
 def make_als_problem(shape=(199, 449, 151), sigmas=(4.0, 4.0, 3.0), q: int = 50000,
                      r: int = 10, seed: int = 0, lam: float = 0.1, rho: float = 1e-6,
                      tol: float = 1e-6, maxit: int = 75, noise: float = 0.01,
-                     init_scale: float = 0.1, name: Optional[str] = None) -> AlsProblem:
+                     init_scale: float = 0.1, name: Optional[str] = None,
+                     finite=(False, False, False)) -> AlsProblem:
     """Shape-only stand-in for the paper's unaligned vortex / Miranda runs:
     Gaussian kernels of the given bandwidths on integer grids, ground-truth
     factors K_k Wk* with Wk* ~ N(0, 1), q entries drawn uniformly without
     replacement (sorted by linear index), 1 % relative noise, and starting
     weights init_scale * N(0, 1).  Draw order: W1*, W2*, W3*, the entry set,
-    noise, W1_0, W2_0, W3_0."""
+    noise, W1_0, W2_0, W3_0.  A mode flagged in `finite` is a plain
+    finite-dimensional mode: no kernel (Ks[k] is None) and its ground-truth
+    factor is Wk* itself."""
     rng = np.random.default_rng(seed)
     Wstar = [rng.standard_normal((nk, r)) for nk in shape]
     n1, n2, n3 = shape
     lin = np.sort(rng.choice(n1 * n2 * n3, size=q, replace=False))
     e = rng.standard_normal(q)
     W0s = [init_scale * rng.standard_normal((nk, r)) for nk in shape]
-    Ks = [kernel_matrix(np.arange(1, nk + 1, dtype=np.float64), "rbf", sg)
-          for nk, sg in zip(shape, sigmas)]
+    Ks = [None if fin else kernel_matrix(np.arange(1, nk + 1, dtype=np.float64), "rbf", sg)
+          for nk, sg, fin in zip(shape, sigmas, finite)]
     coords = np.stack([lin // (n2 * n3), (lin // n3) % n2, lin % n3], axis=1).astype(np.int32)
-    A = [K @ W for K, W in zip(Ks, Wstar)]
+    A = [W if K is None else K @ W for K, W in zip(Ks, Wstar)]
     y0 = np.sum(A[0][coords[:, 0]] * A[1][coords[:, 1]] * A[2][coords[:, 2]], axis=1)
     y = _noisy(y0, e, noise)
     return AlsProblem(name=name or f"als-{n1}x{n2}x{n3}-r{r}", shape=tuple(shape), r=r, Ks=Ks,

@@ -93,3 +93,27 @@ def test_coordinate_out_of_range_is_rejected():
     with pytest.raises(C.CphifiError) as ei:
         AlsSolver(Ks, UKs, dKs, bad, y, p.r, p.lams, p.rho, tol=1e-6, als_tol=0.0, max_outer=1)
     assert ei.value.status == C.INVALID_ARG
+
+
+def test_finite_modes_match_exact_als():
+    """Samples x features x time (two finite modes, one RKHS mode): the finite
+    modes' CP-ALS row updates and the RKHS mode's tight solves against the
+    oracle's exact block updates, 4 outer iterations."""
+    p = make_als_problem(shape=(11, 8, 13), sigmas=(1.0, 1.0, 1.5), q=500, r=3, seed=4,
+                         lam=0.1, rho=1e-6, init_scale=0.5, finite=(True, True, False))
+    ref = O.cp_hifi_als(p.Ks, p.coords, p.y, p.W0s, p.lams, p.rho, max_outer=4, als_tol=0.0,
+                        solver="dense")
+    K2 = dev(p.Ks[2])
+    UK2, dK2 = kernel_eig(K2)
+    s = AlsSolver([None, None, K2], [None, None, UK2], [None, None, dK2],
+                  dev(p.coords, torch.int32), dev(p.y), p.r, p.lams, p.rho, tol=1e-12,
+                  als_tol=0.0, max_outer=4, maxit=2000, n=[11, 8, 13])
+    Ws, Fs, info, errors = s.run([dev(W) for W in p.W0s])
+    assert info.outer == 4
+    assert np.allclose(errors, ref.errors, rtol=1e-8, atol=0)
+    for k in range(2):
+        Wk = host(Ws[k])
+        assert np.linalg.norm(Wk - ref.Ws[k]) <= 1e-7 * np.linalg.norm(ref.Ws[k])
+        assert np.array_equal(host(Fs[k]), Wk)
+    assert O.e_kw(p.Ks[2], host(Ws[2]), ref.Ws[2]) <= 1e-7
+    s.close()

@@ -95,3 +95,45 @@ def test_stop_rule_and_history_length():
     assert abs(res.errors[-1] - res.errors[-2]) < 1e-3
     if res.outer > 1:
         assert abs(res.errors[-2] - res.errors[-3]) >= 1e-3
+
+
+def mixed_modes(seed=4, r=3):
+    """Samples x features x time: two finite modes and one RKHS mode."""
+    return make_als_problem(shape=(11, 8, 13), sigmas=(1.0, 1.0, 1.5), q=500, r=r, seed=seed,
+                            lam=0.1, rho=1e-6, init_scale=0.5, finite=(True, True, False))
+
+
+def test_finite_mode_row_solve_is_ridge_least_squares():
+    """Each row of a finite-mode update against an independent solve of the
+    stacked least-squares problem [Z_i; sqrt(rho) I] a = [y_i; 0] (SVD)."""
+    p = mixed_modes()
+    F = [p.W0s[0], p.W0s[1], p.Ks[2] @ p.W0s[2]]
+    W = O.finite_mode_update(p.coords, p.y, F, 0, p.W0s[0].shape[0], 10 * p.rho)
+    for row in range(W.shape[0]):
+        sel = p.coords[:, 0] == row
+        Z = F[1][p.coords[sel, 1]] * F[2][p.coords[sel, 2]]
+        M = np.vstack([Z, np.sqrt(10 * p.rho) * np.eye(p.r)])
+        rhs = np.concatenate([p.y[sel], np.zeros(p.r)])
+        want = np.linalg.lstsq(M, rhs, rcond=None)[0]
+        assert np.allclose(W[row], want, rtol=1e-9, atol=1e-12)
+
+
+def test_finite_and_rkhs_blocks_stationary_and_monotone():
+    p = mixed_modes()
+    seen = []
+    res = O.cp_hifi_als(p.Ks, p.coords, p.y, p.W0s, p.lams, p.rho, max_outer=2, als_tol=0.0,
+                        solver="dense", track_objective=True,
+                        on_block=lambda it, k, Ws: seen.append((k, [W.copy() for W in Ws])))
+    f0 = O.als_objective(p.Ks, p.W0s, p.coords, p.y, p.lams, p.rho)
+    seq = [f0] + res.objectives
+    for a, b in zip(seq, seq[1:]):
+        assert b <= a * (1 + 1e-12) + 1e-14
+    rng = np.random.default_rng(12)
+    for k, Ws in seen:
+        E = rng.standard_normal(Ws[k].shape)
+        E *= np.linalg.norm(Ws[k]) / np.linalg.norm(E)
+        g0 = _dir_deriv(p, Ws, k, E)
+        Ws1 = [W.copy() for W in Ws]
+        Ws1[k] = Ws[k] + E
+        g1 = _dir_deriv(p, Ws1, k, E)
+        assert abs(g0) <= 1e-7 * abs(g1), (k, g0, g1)
