@@ -452,6 +452,16 @@ CPHIFI_API int cphifi_product_static(int elt, int trans, int mw, int s, int kspl
                                      const void* U, int64_t ldu, const double* X, int64_t r,
                                      const double* xscale, double* Y, void* stream);
 
+/* Measurement helper: reads `bytes` of device memory at `buf` once (16-byte
+ * loads, `blocks` workgroups of 256 threads striding over the buffer) and
+ * writes each workgroup's sum of the doubles it read to partial[blockIdx]
+ * (device, >= blocks doubles).  Its duration gives the achievable HBM read
+ * rate that the products' rates are compared with.  buf 16-byte aligned,
+ * bytes > 0 a multiple of 16, 1 <= blocks <= 65536.  async.  Errors:
+ * INVALID_ARG, HIP_ERROR. */
+CPHIFI_API int cphifi_stream_read(const void* buf, int64_t bytes, int32_t blocks,
+                                  double* partial, void* stream);
+
 /* ------------------------------------------------------- batched solver
  * Many independent UI subproblems (Section 4.4) of uneven n and r solved by
  * the mixed-precision method of cphifi_ui_solve_subproblem (precision

@@ -174,6 +174,7 @@ def _load() -> C.CDLL:
         "cphifi_product_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int,
                                                      C.POINTER(C.c_size_t)]),
         "cphifi_product_tile_ok": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+        "cphifi_stream_read": (C.c_int, [P, C.c_int64, C.c_int32, P, P]),
         "cphifi_product_static_max_bytes": (C.c_size_t, []),
         "cphifi_product_static": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                             C.c_int64, P, C.c_int64, P, C.c_int64, P, P, P]),
@@ -425,6 +426,11 @@ def cphifi_product(elt: int, trans: int, mw: int, s: int, ksplit: int, n: int, U
                                r, C.c_void_p(xscale) if xscale else None, C.c_void_p(Y),
                                C.c_void_p(workspace), C.c_size_t(workspace_bytes),
                                C.c_void_p(stream)), "cphifi_product")
+
+
+def cphifi_stream_read(buf: int, nbytes: int, blocks: int, partial: int, stream: int = 0) -> None:
+    _check(_lib.cphifi_stream_read(C.c_void_p(buf), nbytes, blocks, C.c_void_p(partial),
+                                   C.c_void_p(stream)), "cphifi_stream_read")
 
 
 def cphifi_product_static_max_bytes() -> int:

@@ -3,6 +3,8 @@
 #include "cphifi_internal.h"
 #include "obs_tile.h"
 
+#include <cstdlib>
+
 namespace cphifi {
 namespace {
 
@@ -39,10 +41,15 @@ __global__ __launch_bounds__(256) void obs_rows_kernel(ObsDev d, const int32_t* 
 // B (J x r, FP64 or the FP32 copy) staged in LDS once per workgroup, then read
 // from there by every observation; the workgroups stride over the tasks (or
 // short-segment wave units) so the staging is amortised.  Used in the implicit
-// and owner forms when the J r elements fit kObsLdsBytes: a larger copy limits the
-// workgroups per CU, and the gather is latency-bound (at J r = 8000 the LDS
-// form measured 190-210 us against 177-187 us reading B through L2).
-constexpr int kObsLdsBytes = 16384;
+// and owner forms when the copy fits the element type's limit: a larger copy
+// limits the workgroups per CU.  Measured at J r = 8000 (n = 30658, 200
+// observations per time point, lane-row form): FP64, 64000 bytes, two
+// workgroups per CU, 116 us against 150 us reading B through L2 (MTTKRP 124
+// against 188 us); FP32, 32000 bytes, 66 against 63 us, so FP32 (and the task
+// form, not measured at this size) keeps the L2 form above 16 KB.
+// CPHIFI_OBS_LDS_BYTES overrides the limits (at most 64 KB).
+constexpr int kObsLdsBytesF64 = 65536;
+constexpr int kObsLdsBytesF32 = 16384;
 constexpr int kObsLdsGrid = 1024;  // workgroups of the staged form (grid-stride)
 
 template <typename T>
@@ -111,11 +118,22 @@ int rows_per_wave(int64_t nseg) {
   return (int)std::max<int64_t>(ROWS, std::min<int64_t>(kSegPerWave, spw));
 }
 
+// LDS limit of the staged form for FP32 (pf) or FP64 factor rows, in the
+// lane-row form (rows) or the task form; the override is read once.
+size_t obs_lds_limit(bool pf, bool rows) {
+  static const long env = [] {
+    const char* v = std::getenv("CPHIFI_OBS_LDS_BYTES");
+    return v != nullptr ? std::atol(v) : -1L;
+  }();
+  if (env >= 0) return (size_t)std::min<long>(env, 65536L);
+  return (pf || !rows) ? (size_t)kObsLdsBytesF32 : (size_t)kObsLdsBytesF64;
+}
+
 template <int L, int CPL, int FORM, int MODE>
 int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hipStream_t st) {
   const size_t lds = (pf ? sizeof(float) : sizeof(double)) * (size_t)d.J * d.a.r;
   const int spw = rows_per_wave<L>(t.nseg);
-  if (FORM != tiles::kExplicit && lds <= (size_t)kObsLdsBytes) {
+  if (FORM != tiles::kExplicit && lds <= obs_lds_limit(pf, t.rows)) {
     if (t.rows) {
       const int64_t units = (t.nseg + spw - 1) / spw;
       const int64_t blocks = std::min<int64_t>(kObsLdsGrid, (units + 3) / 4);

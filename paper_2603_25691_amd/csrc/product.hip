@@ -119,9 +119,59 @@ int check_product_args(int elt, int trans, int mw, int s, int64_t n, const void*
   return CPHIFI_OK;
 }
 
+// Streaming read of a device buffer (the achievable HBM read rate against
+// which the products are compared): 16-byte non-temporal loads, four in flight
+// per thread, grid-stride; each workgroup sums what it read and writes one
+// partial, so no load can be dropped.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void stream_read_kernel(const dvec2* __restrict__ p,
+                                                          int64_t n2, double* partial) {
+  __shared__ double red[256];
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (; i + 3 * stride < n2; i += 4 * stride) {
+    const dvec2 a = __builtin_nontemporal_load(p + i);
+    const dvec2 b = __builtin_nontemporal_load(p + i + stride);
+    const dvec2 c = __builtin_nontemporal_load(p + i + 2 * stride);
+    const dvec2 d = __builtin_nontemporal_load(p + i + 3 * stride);
+    s0 += (a.x + b.x) + (c.x + d.x);
+    s1 += (a.y + b.y) + (c.y + d.y);
+  }
+  for (; i < n2; i += stride) {
+    const dvec2 a = __builtin_nontemporal_load(p + i);
+    s0 += a.x;
+    s1 += a.y;
+  }
+  red[threadIdx.x] = s0 + s1;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 }  // namespace
 
 extern "C" {
+
+int cphifi_stream_read(const void* buf, int64_t bytes, int32_t blocks, double* partial,
+                       void* stream) {
+  if (buf == nullptr || partial == nullptr || bytes <= 0 || bytes % 16 != 0 ||
+      ((uintptr_t)buf % 16) != 0 || blocks < 1 || blocks > 65536) {
+    set_error("cphifi_stream_read: need a 16-byte aligned buffer, bytes > 0 a multiple of 16, "
+              "1 <= blocks <= 65536 (bytes=%lld blocks=%d)", (long long)bytes, blocks);
+    return CPHIFI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(stream_read_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                     (const dvec2*)buf, bytes / 16, partial);
+  CPHIFI_CHECK_LAUNCH();
+  return CPHIFI_OK;
+}
+
 
 int cphifi_product_workspace_bytes(int64_t n, int64_t r, int elt, size_t* bytes) {
   clear_error();

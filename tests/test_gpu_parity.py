@@ -137,6 +137,31 @@ def test_apply_matches_oracle(name, uploaded):
     assert row_err(y, want) <= 1e-12
 
 
+@pytest.mark.parametrize("J", [120, 230])
+@pytest.mark.parametrize("form", ["owner", "implicit"])
+def test_wide_feature_gather_matches_oracle(J, form):
+    """Lane-row gathers with J r = 4800 (FP64 rows of B staged in LDS) and
+    J r = 9200 (read through L2), in the one-sample-per-time-point form (the
+    large case's recipe at I = 12) and the general form: the FP64 apply and
+    the observed MTTKRP against the oracle, element by element."""
+    if form == "owner":
+        p = config_c3(seed=3, I=12, J=J)
+    else:
+        p = make_small(37, n=300, I=6, J=J, r=40, q=9000, kernel_param=0.1)
+    dp = upload(p)
+    s = UISolver(dp, p.lam, p.rho, p.tol)
+    X = np.random.default_rng(6).standard_normal((p.n, p.r))
+    y = host(s.apply(dev(X)))
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    want = O.matvec_twostep(p.K, Zhat, p.obs_t, p.lam, p.rho, X)
+    assert rel(y, want) <= 1e-12
+    assert row_err(y, want) <= 1e-12
+    b = host(s.rhs())
+    want_b = O.rhs_matrix(p.K, O.mttkrp_observed(p.y, Zhat, p.obs_t, p.n))
+    assert rel(b, want_b) <= 1e-12
+    assert row_err(b, want_b) <= 1e-12
+
+
 def test_transposed_eigenvector_copy():
     """n >= 4096: the plan keeps a transposed copy of U_K, so U_K^T X runs the
     transposed FP64 kernel.  Preconditioner against the oracle's eq. fx, and

@@ -106,3 +106,18 @@ def test_fp64_stream_k_product(n, r, monkeypatch):
         gh = product(Ud, Xd, "fp64", True, tile, 0, sd).cpu().numpy()
         rerr = np.max(np.linalg.norm(gh - want, axis=1) / np.linalg.norm(want, axis=1))
         assert rerr <= 1e-12, (tile, rerr)
+
+
+@pytest.mark.parametrize("count,blocks", [(1 << 20, 64), (3 * (1 << 20) + 6, 1000)])
+def test_stream_read_reads_every_element(count, blocks):
+    """The streaming-read helper (the achievable-bandwidth probe) visits every
+    element once: the partial sums add up to the buffer's sum (integer values,
+    so every order of addition gives the exact total)."""
+    g = torch.Generator(device="cuda").manual_seed(9)
+    buf = torch.randint(-1000, 1000, (count,), generator=g, device="cuda").to(torch.float64)
+    part = torch.zeros(blocks, dtype=torch.float64, device="cuda")
+    C.cphifi_stream_read(buf.data_ptr(), count * 8, blocks, part.data_ptr(), 0)
+    torch.cuda.synchronize()
+    assert float(part.sum()) == float(buf.sum())
+    with pytest.raises(C.CphifiError):
+        C.cphifi_stream_read(buf.data_ptr(), count * 8 - 8, blocks, part.data_ptr(), 0)
