@@ -206,11 +206,13 @@ def bench_small(torch, C, steps: int):
            "n": p.n, "q": p.q, "r": p.r,
            "oracle_dense_ms": 1e3 * t_dense, "oracle_lstsq_ms": 1e3 * t_brute}
     timer = StepTimer(torch)
-    # fp64: replays of a captured graph of PCG iterations (the default at this
-    # size); fp64_launches: the launch-by-launch loop (CPHIFI_FLAG_NO_GRAPH);
-    # fp64_persistent: one persistent workgroup (CPHIFI_FLAG_PERSISTENT)
-    legs = (("fp64", "fp64", 1e-10, 0), ("fp64_launches", "fp64", 1e-10, C.FLAG_NO_GRAPH),
-            ("fp64_persistent", "fp64", 1e-10, C.FLAG_PERSISTENT),
+    # fp64: the default at this size, one persistent launch of co-resident
+    # workgroups (CPHIFI_FLAG_PERSISTENT); fp64_graph: replays of a captured
+    # graph of PCG iterations (CPHIFI_FLAG_NO_PERSISTENT); fp64_launches: the
+    # launch-by-launch loop (and CPHIFI_FLAG_NO_GRAPH)
+    legs = (("fp64", "fp64", 1e-10, 0),
+            ("fp64_graph", "fp64", 1e-10, C.FLAG_NO_PERSISTENT),
+            ("fp64_launches", "fp64", 1e-10, C.FLAG_NO_PERSISTENT | C.FLAG_NO_GRAPH),
             ("mixed_bf16", "mixed_bf16", MIXED_TOL, 0))
     for label, prec, tol, flags in legs:
         s = UISolver(dp, p.lam, p.rho, tol, precision=prec, flags=flags)
@@ -224,9 +226,9 @@ def bench_small(torch, C, steps: int):
                      "tol": tol}
         s.close()
     out["gpu_vs_oracle_dense"] = out["oracle_dense_ms"] / (out["fp64"]["us_per_solve"] / 1e3)
-    log(f"small: fp64 {out['fp64']['us_per_solve']:.0f} us (launch loop "
-        f"{out['fp64_launches']['us_per_solve']:.0f} us, persistent workgroup "
-        f"{out['fp64_persistent']['us_per_solve']:.0f} us), mixed "
+    log(f"small: fp64 {out['fp64']['us_per_solve']:.0f} us (persistent launch; graph "
+        f"{out['fp64_graph']['us_per_solve']:.0f} us, launch loop "
+        f"{out['fp64_launches']['us_per_solve']:.0f} us), mixed "
         f"{out['mixed_bf16']['us_per_solve']:.0f} us per solve; oracle dense "
         f"{out['oracle_dense_ms']:.1f} ms, lstsq {out['oracle_lstsq_ms']:.1f} ms")
     return out

@@ -93,15 +93,19 @@ enum cphifi_flags {
                                    transposed FP64 product (the rotations, the
                                    FP64 residuals and the certificate) instead
                                    of the low-precision one */
-  CPHIFI_FLAG_PERSISTENT = 128, /* FP64, small subproblems (n <= 2048, n r <=
-                                   4096, n^2 r <= 2e6, q r <= 5e5; paper form,
-                                   no kernel timing, no structured form): the
-                                   whole PCG in one persistent workgroup, no
-                                   launch or host poll per iteration.  Opt-in:
-                                   at the small case (n = 208, r = 5) it ran
-                                   3.97 ms per solve against 2.32 ms for the
-                                   launch loop (one workgroup cannot keep
-                                   enough loads in flight) */
+  CPHIFI_FLAG_PERSISTENT = 128, /* FP64 paper form, n <= 2048, r <= 32, no kernel
+                                   timing, no eigenbasis or structured form:
+                                   run the whole PCG in one persistent launch
+                                   of co-resident workgroups that meet at
+                                   grid barriers (no launch or host poll per
+                                   iteration).  Plans with r <= 8 and n r <=
+                                   2560 take it without the flag (at n = 208,
+                                   r = 5: 1.25 against 2.20 ms per solve);
+                                   above that the multi-kernel loop is as fast
+                                   or faster.  Should the
+                                   workgroups not all be resident (a barrier
+                                   wait times out), the solve falls back to the
+                                   multi-kernel loop */
   CPHIFI_FLAG_TOEPLITZ_K = 256, /* K is symmetric Toeplitz, K(s,k) = c(|s-k|) (a
                                    translation-invariant kernel on a uniform
                                    grid; Section 4.4.1 notes the structure):
@@ -117,6 +121,8 @@ enum cphifi_flags {
                                    (made on the plan's first solve; the host
                                    checks convergence between replays); this
                                    flag keeps the launch-by-launch loop */
+  CPHIFI_FLAG_NO_PERSISTENT = 2048, /* never take the persistent launch of
+                                   CPHIFI_FLAG_PERSISTENT (not even by default) */
   CPHIFI_FLAG_FIBER_COLLAPSE = 512 /* every (time, sample) pair that is observed
                                    at all is observed at all J features once:
                                    the gather-scatter of eqs. vl / yhat1 runs

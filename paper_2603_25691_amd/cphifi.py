@@ -42,6 +42,7 @@ FLAG_PERSISTENT = 128
 FLAG_TOEPLITZ_K = 256
 FLAG_FIBER_COLLAPSE = 512
 FLAG_NO_GRAPH = 1024
+FLAG_NO_PERSISTENT = 2048
 
 PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 

@@ -30,7 +30,6 @@ struct Layout {
   size_t V, UV, dV, D, dKc;
   size_t ulp, utlp, xthi, xtlo, ukt, a32, b32;
   size_t toep, fptr, fidx, fgram;  // structured forms (Toeplitz K, fiber collapse)
-  size_t obst;                     // small plans: time index per observation
   size_t total;
   int64_t ldl;
   int64_t ntask_max, nslot_max, nmulti_max;
@@ -41,15 +40,22 @@ inline int64_t eff_ldk(const cphifi_ui_desc& d) { return d.ldk > 0 ? d.ldk : d.n
 // Plans of this size or larger keep a transposed copy of U_K (see
 // CPHIFI_FLAG_NO_UKT_COPY).
 constexpr int64_t kUktMinN = 4096;
-// FP64 plans that asked for the persistent PCG (small.hip) and fit it; they
-// keep the copy of U_K too (all products of that kernel read the transposed
-// layout) and the time index of every observation.
+// FP64 plans that run the persistent PCG (small.hip): asked for, or small
+// enough that it is the faster form.  Measured per solve against the graph
+// replays: n = 208, r = 5 / 8: 1.25 / 1.25 against 2.20 / 1.90 ms; n = 500,
+// r = 5: 1.20 against 1.51 ms; n = 500, r = 8: 1.88 against 1.82 ms; r = 16
+// or n = 1000: slower (up to 2.4x).  They keep the copy of U_K too (the
+// preconditioner reads rows of U and of U^T).
+constexpr int kSmallDefaultMaxR = 8;
+constexpr int64_t kSmallDefaultMaxNR = 2560;
 inline bool small_plan(const cphifi_ui_desc& d) {
   constexpr int32_t kOff = CPHIFI_FLAG_EIGENBASIS | CPHIFI_FLAG_TOEPLITZ_K |
                            CPHIFI_FLAG_FIBER_COLLAPSE | CPHIFI_FLAG_NO_UKT_COPY |
-                           CPHIFI_FLAG_TIME_KERNELS;
-  return d.precision == CPHIFI_FP64 && (d.flags & CPHIFI_FLAG_PERSISTENT) && !(d.flags & kOff) &&
-         small_path_fits(d.n, (int)d.r, d.q, (int64_t)kMaxSplit * d.n * round_up(d.r, 16));
+                           CPHIFI_FLAG_TIME_KERNELS | CPHIFI_FLAG_NO_PERSISTENT;
+  const bool wanted = (d.flags & CPHIFI_FLAG_PERSISTENT) ||
+                      (d.r <= kSmallDefaultMaxR && d.n * d.r <= kSmallDefaultMaxNR);
+  return d.precision == CPHIFI_FP64 && wanted && !(d.flags & kOff) &&
+         small_path_fits(d.n, (int)d.r);
 }
 inline bool keeps_ukt(const cphifi_ui_desc& d) {
   return (d.n >= kUktMinN && !(d.flags & CPHIFI_FLAG_NO_UKT_COPY)) || small_plan(d);
@@ -100,7 +106,7 @@ struct cphifi_plan {
   int32_t* fidx = nullptr;     //   fidx[fptr[s] .. fptr[s+1]) (their sample index)
   double* fgram = nullptr;     //   and G = B^T B
   int32_t fmax = 0;            //   most fibers at one time point
-  int32_t* obst = nullptr;     // small plans: time index of every observation
+  bool small = false;          // FLAG_PERSISTENT taken: the persistent PCG (small.hip)
   hipGraphExec_t pcg_graph = nullptr;  // captured FP64 PCG iterations (paper form)
   GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
   int last_ksplit = 1;  // split-K depth of the partials the last product wrote

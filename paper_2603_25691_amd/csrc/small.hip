@@ -1,24 +1,32 @@
-// Persistent single-workgroup FP64 PCG for small subproblems (Section 4.4).
+// Persistent multi-workgroup FP64 PCG for small subproblems (Section 4.4).
 //
 // For a small UI subproblem (K of a few hundred points, a few thousand
 // observations) every step of a PCG iteration is a few microseconds of work,
-// and a multi-kernel iteration spends its time in launches and in the host's
-// convergence polls.  Here the whole iteration loop -- the two-step product
-// (Section 4.4.1, eqs. vl, yhat1), the eq. (fx) preconditioner (Section
-// 4.4.2) and the textbook PCG recurrence -- runs in ONE workgroup of 1024
-// threads.  Every reduction is a fixed-order workgroup sum, so the result does
-// not depend on scheduling, and the scalars stay in registers.
-//
-// The steps are laid out for latency, not bandwidth (the operands sit in L2):
-//  * the n x n products are all of the form Y(s, c) = sum_k M[k ldm + s] X(k, c)
-//    (K is symmetric; U and U^T come from the two stored layouts), so a wave's
-//    64 lanes read 64 consecutive entries of a row of M per k; X is staged in
-//    LDS; the k range is split over the waves that share a (64-row block,
-//    4-column group) item, with 8 loads per lane in flight, and the slices
-//    are added in a fixed order through LDS;
-//  * the gather-scatter runs one thread per observation (its time index from
-//    a per-observation copy), writing x_l Zhat(l, :) to a scratch row, then one
-//    thread per (row, column) adds its segment's rows in order.
+// and a multi-kernel iteration spends its time in the minimum duration of
+// each of its ~11 dependent launches.  Here the whole iteration loop -- the
+// two-step product (Section 4.4.1, eqs. vl, yhat1), the eq. (fx)
+// preconditioner (Section 4.4.2) and the textbook PCG recurrence -- runs in
+// ONE launch of up to 128 co-resident workgroups that meet at bounded grid
+// barriers.  Each wave owns rows s = w, w + W, ... (W waves in the grid) of
+// every n x r vector, and a step is done row by row:
+//  * products Y(s,:) = sum_k M(s,k) X(k,:) with M one of K (symmetric), U^T
+//    (the stored eigenvector rows) and U (the transposed copy), so row s of M
+//    is contiguous: lanes stride over k, each lane keeps r running sums, and a
+//    butterfly over the 64 lanes adds them (every lane ends with the same
+//    bits);
+//  * the gather-scatter of a row runs over its time point's observations, one
+//    per lane: x_l = Xhat(s,:) . Zhat(l,:) (eq. vl), then x_l Zhat(l,:) summed
+//    over the lanes (eq. yhat1);
+//  * the r x r middle step of eq. (fx) per row, lanes over the columns.
+// A vector that every row reads in the next step and that the recurrence
+// updates in place (the residual and the search direction) is kept in two
+// buffers and its update is formed on the fly by the reading product, so an
+// iteration needs four barriers: after the gather, after p^T q, after the
+// residual update and first preconditioner step, after r^T z.  Dot products
+// are summed per workgroup in a fixed order, then over the workgroups in a
+// fixed order by every workgroup alike, so all take the same decisions and the
+// result does not depend on the schedule.  Every barrier wait is bounded: a
+// workgroup that waits too long raises an error flag on which all leave.
 // The setup (V, eig(V), D), the right-hand side and the FP64 certificate stay
 // the library's ordinary kernels.
 #include "cphifi_internal.h"
@@ -30,235 +38,415 @@ namespace cphifi {
 namespace {
 
 constexpr int kT = kSmallThreads;
-constexpr int kW = kT / 64;
-constexpr int kSC = kSmallCols;
-constexpr int kUnroll = 8;
+constexpr int kWaves = kT / 64;
+constexpr int kSmallGrid = 64;  // workgroups of a launch (at most kSmallMaxWG)
+static_assert(kSmallGrid <= kSmallMaxWG, "flags and partials sized for kSmallMaxWG");
+// k steps per lane whose loads are issued together (fewer for wide rows, whose
+// r running sums and staged rows fill the registers)
+template <int RC>
+constexpr int k_steps() {
+  return RC <= 8 ? 4 : RC <= 16 ? 2 : 1;
+}
 
-struct Lds {
-  double xs[kSmallMaxNR];         // X of the current product
-  double red[kW * 64 * kSC];      // k-slice partial sums (also the workgroup sums)
-};
-
-__device__ double wg_sum(double v, double* red) {
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < kW; ++w) t += red[w];
-  return t;
+  return v;
 }
 
-// Y (n x r) = op(M) X with op(M)(s, k) = M[k ldm + s].
-__device__ void sprod(const double* __restrict__ M, int64_t ldm, const double* __restrict__ X,
-                      double* __restrict__ Y, int n, int r, Lds& L) {
-  __syncthreads();  // X complete, xs / red free
-  for (int e = threadIdx.x; e < n * r; e += kT) L.xs[e] = X[e];
+// Bounded grid barrier on per-workgroup arrival flags: thread 0 releases the
+// workgroup's writes and publishes the barrier count in its own line; the
+// first wave waits until every workgroup's count has reached it (one load per
+// lane per poll), then thread 0 acquires the other workgroups' writes.  With
+// no shared counter the arrivals do not queue on one atomic (at 52
+// workgroups 3.2 against 4.3 us per barrier).  False when a wait timed out here
+// or in another workgroup.
+__device__ __forceinline__ bool grid_sync(SmallCtl* ctl, uint32_t epoch, int64_t spin_limit,
+                                          int* s_ok) {
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nb = (n + 63) / 64, ng = (r + kSC - 1) / kSC;
-  const int items = nb * ng;
-  const int nsl = max(1, kW / items);      // waves per item (k slices)
-  const int ngroups = kW / nsl;            // items in flight
-  const int grp = wave / nsl, sl = wave % nsl;
-  const int kchunk = (n + nsl - 1) / nsl;
-  const int kb = min(n, sl * kchunk), ke = min(n, kb + kchunk);
-  const int trips = (items + ngroups - 1) / ngroups;
-  for (int t = 0; t < trips; ++t) {
-    const int it = grp + t * ngroups;
-    const bool active = grp < ngroups && it < items;
-    int s = 0, c0 = 0, nc = 0;
-    if (active) {
-      const int b = it / ng, g = it % ng;
-      c0 = g * kSC;
-      nc = min(kSC, r - c0);
-      s = b * 64 + lane;
-      double acc[kSC];
-#pragma unroll
-      for (int j = 0; j < kSC; ++j) acc[j] = 0.0;
-      const double* mp = M + min(s, n - 1);  // lanes past n compute a row they do not store
-      int k = kb;
-      for (; k + kUnroll <= ke; k += kUnroll) {
-        double m[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) m[u] = mp[(int64_t)(k + u) * ldm];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const double* xr = L.xs + (k + u) * r + c0;
-#pragma unroll
-          for (int j = 0; j < kSC; ++j)
-            if (j < nc) acc[j] = fma(m[u], xr[j], acc[j]);
-        }
-      }
-      for (; k < ke; ++k) {
-        const double mv = mp[(int64_t)k * ldm];
-        const double* xr = L.xs + k * r + c0;
-#pragma unroll
-        for (int j = 0; j < kSC; ++j)
-          if (j < nc) acc[j] = fma(mv, xr[j], acc[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < kSC; ++j) L.red[(wave * 64 + lane) * kSC + j] = acc[j];
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0) {
+      __threadfence();  // release this workgroup's writes device-wide
+      __hip_atomic_store(&ctl->flag[blockIdx.x * 16], epoch, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (active && sl == 0 && s < n) {
-      for (int j = 0; j < nc; ++j) {
-        double v = 0.0;
-        for (int q = 0; q < nsl; ++q) v += L.red[((wave + q) * 64 + lane) * kSC + j];
-        Y[(int64_t)s * r + c0 + j] = v;
+    int ok = 1;
+    for (int64_t spin = 0;; ++spin) {
+      bool mine = true;
+      for (int g = threadIdx.x; g < (int)gridDim.x; g += 64)
+        mine = mine && __hip_atomic_load(&ctl->flag[g * 16], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+      if (__all(mine)) break;
+      if ((spin & 63) == 63 &&
+          __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 0;
+        break;
       }
+      if (spin >= spin_limit) {
+        if (threadIdx.x == 0)
+          __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
     }
-    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();  // acquire the other workgroups' writes
+      *s_ok = ok;
+    }
   }
+  __syncthreads();
+  return *s_ok != 0;
 }
 
-// Y1 = G(Xh): x_l = <Xh(t_l,:), Zhat(l,:)> (eq. vl), Y1(s,:) = sum over the
-// segment of x_l Zhat(l,:) (eq. yhat1).
-__device__ void sgather(const SmallArgs& a, const int32_t* __restrict__ obs_t, int64_t q,
-                        const double* __restrict__ Xh, double* __restrict__ Y1) {
-  const int r = a.r;
-  __syncthreads();  // Xh complete
-  for (int64_t l = threadIdx.x; l < q; l += kT) {
-    const int32_t t = obs_t[l];
-    const double* xh = Xh + (int64_t)t * r;
-    double* w = a.Wq + l * r;
+// acc(c) = sum_k M[row ldm + k] X(k, c), X(k,:) = X1(k,:) + coef X2(k,:) when X2
+// is given (formed with the same fma as the owner's stored copy); every lane
+// returns the full sums.
+template <int RC>
+__device__ __forceinline__ void row_product(const double* __restrict__ M, int64_t ldm, int64_t row,
+                                            int n, int r, const double* __restrict__ X1,
+                                            const double* __restrict__ X2, double coef,
+                                            double (&acc)[RC]) {
+  constexpr int kKU = k_steps<RC>();
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+  const double* mrow = M + row * ldm;
+  for (int k0 = lane; k0 < n; k0 += 64 * kKU) {
+    double m[kKU];
+    double x[kKU][RC];
+#pragma unroll
+    for (int u = 0; u < kKU; ++u) {
+      const int k = k0 + 64 * u;
+      const bool on = k < n;
+      const int kc = on ? k : 0;
+      m[u] = on ? mrow[kc] : 0.0;
+      const double* x1 = X1 + (int64_t)kc * r;
+      const double* x2 = X2 != nullptr ? X2 + (int64_t)kc * r : nullptr;
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        double v = 0.0;
+        if (c < r) v = x2 != nullptr ? fma(coef, x2[c], x1[c]) : x1[c];
+        x[u][c] = v;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kKU; ++u)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) acc[c] = fma(m[u], x[u][c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < RC; ++c) acc[c] = c < r ? wave_sum(acc[c]) : 0.0;
+}
+
+// Yhat1(s,:) from Xhat(s,:) = xh: eqs. (vl), (yhat1) over the observations of
+// time point s, one per lane.
+template <int RC>
+__device__ __forceinline__ void row_gather(const SmallArgs& a, int64_t s, const double (&xh)[RC],
+                                           double (&acc)[RC]) {
+  const int lane = threadIdx.x & 63, r = a.r;
+#pragma unroll
+  for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+  const int32_t beg = a.obs_ptr[s], end = a.obs_ptr[s + 1];
+  for (int32_t l = beg + lane; l < end; l += 64) {
+    double z[RC];
     if (a.Zhat != nullptr) {
-      const double* z = a.Zhat + l * r;
-      double x = 0.0;
-      for (int c = 0; c < r; ++c) x = fma(xh[c], z[c], x);
-      for (int c = 0; c < r; ++c) w[c] = x * z[c];
+      const double* zr = a.Zhat + (int64_t)l * r;
+#pragma unroll
+      for (int c = 0; c < RC; ++c) z[c] = c < r ? zr[c] : 0.0;
     } else {
       const double* za = a.A + (int64_t)a.obs_i[l] * r;
       const double* zb = a.B + (int64_t)a.obs_j[l] * r;
-      double x = 0.0;
-      for (int c = 0; c < r; ++c) x = fma(xh[c], za[c] * zb[c], x);
-      for (int c = 0; c < r; ++c) w[c] = x * (za[c] * zb[c]);
+#pragma unroll
+      for (int c = 0; c < RC; ++c) z[c] = c < r ? za[c] * zb[c] : 0.0;
     }
+    double x = 0.0;
+#pragma unroll
+    for (int c = 0; c < RC; ++c) x = fma(xh[c], z[c], x);
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = fma(x, z[c], acc[c]);
   }
-  __syncthreads();
-  const int64_t len = a.n * r;
-  for (int64_t e = threadIdx.x; e < len; e += kT) {
-    const int64_t s = e / r;
-    const int c = (int)(e % r);
-    const int32_t b0 = a.obs_ptr[s], e0 = a.obs_ptr[s + 1];
-    double acc = 0.0;
-    int32_t l = b0;
-    for (; l + 4 <= e0; l += 4) {
-      const double w0 = a.Wq[(int64_t)l * r + c], w1 = a.Wq[(int64_t)(l + 1) * r + c];
-      const double w2 = a.Wq[(int64_t)(l + 2) * r + c], w3 = a.Wq[(int64_t)(l + 3) * r + c];
-      acc += w0;
-      acc += w1;
-      acc += w2;
-      acc += w3;
-    }
-    for (; l < e0; ++l) acc += a.Wq[(int64_t)l * r + c];
-    Y1[e] = acc;
-  }
+#pragma unroll
+  for (int c = 0; c < RC; ++c) acc[c] = c < r ? wave_sum(acc[c]) : 0.0;
 }
 
-// Z = M^{-1} R by eq. fx: T1 = U^T R, T2(s,:) = ((T1(s,:) U_V) had D(s,:)) U_V^T,
-// Z = U T2.
-__device__ void sprecond(const SmallArgs& a, const double* R, double* Z, Lds& L) {
+// The Zhat rows of time point s's observations, one per lane (zero past the
+// segment); false when the segment is longer than a wave.
+template <int RC>
+__device__ __forceinline__ bool row_obs(const SmallArgs& a, int64_t s, double (&z)[RC]) {
+  const int lane = threadIdx.x & 63, r = a.r;
+  const int32_t beg = a.obs_ptr[s], end = a.obs_ptr[s + 1];
+#pragma unroll
+  for (int c = 0; c < RC; ++c) z[c] = 0.0;
+  if (end - beg > 64) return false;
+  const int32_t l = beg + lane;
+  if (l < end) {
+    if (a.Zhat != nullptr) {
+      const double* zr = a.Zhat + (int64_t)l * r;
+#pragma unroll
+      for (int c = 0; c < RC; ++c) z[c] = c < r ? zr[c] : 0.0;
+    } else {
+      const double* za = a.A + (int64_t)a.obs_i[l] * r;
+      const double* zb = a.B + (int64_t)a.obs_j[l] * r;
+#pragma unroll
+      for (int c = 0; c < RC; ++c) z[c] = c < r ? za[c] * zb[c] : 0.0;
+    }
+  }
+  return true;
+}
+
+// row_gather with the observation rows already in registers (the same
+// arithmetic: lanes past the segment add zeros).
+template <int RC>
+__device__ __forceinline__ void row_gather_reg(int r, const double (&z)[RC],
+                                               const double (&xh)[RC], double (&acc)[RC]) {
+  double x = 0.0;
+#pragma unroll
+  for (int c = 0; c < RC; ++c) x = fma(xh[c], z[c], x);
+#pragma unroll
+  for (int c = 0; c < RC; ++c) acc[c] = c < r ? wave_sum(fma(x, z[c], 0.0)) : 0.0;
+}
+
+// T2(s,:) = ((T1(s,:) U_V) had D(s,:)) U_V^T, the middle step of eq. (fx);
+// returns lane c's entry (c < r).
+template <int RC>
+__device__ __forceinline__ double row_mid(const SmallArgs& a, int64_t s, const double (&t1)[RC]) {
+  const int lane = threadIdx.x & 63, r = a.r;
+  double w = 0.0;
+  if (lane < r) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < RC; ++i)
+      if (i < r) v = fma(t1[i], a.UV[i * r + lane], v);
+    w = v * a.D[s * r + lane];
+  }
+  double t = 0.0;
+  for (int j = 0; j < r; ++j) {
+    const double wj = __shfl(w, j, 64);
+    if (lane < r) t = fma(wj, a.UV[lane * r + j], t);
+  }
+  return t;
+}
+
+// Sum of v over the workgroup in a fixed order, written to dst[blockIdx.x].
+__device__ __forceinline__ void wg_partial(double v, double* dst, double* s_red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += s_red[w];
+    dst[blockIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// Sum of the workgroups' partials, in the same order in every wave.
+__device__ __forceinline__ double grid_total(const double* src) {
+  double v = 0.0;
+  for (int i = threadIdx.x & 63; i < (int)gridDim.x; i += 64) v += src[i];
+  return wave_sum(v);
+}
+
+template <int RC>
+__global__ __launch_bounds__(kT) void small_pcg_kernel(SmallArgs a) {
+  __shared__ double s_red[kWaves];
+  __shared__ int s_ok;
+  SmallCtl* ctl = (SmallCtl*)a.scratch;
+  double* part = (double*)((char*)a.scratch + sizeof(SmallCtl));
+  double* p_pq = part;
+  double* p_rr = part + kSmallMaxWG;
+  double* p_rz = part + 2 * kSmallMaxWG;
+  double* p_bb = part + 3 * kSmallMaxWG;
   const int n = (int)a.n, r = a.r;
-  sprod(a.UKT, a.ldk, R, a.T1, n, r, L);
-  __syncthreads();
-  const int64_t len = a.n * r;
-  for (int64_t e = threadIdx.x; e < len; e += kT) {
-    const int64_t s = e / r;
-    const int c = (int)(e % r);
-    const double* t1 = a.T1 + s * r;
-    double acc = 0.0;
-    for (int j = 0; j < r; ++j) {
-      double v = 0.0;
-      for (int i = 0; i < r; ++i) v = fma(t1[i], a.UV[i * r + j], v);
-      acc = fma(v * a.D[s * r + j], a.UV[c * r + j], acc);
-    }
-    a.T2[e] = acc;
+  const int lane = threadIdx.x & 63;
+  const int w0 = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int nw = gridDim.x * kWaves;
+  const bool lc = lane < r;  // the lane that stores column `lane` of a row
+  uint32_t nbar = 0;
+  bool ok = true;
+  auto sync = [&]() {
+    ++nbar;
+    ok = ok && grid_sync(ctl, nbar, a.spin_limit, &s_ok);
+    return ok;
+  };
+  auto at = [&](double* v, int64_t s) { return v + s * r + lane; };
+  auto atc = [&](const double* v, int64_t s) { return v[s * r + lane]; };
+  double acc[RC], t[RC];
+  // The observation rows of the wave's first two rows stay in registers for
+  // the whole solve when their segments fit a wave: the gather then reads
+  // only Xhat.
+  constexpr bool kCache = RC <= 16;
+  double zc0[RC], zc1[RC];
+  bool c0 = false, c1 = false;
+  if (kCache) {
+    if (w0 < n) c0 = row_obs<RC>(a, w0, zc0);
+    if (w0 + nw < n) c1 = row_obs<RC>(a, w0 + nw, zc1);
   }
-  sprod(a.UK, a.ldk, a.T2, Z, n, r, L);
-}
-
-// Q = A P (paper form): Xh = K P, Y1 = G(Xh), Q = K Y1 + lambda Xh + rho P.
-__device__ void sapply(const SmallArgs& a, const int32_t* obs_t, int64_t q, const double* P,
-                       double* Q, Lds& L) {
-  const int n = (int)a.n, r = a.r;
-  sprod(a.K, a.ldk, P, a.Xh, n, r, L);
-  sgather(a, obs_t, q, a.Xh, a.Y1);
-  sprod(a.K, a.ldk, a.Y1, a.T2, n, r, L);
-  __syncthreads();
-  const int64_t len = a.n * r;
-  for (int64_t e = threadIdx.x; e < len; e += kT) Q[e] = a.T2[e] + a.lam * a.Xh[e] + a.rho * P[e];
-}
-
-__global__ __launch_bounds__(kT) void small_pcg_kernel(SmallArgs a, const int32_t* obs_t,
-                                                       int64_t q) {
-  __shared__ Lds L;
-  double* red = L.red;
-  const int64_t len = a.n * a.r;
-  double* X = a.X;
-  double* R = a.R;
-  double* Z = a.Z;
-  double* P = a.P;
-  double* Q = a.Q;
-  // r = b (x0 = 0) or b - A x0
-  if (a.warm) {
-    sapply(a, obs_t, q, X, Q, L);
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < len; e += kT) R[e] = a.b[e] - Q[e];
-  } else {
-    for (int64_t e = threadIdx.x; e < len; e += kT) {
-      X[e] = 0.0;
-      R[e] = a.b[e];
-    }
-  }
-  double bb = 0.0, rr = 0.0;
-  for (int64_t e = threadIdx.x; e < len; e += kT) bb += a.b[e] * a.b[e];
-  bb = wg_sum(bb, red);
-  for (int64_t e = threadIdx.x; e < len; e += kT) rr += R[e] * R[e];
-  rr = wg_sum(rr, red);
-  const double tol2 = a.tol * a.tol * bb;
-  if (a.hist != nullptr && threadIdx.x == 0) a.hist[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-  int status = CPHIFI_NOT_CONVERGED, it = 0;
-  if (!isfinite(bb) || !isfinite(rr)) {
-    status = CPHIFI_NUMERIC;
-  } else if (bb == 0.0 || rr <= tol2) {
-    status = CPHIFI_OK;
-  } else {
-    if (a.precond)
-      sprecond(a, R, Z, L);
+  auto gather = [&](int j, int64_t s, const double (&xh)[RC], double (&out)[RC]) {
+    if (kCache && j == 0 && c0)
+      row_gather_reg<RC>(r, zc0, xh, out);
+    else if (kCache && j == 1 && c1)
+      row_gather_reg<RC>(r, zc1, xh, out);
     else
-      for (int64_t e = threadIdx.x; e < len; e += kT) Z[e] = R[e];
-    __syncthreads();
-    double rz = 0.0;
-    for (int64_t e = threadIdx.x; e < len; e += kT) {
-      P[e] = Z[e];
-      rz += R[e] * Z[e];
+      row_gather<RC>(a, s, xh, out);
+  };
+
+  // x0 and r0 = b - A x0
+  double bbl = 0.0, rrl = 0.0;
+  if (a.warm) {
+    int j = 0;
+    for (int64_t s = w0; s < n; s += nw, ++j) {
+      row_product<RC>(a.K, a.ldk, s, n, r, a.X, nullptr, 0.0, acc);
+      gather(j, s, acc, t);
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < r && lane == c) {
+          a.Xh[s * r + c] = acc[c];
+          a.Y1[s * r + c] = t[c];
+        }
     }
-    rz = wg_sum(rz, red);
-    if (!(rz > 0.0) || !isfinite(rz)) status = isfinite(rz) ? CPHIFI_BREAKDOWN : CPHIFI_NUMERIC;
+    if (!sync()) goto out;
+    for (int64_t s = w0; s < n; s += nw) {
+      row_product<RC>(a.K, a.ldk, s, n, r, a.Y1, nullptr, 0.0, acc);
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < r && lane == c) {
+          const int64_t e = s * r + c;
+          const double q = acc[c] + a.lam * a.Xh[e] + a.rho * a.X[e];
+          const double v = a.b[e] - q;
+          a.R0[e] = v;
+          rrl += v * v;
+          bbl += a.b[e] * a.b[e];
+        }
+    }
+  } else {
+    for (int64_t s = w0; s < n; s += nw)
+      if (lc) {
+        const double v = atc(a.b, s);
+        *at(a.X, s) = 0.0;
+        *at(a.R0, s) = v;
+        bbl += v * v;
+      }
+    rrl = bbl;
+  }
+  for (int64_t s = w0; s < n; s += nw)
+    if (lc) *at(a.P1, s) = 0.0;  // the "previous" direction of the first iteration
+  wg_partial(bbl, p_bb, s_red);
+  wg_partial(rrl, p_rr, s_red);
+  {
+    if (!sync()) goto out;
+    const double bb = grid_total(p_bb);
+    double rr = grid_total(p_rr);
+    const double tol2 = a.tol * a.tol * bb;
+    if (a.hist != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
+      a.hist[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    int status = CPHIFI_NOT_CONVERGED, it = 0;
+    double rz = 0.0, beta = 0.0;
+    if (!isfinite(bb) || !isfinite(rr)) {
+      status = CPHIFI_NUMERIC;
+    } else if (bb == 0.0 || rr <= tol2) {
+      status = CPHIFI_OK;
+    } else {
+      // z0 = M^{-1} r0 (eq. fx), rz = r0 . z0
+      double rzl = 0.0;
+      if (a.precond) {
+        for (int64_t s = w0; s < n; s += nw) {
+          row_product<RC>(a.UK, a.ldk, s, n, r, a.R0, nullptr, 0.0, acc);
+          const double v = row_mid<RC>(a, s, acc);
+          if (lc) *at(a.T2, s) = v;
+        }
+        if (!sync()) goto out;
+        for (int64_t s = w0; s < n; s += nw) {
+          row_product<RC>(a.UKT, a.ldk, s, n, r, a.T2, nullptr, 0.0, acc);
+#pragma unroll
+          for (int c = 0; c < RC; ++c)
+            if (c < r && lane == c) {
+              a.Z[s * r + c] = acc[c];
+              rzl += a.R0[s * r + c] * acc[c];
+            }
+        }
+      } else {
+        for (int64_t s = w0; s < n; s += nw)
+          if (lc) {
+            const double v = atc(a.R0, s);
+            *at(a.Z, s) = v;
+            rzl += v * v;
+          }
+      }
+      wg_partial(rzl, p_rz, s_red);
+      if (!sync()) goto out;
+      rz = grid_total(p_rz);
+      if (!(rz > 0.0) || !isfinite(rz)) status = isfinite(rz) ? CPHIFI_BREAKDOWN : CPHIFI_NUMERIC;
+    }
     while (status == CPHIFI_NOT_CONVERGED && it < a.maxit) {
-      sapply(a, obs_t, q, P, Q, L);
-      __syncthreads();
-      double pq = 0.0;
-      for (int64_t e = threadIdx.x; e < len; e += kT) pq += P[e] * Q[e];
-      pq = wg_sum(pq, red);
+      double* Pc = (it & 1) ? a.P1 : a.P0;   // this iteration's direction
+      double* Pp = (it & 1) ? a.P0 : a.P1;   // the previous one
+      double* Ro = (it & 1) ? a.R1 : a.R0;   // residual before the update
+      double* Rn = (it & 1) ? a.R0 : a.R1;   // and after it
+      // Xhat = K p with p = z + beta p_prev formed on the fly; Yhat1 = G(Xhat)
+      int j = 0;
+      for (int64_t s = w0; s < n; s += nw, ++j) {
+        row_product<RC>(a.K, a.ldk, s, n, r, a.Z, Pp, beta, acc);
+        gather(j, s, acc, t);
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c < r && lane == c) {
+            const int64_t e = s * r + c;
+            Pc[e] = fma(beta, Pp[e], a.Z[e]);
+            a.Xh[e] = acc[c];
+            a.Y1[e] = t[c];
+          }
+      }
+      if (!sync()) goto out;
+      // q = K Yhat1 + lambda Xhat + rho p, p . q
+      double pql = 0.0;
+      for (int64_t s = w0; s < n; s += nw) {
+        row_product<RC>(a.K, a.ldk, s, n, r, a.Y1, nullptr, 0.0, acc);
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c < r && lane == c) {
+            const int64_t e = s * r + c;
+            const double q = acc[c] + a.lam * a.Xh[e] + a.rho * Pc[e];
+            a.Q[e] = q;
+            pql += Pc[e] * q;
+          }
+      }
+      wg_partial(pql, p_pq, s_red);
+      if (!sync()) goto out;
+      const double pq = grid_total(p_pq);
       if (!(pq > 0.0) || !isfinite(pq)) {
         status = isfinite(pq) ? CPHIFI_BREAKDOWN : CPHIFI_NUMERIC;
         break;
       }
       const double alpha = rz / pq;
-      double rrl = 0.0;
-      for (int64_t e = threadIdx.x; e < len; e += kT) {
-        X[e] += alpha * P[e];
-        const double v = R[e] - alpha * Q[e];
-        R[e] = v;
-        rrl += v * v;
+      // x += alpha p, r_new = r - alpha q, ||r_new||^2; first step of eq. fx
+      // on r_new (formed on the fly from r and q)
+      double rrn = 0.0, rzn = 0.0;
+      for (int64_t s = w0; s < n; s += nw) {
+        if (a.precond) row_product<RC>(a.UK, a.ldk, s, n, r, Ro, a.Q, -alpha, acc);
+        const double mid = a.precond ? row_mid<RC>(a, s, acc) : 0.0;
+        if (lc) {
+          const int64_t e = s * r + lane;
+          a.X[e] += alpha * Pc[e];
+          const double v = fma(-alpha, a.Q[e], Ro[e]);
+          Rn[e] = v;
+          rrn += v * v;
+          if (a.precond) {
+            a.T2[e] = mid;
+          } else {
+            a.Z[e] = v;
+            rzn += v * v;
+          }
+        }
       }
-      rr = wg_sum(rrl, red);
+      wg_partial(rrn, p_rr, s_red);
+      if (!a.precond) wg_partial(rzn, p_rz, s_red);
+      if (!sync()) goto out;
+      rr = grid_total(p_rr);
       ++it;
-      if (a.hist != nullptr && threadIdx.x == 0 && it < a.hist_len)
+      if (a.hist != nullptr && blockIdx.x == 0 && threadIdx.x == 0 && it < a.hist_len)
         a.hist[it] = sqrt(rr / bb);
       if (!isfinite(rr)) {
         status = CPHIFI_NUMERIC;
@@ -269,46 +457,73 @@ __global__ __launch_bounds__(kT) void small_pcg_kernel(SmallArgs a, const int32_
         break;
       }
       if (it >= a.maxit) break;
-      if (a.precond)
-        sprecond(a, R, Z, L);
-      else
-        for (int64_t e = threadIdx.x; e < len; e += kT) Z[e] = R[e];
-      __syncthreads();
-      double rzl = 0.0;
-      for (int64_t e = threadIdx.x; e < len; e += kT) rzl += R[e] * Z[e];
-      const double rz_new = wg_sum(rzl, red);
+      if (a.precond) {
+        // z = U T2 (eq. fx), r . z
+        for (int64_t s = w0; s < n; s += nw) {
+          row_product<RC>(a.UKT, a.ldk, s, n, r, a.T2, nullptr, 0.0, acc);
+#pragma unroll
+          for (int c = 0; c < RC; ++c)
+            if (c < r && lane == c) {
+              a.Z[s * r + c] = acc[c];
+              rzn += Rn[s * r + c] * acc[c];
+            }
+        }
+        wg_partial(rzn, p_rz, s_red);
+        if (!sync()) goto out;
+      }
+      const double rz_new = grid_total(p_rz);
       if (!(rz_new > 0.0) || !isfinite(rz_new)) {
         status = isfinite(rz_new) ? CPHIFI_BREAKDOWN : CPHIFI_NUMERIC;
         break;
       }
-      const double beta = rz_new / rz;
+      beta = rz_new / rz;
       rz = rz_new;
-      for (int64_t e = threadIdx.x; e < len; e += kT) P[e] = Z[e] + beta * P[e];
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.out->iters = it;
+      a.out->status = status;
+      a.out->rr = rr;
+      a.out->bb = bb;
+    }
+    return;
   }
-  if (threadIdx.x == 0) {
-    a.out->iters = it;
-    a.out->status = status;
-    a.out->rr = rr;
-    a.out->bb = bb;
+out:
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.out->iters = 0;
+    a.out->status = kSmallTimeout;
+    a.out->rr = 0.0;
+    a.out->bb = 0.0;
   }
+}
+
+__global__ __launch_bounds__(256) void small_reset_kernel(SmallCtl* ctl) {
+  for (int i = threadIdx.x; i < kSmallMaxWG * 16; i += blockDim.x) ctl->flag[i] = 0u;
+  if (threadIdx.x == 0) ctl->err = 0;
 }
 
 }  // namespace
 
-bool small_path_fits(int64_t n, int r, int64_t q, int64_t wq_cap) {
-  return n <= kSmallMaxN && r <= kSmallMaxRank && n * r <= kSmallMaxNR &&
-         (double)n * (double)n * r <= kSmallMaxProductWork &&
-         (double)q * r <= kSmallMaxObsWork && q * r <= wq_cap;
+bool small_path_fits(int64_t n, int r) {
+  return n >= 1 && n <= kSmallMaxN && r >= 1 && r <= kSmallMaxRank;
 }
 
-int launch_small_pcg(const SmallArgs& a, const int32_t* obs_t, int64_t q, hipStream_t st) {
-  if (!small_path_fits(a.n, a.r, q, q * a.r) || a.UKT == nullptr || a.Wq == nullptr ||
-      (q > 0 && obs_t == nullptr)) {
+int launch_small_pcg(const SmallArgs& a, hipStream_t st) {
+  if (!small_path_fits(a.n, a.r) || a.UKT == nullptr || a.UK == nullptr ||
+      a.scratch == nullptr || a.out == nullptr || a.spin_limit < 1) {
     set_error("internal: persistent PCG launched outside its bounds");
     return CPHIFI_INVALID_ARG;
   }
-  hipLaunchKernelGGL(small_pcg_kernel, dim3(1), dim3(kT), 0, st, a, obs_t, q);
+  // one row per wave up to 256 rows, then 64 workgroups (a barrier over more
+  // workgroups costs more than the rows it spreads: 3.2 us at 52, 7.2 at 128)
+  const int grid = (int)std::min<int64_t>(kSmallGrid, (a.n + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(small_reset_kernel, dim3(1), dim3(256), 0, st, (SmallCtl*)a.scratch);
+  CPHIFI_CHECK_LAUNCH();
+  if (a.r <= 8)
+    hipLaunchKernelGGL(small_pcg_kernel<8>, dim3(grid), dim3(kT), 0, st, a);
+  else if (a.r <= 16)
+    hipLaunchKernelGGL(small_pcg_kernel<16>, dim3(grid), dim3(kT), 0, st, a);
+  else
+    hipLaunchKernelGGL(small_pcg_kernel<32>, dim3(grid), dim3(kT), 0, st, a);
   CPHIFI_CHECK_LAUNCH();
   return CPHIFI_OK;
 }

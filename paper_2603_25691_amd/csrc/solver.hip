@@ -53,7 +53,9 @@ Layout make_layout(const cphifi_ui_desc& d) {
     return o;
   };
   for (int i = 0; i < NVEC; ++i) L.vec[i] = take(sizeof(double) * nr);
-  L.part = take(sizeof(double) * (size_t)kMaxSplit * n * ldp);
+  // (the persistent PCG keeps its barrier counter and partial sums here)
+  L.part = take(std::max(sizeof(double) * (size_t)kMaxSplit * n * ldp,
+                         small_plan(d) ? small_scratch_bytes() : size_t(0)));
   L.ntask_max = n + q / kObsChunk + 1;
   L.nslot_max = 2 * (q / kObsChunk) + 2;
   L.nmulti_max = q / kObsChunk + 1;
@@ -78,7 +80,6 @@ Layout make_layout(const cphifi_ui_desc& d) {
   L.dKc = take(sizeof(double) * n);
   if (keeps_ukt(d)) L.ukt = take(sizeof(double) * (size_t)n * eff_ldk(d));
   if (d.flags & CPHIFI_FLAG_TOEPLITZ_K) L.toep = take(sizeof(double) * n);
-  if (small_plan(d)) L.obst = take(sizeof(int32_t) * std::max<int64_t>(q, 1));
   if ((d.flags & CPHIFI_FLAG_FIBER_COLLAPSE) && d.J > 0) {
     L.fptr = take(sizeof(int32_t) * (n + 1));
     L.fidx = take(sizeof(int32_t) * (q / d.J + 1));
@@ -575,7 +576,7 @@ int plan_times_K(cphifi_plan* p, const double* X, double* out) {
 
 namespace {
 
-// The whole FP64 PCG of a small subproblem in one persistent workgroup
+// The whole FP64 PCG of a small subproblem in one persistent launch
 // (small.hip): no launch or host poll per iteration.
 int run_small_pcg(cphifi_plan* p, const double* b, double* W, bool warm, int maxit,
                   PcgOut* out) {
@@ -590,6 +591,10 @@ int run_small_pcg(cphifi_plan* p, const double* b, double* W, bool warm, int max
   a.lam = p->d.lambda;
   a.rho = p->d.rho;
   a.tol = p->d.tol;
+  // CPHIFI_SMALL_SPIN_LIMIT shortens the barrier waits (tests of the fallback)
+  const char* spin_env = std::getenv("CPHIFI_SMALL_SPIN_LIMIT");
+  a.spin_limit = (spin_env != nullptr && std::atoll(spin_env) > 0) ? std::atoll(spin_env)
+                                                                   : kSmallSpinLimit;
   a.K = p->in.K;
   a.UK = p->in.UK;
   a.UKT = p->ukt;
@@ -603,21 +608,31 @@ int run_small_pcg(cphifi_plan* p, const double* b, double* W, bool warm, int max
   a.Zhat = p->in.Zhat;
   a.b = b;
   a.X = W;
-  a.R = p->vec[V_R];
+  a.R0 = p->vec[V_R];
+  a.R1 = p->vec[V_R2];
+  a.P0 = p->vec[V_P];
+  a.P1 = p->vec[V_P2];
   a.Z = p->vec[V_Z];
-  a.P = p->vec[V_P];
   a.Q = p->vec[V_Q];
   a.Xh = p->vec[V_XHAT];
   a.Y1 = p->vec[V_Y1];
-  a.T1 = p->vec[V_T2];
-  a.T2 = p->vec[V_TMP];
-  a.Wq = (double*)p->part;
+  a.T2 = p->vec[V_T2];
+  a.scratch = p->part;
   a.hist = p->hist;
   a.out = (SmallOut*)p->sc2;  // the certificate's scalars are free until it runs
-  TRY(launch_small_pcg(a, p->obst, p->q, p->st));
+  // The kernel updates W in place: keep the starting point of a warm start
+  // for the fallback below.
+  if (warm) TRY(launch_copy(p->vec[V_XB], W, p->n * p->r, p->st));
+  TRY(launch_small_pcg(a, p->st));
   SmallOut h{};
   CPHIFI_HIP(hipMemcpyAsync(&h, a.out, sizeof(h), hipMemcpyDeviceToHost, p->st));
   CPHIFI_HIP(hipStreamSynchronize(p->st));
+  if (h.status == kSmallTimeout) {
+    // Not every workgroup was resident (other work on the device): the
+    // caller runs the multi-kernel loop instead, from the same start.
+    if (warm) TRY(launch_copy(W, p->vec[V_XB], p->n * p->r, p->st));
+    return kSmallTimeout;
+  }
   out->iters = h.iters;
   out->status = h.status;
   out->relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
@@ -628,9 +643,16 @@ int solve_fp64(cphifi_plan* p, const double* b, double* W, cphifi_solve_info* in
   const bool warm = (p->d.flags & CPHIFI_FLAG_WARM_START) != 0;
   const int maxit = eff_maxit(p->d);
   PcgOut o;
-  const bool small = p->obst != nullptr && p->ukt != nullptr && !p->timing;
+  bool small = p->small && p->ukt != nullptr && !p->timing;
   if (small) {
-    TRY(run_small_pcg(p, b, W, warm, maxit, &o));
+    const int rs = run_small_pcg(p, b, W, warm, maxit, &o);
+    if (rs == kSmallTimeout)
+      small = false;
+    else
+      TRY(rs);
+  }
+  if (small) {
+    // done
   } else if (p->d.flags & CPHIFI_FLAG_EIGENBASIS) {
     // x = U xbar: PCG on the rotated system, then rotate back.
     TRY(rotate_in(p, Elt::F64, b, p->vec[V_RB]));
@@ -1233,18 +1255,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
                            choose_gemm(Elt::F64, false, n, rr, p->num_cu), p->num_cu);
   p->gp64t = plan_from_env("CPHIFI_TILE_F64T", Elt::F64, true, n, rr,
                            choose_gemm(Elt::F64, true, n, rr, p->num_cu), p->num_cu);
-  if (small_plan(*d)) {
-    p->obst = (int32_t*)(ws + L.obst);
-    std::vector<int32_t> ot(q);
-    for (int64_t s = 0; s < n; ++s)
-      for (int32_t l = ptr[s]; l < ptr[s + 1]; ++l) ot[l] = (int32_t)s;
-    if ((rc = up(p->obst, ot))) return fail(rc);
-    // the copy above is asynchronous: keep the host vector until the stream drains
-    if (hipStreamSynchronize(st) != hipSuccess) {
-      set_error("plan_create: upload of the observation times failed");
-      return fail(CPHIFI_HIP_ERROR);
-    }
-  }
+  p->small = small_plan(*d);
   if (d->flags & CPHIFI_FLAG_FIBER_COLLAPSE) {
     p->fptr = (int32_t*)(ws + L.fptr);
     p->fidx = (int32_t*)(ws + L.fidx);

@@ -18,10 +18,11 @@ Tolerances
   tests/test_oracle_spread.py;
 * mixed-precision solves refined to relres 1e-7: e_KW <= 1e-6.
 
-The FP64 solves of small plans replay a captured HIP graph of PCG iterations
-(FLAG_NO_GRAPH keeps the launch-by-launch loop; FLAG_PERSISTENT runs the
-single-workgroup iteration instead); the solve and failure tests run all three
-paths (`paths`), and two tests compare them with each other.
+The FP64 solves of small plans run three ways: the persistent multi-workgroup
+launch (FLAG_PERSISTENT; the default for r <= 8, n r <= 2560), a captured HIP
+graph of PCG iterations (FLAG_NO_PERSISTENT) and the launch-by-launch loop
+(FLAG_NO_PERSISTENT | FLAG_NO_GRAPH); the solve and failure tests run all three
+paths (`path_flags`), and two tests compare them with each other.
 """
 
 import numpy as np
@@ -73,14 +74,15 @@ def small_cases():
 
 CASES = small_cases()
 
-# FP64 iteration paths: graph replays (the default for small plans), the
-# launch-by-launch loop, and the persistent single-workgroup loop.
+# FP64 iteration paths: graph replays, the launch-by-launch loop, and the
+# persistent multi-workgroup launch.
 PATHS = ["graph", "launches", "persistent"]
 
 
 @pytest.fixture(params=PATHS)
 def path_flags(request):
-    return {"graph": 0, "launches": C.FLAG_NO_GRAPH,
+    return {"graph": C.FLAG_NO_PERSISTENT,
+            "launches": C.FLAG_NO_PERSISTENT | C.FLAG_NO_GRAPH,
             "persistent": C.FLAG_PERSISTENT}[request.param]
 
 
@@ -315,7 +317,7 @@ def test_graph_and_launch_loop_are_bitwise_equal(name, uploaded):
     graph) and on a second solve of the same plan (which replays it)."""
     p, dp = uploaded(name)
     outs = []
-    for flags in (0, C.FLAG_NO_GRAPH):
+    for flags in (C.FLAG_NO_PERSISTENT, C.FLAG_NO_PERSISTENT | C.FLAG_NO_GRAPH):
         s = UISolver(dp, p.lam, p.rho, 1e-12, flags=flags)
         for _ in range(2):
             h = np.zeros(600)
@@ -328,6 +330,22 @@ def test_graph_and_launch_loop_are_bitwise_equal(name, uploaded):
         assert ik == i0 and np.array_equal(Wk, W0) and np.array_equal(hk, h0)
 
 
+@pytest.mark.parametrize("warm", [False, True])
+def test_persistent_barrier_timeout_falls_back(warm, uploaded, monkeypatch):
+    """A barrier wait of the persistent launch that times out (forced here by a
+    one-spin limit) hands the solve to the multi-kernel loop from the same
+    start: the result still meets the dense gate, warm start included."""
+    p, dp = uploaded("c1")
+    Wd, gate = _dense_gate(p)
+    monkeypatch.setenv("CPHIFI_SMALL_SPIN_LIMIT", "1")
+    flags = C.FLAG_PERSISTENT | (C.FLAG_WARM_START if warm else 0)
+    s = UISolver(dp, p.lam, p.rho, 1e-12, flags=flags)
+    W0 = dev(0.5 * Wd) if warm else None
+    W, info = s.solve_subproblem(W=W0)
+    assert info.status == C.OK, info.as_dict()
+    assert O.e_kw(p.K, host(W), Wd) <= gate
+
+
 @pytest.mark.parametrize("name", ["c1", "ragged-r3", "ragged-r17", "c1-drop"])
 def test_persistent_and_multi_kernel_paths_agree(name, uploaded):
     """The same recurrence on the same data: iteration counts within one, the
@@ -338,7 +356,7 @@ def test_persistent_and_multi_kernel_paths_agree(name, uploaded):
     s1 = UISolver(dp, p.lam, p.rho, 1e-12, flags=C.FLAG_PERSISTENT)
     W1, i1 = s1.solve_subproblem(history=h1)
     W1 = host(W1)
-    s2 = UISolver(dp, p.lam, p.rho, 1e-12)
+    s2 = UISolver(dp, p.lam, p.rho, 1e-12, flags=C.FLAG_NO_PERSISTENT)
     W2, i2 = s2.solve_subproblem(history=h2)
     assert i1.status == C.OK and i2.status == C.OK
     assert abs(i1.iters - i2.iters) <= 1
