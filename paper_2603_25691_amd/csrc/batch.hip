@@ -209,16 +209,20 @@ struct BState {
 };
 
 // Batch-wide control words.
+constexpr int kBatchMaxGrid = 2048;  // workgroups of a launch (one barrier flag each)
+
 struct BCtl {
-  uint32_t bar;    // grid barrier arrivals (monotonic within a launch)
   uint32_t fc[4];  // work-item counters of the last four phases
   int32_t err;     // a wait timed out: every workgroup leaves
   int32_t rounds;  // rounds executed by the last launch
-  int32_t pad;
   // Real-time clock ticks (100 MHz) spent in each phase, seen by workgroup 0
   // from one barrier exit to the next: [kSlots] phases, then the round setup.
   uint64_t ticks[kSlots + 1];
+  // Grid-barrier arrival flags, one 64-byte line per workgroup: the number of
+  // barriers the workgroup has reached (the host reads only the words above).
+  uint32_t flag[kBatchMaxGrid * 16];
 };
+constexpr size_t kCtlHostBytes = offsetof(BCtl, flag);
 
 struct BArgs {
   const BSub* sub;
@@ -998,31 +1002,44 @@ __device__ __forceinline__ void run_item(const BSub& S, BState* st, int slot, in
   }
 }
 
-// Bounded grid barrier: returns false when a wait timed out (here or in any
-// other workgroup); the caller then leaves the kernel.
-__device__ __forceinline__ bool grid_sync(BCtl* ctl, uint32_t target, int64_t spin_limit, int* s_ok) {
+// Bounded grid barrier on per-workgroup arrival flags: thread 0 releases the
+// workgroup's writes and stores the barrier count in its own line; the first
+// wave polls every workgroup's flag (a few per lane) until all have reached
+// it, then thread 0 acquires the others' writes.  No shared counter, so the
+// arrivals do not queue on one atomic.  Returns false when a wait timed out
+// (here or in any other workgroup); the caller then leaves the kernel.
+__device__ __forceinline__ bool grid_sync(BCtl* ctl, uint32_t epoch, int64_t spin_limit, int* s_ok) {
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0) {
+      __threadfence();  // release this workgroup's writes device-wide
+      __hip_atomic_store(&ctl->flag[blockIdx.x * 16], epoch, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
     int ok = 1;
-    __threadfence();  // release this workgroup's writes device-wide
-    __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int64_t spin = 0;; ++spin) {
-      const uint32_t v = __hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v >= target) break;
+      bool mine = true;
+      for (int g = threadIdx.x; g < (int)gridDim.x; g += 64)
+        mine = mine && __hip_atomic_load(&ctl->flag[g * 16], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+      if (__all(mine)) break;
       if ((spin & 63) == 63 &&
           __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         ok = 0;
         break;
       }
       if (spin >= spin_limit) {
-        __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0)
+          __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();  // acquire the other workgroups' writes
-    *s_ok = ok;
+    if (threadIdx.x == 0) {
+      __threadfence();  // acquire the other workgroups' writes
+      *s_ok = ok;
+    }
   }
   __syncthreads();
   return *s_ok != 0;
@@ -1098,6 +1115,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
       if (blockIdx.x == 0 && tid == 0)
         __hip_atomic_store(&a.ctl->fc[(pi + 2) & 3], 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+      // Products and the gather take their items from a counter (their costs
+      // differ by member); the row steps' items are uniform and dealt
+      // round-robin, with no atomic per item.
+      const bool dyn = slot == S_A || slot == S_B || slot == S_OBS;
       int item = blockIdx.x;
       while (item < total) {
         // member b: last one whose range starts at or before the item
@@ -1115,17 +1136,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
         run_item(S, &a.st[b], slot, __builtin_amdgcn_readfirstlane(s_mode[b]),
                  __builtin_amdgcn_readfirstlane(s_it[b]),
                  __builtin_amdgcn_readfirstlane(item - s_pref[slot][b]), smem, s_red);
-        __syncthreads();
-        if (tid == 0)
-          s_item = (int)gridDim.x + (int)__hip_atomic_fetch_add(&a.ctl->fc[pi & 3], 1u,
-                                                                 __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        item = s_item;
+        if (dyn) {
+          __syncthreads();
+          if (tid == 0)
+            s_item = (int)gridDim.x + (int)__hip_atomic_fetch_add(&a.ctl->fc[pi & 3], 1u,
+                                                                   __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT);
+          __syncthreads();
+          item = s_item;
+        } else {
+          item += (int)gridDim.x;
+        }
       }
       ++pi;
       ++nbar;
-      if (!grid_sync(a.ctl, nbar * gridDim.x, a.spin_limit, &s_ok)) return;
+      if (!grid_sync(a.ctl, nbar, a.spin_limit, &s_ok)) return;
       if (clock0) {
         const uint64_t t = __builtin_amdgcn_s_memrealtime();
         s_tick[slot] += t - t_last;
@@ -1142,12 +1167,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 // Start state of a launch: control words cleared, every member at SETUP.
 __global__ void batch_reset_kernel(BArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctl->bar = 0;
     for (int j = 0; j < 4; ++j) a.ctl->fc[j] = 0;
     a.ctl->err = 0;
     a.ctl->rounds = 0;
     for (int j = 0; j <= kSlots; ++j) a.ctl->ticks[j] = 0;
   }
+  for (int g = threadIdx.x; g < kBatchMaxGrid; g += blockDim.x) a.ctl->flag[g * 16] = 0u;
   for (int b = threadIdx.x; b < a.count; b += blockDim.x) {
     BState s{};
     s.mode = M_SETUP;
@@ -1527,7 +1552,7 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     set_error("occupancy query of the batched kernel failed");
     return fail(CPHIFI_HIP_ERROR);
   }
-  bt->grid = num_cu * per_cu;
+  bt->grid = std::min(num_cu * per_cu, kBatchMaxGrid);
   {
     const char* e = std::getenv("CPHIFI_BATCH_GRID");
     if (e != nullptr && std::atoi(e) > 0) bt->grid = std::min(bt->grid, std::atoi(e));
@@ -1605,7 +1630,7 @@ int cphifi_batch_info(cphifi_batch* bt, cphifi_solve_info* infos) {
   }
   CPHIFI_HIP(hipMemcpyAsync(bt->h_st, bt->d_st, sizeof(BState) * bt->count,
                             hipMemcpyDeviceToHost, bt->st));
-  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, sizeof(BCtl), hipMemcpyDeviceToHost, bt->st));
+  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, kCtlHostBytes, hipMemcpyDeviceToHost, bt->st));
   CPHIFI_HIP(hipStreamSynchronize(bt->st));
   const bool timed_out = bt->h_ctl->err != 0;
   int worst = CPHIFI_OK;
@@ -1657,7 +1682,7 @@ int cphifi_batch_rounds(cphifi_batch* bt, int* rounds, int* grid) {
     set_error("bad arguments");
     return CPHIFI_INVALID_ARG;
   }
-  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, sizeof(BCtl), hipMemcpyDeviceToHost, bt->st));
+  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, kCtlHostBytes, hipMemcpyDeviceToHost, bt->st));
   CPHIFI_HIP(hipStreamSynchronize(bt->st));
   *rounds = bt->h_ctl->rounds;
   *grid = bt->grid;
@@ -1670,7 +1695,7 @@ int cphifi_batch_phase_ms(cphifi_batch* bt, double* ms) {
     set_error("bad arguments");
     return CPHIFI_INVALID_ARG;
   }
-  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, sizeof(BCtl), hipMemcpyDeviceToHost, bt->st));
+  CPHIFI_HIP(hipMemcpyAsync(bt->h_ctl, bt->d_ctl, kCtlHostBytes, hipMemcpyDeviceToHost, bt->st));
   CPHIFI_HIP(hipStreamSynchronize(bt->st));
   for (int j = 0; j <= kSlots; ++j) ms[j] = 1e-5 * (double)bt->h_ctl->ticks[j];  // 100 MHz
   return CPHIFI_OK;
