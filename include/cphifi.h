@@ -99,10 +99,11 @@ enum cphifi_flags {
                                    of co-resident workgroups that meet at
                                    grid barriers (no launch or host poll per
                                    iteration).  Plans with r <= 8 and n r <=
-                                   2560 take it without the flag (at n = 208,
-                                   r = 5: 1.25 against 2.20 ms per solve);
-                                   above that the multi-kernel loop is as fast
-                                   or faster.  Should the
+                                   2560, or r <= 12 and n <= 256, take it
+                                   without the flag (at n = 208, r = 5: 1.25
+                                   against 2.20 ms per solve); above that the
+                                   multi-kernel loop is as fast or faster.
+                                   Should the
                                    workgroups not all be resident (a barrier
                                    wait times out), the solve falls back to the
                                    multi-kernel loop */

@@ -42,18 +42,22 @@ inline int64_t eff_ldk(const cphifi_ui_desc& d) { return d.ldk > 0 ? d.ldk : d.n
 constexpr int64_t kUktMinN = 4096;
 // FP64 plans that run the persistent PCG (small.hip): asked for, or small
 // enough that it is the faster form.  Measured per solve against the graph
-// replays: n = 208, r = 5 / 8: 1.25 / 1.25 against 2.20 / 1.90 ms; n = 500,
-// r = 5: 1.20 against 1.51 ms; n = 500, r = 8: 1.88 against 1.82 ms; r = 16
-// or n = 1000: slower (up to 2.4x).  They keep the copy of U_K too (the
-// preconditioner reads rows of U and of U^T).
+// replays: n = 208, r = 5 / 8: 1.25 / 1.25 against 2.20 / 1.90 ms; n = 151 /
+// 199, r = 10: 1.54 / 1.49 against 1.99 / 2.08 ms; n = 500, r = 5: 1.20
+// against 1.51 ms; slower at n = 500, r = 8 (1.86 / 1.80), n = 269, r = 10
+// (2.65 / 2.18), r = 16 or n = 1000 (up to 2.4x).  They keep the copy of U_K
+// too (the preconditioner reads rows of U and of U^T).
 constexpr int kSmallDefaultMaxR = 8;
 constexpr int64_t kSmallDefaultMaxNR = 2560;
+constexpr int kSmallDefaultWideR = 12;     // with one row per wave:
+constexpr int64_t kSmallDefaultWideN = 256;  // n <= 4 x 64 workgroups
 inline bool small_plan(const cphifi_ui_desc& d) {
   constexpr int32_t kOff = CPHIFI_FLAG_EIGENBASIS | CPHIFI_FLAG_TOEPLITZ_K |
                            CPHIFI_FLAG_FIBER_COLLAPSE | CPHIFI_FLAG_NO_UKT_COPY |
                            CPHIFI_FLAG_TIME_KERNELS | CPHIFI_FLAG_NO_PERSISTENT;
   const bool wanted = (d.flags & CPHIFI_FLAG_PERSISTENT) ||
-                      (d.r <= kSmallDefaultMaxR && d.n * d.r <= kSmallDefaultMaxNR);
+                      (d.r <= kSmallDefaultMaxR && d.n * d.r <= kSmallDefaultMaxNR) ||
+                      (d.r <= kSmallDefaultWideR && d.n <= kSmallDefaultWideN);
   return d.precision == CPHIFI_FP64 && wanted && !(d.flags & kOff) &&
          small_path_fits(d.n, (int)d.r);
 }

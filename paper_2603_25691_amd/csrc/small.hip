@@ -277,17 +277,16 @@ __global__ __launch_bounds__(kT) void small_pcg_kernel(SmallArgs a) {
   // The observation rows of the wave's first two rows stay in registers for
   // the whole solve when their segments fit a wave: the gather then reads
   // only Xhat.
-  constexpr bool kCache = RC <= 16;
+  // (two rows at r <= 8, one at r <= 16: wider rows would crowd the registers)
+  constexpr int kCache = RC <= 8 ? 2 : RC <= 16 ? 1 : 0;
   double zc0[RC], zc1[RC];
   bool c0 = false, c1 = false;
-  if (kCache) {
-    if (w0 < n) c0 = row_obs<RC>(a, w0, zc0);
-    if (w0 + nw < n) c1 = row_obs<RC>(a, w0 + nw, zc1);
-  }
+  if (kCache >= 1 && w0 < n) c0 = row_obs<RC>(a, w0, zc0);
+  if (kCache >= 2 && w0 + nw < n) c1 = row_obs<RC>(a, w0 + nw, zc1);
   auto gather = [&](int j, int64_t s, const double (&xh)[RC], double (&out)[RC]) {
-    if (kCache && j == 0 && c0)
+    if (kCache >= 1 && j == 0 && c0)
       row_gather_reg<RC>(r, zc0, xh, out);
-    else if (kCache && j == 1 && c1)
+    else if (kCache >= 2 && j == 1 && c1)
       row_gather_reg<RC>(r, zc1, xh, out);
     else
       row_gather<RC>(a, s, xh, out);
