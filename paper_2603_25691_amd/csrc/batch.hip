@@ -1012,7 +1012,9 @@ __device__ __forceinline__ bool grid_sync(BCtl* ctl, uint32_t epoch, int64_t spi
   __syncthreads();
   if (threadIdx.x < 64) {
     if (threadIdx.x == 0) {
-      __threadfence();  // release this workgroup's writes device-wide
+      // release this workgroup's writes device-wide (a release fence: the L2
+      // write-back only, no invalidation)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_store(&ctl->flag[blockIdx.x * 16], epoch, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1037,7 +1039,8 @@ __device__ __forceinline__ bool grid_sync(BCtl* ctl, uint32_t epoch, int64_t spi
       __builtin_amdgcn_s_sleep(1);
     }
     if (threadIdx.x == 0) {
-      __threadfence();  // acquire the other workgroups' writes
+      // acquire the other workgroups' writes (an acquire fence: invalidation only)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       *s_ok = ok;
     }
   }

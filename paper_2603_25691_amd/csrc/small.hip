@@ -66,7 +66,9 @@ __device__ __forceinline__ bool grid_sync(SmallCtl* ctl, uint32_t epoch, int64_t
   __syncthreads();
   if (threadIdx.x < 64) {
     if (threadIdx.x == 0) {
-      __threadfence();  // release this workgroup's writes device-wide
+      // release this workgroup's writes device-wide (a release fence: the L2
+      // write-back only, no invalidation)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_store(&ctl->flag[blockIdx.x * 16], epoch, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -91,7 +93,8 @@ __device__ __forceinline__ bool grid_sync(SmallCtl* ctl, uint32_t epoch, int64_t
       __builtin_amdgcn_s_sleep(1);
     }
     if (threadIdx.x == 0) {
-      __threadfence();  // acquire the other workgroups' writes
+      // acquire the other workgroups' writes (an acquire fence: invalidation only)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       *s_ok = ok;
     }
   }
