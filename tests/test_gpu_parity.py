@@ -417,6 +417,39 @@ def test_explicit_zhat_solve(uploaded):
     assert O.e_kw(p.K, host(W), _dense(p)) <= 1e-10
 
 
+@pytest.mark.parametrize("explicit", [False, True])
+def test_persistent_long_segments_many_rows(explicit):
+    """The persistent launch where its register-held observation rows do not
+    apply: about 100 observations per time point (more than a wave) and n =
+    700 (three rows for some waves), in the implicit and the explicit Zhat
+    form, against the dense oracle; the multi-kernel loop agrees."""
+    p = make_small(38, n=700, I=10, J=12, r=4, q=70000, kernel_param=0.1)
+    Wd, gate = _dense_gate(p)
+    # Here the dense reference's own forward error exceeds its one-step estimate:
+    # the oracle's PCG converged to 1e-14 sits ~1.6e-10 from it.  Gate against
+    # that PCG solution, and against the dense one with its distance added.
+    Zh = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    Wp = O.solve_pcg(p.K, Zh, p.obs_t, p.y, p.lam, p.rho, p.gamma, O.gram_V(p.A, p.B),
+                     1e-14, 3000).X
+    d_ref = O.e_kw(p.K, Wp, Wd)
+    dp = upload(p)
+    if explicit:
+        Zhat = p.A[p.obs_i] * p.B[p.obs_j]
+        V = (p.A.T @ p.A) * (p.B.T @ p.B)
+        dp = upload(p, explicit=(Zhat, V), eig=(host(dp.UK), host(dp.dK)))
+    kw = {"gamma": p.gamma} if explicit else {}
+    s = UISolver(dp, p.lam, p.rho, 1e-12, flags=C.FLAG_PERSISTENT, **kw)
+    W, info = s.solve_subproblem()
+    assert info.status == C.OK, info.as_dict()
+    W = host(W)
+    assert O.e_kw(p.K, W, Wp) <= gate
+    assert O.e_kw(p.K, W, Wd) <= d_ref + gate
+    s2 = UISolver(dp, p.lam, p.rho, 1e-12, flags=C.FLAG_NO_PERSISTENT, **kw)
+    W2, info2 = s2.solve_subproblem()
+    assert info2.status == C.OK and abs(info.iters - info2.iters) <= 1
+    assert O.e_kw(p.K, W, host(W2)) <= gate
+
+
 def test_aligned_case_converges_in_one_iteration():
     p = make_aligned(3, I=6, J=5, n=40, r=4, sigma=0.1, lam=1e-3, rho=1e-6, tol=1e-10)
     dp = upload(p)
