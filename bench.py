@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-only", action="store_true",
                     help="measure only the batched workload (prints its JSON object)")
+    ap.add_argument("--small-only", action="store_true",
+                    help="run only the small workload and print its JSON (profiling)")
     ap.add_argument("--no-small", action="store_true", help="skip the small workload")
     ap.add_argument("--no-aligned", action="store_true", help="skip the aligned workload")
     ap.add_argument("--no-paper-shapes", action="store_true",
@@ -606,6 +608,9 @@ def main():
     from synth import config_c3
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.small_only:
+        print(json.dumps(bench_small(torch, C, max(a.steps, 10))), flush=True)
+        return
     if a.batch_only:
         if a.calib_copy_mb > 0:
             src = torch.empty(a.calib_copy_mb * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
