@@ -146,7 +146,9 @@ typedef struct cphifi_ui_desc {
   double rho;         /* shift of Section 4.1, > 0 */
   double gamma;       /* density of the preconditioner; <= 0 means q / (n I J) */
   double tol;         /* relative residual target ||b - A w|| / ||b|| */
-  double inner_tol;   /* mixed forms: inner PCG relative tolerance (<= 0: 1e-3) */
+  double inner_tol;   /* mixed forms: inner PCG relative tolerance of every refinement
+                         step (<= 0: 1e-3 on the step that can reach tol, 3e-3 on the
+                         earlier ones, which cannot) */
   int32_t precision;  /* enum cphifi_precision */
   int32_t flags;      /* OR of enum cphifi_flags */
   int32_t maxit;      /* PCG iteration cap (FP64) or inner cap (mixed); <= 0: 500 */

@@ -131,7 +131,8 @@ struct BSub {
   int32_t bf_mw, bf_ks, bf_nrb, fn_ks, fn_nrb, fn_vw, ft_mw, ft_ks, ft_nrb, pad0;
   int64_t bf_kper, fn_kper, ft_kper;
   double lam, rho, gamma, tol, inner_tol2;
-  int32_t maxit, max_refine, warm, pad1;
+  int32_t maxit, max_refine, warm;
+  int32_t adapt;  // default inner tolerance: loosened on steps that cannot reach tol
 };
 
 template <typename P>
@@ -899,7 +900,8 @@ __device__ __forceinline__ void ctrl_item(const BSub& S, BState* st, int mode, i
           finish_member(st, M_DONE, CPHIFI_NUMERIC);
         } else if (on && rz0 > 0.0) {
           const double rr = rel * rel * st->bbar;
-          st->tol2 = S.inner_tol2 * rr;
+          const bool loose = S.adapt && rel * kInnerLoose > S.tol;
+          st->tol2 = (loose ? fmax(S.inner_tol2, kInnerLoose * kInnerLoose) : S.inner_tol2) * rr;
           st->rz[0] = rz0;
           st->it = 0;
           finish_member(st, M_INNER, 0);
@@ -1538,6 +1540,7 @@ int cphifi_batch_create(cphifi_batch** out, int count, const cphifi_ui_desc* des
     S.tol = d.tol;
     const double itol = d.inner_tol > 0.0 ? d.inner_tol : kInnerTol;
     S.inner_tol2 = itol * itol;
+    S.adapt = d.inner_tol > 0.0 ? 0 : 1;
     S.maxit = eff_maxit(d);
     S.max_refine = d.max_refine > 0 ? d.max_refine : 30;
     S.warm = (d.flags & CPHIFI_FLAG_WARM_START) ? 1 : 0;

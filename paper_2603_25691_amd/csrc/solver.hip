@@ -845,8 +845,13 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
         break;
       }
     }
+    // the default inner tolerance is loosened for the steps that cannot reach
+    // tol anyway (kInnerLoose); an explicit one holds for every step
+    const double step_tol = (p->d.inner_tol <= 0.0 && rel * kInnerLoose > p->d.tol)
+                                ? std::max(inner_tol, kInnerLoose)
+                                : inner_tol;
     PcgOut o;
-    TRY(run_pcg(p, A, M, rbar, p->vec[V_XB], false, inner_tol, maxit,
+    TRY(run_pcg(p, A, M, rbar, p->vec[V_XB], false, step_tol, maxit,
                 PcgVecs{p->vec[V_R2], p->vec[V_Z2], p->vec[V_P2], p->vec[V_Q2]}, p->sc, nullptr,
                 0, &o, true));
     total_inner += o.iters;
