@@ -57,7 +57,7 @@ MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2, true>", 30658, 40): 1.9480e9,
                     ("gemm_f64_kernel<10, 4, 2, true, 1>", 30658, 40): 7.6591e9}
 # HBM bytes per launch of the batched kernel on the 64-member workload, from the
 # same two counters (profiles/c5_batch64_hbm_counters.md); clear on a change.
-BATCH_TRAFFIC = 2.341e11
+BATCH_TRAFFIC = 2.312e11
 F64_KERNEL = "gemm_f64_kernel<10, 4, 2, true, 1>"
 BF16_KERNEL = "gemm_bf16_kernel<3, 4, 2, true>"
 # relative residual the mixed solves are refined to (e_KW within 1e-6), and

@@ -450,6 +450,26 @@ def test_persistent_long_segments_many_rows(explicit):
     assert O.e_kw(p.K, W, host(W2)) <= gate
 
 
+@pytest.mark.parametrize("shape", [(1, 2, 3, 1, 4), (2, 3, 4, 32, 20), (5, 2, 3, 3, 25)])
+def test_persistent_tiny_shapes(shape):
+    """Degenerate sizes of the persistent launch: one time point (one
+    workgroup, one busy wave), r = 32 (the widest row layout) with fewer
+    observations than unknowns, and n = 5: against the dense oracle and the
+    multi-kernel loop."""
+    n, I, J, r, q = shape
+    p = make_small(50, n=n, I=I, J=J, r=r, q=q, kernel_param=0.2)
+    Wd, gate = _dense_gate(p)
+    dp = upload(p)
+    out = []
+    for flags in (C.FLAG_PERSISTENT, C.FLAG_NO_PERSISTENT):
+        s = UISolver(dp, p.lam, p.rho, 1e-12, flags=flags)
+        W, info = s.solve_subproblem()
+        assert info.status == C.OK, (flags, info.as_dict())
+        out.append(host(W))
+        assert O.e_kw(p.K, out[-1], Wd) <= gate
+    assert O.e_kw(p.K, out[0], out[1]) <= gate
+
+
 def test_aligned_case_converges_in_one_iteration():
     p = make_aligned(3, I=6, J=5, n=40, r=4, sigma=0.1, lam=1e-3, rho=1e-6, tol=1e-10)
     dp = upload(p)
