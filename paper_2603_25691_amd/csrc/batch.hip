@@ -364,9 +364,11 @@ __device__ __forceinline__ void gemm_item_nb(const BSub& S, int kind, const doub
     const int64_t bx = i % S.bf_nrb, by = i / S.bf_nrb;
     // the member plans hold U and U^T in the tiled BF16 layout
     if (S.bf_mw == 4)
-      tiles::gemm_bf16_tile<NB, 4, 2, true>(g, bx, by, (__bf16*)smem, item_tid());
+      tiles::gemm_bf16_tile<NB, 4, 2, true>(g, bx, by * g.kper, min(g.n, (by + 1) * g.kper), by,
+                                              (__bf16*)smem, item_tid());
     else
-      tiles::gemm_bf16_tile<NB, 2, 2, true>(g, bx, by, (__bf16*)smem, item_tid());
+      tiles::gemm_bf16_tile<NB, 2, 2, true>(g, bx, by * g.kper, min(g.n, (by + 1) * g.kper), by,
+                                              (__bf16*)smem, item_tid());
   } else if (kind == G_UKT) {
     g.U = S.UK;
     g.ldu = S.ldk;

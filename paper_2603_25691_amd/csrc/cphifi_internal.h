@@ -122,6 +122,9 @@ struct GemmPlan {
                 // workgroups (ksplit then counts the slabs every row receives)
 };
 GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu);
+// The stream-K form of a BF16 plan whose operand is in the tiled layout, when
+// it applies (else gp unchanged).
+GemmPlan bf16_stream_k(const GemmPlan& gp, int64_t n, int num_cu);
 // Plan with an explicit tile; ksplit_req <= 0 picks the split from the CU count
 // and the kernel's occupancy.
 GemmPlan make_gemm_plan(Elt elt, bool trans, int64_t n, int r, int mw, int s, int ksplit_req,

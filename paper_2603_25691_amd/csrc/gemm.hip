@@ -101,8 +101,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TILED ? 1 :
     GArgs g) {
   if (g.done != nullptr && *g.done) return;
   __shared__ __attribute__((aligned(16))) __bf16 xs[tiles::bf16_lds_elems<NB, S>()];
-  tiles::gemm_bf16_tile<NB, MW, S, TILED, bf16_depth(TILED)>(g, blockIdx.x, blockIdx.y, xs,
-                                                              threadIdx.x);
+  const int64_t kb = (int64_t)blockIdx.y * g.kper;
+  tiles::gemm_bf16_tile<NB, MW, S, TILED, bf16_depth(TILED)>(
+      g, blockIdx.x, kb, min(g.n, kb + g.kper), blockIdx.y, xs, threadIdx.x);
+}
+
+// Stream-K form of the tiled BF16 product: the (row block, k chunk) iterations
+// dealt evenly to exactly one workgroup per CU (the split-K grid of 120 x 2 at
+// n = 30658 leaves 16 CUs idle); a workgroup writes one partial slab per row
+// block it touches, and the last contributor of a row block zeroes the slabs
+// no one writes, so every row sums `ksplit` slabs as in the split-K form.
+template <int NB, int MW, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gemm_bf16_sk_kernel(
+    GArgs g, SkArgs sk) {
+  if (g.done != nullptr && *g.done) return;
+  __shared__ __attribute__((aligned(16))) __bf16 xs[tiles::bf16_lds_elems<NB, S>()];
+  constexpr int BK = 32 * S;
+  constexpr int64_t ROWS = 4 * MW * 16;
+  const int64_t T = sk.nrb * sk.nch;
+  const int64_t w = blockIdx.x;
+  const int64_t c1 = (w + 1) * T / sk.wgs;
+  for (int64_t c = w * T / sk.wgs; c < c1;) {
+    const int64_t b = c / sk.nch;
+    const int64_t cend = min(c1, (b + 1) * sk.nch);
+    const int64_t wf = sk_first(b * sk.nch, sk.wgs, T);
+    const int64_t wl = sk_first((b + 1) * sk.nch - 1, sk.wgs, T);
+    if (w == wl) {  // last contributor: zero the unused slabs of this row block
+      const int64_t r0 = b * ROWS, r1 = min(g.n, r0 + ROWS);
+      float* part = (float*)g.part;
+      for (int64_t sl = wl - wf + 1; sl < sk.ksplit; ++sl)
+        for (int64_t e = threadIdx.x; e < (r1 - r0) * g.ldp; e += 256)
+          part[(sl * g.n + r0) * g.ldp + e] = 0.0f;
+    }
+    tiles::gemm_bf16_tile<NB, MW, S, true, bf16_depth(true)>(
+        g, b, (c - b * sk.nch) * BK, min(g.n, (cend - b * sk.nch) * BK), w - wf, xs,
+        threadIdx.x);
+    __syncthreads();  // the next row block's first chunk reuses the LDS
+    c = cend;
+  }
 }
 
 // X (n x r, row-major, optionally row-scaled) -> hi/lo bf16, c-major rows of
@@ -381,6 +417,7 @@ bool gemm_cfg_valid(Elt elt, int mw, int s) {
 
 // Stream-K for the transposed FP64 product unless CPHIFI_F64_STREAMK says otherwise.
 constexpr bool kF64StreamKDefault = false;
+constexpr bool kBf16StreamKDefault = false;
 
 GemmPlan make_gemm_plan(Elt elt, bool trans, int64_t n, int r, int mw, int s, int ksplit_req,
                         int num_cu) {
@@ -504,6 +541,37 @@ bool gemm_table_lookup(const char* path, Elt elt, bool trans, int64_t n, int r, 
 
 // Tile for a product: the autotuner's table when one is loaded and covers
 // (n, r), else defaults measured at n = 30658, r = 40 on MI355X.
+// Stream-K form of a tiled BF16 product plan (one workgroup per CU: the
+// split-K grid of these plans leaves CUs idle, e.g. 240 of 256 at n = 30658);
+// CPHIFI_BF16_STREAMK=1 turns it on.  Off by default: at n = 30658, r = 40 it
+// ran 0.346-0.358 ms against 0.330-0.350 ms for the 240-workgroup split-K
+// grid (this HBM-bound product reads faster from fewer concurrent row
+// streams).  Only the 4 x 2 tile, only without an explicit split.
+GemmPlan bf16_stream_k(const GemmPlan& gp, int64_t n, int num_cu) {
+  const char* env = std::getenv("CPHIFI_BF16_STREAMK");
+  const bool want = env != nullptr ? std::atoi(env) != 0 : kBf16StreamKDefault;
+  if (!want || gp.sk > 0 || gp.mw != 4 || gp.s != 2) return gp;
+  const int64_t rows = 4LL * gp.mw * 16;
+  const int64_t nrowblk = (n + rows - 1) / rows;
+  const int64_t bk = gemm_bk(Elt::BF16, gp.s);
+  const int64_t nch = (n + bk - 1) / bk;
+  const int64_t T = nrowblk * nch;
+  const int64_t W = num_cu > 0 ? num_cu : 256;
+  if (nrowblk * gp.ksplit >= W || T < W) return gp;
+  int ksp = 1;
+  for (int64_t b = 0; b < nrowblk; ++b) {
+    const int64_t wf = ((b * nch + 1) * W - 1) / T;
+    const int64_t wl = (((b + 1) * nch) * W - 1) / T;
+    ksp = std::max<int>(ksp, (int)(wl - wf + 1));
+  }
+  if (ksp > kMaxSplit) return gp;
+  GemmPlan out = gp;
+  out.sk = (int)W;
+  out.ksplit = ksp;
+  out.kper = nch * bk;
+  return out;
+}
+
 GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu) {
   int mw = 0, s = 0, ks = 0;
   if (table_tile(elt, trans && elt != Elt::BF16, n, r, &mw, &s, &ks))
@@ -532,8 +600,8 @@ GemmPlan choose_gemm(Elt elt, bool trans, int64_t n, int r, int num_cu) {
 
 static bool plan_ok(Elt elt, const GemmPlan& gp, int64_t n, int r) {
   if (gp.sk > 0)
-    return elt == Elt::F64 && r >= 1 && r <= kMaxRank && n >= 1 && gp.ksplit >= 1 &&
-           gp.ksplit <= kMaxSplit && gemm_cfg_valid(elt, gp.mw, gp.s);
+    return (elt == Elt::F64 || elt == Elt::BF16) && r >= 1 && r <= kMaxRank && n >= 1 &&
+           gp.ksplit >= 1 && gp.ksplit <= kMaxSplit && gemm_cfg_valid(elt, gp.mw, gp.s);
   return r >= 1 && r <= kMaxRank && n >= 1 && gp.ksplit >= 1 && gp.ksplit <= kMaxSplit &&
          gemm_cfg_valid(elt, gp.mw, gp.s) && gp.kper % gemm_bk(elt, gp.s) == 0 &&
          (int64_t)gp.ksplit * gp.kper >= n && (int64_t)(gp.ksplit - 1) * gp.kper < n;
@@ -616,6 +684,25 @@ int launch_gemm_bf16(const GemmPlan& gp, const __bf16* U, int64_t ldu, int64_t n
   g.xt_hi = xt_hi;
   g.xt_lo = xt_lo;
   g.ldxt = ldxt;
+  if (gp.sk > 0) {
+    if (!tiled || gp.mw != 4 || gp.s != 2) {
+      set_error("launch_gemm_bf16: the stream-K form needs the tiled layout and the 4x2 tile");
+      return CPHIFI_INVALID_ARG;
+    }
+    SkArgs sk{};
+    sk.nrb = (n + 255) / 256;  // rows of the 4x2 tile: 4 waves x 4 blocks x 16
+    sk.nch = (n + bk - 1) / bk;
+    sk.wgs = gp.sk;
+    sk.ksplit = gp.ksplit;
+    switch (nb) {
+      case 1: hipLaunchKernelGGL((gemm_bf16_sk_kernel<1, 4, 2>), dim3((unsigned)gp.sk), dim3(256), 0, st, g, sk); break;
+      case 2: hipLaunchKernelGGL((gemm_bf16_sk_kernel<2, 4, 2>), dim3((unsigned)gp.sk), dim3(256), 0, st, g, sk); break;
+      case 3: hipLaunchKernelGGL((gemm_bf16_sk_kernel<3, 4, 2>), dim3((unsigned)gp.sk), dim3(256), 0, st, g, sk); break;
+      default: hipLaunchKernelGGL((gemm_bf16_sk_kernel<4, 4, 2>), dim3((unsigned)gp.sk), dim3(256), 0, st, g, sk); break;
+    }
+    CPHIFI_CHECK_LAUNCH();
+    return CPHIFI_OK;
+  }
   return tiled ? dispatch_cfg_bf16<true>(gp.mw, gp.s, nb, g, gp.ksplit, st)
                : dispatch_cfg_bf16<false>(gp.mw, gp.s, nb, g, gp.ksplit, st);
 }

@@ -494,9 +494,12 @@ __host__ __device__ __forceinline__ int64_t bf16_tiled_off(int64_t i, int64_t k,
 // pre-split as hi + lo bf16 parts, transposed to c-major rows of stride ldxt,
 // so the product carries ~16 significant bits of X while U stays at bf16.
 // Accumulation is FP32.  xs: LDS of bf16_lds_elems<NB, S>().
+// Rows [bx*tile_rows(MW), ...) over k in [kbeg, kend) (kbeg a multiple of the
+// chunk, 32 S) into partial slab `slab`.
 template <int NB, int MW, int S, bool TILED = false, int DEPTH = 2>
-__device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64_t by,
-                                               __bf16* xs, int tid) {
+__device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64_t kbeg,
+                                               int64_t kend, int64_t slab, __bf16* xs,
+                                               int tid) {
   static_assert(DEPTH == 2 || DEPTH == 3, "U chunks in flight: 2 or 3");
   constexpr int BK = 32 * S;
   constexpr int NC = NB * 16;
@@ -511,8 +514,6 @@ __device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64
   const int li = lane & 15, kk = lane >> 4;
   const int64_t n = g.n;
   const int64_t mbase = bx * (4 * MW * 16) + (int64_t)wave * (MW * 16);
-  const int64_t kbeg = by * g.kper;
-  const int64_t kend = min(n, kbeg + g.kper);
   const __bf16* __restrict__ U = (const __bf16*)g.U;
 
   // Offset of the lane's first element of a chunk starting at k0 = 0: its row
@@ -668,7 +669,7 @@ __device__ __forceinline__ void gemm_bf16_tile(const GArgs& g, int64_t bx, int64
     }
   }
 
-  float* part = (float*)g.part + by * n * g.ldp;
+  float* part = (float*)g.part + slab * n * g.ldp;
 #pragma unroll
   for (int mb = 0; mb < MW; ++mb)
 #pragma unroll

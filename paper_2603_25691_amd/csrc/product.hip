@@ -205,7 +205,8 @@ int cphifi_product(int elt, int trans, int mw, int s, int ksplit, int64_t n, con
     set_error("cphifi_product: workspace must be >= %zu bytes, 256-byte aligned", L.total);
     return CPHIFI_INVALID_ARG;
   }
-  const GemmPlan gp = make_gemm_plan(e, trans != 0, n, (int)r, mw, s, ksplit, num_cus());
+  GemmPlan gp = make_gemm_plan(e, trans != 0, n, (int)r, mw, s, ksplit, num_cus());
+  if (tiled && ksplit <= 0) gp = bf16_stream_k(gp, n, num_cus());
   return run_product(e, tiled, trans, gp, n, U, ldu, X, r, xscale, Y, (char*)workspace, L,
                      (hipStream_t)stream);
 }

@@ -1323,8 +1323,10 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
     p->utlp = ws + L.utlp;
     p->xthi = (__bf16*)(ws + L.xthi);
     p->xtlo = (__bf16*)(ws + L.xtlo);
-    p->gplpn = plan_from_env("CPHIFI_TILE_BF16", Elt::BF16, false, n, rr,
-                             choose_gemm(Elt::BF16, false, n, rr, p->num_cu), p->num_cu);
+    p->gplpn = bf16_stream_k(plan_from_env("CPHIFI_TILE_BF16", Elt::BF16, false, n, rr,
+                                           choose_gemm(Elt::BF16, false, n, rr, p->num_cu),
+                                           p->num_cu),
+                             n, p->num_cu);
     if ((rc = launch_convert_lowp(Elt::BF16, false, in->UK, p->ldk, n, p->utlp, L.ldl, st,
                                   true)) ||
         (rc = launch_convert_lowp(Elt::BF16, true, in->UK, p->ldk, n, p->ulp, L.ldl, st, true)))

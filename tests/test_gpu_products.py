@@ -108,6 +108,27 @@ def test_fp64_stream_k_product(n, r, monkeypatch):
         assert rerr <= 1e-12, (tile, rerr)
 
 
+@pytest.mark.parametrize("n,r", [(5000, 40), (12345, 7)])
+def test_bf16_stream_k_product(n, r, monkeypatch):
+    """The stream-K form of the tiled BF16 product (CPHIFI_BF16_STREAMK=1;
+    these sizes leave CUs idle under split-K, so the plan takes it, with up to
+    14 contributors per row block): every row against numpy on the rounded
+    operands."""
+    monkeypatch.setenv("CPHIFI_BF16_STREAMK", "1")
+    U, X, scale = _case(n, r, n + r)
+    ld = (n + 255) // 256 * 256
+    Ud = torch.zeros(n, ld, dtype=torch.bfloat16, device="cuda")
+    Ud[:, :n] = torch.from_numpy(U).cuda().to(torch.bfloat16)
+    want = _rnd(U, torch.bfloat16) @ _split_bf16(scale[:, None] * X)
+    del U
+    Xd = torch.from_numpy(X).cuda()
+    sd = torch.from_numpy(scale).cuda()
+    gh = product(bf16_tiles(Ud), Xd, "bf16_tiled", False, (4, 2), 0, sd).cpu().numpy()
+    assert np.linalg.norm(gh - want) / np.linalg.norm(want) <= 1e-5
+    rerr = np.max(np.linalg.norm(gh - want, axis=1) / np.linalg.norm(want, axis=1))
+    assert rerr <= 1e-4, rerr
+
+
 @pytest.mark.parametrize("count,blocks", [(1 << 20, 64), (3 * (1 << 20) + 6, 1000)])
 def test_stream_read_reads_every_element(count, blocks):
     """The streaming-read helper (the achievable-bandwidth probe) visits every
