@@ -317,22 +317,50 @@ __global__ __launch_bounds__(256) void prec_mid_mfma_kernel(const PT* part, int 
   double loc = 0.0, loc_rr = 0.0;
   for (int64_t rb = (int64_t)blockIdx.x * 4 + wave; rb * 16 < n; rb += (int64_t)gridDim.x * 4) {
     const int64_t row0 = rb * 16;
-    for (int e = lane; e < 16 * RP; e += 64) {
-      const int i = e / RP, c = e % RP;
-      const int64_t s = row0 + i;
-      double v = 0.0;
-      if (s < n && c < r) {
-        const int64_t o = s * r + c;
-        if (UPD) {
-          u.x[o] += alpha * u.p[o];
-          v = u.r[o] - alpha * u.q[o];
+    if (UPD) {
+      // Every load of the block's x, p, r, q first, then the updates: the
+      // stores to x and r would otherwise hold each later load back (the
+      // pointers may alias), one memory round trip per element.
+      constexpr int EPL = 16 * RP / 64;  // elements per lane (= NC4)
+      double xv[EPL], pv[EPL], rv[EPL], qv[EPL];
+#pragma unroll
+      for (int k = 0; k < EPL; ++k) {
+        const int e = lane + 64 * k;
+        const int i = e / RP, c = e % RP;
+        const int64_t s = row0 + i;
+        const bool on = s < n && c < r;
+        const int64_t o = on ? s * r + c : 0;
+        xv[k] = on ? u.x[o] : 0.0;
+        pv[k] = on ? u.p[o] : 0.0;
+        rv[k] = on ? u.r[o] : 0.0;
+        qv[k] = on ? u.q[o] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < EPL; ++k) {
+        const int e = lane + 64 * k;
+        const int i = e / RP, c = e % RP;
+        const int64_t s = row0 + i;
+        double v = 0.0;
+        if (s < n && c < r) {
+          const int64_t o = s * r + c;
+          u.x[o] = xv[k] + alpha * pv[k];
+          v = rv[k] - alpha * qv[k];
           u.r[o] = v;
           loc_rr += v * v;
-        } else {
+        }
+        wt[i * LT + c] = v;
+      }
+    } else {
+      for (int e = lane; e < 16 * RP; e += 64) {
+        const int i = e / RP, c = e % RP;
+        const int64_t s = row0 + i;
+        double v = 0.0;
+        if (s < n && c < r) {
+          const int64_t o = s * r + c;
           v = part != nullptr ? part_sum(part, ksplit, n, ldp, s, c) : in[o];
         }
+        wt[i * LT + c] = v;
       }
-      wt[i * LT + c] = v;
     }
     __builtin_amdgcn_wave_barrier();
     double acc[NC4];
