@@ -53,11 +53,11 @@ BATCH_TILES = os.path.join(ROOT, "paper_2603_25691_amd", "tiles_batch_mi355x.txt
 # stored as above), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled
 # by a calibration copy (profiles/products_n30658_r40_hbm_counters.md).  Keyed
 # by kernel and shape; clear an entry whenever that kernel changes.
-MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2, true>", 30658, 40): 1.9480e9,
+MEASURED_TRAFFIC = {("gemm_bf16_kernel<3, 4, 2, true>", 30658, 40): 1.9539e9,
                     ("gemm_f64_kernel<10, 4, 2, true, 1>", 30658, 40): 7.6591e9}
 # HBM bytes per launch of the batched kernel on the 64-member workload, from the
 # same two counters (profiles/c5_batch64_hbm_counters.md); clear on a change.
-BATCH_TRAFFIC = 2.312e11
+BATCH_TRAFFIC = 2.314e11
 F64_KERNEL = "gemm_f64_kernel<10, 4, 2, true, 1>"
 BF16_KERNEL = "gemm_bf16_kernel<3, 4, 2, true>"
 # relative residual the mixed solves are refined to (e_KW within 1e-6), and
