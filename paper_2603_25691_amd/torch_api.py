@@ -275,12 +275,25 @@ class BatchSolver:
         """The members' observed values (the batched solve starts from them)."""
         return [p.y for p in self.probs]
 
+    def _check_bound(self, ys, Ws):
+        # the C ABI takes raw pointers: the shapes are checked here
+        if len(ys) != len(self.probs) or len(Ws) != len(self.probs):
+            raise ValueError("one observed-value vector and one W per member")
+        for k, (pr, y, W) in enumerate(zip(self.probs, ys, Ws)):
+            _need(y, torch.float64, (pr.q,), f"y[{k}]")
+            _need(W, torch.float64, (pr.n, pr.r), f"W[{k}]")
+
     def bind(self, ys, Ws):
+        """Bind each member's observed values ys[k] (device, q_k doubles) and
+        its output Ws[k] (n_k x r_k)."""
+        self._check_bound(ys, Ws)
         _c.cphifi_batch_bind(self.batch, [y.data_ptr() for y in ys], [W.data_ptr() for W in Ws])
 
     def solve(self, ys=None, Ws=None, wait: bool = True):
         """Solve every member from its observed values ys (device q_i doubles)
         into Ws (n_i x r_i).  Returns (status, infos) when wait, else None."""
+        if ys is not None and Ws is not None:
+            self._check_bound(ys, Ws)
         return _c.cphifi_batch_solve(self.batch, len(self.probs),
                                      None if ys is None else [y.data_ptr() for y in ys],
                                      None if Ws is None else [W.data_ptr() for W in Ws], wait)

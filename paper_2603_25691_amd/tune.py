@@ -144,7 +144,7 @@ def measure(n: int, r: int, elts, reps: int, calib_mb: int, trans: bool = False,
         torch.cuda.empty_cache()
 
 
-BATCH_KRANGE = (1024, 2048, 4096)
+BATCH_KRANGE = (768, 1024, 1536, 2048, 3072, 4096)
 BATCH_BF16_MW = (2, 4)
 BATCH_BIN = 512  # n bins of the batch table
 
@@ -188,9 +188,10 @@ def batch(count: int, seed: int, out_path: str, reps: int = 3) -> None:
             bs = BatchSolver(dps, [p.lam for p in probs], [p.rho for p in probs], probs[0].tol,
                              tile_table=path)
             try:
-                rhs = bs.rhs()
-                Ws = [torch.empty_like(b) for b in rhs]
-                bs.bind(rhs, Ws)
+                # the batched solve starts from the observed values
+                Ws = [torch.empty(p.n, p.r, dtype=torch.float64, device=p.K.device)
+                      for p in dps]
+                bs.bind(bs.ys(), Ws)
                 status, _ = bs.solve()
                 ms = _time(lambda: bs.solve(wait=False), reps)
                 status, infos = bs.info()

@@ -138,6 +138,20 @@ def test_batch_rebind_scaled_observations(batch):
         assert O.e_kw(p.K, host(W), 2.0 * batch["W"][k]) <= 1e-6
 
 
+def test_batch_binding_checks_shapes(batch):
+    """The C ABI takes raw pointers, so the binding checks what it hands over:
+    right-hand sides (n x r) where observed values (q) belong are refused
+    before any launch."""
+    bs = batch["bs"]
+    Ws = [torch.empty_like(b) for b in batch["rhs"]]
+    with pytest.raises(ValueError):
+        bs.bind(batch["rhs"], Ws)
+    with pytest.raises(ValueError):
+        bs.solve(batch["rhs"], Ws)
+    with pytest.raises(ValueError):
+        bs.bind(bs.ys(), Ws[:-1])
+
+
 def test_batch_zero_observations_and_async_info(batch):
     bs = batch["bs"]
     zeros = [torch.zeros_like(y) for y in bs.ys()]
