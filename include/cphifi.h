@@ -518,7 +518,8 @@ CPHIFI_API int cphifi_batch_rhs(cphifi_batch* bt, const double* const* y, double
 /* Bind the observed values y_i (q_i doubles, device; may be NULL when
  * q_i = 0) and solutions W_i (n_i x r_i, device; x0 on entry for members with
  * FLAG_WARM_START) that the graph reads and writes.  y, W: host arrays of
- * `count` device pointers.  stream-ordered. */
+ * `count` device pointers.  The sizes cannot be checked through raw pointers:
+ * a shorter buffer is read or written past its end.  stream-ordered. */
 CPHIFI_API int cphifi_batch_bind(cphifi_batch* bt, const double* const* y, double* const* W);
 
 /* Solve all members: binds y / W when given (else the last binding), launches
