@@ -52,6 +52,7 @@ constexpr int kObsLdsBytesF64 = 65536;
 constexpr int kObsLdsBytesF32 = 16384;
 constexpr int kObsLdsGrid = 1024;  // workgroups of the staged form (grid-stride)
 
+
 template <typename T>
 __device__ __forceinline__ void stage_rows(T* dst, const T* src, int64_t len) {
   for (int64_t e = threadIdx.x; e < len; e += blockDim.x) dst[e] = src[e];
@@ -72,7 +73,8 @@ __global__ __launch_bounds__(256) void obs_lds_kernel(TaskView t, ObsDev d) {
     obs_task<L, CPL, FORM, MODE, PT, true, PT>(t, d, task, threadIdx.x & 63, sB);
 }
 
-template <int L, int CPL, int FORM, int MODE, typename PT>
+// G: observations per lane row in flight per step.
+template <int L, int CPL, int FORM, int MODE, typename PT, int G = tiles::kGroups>
 __global__ __launch_bounds__(256) void obs_rows_lds_kernel(ObsDev d, const int32_t* obs_ptr,
                                                            int64_t n, int spw) {
   if (d.a.done != nullptr && *d.a.done) return;
@@ -86,9 +88,8 @@ __global__ __launch_bounds__(256) void obs_rows_lds_kernel(ObsDev d, const int32
     for (int k = 0; k < spw; k += ROWS) {
       const int64_t s0 = sb + k;
       if (s0 >= n) break;
-      tiles::obs_rows<L, CPL, FORM, MODE, PT, true, PT>(d, obs_ptr, s0,
-                                                        (int)min((int64_t)ROWS, n - s0),
-                                                        threadIdx.x & 63, sB);
+      tiles::obs_rows<L, CPL, FORM, MODE, PT, true, PT, G>(
+          d, obs_ptr, s0, (int)min((int64_t)ROWS, n - s0), threadIdx.x & 63, sB);
     }
   }
 }
@@ -140,6 +141,12 @@ int launch_c(bool pf, const TaskView& tv, const ObsDev& d, const ObsTasks& t, hi
       if (blocks == 0) return CPHIFI_OK;
       if (pf)
         hipLaunchKernelGGL((obs_rows_lds_kernel<L, CPL, FORM, MODE, float>),
+                           dim3((unsigned)blocks), dim3(256), lds, st, d, t.obs_ptr, t.nseg,
+                           spw);
+      else if (lds > (size_t)kObsLdsBytesF32)
+        // a copy of B above 16 KB holds the kernel at two workgroups per CU,
+        // so the registers allow eight observations per lane row in flight
+        hipLaunchKernelGGL((obs_rows_lds_kernel<L, CPL, FORM, MODE, double, 8>),
                            dim3((unsigned)blocks), dim3(256), lds, st, d, t.obs_ptr, t.nseg,
                            spw);
       else

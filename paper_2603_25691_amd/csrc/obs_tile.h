@@ -95,7 +95,8 @@ __device__ __forceinline__ const char* factor_bytes(const double* f64, const flo
 // VT: element type of the factor rows and of the arithmetic (double, or float
 // for the low-precision inner operator: half the bytes per factor row, one
 // DPP step per lane-row reduction step instead of two).
-template <int L, int CPL, int FORM, int MODE, bool BL = false, typename VT = double>
+template <int L, int CPL, int FORM, int MODE, bool BL = false, typename VT = double,
+          int G = kGroups>
 struct ObsRow {
   uint32_t cidx[CPL];  // in-bounds column index used for loads
   bool con[CPL];       // real column
@@ -106,7 +107,7 @@ struct ObsRow {
   VT arow[CPL];  // kOwner: A(i, :) of the segment's sample
   VT xv[CPL];    // Xhat(s,:), times A(i,:) for kOwner (zero in padding)
   VT acc[CPL];
-  int32_t ii[kGroups], jj[kGroups];  // indices of the current step
+  int32_t ii[G], jj[G];  // indices of the current step
 
   __device__ __forceinline__ void init(const ObsDev& d, int cl, const VT* Bsrc) {
     const int r = d.a.r;
@@ -126,7 +127,7 @@ struct ObsRow {
     Abytes = factor_bytes(d.a.A, d.a.A32, VT(0));
     Bbytes = BL ? (const char*)Bsrc : factor_bytes(d.a.B, d.a.B32, VT(0));
 #pragma unroll
-    for (int u = 0; u < kGroups; ++u) ii[u] = jj[u] = 0;
+    for (int u = 0; u < G; ++u) ii[u] = jj[u] = 0;
   }
 
   // kOwner: the segment's sample row, from its first observation `o` (< 0:
@@ -155,10 +156,10 @@ struct ObsRow {
   }
 
   // Index loads of observations o_u (< 0: none).
-  __device__ __forceinline__ void fetch(const ObsDev& d, const int64_t (&o)[kGroups],
-                                        int32_t (&ii_)[kGroups], int32_t (&jj_)[kGroups]) {
+  __device__ __forceinline__ void fetch(const ObsDev& d, const int64_t (&o)[G],
+                                        int32_t (&ii_)[G], int32_t (&jj_)[G]) {
 #pragma unroll
-    for (int u = 0; u < kGroups; ++u) {
+    for (int u = 0; u < G; ++u) {
       ii_[u] = 0;
       jj_[u] = 0;
       if (FORM != kExplicit && o[u] >= 0) {
@@ -169,13 +170,13 @@ struct ObsRow {
   }
 
   // One step: observations o_u (masked by on_u; o_u in bounds or < 0).
-  __device__ __forceinline__ void step(const ObsDev& d, const int64_t (&o)[kGroups],
-                                       const bool (&on)[kGroups]) {
+  __device__ __forceinline__ void step(const ObsDev& d, const int64_t (&o)[G],
+                                       const bool (&on)[G]) {
     const ObsArgs& a = d.a;
-    VT z[kGroups][CPL];
-    VT w[kGroups];
+    VT z[G][CPL];
+    VT w[G];
 #pragma unroll
-    for (int u = 0; u < kGroups; ++u) {
+    for (int u = 0; u < G; ++u) {
       if (FORM == kExplicit) {
 #pragma unroll
         for (int j = 0; j < CPL; ++j)
@@ -198,7 +199,7 @@ struct ObsRow {
     }
     if (MODE == 0) {
 #pragma unroll
-      for (int u = 0; u < kGroups; ++u) {
+      for (int u = 0; u < G; ++u) {
         VT part = VT(0);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) part += z[u][j] * xv[j];
@@ -207,7 +208,7 @@ struct ObsRow {
       }
     }
 #pragma unroll
-    for (int u = 0; u < kGroups; ++u)
+    for (int u = 0; u < G; ++u)
 #pragma unroll
       for (int j = 0; j < CPL; ++j) acc[j] += w[u] * z[u][j];  // eq. yhat1 / MTTKRP
   }
@@ -279,7 +280,8 @@ __device__ __forceinline__ void obs_task(const TaskView& t, const ObsDev& d, int
 // [s0, s0 + nseg), nseg <= 64/L, read from the CSR obs_ptr; for segments that
 // are not split over several tasks (the caller checks) this gives the same
 // rows as obs_task.
-template <int L, int CPL, int FORM, int MODE, typename PT, bool BL = false, typename VT = double>
+template <int L, int CPL, int FORM, int MODE, typename PT, bool BL = false, typename VT = double,
+          int G = kGroups>
 __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr, int64_t s0,
                                          int nseg, int lane, const VT* Bsrc = nullptr) {
   const ObsArgs& a = d.a;
@@ -290,24 +292,24 @@ __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr
   const int64_t end = row_on ? (int64_t)obs_ptr[s + 1] : beg;
   const int64_t last = end > beg ? end - 1 : -1;  // clamp target of masked loads
 
-  ObsRow<L, CPL, FORM, MODE, BL, VT> R;
+  ObsRow<L, CPL, FORM, MODE, BL, VT, G> R;
   R.init(d, cl, Bsrc);
   // wave-uniform step count: the longest segment of the wave
   int maxlen = (int)(end - beg);
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, 64));
-  const int nstep = (maxlen + kGroups - 1) / kGroups;
-  auto obs_of = [&](int st, int64_t (&o)[kGroups], bool (&on)[kGroups]) {
+  const int nstep = (maxlen + G - 1) / G;
+  auto obs_of = [&](int st, int64_t (&o)[G], bool (&on)[G]) {
 #pragma unroll
-    for (int u = 0; u < kGroups; ++u) {
-      const int64_t l = beg + (int64_t)st * kGroups + u;
+    for (int u = 0; u < G; ++u) {
+      const int64_t l = beg + (int64_t)st * G + u;
       on[u] = l < end;
       o[u] = on[u] ? l : last;
     }
   };
   if (nstep > 0) {
-    int64_t o[kGroups];
-    bool on[kGroups];
+    int64_t o[G];
+    bool on[G];
     obs_of(0, o, on);
     R.fetch(d, o, R.ii, R.jj);
   }
@@ -315,19 +317,19 @@ __device__ __forceinline__ void obs_rows(const ObsDev& d, const int32_t* obs_ptr
   if (MODE == 0) R.template xhat<PT>(d, s, row_on);
 
   for (int st = 0; st < nstep; ++st) {
-    int32_t ii_nxt[kGroups] = {}, jj_nxt[kGroups] = {};
+    int32_t ii_nxt[G] = {}, jj_nxt[G] = {};
     if (st + 1 < nstep) {
-      int64_t on_[kGroups];
-      bool onn[kGroups];
+      int64_t on_[G];
+      bool onn[G];
       obs_of(st + 1, on_, onn);
       R.fetch(d, on_, ii_nxt, jj_nxt);
     }
-    int64_t o[kGroups];
-    bool on[kGroups];
+    int64_t o[G];
+    bool on[G];
     obs_of(st, o, on);
     R.step(d, o, on);
 #pragma unroll
-    for (int u = 0; u < kGroups; ++u) {
+    for (int u = 0; u < G; ++u) {
       R.ii[u] = ii_nxt[u];
       R.jj[u] = jj_nxt[u];
     }
