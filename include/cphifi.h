@@ -250,7 +250,12 @@ CPHIFI_API int cphifi_ui_solve(cphifi_plan* p, const double* b, double* W,
  * b = K B, Section 4.4): U_K^T b = D_K U_K^T B takes one pass over U_K and b
  * is never formed; relres_true is ||K (B - Yhat1 - lambda W) - rho W|| /
  * ||b||, the same FP64 paper-form residual, with ||b|| = ||U_K^T b||.  The
- * FP64 form forms b (cphifi_ui_rhs) and calls cphifi_ui_solve.  sync. */
+ * FP64 form forms b (cphifi_ui_rhs) and calls cphifi_ui_solve.  The setup's
+ * r x r eigendecomposition of V runs on a second stream of the plan (made on
+ * the first call, default priority) while the plan's stream forms the
+ * right-hand side; the plan's stream waits for it before the first
+ * preconditioner application, so all of the call's work is ordered before
+ * later work on the plan's stream.  sync. */
 CPHIFI_API int cphifi_ui_solve_subproblem(cphifi_plan* p, const double* y, double* W,
                                cphifi_solve_info* info);
 

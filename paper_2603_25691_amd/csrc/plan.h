@@ -123,6 +123,12 @@ struct cphifi_plan {
   int32_t* h_flag = nullptr;  // host-mapped, coherent
   int32_t* d_flag = nullptr;  // its device address
   hipEvent_t pev[kPollRing]{};
+  // Side stream of the whole-subproblem solve: the setup's eig(V) chain (V,
+  // its Jacobi eigendecomposition, the eq. fx diagonal) runs there, forked
+  // from and joined back into st, while st forms the right-hand side.
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  bool join_pending = false;  // st has not yet waited for join_ev
   bool timing = false;
   Elt timed_elt = Elt::F64;  // product type whose launches are timed ...
   bool timed_trans = false;  // ... and orientation (one kernel symbol)

@@ -377,6 +377,15 @@ int check_every(const cphifi_plan* p) {
   return std::min(e, kPollRing - 1);
 }
 
+// Makes the plan's stream wait for the eig(V) chain that setup_plan left on
+// the side stream.  Whatever reads V, U_V, d_V or D runs after this.
+int join_setup(cphifi_plan* p) {
+  if (!p->join_pending) return CPHIFI_OK;
+  p->join_pending = false;
+  CPHIFI_HIP(hipStreamWaitEvent(p->st, p->join_ev, 0));
+  return CPHIFI_OK;
+}
+
 // Textbook PCG with device-resident scalars.  Every kernel of an iteration
 // checks sc->done, so iterations can be enqueued ahead of the host's check:
 // after enqueuing iteration it, the host waits for iteration it - every and
@@ -789,6 +798,7 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
   // those of K to working accuracy), and every later step starts from the
   // certificate's own residual b - A W, rotated by U^T.
   bool true_res = false;
+  TRY(join_setup(p));  // the inner PCG applies the eq. fx preconditioner
   for (;;) {
     // The residual of xbar in the eigenbasis.
     bool certified = false;
@@ -942,14 +952,78 @@ int mttkrp(cphifi_plan* p, const double* y, double* out) {
   return launch_obs(ObsMode::Mttkrp, false, p->tasks, a, p->I, p->J, p->st);
 }
 
-// Pinned host memory and events of a plan.
+// Pinned host memory, events and side stream of a plan.
 void release_host(cphifi_plan* p) {
+  if (p->side != nullptr) {
+    (void)hipStreamSynchronize(p->side);
+    (void)hipStreamDestroy(p->side);
+    p->side = nullptr;
+  }
+  for (hipEvent_t* e : {&p->fork_ev, &p->join_ev})
+    if (*e != nullptr) (void)hipEventDestroy(*e), *e = nullptr;
   for (hipEvent_t& e : p->pev)
     if (e != nullptr) (void)hipEventDestroy(e), e = nullptr;
   if (p->h_flag) (void)hipHostFree(p->h_flag);
   if (p->h_sc) (void)hipHostFree(p->h_sc);
   p->h_flag = p->d_flag = nullptr;
   p->h_sc = p->d_sc = nullptr;
+}
+
+// The side stream and its two events, made on first use (plans that serve
+// only the batched solver never need them).  False if they cannot be made:
+// the setup then runs in order on the plan's stream.
+bool make_side(cphifi_plan* p) {
+  if (p->side != nullptr) return true;
+  bool ok = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) == hipSuccess &&
+            // default priority, like every stream of the library
+            hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();  // leave no error for the next launch check
+    for (hipEvent_t* e : {&p->fork_ev, &p->join_ev})
+      if (*e != nullptr) (void)hipEventDestroy(*e), *e = nullptr;
+    p->side = nullptr;
+  }
+  return ok;
+}
+
+// Per-solve setup: V = (A^T A) had (B^T B) (or the given V), its eigenpairs,
+// the eq. fx diagonal D, and the copies and clamps the operators read.  With
+// overlap, the V chain (one workgroup for the Jacobi sweeps: ~0.4 ms at
+// r = 40) runs on the side stream, forked from the plan's stream, and the
+// caller must call join_setup before the first preconditioner application;
+// the rest of the setup and the right-hand side go on meanwhile.
+int setup_plan(cphifi_plan* p, bool overlap) {
+  const int r = (int)p->r;
+  TRY(join_setup(p));  // a chain still in flight writes what this one writes
+  hipStream_t vs = p->st;
+  if (overlap && make_side(p)) {
+    CPHIFI_HIP(hipEventRecord(p->fork_ev, p->st));
+    CPHIFI_HIP(hipStreamWaitEvent(p->side, p->fork_ev, 0));
+    vs = p->side;
+  }
+  int rc = p->in.V != nullptr ? launch_copy(p->V, p->in.V, (int64_t)r * r, vs)
+                              : launch_gram(p->in.A, p->I, p->in.B, p->J, r, p->V, vs);
+  if (rc == CPHIFI_OK) rc = launch_jacobi_eig(p->V, r, p->UV, p->dV, vs);
+  if (rc == CPHIFI_OK)
+    rc = launch_precond_diag(p->in.dK, p->dV, p->n, r, p->gamma, p->d.lambda, p->d.rho, p->D,
+                             vs);
+  if (vs != p->st) {
+    // join whatever was enqueued, also after a failed launch
+    CPHIFI_HIP(hipEventRecord(p->join_ev, vs));
+    p->join_pending = true;
+  }
+  TRY(rc);
+  // The FP32 factor copies of the low-precision gather follow A and B, which
+  // may have changed since the plan was made (alternating optimisation).
+  if (p->fgram != nullptr) TRY(launch_fiber_gram(p->in.B, p->J, r, p->fgram, p->st));
+  if (p->a32 != nullptr) {
+    TRY(launch_to_f32(p->a32, p->in.A, p->I * r, p->st));
+    TRY(launch_to_f32(p->b32, p->in.B, p->J * r, p->st));
+  }
+  TRY(launch_clamp_nonneg(p->in.dK, p->dKc, p->n, p->st));
+  p->setup_done = true;
+  return CPHIFI_OK;
 }
 
 }  // namespace
@@ -1364,25 +1438,7 @@ int cphifi_ui_setup(cphifi_plan* p) {
     set_error("plan is NULL");
     return CPHIFI_INVALID_ARG;
   }
-  const int r = (int)p->r;
-  if (p->in.V != nullptr) {
-    TRY(launch_copy(p->V, p->in.V, (int64_t)r * r, p->st));
-  } else {
-    TRY(launch_gram(p->in.A, p->I, p->in.B, p->J, r, p->V, p->st));
-  }
-  TRY(launch_jacobi_eig(p->V, r, p->UV, p->dV, p->st));
-  // The FP32 factor copies of the low-precision gather follow A and B, which
-  // may have changed since the plan was made (alternating optimisation).
-  if (p->fgram != nullptr) TRY(launch_fiber_gram(p->in.B, p->J, r, p->fgram, p->st));
-  if (p->a32 != nullptr) {
-    TRY(launch_to_f32(p->a32, p->in.A, p->I * r, p->st));
-    TRY(launch_to_f32(p->b32, p->in.B, p->J * r, p->st));
-  }
-  TRY(launch_clamp_nonneg(p->in.dK, p->dKc, p->n, p->st));
-  TRY(launch_precond_diag(p->in.dK, p->dV, p->n, r, p->gamma, p->d.lambda, p->d.rho, p->D,
-                          p->st));
-  p->setup_done = true;
-  return CPHIFI_OK;
+  return setup_plan(p, false);
 }
 
 int cphifi_ui_rhs(cphifi_plan* p, const double* y, double* b) {
@@ -1456,7 +1512,10 @@ int cphifi_ui_solve(cphifi_plan* p, const double* b, double* W, cphifi_solve_inf
   std::memset(info, 0, sizeof(*info));
   info->history = hist;
   p->ev_used = 0;
-  if (p->d.precision == CPHIFI_FP64) return solve_fp64(p, b, W, info);
+  if (p->d.precision == CPHIFI_FP64) {
+    TRY(join_setup(p));
+    return solve_fp64(p, b, W, info);
+  }
   return solve_mixed(p, b, nullptr, W, info);
 }
 
@@ -1467,22 +1526,33 @@ int cphifi_ui_solve_subproblem(cphifi_plan* p, const double* y, double* W,
     set_error("solve_subproblem: bad arguments");
     return CPHIFI_INVALID_ARG;
   }
-  TRY(cphifi_ui_setup(p));
-  if (p->d.precision == CPHIFI_FP64) {
-    TRY(cphifi_ui_rhs(p, y, p->vec[V_B]));
-    return cphifi_ui_solve(p, p->vec[V_B], W, info);
-  }
-  // Mixed forms: the refinement starts from Bm (no pass over K for b).
-  if (y == nullptr && p->q > 0) {
+  if (p->d.precision != CPHIFI_FP64 && y == nullptr && p->q > 0) {
     set_error("solve_subproblem: y is NULL");
     return CPHIFI_INVALID_ARG;
   }
-  TRY(mttkrp(p, y, p->vec[V_B]));
-  double* hist = info->history;
-  std::memset(info, 0, sizeof(*info));
-  info->history = hist;
-  p->ev_used = 0;
-  return solve_mixed(p, nullptr, p->vec[V_B], W, info);
+  // The setup's eig(V) chain overlaps the right-hand side (the gather and
+  // one n x n pass); the solves join it before their first preconditioner
+  // application, and every return joins it, so nothing of this call is left
+  // outside the plan's stream.
+  int rc = setup_plan(p, true);
+  if (rc == CPHIFI_OK) {
+    if (p->d.precision == CPHIFI_FP64) {
+      rc = cphifi_ui_rhs(p, y, p->vec[V_B]);
+      if (rc == CPHIFI_OK) rc = cphifi_ui_solve(p, p->vec[V_B], W, info);
+    } else {
+      // Mixed forms: the refinement starts from Bm (no pass over K for b).
+      rc = mttkrp(p, y, p->vec[V_B]);
+      if (rc == CPHIFI_OK) {
+        double* hist = info->history;
+        std::memset(info, 0, sizeof(*info));
+        info->history = hist;
+        p->ev_used = 0;
+        rc = solve_mixed(p, nullptr, p->vec[V_B], W, info);
+      }
+    }
+  }
+  const int rj = join_setup(p);
+  return rc != CPHIFI_OK ? rc : rj;
 }
 
 int cphifi_ui_plan_destroy(cphifi_plan* p) {

@@ -406,6 +406,50 @@ def test_mixed_subproblem_from_mttkrp_matches_solve_from_b(name, uploaded):
     assert O.e_kw(p.K, host(W1), host(W2)) <= 1e-6
 
 
+@pytest.mark.parametrize("precision,flags,n,r", [
+    ("fp64", "launches", 650, 40), ("fp64", "persistent", 300, 8),
+    ("mixed_bf16", None, 650, 40)])
+def test_subproblem_reused_plan_sees_new_factors(precision, flags, n, r):
+    """cphifi_ui_solve_subproblem runs the setup's eig(V) chain (V, its Jacobi
+    eigenpairs, the eq. fx diagonal) on a second stream beside the right-hand
+    side.  Once the factors change, a reused plan must solve with the new
+    preconditioner: the same W, iteration count and residual history as a
+    fresh plan on the new factors (bitwise: the same kernels on the same
+    inputs), certified by the oracle.  At n = 650 the right-hand side takes
+    far less time than the r = 40 Jacobi sweeps, so a solve that did not wait
+    for the chain would start from the old factors' preconditioner (the
+    persistent launch takes r <= 32: n = 300, r = 8 there)."""
+    p = make_small(33, n=n, I=20, J=30, r=r, q=30 * n, kernel="matern32",
+                   kernel_param=0.1)
+    dp = upload(p)
+    fl = {"launches": C.FLAG_NO_PERSISTENT | C.FLAG_NO_GRAPH,
+          "persistent": C.FLAG_PERSISTENT, None: 0}[flags]
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    s = UISolver(dp, p.lam, p.rho, tol, precision=precision, flags=fl)
+    h = np.zeros(600)
+    W0, i0 = s.solve_subproblem(history=h)
+    assert i0.status == C.OK, i0.as_dict()
+    rng = np.random.default_rng(5)
+    A2 = p.A * (1.0 + 0.5 * rng.standard_normal(p.A.shape))
+    B2 = p.B[::-1].copy() * 1.5
+    dp.A.copy_(dev(A2))
+    dp.B.copy_(dev(B2))
+    h2, h3 = np.zeros(600), np.zeros(600)
+    W2, i2 = s.solve_subproblem(history=h2)
+    W2 = W2.clone()
+    fresh = UISolver(dp, p.lam, p.rho, tol, precision=precision, flags=fl)
+    W3, i3 = fresh.solve_subproblem(history=h3)
+    assert i2.status == C.OK and i3.status == C.OK, (i2.as_dict(), i3.as_dict())
+    assert i2.iters == i3.iters and i2.refine_steps == i3.refine_steps
+    assert np.array_equal(h2, h3)
+    assert torch.equal(W2, W3)
+    Zhat = O.khatri_rao_rows(A2, B2, p.obs_i, p.obs_j)
+    cert = O.relres(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, host(W2))
+    assert cert <= 2 * tol
+    # the new factors change the solution
+    assert rel(host(W2), host(W0)) > 1e-3
+
+
 def test_explicit_zhat_solve(uploaded):
     p, dp = uploaded("ragged-r17")
     Zhat = p.A[p.obs_i] * p.B[p.obs_j]
