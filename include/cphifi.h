@@ -124,6 +124,16 @@ enum cphifi_flags {
                                    flag keeps the launch-by-launch loop */
   CPHIFI_FLAG_NO_PERSISTENT = 2048, /* never take the persistent launch of
                                    CPHIFI_FLAG_PERSISTENT (not even by default) */
+  CPHIFI_FLAG_FP64_RESIDUALS = 4096, /* MIXED_BF16 plans with n >= 4096 keep an
+                                   FP32 copy of U_K^T (4 n round_up(n, 256)
+                                   bytes, made at plan creation) and form the
+                                   refinement residual of a step in FP32 when
+                                   the step can only bring the residual to
+                                   >= 1e-3 of ||b|| (FP32 rounding, ~1e-7 of
+                                   ||b||, is then far below what the next step
+                                   needs); later residuals and the certificate
+                                   stay FP64.  This flag keeps every residual
+                                   in FP64 (no copy) */
   CPHIFI_FLAG_FIBER_COLLAPSE = 512 /* every (time, sample) pair that is observed
                                    at all is observed at all J features once:
                                    the gather-scatter of eqs. vl / yhat1 runs

@@ -43,6 +43,7 @@ FLAG_TOEPLITZ_K = 256
 FLAG_FIBER_COLLAPSE = 512
 FLAG_NO_GRAPH = 1024
 FLAG_NO_PERSISTENT = 2048
+FLAG_FP64_RESIDUALS = 4096
 
 PRECISIONS = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 

@@ -1220,7 +1220,8 @@ struct BatchLayout {
 // given, so the plan needs no transposed copy of U_K.
 cphifi_ui_desc member_desc(const cphifi_ui_desc& d) {
   cphifi_ui_desc m = d;
-  m.flags |= CPHIFI_FLAG_NO_UKT_COPY;
+  // the batched kernel runs its own refinement: no copies for the single-solve path
+  m.flags |= CPHIFI_FLAG_NO_UKT_COPY | CPHIFI_FLAG_FP64_RESIDUALS;
   return m;
 }
 

@@ -65,6 +65,13 @@ constexpr double kInnerLoose = 3e-3;
 // contraction applied once more) is below kCertifyFirst * tol goes straight to
 // the certificate.
 constexpr double kCertifyFirst = 0.1;
+// A refinement step whose residual is predicted (last residual times the
+// last inner tolerance) at >= kF32Residual of ||b|| forms it in FP32 when the
+// plan keeps an FP32 copy of U_K^T: the FP32 rounding of that residual (~1e-7
+// of ||b||; the D_K factors on both sides of U damp it in the ill-conditioned
+// directions, as they damp the BF16 rounding of the inner operator) stays two
+// orders below the 1e-5 or so that the next step reaches.
+constexpr double kF32Residual = 1e-3;
 
 // Thread index behind an opaque register move.  The tiles also run as work
 // items inside the loop of a persistent kernel; there the compiler would hoist

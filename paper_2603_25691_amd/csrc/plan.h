@@ -28,7 +28,7 @@ struct Layout {
   size_t red[3];
   size_t sc, sc2, hist;
   size_t V, UV, dV, D, dKc;
-  size_t ulp, utlp, xthi, xtlo, ukt, a32, b32;
+  size_t ulp, utlp, xthi, xtlo, ukt, a32, b32, ut32;
   size_t toep, fptr, fidx, fgram;  // structured forms (Toeplitz K, fiber collapse)
   size_t total;
   int64_t ldl;
@@ -63,6 +63,14 @@ inline bool small_plan(const cphifi_ui_desc& d) {
 }
 inline bool keeps_ukt(const cphifi_ui_desc& d) {
   return (d.n >= kUktMinN && !(d.flags & CPHIFI_FLAG_NO_UKT_COPY)) || small_plan(d);
+}
+// MIXED_BF16 plans of this size or larger keep an FP32 copy of U_K^T for the
+// early refinement residuals (see CPHIFI_FLAG_FP64_RESIDUALS): there an FP64
+// pass over U_K costs ~1.5 ms (n = 30658), an FP32 one about half.
+constexpr int64_t kUt32MinN = 4096;
+inline bool keeps_ut32(const cphifi_ui_desc& d) {
+  return d.precision == CPHIFI_MIXED_BF16 && d.n >= kUt32MinN &&
+         !(d.flags & CPHIFI_FLAG_FP64_RESIDUALS);
 }
 inline int eff_maxit(const cphifi_ui_desc& d) { return d.maxit > 0 ? d.maxit : 500; }
 
@@ -104,6 +112,8 @@ struct cphifi_plan {
   void* ulp = nullptr;   // U_K rounded: U (BF16 form only; 16 x 64 tiles)
   void* utlp = nullptr;  // U_K rounded: U^T, eigenvector k = row k (FP32 row-major,
                          // BF16 in 16 x 64 tiles)
+  float* ut32 = nullptr; // BF16 plans: U^T in FP32 as well, for the early
+                         // refinement residuals (keeps_ut32), or NULL
   __bf16 *xthi = nullptr, *xtlo = nullptr;
   double* toep = nullptr;      // FLAG_TOEPLITZ_K: the first row c of K
   int32_t* fptr = nullptr;     // FLAG_FIBER_COLLAPSE: fibers of time s are
@@ -113,6 +123,7 @@ struct cphifi_plan {
   bool small = false;          // FLAG_PERSISTENT taken: the persistent PCG (small.hip)
   hipGraphExec_t pcg_graph = nullptr;  // captured FP64 PCG iterations (paper form)
   GemmPlan gp64n{}, gp64t{}, gplpn{}, gplpt{};  // NN / transposed product plans
+  GemmPlan gp32n{}, gp32t{};                    // the same on ut32
   int last_ksplit = 1;  // split-K depth of the partials the last product wrote
   DevScalars* h_sc = nullptr;  // host mirror (mapped, coherent) ...
   DevScalars* d_sc = nullptr;  // ... and its device address

@@ -99,6 +99,7 @@ Layout make_layout(const cphifi_ui_desc& d) {
   } else if (d.precision == CPHIFI_MIXED_FP32) {
     L.utlp = take(sizeof(float) * (size_t)n * L.ldl);
   }
+  if (keeps_ut32(d)) L.ut32 = take(sizeof(float) * (size_t)n * L.ldl);
   L.total = align_up(off, kAlign);
   return L;
 }
@@ -185,11 +186,20 @@ int prod_U(cphifi_plan* p, Elt elt, const double* X, const double* xscale,
                       xscale, p->part, done, p->st));
       p->last_ksplit = p->gp64t.ksplit;
       break;
-    case Elt::F32:
-      TRY(launch_gemm(Elt::F32, true, p->gplpt, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
-                      xscale, p->part, done, p->st));
-      p->last_ksplit = p->gplpt.ksplit;
+    case Elt::F32: {
+      // the FP32 plan's own copy, or a BF16 plan's FP32 copy of U^T
+      const bool own = p->lp == Elt::F32;
+      const GemmPlan& gp = own ? p->gplpt : p->gp32t;
+      const void* m = own ? p->utlp : (const void*)p->ut32;
+      if (m == nullptr) {
+        set_error("internal: FP32 product without an FP32 copy of U_K");
+        return CPHIFI_INVALID_ARG;
+      }
+      TRY(launch_gemm(Elt::F32, true, gp, m, p->L.ldl, p->n, X, p->r, (int)p->r, xscale,
+                      p->part, done, p->st));
+      p->last_ksplit = gp.ksplit;
       break;
+    }
     case Elt::BF16:
       TRY(launch_gemm_bf16(p->gplpn, (const __bf16*)p->ulp, p->L.ldl, p->n, X, p->r, (int)p->r,
                            xscale, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st, true));
@@ -221,11 +231,19 @@ int prod_Ut(cphifi_plan* p, Elt elt, const double* X, const int32_t* done,
         p->last_ksplit = p->gp64n.ksplit;
       }
       break;
-    case Elt::F32:
-      TRY(launch_gemm(Elt::F32, false, p->gplpn, p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
-                      nullptr, p->part, done, p->st));
-      p->last_ksplit = p->gplpn.ksplit;
+    case Elt::F32: {
+      const bool own = p->lp == Elt::F32;
+      const GemmPlan& gp = own ? p->gplpn : p->gp32n;
+      const void* m = own ? p->utlp : (const void*)p->ut32;
+      if (m == nullptr) {
+        set_error("internal: FP32 product without an FP32 copy of U_K");
+        return CPHIFI_INVALID_ARG;
+      }
+      TRY(launch_gemm(Elt::F32, false, gp, m, p->L.ldl, p->n, X, p->r, (int)p->r, nullptr,
+                      p->part, done, p->st));
+      p->last_ksplit = gp.ksplit;
       break;
+    }
     case Elt::BF16:
       TRY(launch_gemm_bf16(p->gplpn, (const __bf16*)p->utlp, p->L.ldl, p->n, X, p->r, (int)p->r,
                            nullptr, p->part, p->xthi, p->xtlo, p->L.ldl, done, p->st, true));
@@ -798,6 +816,7 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
   // those of K to working accuracy), and every later step starts from the
   // certificate's own residual b - A W, rotated by U^T.
   bool true_res = false;
+  double last_step_tol = 0.0;  // none yet: a warm start's first residual is FP64
   TRY(join_setup(p));  // the inner PCG applies the eq. fx preconditioner
   for (;;) {
     // The residual of xbar in the eigenbasis.
@@ -825,7 +844,12 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
       true_res = true;
       TRY(rotate_in(p, Elt::F64, p->vec[V_RF], rbar));
     } else {
-      TRY(op_apply_eig(p, Elt::F64, xbar, p->vec[V_Q], nullptr, nullptr, nullptr));
+      // FP32 when the residual is predicted large enough (kF32Residual)
+      const Elt re = p->ut32 != nullptr && last_step_tol > 0.0 &&
+                             rel * last_step_tol >= kF32Residual
+                         ? Elt::F32
+                         : Elt::F64;
+      TRY(op_apply_eig(p, re, xbar, p->vec[V_Q], nullptr, nullptr, nullptr));
       TRY(launch_copy(rbar, bbar, len, p->st));
       TRY(launch_axpby(rbar, -1.0, p->vec[V_Q], 1.0, len, nullptr, p->st));
     }
@@ -864,6 +888,7 @@ int solve_mixed(cphifi_plan* p, const double* b, const double* Bm, double* W,
     TRY(run_pcg(p, A, M, rbar, p->vec[V_XB], false, step_tol, maxit,
                 PcgVecs{p->vec[V_R2], p->vec[V_Z2], p->vec[V_P2], p->vec[V_Q2]}, p->sc, nullptr,
                 0, &o, true));
+    last_step_tol = step_tol;
     total_inner += o.iters;
     if (o.status == CPHIFI_NUMERIC) {
       status = CPHIFI_NUMERIC;
@@ -1405,6 +1430,13 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
                                   true)) ||
         (rc = launch_convert_lowp(Elt::BF16, true, in->UK, p->ldk, n, p->ulp, L.ldl, st, true)))
       return fail(rc);
+    if (keeps_ut32(*d)) {
+      p->ut32 = (float*)(ws + L.ut32);
+      p->gp32n = choose_gemm(Elt::F32, false, n, rr, p->num_cu);
+      p->gp32t = choose_gemm(Elt::F32, true, n, rr, p->num_cu);
+      if ((rc = launch_convert_lowp(Elt::F32, false, in->UK, p->ldk, n, p->ut32, L.ldl, st)))
+        return fail(rc);
+    }
   } else if (d->precision == CPHIFI_MIXED_FP32) {
     p->lp = Elt::F32;
     p->timed_elt = Elt::F32;

@@ -42,6 +42,23 @@ def test_workspace_holds_transposed_eigenvectors_from_4096():
         c.make_desc(4095, r, 100000, 100, 20, flags=c.FLAG_NO_UKT_COPY))
 
 
+def test_bf16_workspace_holds_fp32_eigenvectors_from_4096():
+    """MIXED_BF16 plans with n >= 4096 keep U_K^T in FP32 too (row pitch
+    round_up(n, 256)) for the early refinement residuals, unless
+    CPHIFI_FLAG_FP64_RESIDUALS; other precisions never do."""
+    n, r = 5000, 10
+    ldl = -(-n // 256) * 256
+
+    def ws(nn, precision, flags=0):
+        return c.cphifi_ui_workspace_bytes(c.make_desc(nn, r, 100000, 100, 20,
+                                                       precision=precision, flags=flags))
+    diff = ws(n, c.MIXED_BF16) - ws(n, c.MIXED_BF16, c.FLAG_FP64_RESIDUALS)
+    assert 4 * n * ldl <= diff <= 4 * n * ldl + 512
+    for prec in (c.FP64, c.MIXED_FP32):
+        assert ws(n, prec) == ws(n, prec, c.FLAG_FP64_RESIDUALS)
+    assert ws(4095, c.MIXED_BF16) == ws(4095, c.MIXED_BF16, c.FLAG_FP64_RESIDUALS)
+
+
 def test_workspace_grows_with_problem_and_precision():
     small = c.cphifi_ui_workspace_bytes(c.make_desc(200, 5, 2000, 20, 10))
     big = c.cphifi_ui_workspace_bytes(c.make_desc(3000, 40, 600000, 100, 200))

@@ -676,6 +676,35 @@ def test_c3_recipe_at_reduced_size():
     assert O.e_kw(p.K, host(Wb), tight.X) <= 1e-6
 
 
+def test_mixed_fp32_early_residual():
+    """MIXED_BF16 plans with n >= 4096 form the refinement residual of a step
+    that can only bring it to >= 1e-3 of ||b|| in FP32 (a copy of U_K^T in
+    FP32); CPHIFI_FLAG_FP64_RESIDUALS keeps every residual in FP64.  Both forms
+    must meet tol by the oracle's own residual of the returned W and agree to
+    e_KW 1e-6, and the FP32 form must run fewer FP64 products (the timed FP64
+    launches of CPHIFI_FLAG_TIME_FP64): the large-case recipe at I = 140
+    (n = 4283, q = 8.6e5, r = 40)."""
+    p = config_c3(I=140)
+    assert p.n >= 4096
+    dp = upload(p)
+    Zhat = O.khatri_rao_rows(p.A, p.B, p.obs_i, p.obs_j)
+    tol = 1e-7
+    timed = C.FLAG_TIME_KERNELS | C.FLAG_TIME_FP64
+    out = {}
+    for name, fl in (("fp32", 0), ("fp64", C.FLAG_FP64_RESIDUALS)):
+        s = UISolver(dp, p.lam, p.rho, tol, precision="mixed_bf16", flags=fl | timed)
+        W, info = s.solve_subproblem()
+        assert info.status == C.OK, (name, info.as_dict())
+        cert = O.relres(p.K, Zhat, p.obs_t, p.y, p.lam, p.rho, host(W))
+        assert cert <= 2 * tol, (name, cert)
+        assert abs(cert - info.relres_true) <= 0.05 * tol + 1e-3 * cert
+        out[name] = (host(W), info)
+    (W32, i32), (W64, i64) = out["fp32"], out["fp64"]
+    assert O.e_kw(p.K, W32, W64) <= 1e-6
+    assert i32.refine_steps >= 2 and i64.refine_steps >= 2
+    assert i32.gemm_launches < i64.gemm_launches, (i32.as_dict(), i64.as_dict())
+
+
 def _perturbed_eig(p, delta, seed):
     """Eigenpairs of K + E, E symmetric with ||E||_2 = delta ||K||_2: a
     caller's eigendecomposition that is off by delta."""
