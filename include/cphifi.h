@@ -30,8 +30,11 @@
  *    eigenvectors of K in LAPACK (column-major) order: eigenvector k occupies
  *    UK[k*ldk + 0 .. k*ldk + n-1], with eigenvalue dK[k].
  *  - All work is enqueued on the plan's HIP stream (`stream`, a hipStream_t;
- *    NULL = the null stream).  Functions marked "async" return before the GPU
- *    finishes; those marked "sync" synchronise the stream before returning.
+ *    NULL = the null stream); cphifi_ui_solve_subproblem also forks part of
+ *    its setup onto a second stream of the plan and joins it back into the
+ *    plan's stream before it returns.  Functions marked "async" return before
+ *    the GPU finishes; those marked "sync" synchronise the stream before
+ *    returning.
  *  - Every function returns a status code (CPHIFI_*).  No exception crosses
  *    the ABI.  On failure cphifi_last_error() gives a thread-local message.
  *  - The library never allocates device memory on the solve path: the caller
