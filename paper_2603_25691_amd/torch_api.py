@@ -399,7 +399,7 @@ def product(U: torch.Tensor, X: torch.Tensor, elt: str = "fp64", trans: bool = F
             else:
                 mw, s = (4, 4) if r <= 48 else (2, 4)
         else:
-            mw, s = (4, 4) if trans else (2, 4)
+            mw, s = (4, 4) if trans or (n >= 4096 and r <= 48) else (2, 4)
     ws_bytes = _c.cphifi_product_workspace_bytes(n, r, e)
     if workspace is None or workspace.numel() < ws_bytes + 256:
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=X.device)

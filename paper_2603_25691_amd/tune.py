@@ -49,15 +49,15 @@ ESIZE = {"fp64": 8, "fp32": 4, "bf16": 2}
 
 def _operand(elt: str, n: int, gen: torch.Generator, ld_align: int = 1) -> torch.Tensor:
     U = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=gen)
-    if elt == "fp64":
+    if elt in ("fp64", "fp32"):
+        if elt == "fp32":
+            U = U.float()
         ld = (n + ld_align - 1) // ld_align * ld_align
         if ld == n:
             return U
-        Up = torch.zeros(n, ld, dtype=torch.float64, device="cuda")
+        Up = torch.zeros(n, ld, dtype=U.dtype, device="cuda")
         Up[:, :n] = U
         return Up[:, :n]  # row stride ld
-    if elt == "fp32":
-        return U.float()
     ld = (n + 255) // 256 * 256
     Ub = torch.zeros(n, ld, dtype=torch.bfloat16, device="cuda")
     Ub[:, :n] = U.to(torch.bfloat16)
@@ -220,7 +220,7 @@ def main(argv=None):
     s.add_argument("--out", default="tiles.txt")
     s.add_argument("--reps", type=int, default=5)
     s.add_argument("--ld-align", type=int, default=1,
-                   help="FP64 operand row stride rounded up to a multiple of this")
+                   help="FP64 / FP32 operand row stride rounded up to a multiple of this")
     m = sub.add_parser("measure")
     m.add_argument("--n", type=int, required=True)
     m.add_argument("--r", type=int, required=True)
@@ -228,7 +228,7 @@ def main(argv=None):
     m.add_argument("--reps", type=int, default=4)
     m.add_argument("--calib-mb", type=int, default=1024)
     m.add_argument("--ld-align", type=int, default=1,
-                   help="FP64 operand row stride rounded up to a multiple of this")
+                   help="FP64 / FP32 operand row stride rounded up to a multiple of this")
     m.add_argument("--trans", action="store_true",
                    help="the transposed product (FP64 / FP32 only)")
     b = sub.add_parser("batch")
