@@ -32,7 +32,8 @@
  *  - All work is enqueued on the plan's HIP stream (`stream`, a hipStream_t;
  *    NULL = the null stream); cphifi_ui_solve_subproblem also forks part of
  *    its setup onto a second stream of the plan and joins it back into the
- *    plan's stream before it returns.  Functions marked "async" return before
+ *    plan's stream before it returns.  Call a plan's functions with the
+ *    device that was current at its creation (its stream's) current.  Functions marked "async" return before
  *    the GPU finishes; those marked "sync" synchronise the stream before
  *    returning.
  *  - Every function returns a status code (CPHIFI_*).  No exception crosses

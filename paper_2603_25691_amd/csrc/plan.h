@@ -137,7 +137,8 @@ struct cphifi_plan {
   // Side stream of the whole-subproblem solve: the setup's eig(V) chain (V,
   // its Jacobi eigendecomposition, the eq. fx diagonal) runs there, forked
   // from and joined back into st, while st forms the right-hand side.
-  hipStream_t side = nullptr;
+  hipStream_t side = nullptr;  // made on the plan's device (`device`)
+  int device = 0;               // device current at plan creation
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool join_pending = false;  // st has not yet waited for join_ev
   bool timing = false;

@@ -999,10 +999,18 @@ void release_host(cphifi_plan* p) {
 // the setup then runs in order on the plan's stream.
 bool make_side(cphifi_plan* p) {
   if (p->side != nullptr) return true;
+  // on the plan's device, whichever is current
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess ||
+      (cur != p->device && hipSetDevice(p->device) != hipSuccess)) {
+    (void)hipGetLastError();
+    return false;
+  }
   bool ok = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming) == hipSuccess &&
             // default priority, like every stream of the library
             hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) == hipSuccess;
+  if (cur != p->device) (void)hipSetDevice(cur);
   if (!ok) {
     (void)hipGetLastError();  // leave no error for the next launch check
     for (hipEvent_t* e : {&p->fork_ev, &p->join_ev})
@@ -1269,6 +1277,7 @@ int cphifi_ui_plan_create(cphifi_plan** out, const cphifi_ui_desc* d, const cphi
   }
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) {
+    p->device = dev;
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         cu > 0)
